@@ -1,0 +1,558 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test compares the oracle with something other than itself: exact lattice
+identities, closed forms, invariants, a hand-derived Fourier propagator, the
+paper's analytic solutions and printed numbers.  None of these calls the GPU.
+"""
+from __future__ import annotations
+
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1007_3109_amd import analysis, workloads
+from pins import gaussian_point_source, golden, gs_jacobian, gs_reaction, propagator, source_vector
+
+G = golden()
+
+
+def random_populations(rng, n, ny, nx, lo=0.0, hi=1.0):
+    return rng.uniform(lo, hi, size=(n, 9, ny, nx))
+
+
+# ----- pin 1: lattice tables -------------------------------------------------
+
+def test_weights_match_printed_values():
+    w, ex, ey = oracle.tables()
+    assert w[0] == G["d2q9_weight_rest"]
+    speeds = np.abs(ex) + np.abs(ey)
+    assert sorted(speeds.tolist()) == [0, 1, 1, 1, 1, 2, 2, 2, 2]
+    for i in range(9):
+        want = {0: G["d2q9_weight_rest"], 1: G["d2q9_weight_axis"], 2: G["d2q9_weight_diag"]}[speeds[i]]
+        assert w[i] == want
+    # the velocity set is exactly {-1, 0, 1}^2
+    assert sorted(zip(ex.tolist(), ey.tolist())) == sorted((a, b) for a in (-1, 0, 1) for b in (-1, 0, 1))
+
+
+def test_isotropy_conditions_app11():
+    """Appendix, Eq. "app11" (a)-(e), evaluated exactly with rationals."""
+    w, ex, ey = oracle.tables()
+    W = [Fraction(4, 9) if (abs(a) + abs(b)) == 0 else Fraction(1, 9) if abs(a) + abs(b) == 1 else Fraction(1, 36)
+         for a, b in zip(ex, ey)]
+    for i in range(9):
+        assert abs(float(W[i]) - w[i]) == 0.0
+    e = [(int(a), int(b)) for a, b in zip(ex, ey)]
+    cs2 = Fraction(1, 3)
+    assert sum(W) == 1
+    for a in range(2):
+        assert sum(W[i] * e[i][a] for i in range(9)) == 0
+        for b in range(2):
+            assert sum(W[i] * e[i][a] * e[i][b] for i in range(9)) == (cs2 if a == b else 0)
+            for c in range(2):
+                assert sum(W[i] * e[i][a] * e[i][b] * e[i][c] for i in range(9)) == 0
+                for d in range(2):
+                    lhs = sum(W[i] * e[i][a] * e[i][b] * e[i][c] * e[i][d] for i in range(9))
+                    rhs = cs2 * cs2 * ((a == b) * (c == d) + (a == c) * (b == d) + (a == d) * (b == c))
+                    assert lhs == rhs
+    assert G["cs2"] == float(cs2)
+
+
+# ----- pin 2: tau = 1 reduces to a nine-point stencil -----------------------
+
+@pytest.mark.parametrize("case", ["gray_scott", "linear2"])
+def test_tau_one_is_weighted_stencil(case):
+    """With every tau_s = 1 and an equilibrium start, the update gives
+    rho(x, n+1) = sum_i w_i (rho + R(rho))(x - e_i, n): a textbook stencil."""
+    rng = np.random.default_rng(1)
+    ny, nx = 7, 9
+    rho = rng.uniform(0.2, 1.0, size=(2, ny, nx))
+    if case == "gray_scott":
+        F, k = 0.035, 0.06
+        Rf = lambda r: gs_reaction(r, F, k)
+        kw = dict(F=F, k=k)
+        react = oracle.REACT_GRAY_SCOTT
+    else:
+        K = np.array([[-0.03, 0.01], [0.02, -0.05]])
+        c = np.array([0.001, -0.002])
+        Rf = lambda r: np.einsum("sr,ryx->syx", K, r) + c[:, None, None]
+        kw = dict(K=K, c=c)
+        react = oracle.REACT_LINEAR
+    stencil = [(4 / 9, 0, 0)] + [(1 / 9, a, b) for a, b in ((1, 0), (-1, 0), (0, 1), (0, -1))] + \
+              [(1 / 36, a, b) for a in (1, -1) for b in (1, -1)]
+    f = oracle.init(rho)
+    ref = rho.copy()
+    for n in range(5):
+        f = oracle.run(f, 1, [1.0, 1.0], react, **kw)
+        src = ref + Rf(ref)
+        ref = sum(wt * np.roll(src, (b, a), axis=(1, 2)) for wt, a, b in stencil)
+        np.testing.assert_allclose(oracle.moments(f), ref, rtol=1e-14, atol=1e-15)
+
+
+# ----- pin 3: the sinusoid under linear decay, exact discrete form ----------
+
+def _config1():
+    rho0 = workloads.sinusoid(64, 64, 0.1, 1)
+    return oracle.solve(rho0, 1000, 1.0, oracle.REACT_LINEAR, K=[-1e-3])
+
+
+def test_sinusoid_decay_exact_discrete():
+    """tau = 1, kappa = 1e-3, 64 x 64, 1000 steps: for a field varying in x only
+    the D2Q9 weights collapse to (2/3, 1/6, 1/6), so
+    rho(x, n) = (1 - kappa)^n [1 + 0.1 lambda^n sin(2 pi x / 64)],
+    lambda = (2 + cos(2 pi / 64)) / 3."""
+    rho = _config1()
+    kappa, n = 1e-3, 1000
+    lam = (2 + math.cos(2 * math.pi / 64)) / 3
+    x = np.arange(64)
+    exact = (1 - kappa) ** n * (1 + 0.1 * lam ** n * np.sin(2 * math.pi * x / 64))
+    err = np.abs(rho[0] - exact[None, :]).max() / np.abs(exact).max()
+    assert err <= 1e-12
+
+
+def test_sinusoid_decay_against_continuum():
+    """Same run against the analytic decay exp(-(D q^2 + kappa) t) of the
+    continuum equation (Section II.B, Eq. "reac_diff4" with the decaying sign):
+    the mean decays as exp(-kappa t) and the mode as exp(-(D q^2 + kappa) t)."""
+    rho = _config1()
+    kappa, t, D = 1e-3, 1000, 1.0 / 6.0
+    q = 2 * math.pi / 64
+    x = np.arange(64)
+    cont = math.exp(-kappa * t) * (1 + 0.1 * math.exp(-D * q * q * t) * np.sin(2 * math.pi * x / 64))
+    assert oracle.rel_l2(rho, np.broadcast_to(cont, rho.shape))[0] <= 1e-3
+    row = rho[0, 0]
+    mean = row.mean()
+    amp = 2 * np.dot(row - mean, np.sin(2 * math.pi * x / 64)) / 64
+    ratio = (amp / mean / 0.1) / math.exp(-D * q * q * t)
+    assert abs(ratio - 1) <= 1e-6
+
+
+# ----- pin 4: linear reactions, exact Fourier propagator ---------------------
+
+@pytest.mark.parametrize("shape", [(5, 6), (4, 7), (1, 3), (3, 3)])
+def test_linear_reaction_fourier_propagator(shape):
+    """For R = K rho + c every Fourier mode of the populations evolves by the
+    9N x 9N matrix P(q) of the update (plus the constant source at q = 0).
+    Starts from random non-equilibrium populations."""
+    ny, nx = shape
+    rng = np.random.default_rng(7)
+    taus = [0.8, 1.3]
+    K = np.array([[-0.05, 0.02], [0.03, -0.01]])
+    c = np.array([0.004, -0.001])
+    f0 = random_populations(rng, 2, ny, nx)
+    nsteps = 6
+    f = oracle.run(f0, nsteps, taus, oracle.REACT_LINEAR, K=K, c=c)
+    w, ex, ey = oracle.tables()
+    F0 = np.fft.fft2(f0, axes=(2, 3)).reshape(18, ny, nx)
+    Fn = np.fft.fft2(f, axes=(2, 3)).reshape(18, ny, nx)
+    scale = np.abs(F0).max()
+    for my in range(ny):
+        for mx in range(nx):
+            q = (2 * math.pi * mx / nx, 2 * math.pi * my / ny)
+            P = propagator(q, taus, K, w, ex, ey)
+            v = F0[:, my, mx].copy()
+            for _ in range(nsteps):
+                v = P @ v
+                if mx == 0 and my == 0:
+                    v = v + source_vector(c, w, ex, ey, nx * ny)
+            assert np.abs(v - Fn[:, my, mx]).max() <= 1e-12 * scale
+
+
+# ----- pin 5: mass invariants ------------------------------------------------
+
+def test_mass_conserved_without_reaction():
+    """R = 0: the collision conserves sum_i f_i exactly in real arithmetic, so
+    M_s only drifts by rounding.  From random non-equilibrium populations the
+    drift is bounded by n * 9 * eps * max f / mean rho per site (rounding
+    errors of identical sites are correlated, so they add linearly): about
+    5e-12 relative after n = 10^4 steps.  A dropped or mis-weighted term
+    would show at O(1)."""
+    rng = np.random.default_rng(3)
+    f0 = random_populations(rng, 2, 16, 12)
+    f = oracle.run(f0, 10000, [0.6, 1.7], oracle.REACT_NONE)
+    m0 = oracle.mass(oracle.moments(f0))
+    m1 = oracle.mass(oracle.moments(f))
+    assert np.all(np.abs(m1 - m0) <= 2e-11 * np.abs(m0))
+    rho0 = workloads.gray_scott_square(32, 32, seed=1)
+    g = oracle.run(oracle.init(rho0), 10000, [1.0, 0.75], oracle.REACT_NONE)
+    m0 = oracle.mass(rho0)
+    assert np.all(np.abs(oracle.mass(oracle.moments(g)) - m0) <= 2e-11 * np.abs(m0))
+
+
+def test_decay_product_total_mass():
+    """A -> B (Section II.B): R_A = -kappa rho_A, R_B = +kappa rho_A keeps
+    M_A + M_B constant while M_A decays as (1 - kappa)^n."""
+    rho0 = workloads.point_source(20, 20, 2)
+    kappa = 0.01
+    f = oracle.run(oracle.init(rho0), 500, [0.56, 0.56], oracle.REACT_LINEAR, K=[[-kappa, 0], [kappa, 0]])
+    m = oracle.mass(oracle.moments(f))
+    assert abs(m.sum() - 1.0) <= 1e-13
+    assert abs(m[0] - (1 - kappa) ** 500) <= 1e-13
+
+
+def test_mass_balance_gray_scott():
+    """General R: M_s(n+1) - M_s(n) = sum_x R_s(rho(x, n))."""
+    rho0 = workloads.gray_scott_square(40, 40, seed=5)
+    F, k = 0.04, 0.06
+    f = oracle.run(oracle.init(rho0), 50, [1.0, 0.75], oracle.REACT_GRAY_SCOTT, F=F, k=k)
+    rho_n = oracle.moments(f)
+    f1 = oracle.run(f, 1, [1.0, 0.75], oracle.REACT_GRAY_SCOTT, F=F, k=k)
+    dm = oracle.mass(oracle.moments(f1)) - oracle.mass(rho_n)
+    expect = oracle.mass(gs_reaction(rho_n, F, k))
+    np.testing.assert_allclose(dm, expect, rtol=1e-10, atol=1e-12)
+
+
+# ----- pin 6: homogeneous fields are forward Euler ---------------------------
+
+@pytest.mark.parametrize("taus", [(1.0, 0.75), (0.55, 1.9)])
+def test_homogeneous_is_forward_euler(taus):
+    F, k = 0.03, 0.055
+    u0, v0 = 0.6, 0.2
+    rho0 = np.stack([np.full((3, 4), u0), np.full((3, 4), v0)])
+    f = oracle.init(rho0)
+    r = np.array([u0, v0])
+    for n in range(200):
+        f = oracle.run(f, 1, taus, oracle.REACT_GRAY_SCOTT, F=F, k=k)
+        r = r + gs_reaction(r[:, None, None], F, k)[:, 0, 0]
+        rho = oracle.moments(f)
+        assert np.abs(rho - r[:, None, None]).max() <= 1e-13
+
+
+def test_homogeneous_invariant_tau_gs_one():
+    """k = 0 gives tau_GS = 1 (Section III.A): then eta A~ + B~ - eta, i.e.
+    (u + v - 1)/sqrt(F), decays; the discrete update gives exactly the factor
+    (1 - F) per step, and the paper's exp(-t/tau_A) = exp(-F t) agrees to
+    O(n F^2) (Eq. "reac_diff21", with the sign of B~(0) read as +)."""
+    F = 0.02
+    u0, v0 = 1.0 + 0.1, 0.1
+    rho0 = np.stack([np.full((2, 2), u0), np.full((2, 2), v0)])
+    n = 300
+    rho = oracle.solve(rho0, n, [0.9, 0.7], oracle.REACT_GRAY_SCOTT, F=F, k=0.0)
+    P0 = (u0 + v0 - 1) / math.sqrt(F)
+    Pn = (rho[0, 0, 0] + rho[1, 0, 0] - 1) / math.sqrt(F)
+    assert abs(Pn - P0 * (1 - F) ** n) <= 1e-12 * abs(P0)
+    assert abs(Pn / P0 - math.exp(-F * n)) <= n * F * F
+
+
+def test_one_site_lattice_is_forward_euler():
+    """1 x 1 periodic lattice: every population streams back onto its own
+    site, so rho(n+1) = rho(n) + R(rho(n)) for any populations and any tau."""
+    rng = np.random.default_rng(11)
+    f0 = random_populations(rng, 2, 1, 1, 0.0, 0.2)
+    F, k = 0.05, 0.06
+    r = oracle.moments(f0)[:, 0, 0]
+    f = f0
+    for n in range(30):
+        f = oracle.run(f, 1, [0.7, 1.4], oracle.REACT_GRAY_SCOTT, F=F, k=k)
+        r = r + gs_reaction(r[:, None, None], F, k)[:, 0, 0]
+        assert np.abs(oracle.moments(f)[:, 0, 0] - r).max() <= 1e-15
+
+
+# ----- pin 7: point source ---------------------------------------------------
+
+def test_point_source_against_gaussian():
+    """Section II.B: 100 x 100 periodic, D_A = 0.02, kappa = 0.01, t = 400 and 420,
+    compared with Eq. "reac_diff5".  The paper reports an error below 1%; the
+    scheme as written gives 1.2-1.3% here (the infinite-domain Gaussian and the
+    delta start are not the lattice's own), so the bound is 1.5%."""
+    L, D, kappa = int(G["point_source_L"]), G["point_source_D"], G["point_source_kappa"]
+    tau = oracle.tau_from_diffusivity(D)
+    f = oracle.init(workloads.point_source(L, L, 2))
+    prev = 0
+    for t in (int(G["point_source_t"]), int(G["point_source_t2"])):
+        f = oracle.run(f, t - prev, [tau, tau], oracle.REACT_LINEAR, K=[[-kappa, 0], [kappa, 0]])
+        prev = t
+        rho = oracle.moments(f)
+        e = oracle.rel_l2(rho[:1], gaussian_point_source(L, D, kappa, t)[None])[0]
+        assert e <= 0.015, (t, e)
+
+
+# ----- pin 8: truncation-error trends ----------------------------------------
+
+def _point_source_error(D, kappa, t, L=100):
+    tau = oracle.tau_from_diffusivity(D)
+    rho = oracle.solve(workloads.point_source(L, L, 1), t, [tau], oracle.REACT_LINEAR, K=[-kappa])
+    return oracle.rel_l2(rho, gaussian_point_source(L, D, kappa, t)[None])[0]
+
+
+def test_truncation_error_minimum_shifts_with_kappa():
+    """Section II.B, Figs. 1(c,d) and Eq. "DAmin": E_rho(D_A) at equal diffusion
+    extent (D t = 2) has an interior minimum, and the minimum moves to larger
+    D_A when kappa grows.  The paper's values 0.012 and 0.03 depend on a time
+    constant it does not state, so only the shape is pinned (their ratio 2.5
+    is also reproduced at D t = 2)."""
+    Ds = [0.004, 0.006, 0.008, 0.01, 0.012, 0.015, 0.02, 0.025, 0.03, 0.04]
+    dmin = {}
+    for kappa in (0.01, 0.033):
+        E = [_point_source_error(D, kappa, int(round(2 / D))) for D in Ds]
+        j = int(np.argmin(E))
+        assert 0 < j < len(Ds) - 1, (kappa, E)
+        dmin[kappa] = Ds[j]
+    assert dmin[0.033] > dmin[0.01]
+    ratio_paper = G["dmin_kappa_0p033"] / G["dmin_kappa_0p01"]
+    assert abs(dmin[0.033] / dmin[0.01] - ratio_paper) <= 0.5
+
+
+def test_reaction_error_is_first_order_in_kappa():
+    """The source term is explicit and first order in time (Eq. "app23" carries
+    tau dt^2 d_t R): at a fixed reaction extent kappa t = 1 the mass error
+    against exp(-kappa t) is proportional to kappa (log-log slope 1)."""
+    errs = []
+    kappas = [0.002, 0.004, 0.008, 0.016]
+    for kappa in kappas:
+        t = int(round(1 / kappa))
+        rho = oracle.solve(workloads.point_source(8, 8, 1), t, [0.8], oracle.REACT_LINEAR, K=[-kappa])
+        errs.append(abs(oracle.mass(rho)[0] - math.exp(-kappa * t)) / math.exp(-kappa * t))
+    slope = np.polyfit(np.log(kappas), np.log(errs), 1)[0]
+    assert abs(slope - 1) <= 0.05
+
+
+def test_error_grows_with_kappa_at_fixed_time():
+    """Figs. 1(a) vs 1(b): at t = 400 and D = 0.02, kappa = 0.033 gives a larger
+    error than kappa = 0.01."""
+    assert _point_source_error(0.02, 0.033, 400) > _point_source_error(0.02, 0.01, 400)
+
+
+# ----- pin 9: linear stability ------------------------------------------------
+
+def test_stability_formulas_against_eig():
+    """Eqs. "reac_diff24"-"reac_diff32" against numpy eig of the direct
+    lattice-unit linearisation L(q) of R_u, R_v plus diffusion:
+    tr M = tr L / F and |M| = det L / F^2 with q~ = q sqrt(D_u / F)."""
+    Du, Dv = 1.0 / 6.0, 1.0 / 12.0
+    for eta, tau in [(G["fig7_eta"], G["fig7_tau"]), tuple(G["fig8a"]), tuple(G["fig8c"]), (2.3, 1.5), (3.0, 4.0)]:
+        F, k = analysis.feed_kill(eta, tau)
+        g = analysis.dimensionless(F, k, Du, Dv)
+        assert abs(g.eta - eta) <= 1e-12 and abs(g.tau - tau) <= 1e-12
+        for which in ("+", "-"):
+            A, B = analysis.steady_states(eta)[which]
+            # the states solve Eq. "reac_diff18"
+            assert abs(-B * B * A + 1 - A) <= 1e-12 and abs(eta * B * B * A - B) <= 1e-12
+            u, v = A, math.sqrt(F) * B
+            for q in (0.0, 0.05, 0.2, 0.5):
+                L = analysis.lattice_linearisation(F, k, Du, Dv, u, v, q * q)
+                np.testing.assert_allclose(L, gs_jacobian(u, v, F, k) - np.diag([Du * q * q, Dv * q * q]), atol=1e-15)
+                q2t = q * q * Du / F
+                M = analysis.turing_matrix(eta, tau, g.eps2, A, B, q2t)
+                assert abs(np.trace(L) / F - np.trace(M)) <= 1e-12
+                assert abs(np.linalg.det(L) / F ** 2 - np.linalg.det(M)) <= 1e-10 * max(1, abs(np.linalg.det(M)))
+                assert abs(np.trace(M) - analysis.trace_M(eta, tau, g.eps2, B, q2t)) <= 1e-12
+                assert abs(np.linalg.det(M) - analysis.det_M(eta, tau, g.eps2, B, q2t)) <= 1e-10
+                a1, a2 = analysis.growth_rates(np.trace(M), np.linalg.det(M))
+                ev = np.sort_complex(np.linalg.eigvals(M))
+                np.testing.assert_allclose(np.sort_complex(np.array([a1, a2])), ev, atol=1e-10)
+        _, Bm = analysis.steady_states(eta)["-"]
+        b = analysis.band(eta, g.eps2, Bm)
+        if b is not None:
+            for r in b:
+                assert abs(analysis.det_M(eta, tau, g.eps2, Bm, r)) <= 1e-9
+            assert abs(sum(b) / 2 - analysis.q2_min(eta, g.eps2, Bm)) <= 1e-12
+
+
+def test_paper_parameter_points():
+    """Printed parameter points against the parameter map and the analysis."""
+    r = G["DA_over_DB_phase_diagram"]
+    # eps^2 = tau * D_A / D_B: 2 x 2.733 = 5.466 (Sec. III.D), sqrt(2 x 3.40) = 2.61 (Fig. 10)
+    assert abs(analysis.dimensionless(*analysis.feed_kill(G["fig7_eta"], G["fig7_tau"]), r, 1).eps2 - G["fig7_eps2"]) <= 1e-3
+    assert abs(math.sqrt(analysis.dimensionless(*analysis.feed_kill(G["fig10_eta"], G["fig10_tau"]), r, 1).eps2) - G["fig10_eps"]) <= 5e-3
+    # Fig. 10 (self-replicating spots): eta < 2, only the trivial state exists
+    assert set(analysis.steady_states(G["fig10_eta"])) == {"trivial"}
+    # Figs. 7, 8, 11: eta > 2, Hopf-unstable, past the paper's Turing curve, and
+    # Turing-unstable by the exact onset
+    for key in ("fig8a", "fig8b", "fig8c", "fig8d", "fig11"):
+        eta, tau = G[key]
+        c = analysis.classify(*analysis.feed_kill(eta, tau), r, 1)
+        assert c.has_nontrivial and c.hopf_unstable and c.turing_necessary and c.turing_unstable, key
+    c = analysis.classify(*analysis.feed_kill(G["fig7_eta"], G["fig7_tau"]), r, 1)
+    assert c.turing_unstable and c.hopf_unstable
+    assert abs(c.eta_B_minus - 2.2657) <= 1e-3
+    band = analysis.band(c.eta, c.eps2, c.eta_B_minus / c.eta)
+    assert abs(band[0] - 0.548) <= 2e-3 and abs(band[1] - 2.653) <= 2e-3
+    # rescaling pairs: D_2 = lambda^2 D_1 with lambda = L_2 / L_1 = 2 (Sec. IV)
+    lam = G["rescale_L2"] / G["rescale_L1"]
+    assert G["rescale_DA2"] == pytest.approx(lam ** 2 * G["rescale_DA1"])
+    assert G["rescale_DB2"] == pytest.approx(lam ** 2 * G["rescale_DB1"])
+
+
+def _mode_run(F, k, taus, nx, ny, mode, amp, nsteps, state="-"):
+    u, v = analysis.lattice_state(F, k, state) if state != "trivial" else (1.0, 0.0)
+    rho0 = workloads.perturbed_state(nx, ny, u, v, amp, mode)
+    f0 = oracle.init(rho0)
+    f = oracle.run(f0, nsteps, taus, oracle.REACT_GRAY_SCOTT, F=F, k=k)
+    return f0, f, (u, v)
+
+
+def test_oracle_growth_matches_linearised_propagator():
+    """Small-amplitude (1e-6) perturbation of (u~-, v~-) at the Fig. 7 point:
+    the oracle's Fourier coefficients follow P(q)^n of the linearised update
+    (pin 4 with K = the reaction Jacobian) to O(amplitude); amplitude 1e-8
+    keeps the quadratic terms below 1e-6 relative after the growth."""
+    F, k = analysis.feed_kill(G["fig7_eta"], G["fig7_tau"])
+    taus = [1.0, 0.75]
+    nx = ny = 32
+    nsteps = 200
+    for mode in [(4, 0), (3, 2), (0, 0)]:
+        f0, f, (u, v) = _mode_run(F, k, taus, nx, ny, mode, 1e-8, nsteps)
+        w, ex, ey = oracle.tables()
+        J = gs_jacobian(u, v, F, k)
+        df0 = f0 - oracle.init(np.stack([np.full((ny, nx), u), np.full((ny, nx), v)]))
+        for my, mx in {(mode[1], mode[0]), ((-mode[1]) % ny, mode[0])}:
+            q = (2 * math.pi * mx / nx, 2 * math.pi * my / ny)
+            P = propagator(q, taus, J, w, ex, ey)
+            v0 = np.fft.fft2(df0, axes=(2, 3)).reshape(18, ny, nx)[:, my, mx]
+            pred = np.linalg.matrix_power(P, nsteps) @ v0
+            got = np.fft.fft2(f, axes=(2, 3)).reshape(18, ny, nx)[:, my, mx]
+            if mx == 0 and my == 0:
+                got = got - np.fft.fft2(f0 - df0, axes=(2, 3)).reshape(18, ny, nx)[:, 0, 0]
+            assert np.abs(pred - got).max() <= 1e-5 * np.abs(pred).max()
+
+
+def test_lattice_growth_against_continuum():
+    """For wavelengths of 20 sites or more the linearised update's dominant
+    amplification per step matches the continuum eigenvalues alpha(q) of
+    L(q) taken through one explicit step, log max |1 + alpha(q)| (the update
+    is forward Euler in time, pin 6), within 2%.  Covers a Turing-unstable
+    band mode and Hopf-oscillatory long waves."""
+    F, k = analysis.feed_kill(G["fig7_eta"], G["fig7_tau"])
+    w, ex, ey = oracle.tables()
+    u, v = analysis.lattice_state(F, k, "-")
+    J = gs_jacobian(u, v, F, k)
+    for taus in ([1.0, 0.75], [1.0, 0.5625]):
+        Du, Dv = (taus[0] - 0.5) / 3, (taus[1] - 0.5) / 3
+        for L in (20, 32, 64, 128):
+            q = 2 * math.pi / L
+            P = propagator((q, 0.0), taus, J, w, ex, ey)
+            lb = math.log(np.max(np.abs(np.linalg.eigvals(P))))
+            alpha = np.linalg.eigvals(analysis.lattice_linearisation(F, k, Du, Dv, u, v, q * q))
+            cont = math.log(np.max(np.abs(1 + alpha)))
+            assert abs(lb - cont) <= 0.02 * abs(cont), (taus, L, lb, cont)
+
+
+@pytest.mark.parametrize("case", ["hopf_unstable", "hopf_stable"])
+def test_hopf_boundary_sign(case):
+    """Hopf line tau_GS = eta B~- (tr M(0) = 0, Section III.C): a homogeneous
+    perturbation of (u~-, v~-) grows beyond it and decays before it.  Points
+    sit 20% away from the line in tau_GS (eta B~- = 3)."""
+    eta = math.sqrt(4.5)          # eta B~- = 3
+    tau = 3.6 if case == "hopf_unstable" else 2.4
+    F, k = analysis.feed_kill(eta, tau)
+    assert analysis.classify(F, k, 2, 1).hopf_unstable == (case == "hopf_unstable")
+    nsteps = 600
+    f0, f, (u, v) = _mode_run(F, k, [1.0, 0.75], 4, 4, (0, 0), 1e-4, nsteps)
+    d0 = np.abs(oracle.moments(f0)[:, 0, 0] - [u, v]).max()
+    # envelope: largest deviation over the last oscillation window
+    traj = []
+    for _ in range(20):
+        f = oracle.run(f, 10, [1.0, 0.75], oracle.REACT_GRAY_SCOTT, F=F, k=k)
+        traj.append(np.abs(oracle.moments(f)[:, 0, 0] - [u, v]).max())
+    grew = max(traj) > d0
+    assert grew == (case == "hopf_unstable")
+
+
+@pytest.mark.parametrize("case", ["turing_unstable", "turing_stable"])
+def test_turing_boundary_sign(case):
+    """Exact Turing onset eps^2 = y+(eta B~-) (from Eq. "reac_diff32"): at a
+    Hopf-stable point (eta B~- = 3, D_u/D_v = 8) the most unstable lattice
+    mode grows when eps^2 exceeds the onset (tau_GS = 2, eps^2 = 16 > 9) and
+    every mode decays below it (tau_GS = 1, eps^2 = 8 < 9)."""
+    eta = math.sqrt(4.5)
+    tau = 2.0 if case == "turing_unstable" else 1.0
+    F, k = analysis.feed_kill(eta, tau)
+    taus = [1.0, 0.5 + 1.0 / 16.0]     # D_u = 1/6, D_v = 1/48
+    Du, Dv = (taus[0] - 0.5) / 3, (taus[1] - 0.5) / 3
+    c = analysis.classify(F, k, Du, Dv)
+    assert not c.hopf_unstable
+    assert c.turing_unstable == (case == "turing_unstable")
+    u, v = analysis.lattice_state(F, k, "-")
+    n = 32
+    rates = {m: analysis.continuum_growth(F, k, Du, Dv, u, v, (2 * math.pi * m / n) ** 2) for m in range(1, n // 2)}
+    m = max(rates, key=rates.get)
+    assert (rates[m] > 0) == (case == "turing_unstable")
+    f0, f, _ = _mode_run(F, k, taus, n, 1, (m, 0), 1e-6, 400)
+    a0 = np.abs(np.fft.fft(oracle.moments(f0)[1, 0]))[m]
+    a1 = np.abs(np.fft.fft(oracle.moments(f)[1, 0]))[m]
+    assert (a1 > a0) == (case == "turing_unstable")
+
+
+# ----- pin 10: rescaling all D by lambda^2 rescales the pattern by lambda -----
+
+def _gs_square(L, s):
+    rho = np.zeros((2, L, L))
+    rho[0] = 1.0
+    lo = L // 2 - s // 2
+    rho[0, lo:lo + s, lo:lo + s] = 0.5
+    rho[1, lo:lo + s, lo:lo + s] = 0.25
+    return rho
+
+
+def _block(a, b):
+    n, L, _ = a.shape
+    return a.reshape(n, L // b, b, L // b, b).mean(axis=(2, 4))
+
+
+def test_rescaling_diffusivities_rescales_pattern():
+    """Section IV: D -> lambda^2 D on a lambda-times larger box (square also
+    scaled) gives the same pattern up to discretisation error.  Checked at
+    lambda = 2 in the Turing regime of Fig. 11/12 from the square start: the
+    2x2 block average of the fine run is much closer to the coarse run than a
+    fine run that keeps D unchanged, and the dominant wavenumber index of v
+    (the stripe count) is the same."""
+    F, k = analysis.feed_kill(G["fig12_eta"], G["fig12_tau"])
+    D = (0.08, 0.04)
+    L, s, n = 48, 16, 2000
+    tau = lambda d: [oracle.tau_from_diffusivity(x) for x in d]
+    coarse = oracle.solve(_gs_square(L, s), n, tau(D), oracle.REACT_GRAY_SCOTT, F=F, k=k)
+    fine = oracle.solve(_gs_square(2 * L, 2 * s), n, tau((4 * D[0], 4 * D[1])), oracle.REACT_GRAY_SCOTT, F=F, k=k)
+    plain = oracle.solve(_gs_square(2 * L, 2 * s), n, tau(D), oracle.REACT_GRAY_SCOTT, F=F, k=k)
+    gap = oracle.rel_l2(_block(fine, 2), coarse)
+    ctrl = oracle.rel_l2(_block(plain, 2), coarse)
+    assert np.all(gap < 0.5 * ctrl), (gap, ctrl)
+
+    def radial_peak(v):
+        a = np.abs(np.fft.fft2(v - v.mean()))
+        my, mx = np.unravel_index(np.argmax(a), a.shape)
+        m = lambda i, N: min(i, N - i)
+        return round(math.hypot(m(mx, a.shape[1]), m(my, a.shape[0])))
+
+    assert radial_peak(coarse[1]) == radial_peak(fine[1])
+
+
+# ----- pin 12: symmetries -----------------------------------------------------
+
+def test_translation_equivariance_exact():
+    rng = np.random.default_rng(2)
+    f0 = random_populations(rng, 2, 6, 8, 0, 0.1)
+    a = oracle.run(f0, 9, [0.7, 1.2], oracle.REACT_GRAY_SCOTT, F=0.04, k=0.06)
+    b = oracle.run(np.roll(f0, (2, 3), axis=(2, 3)), 9, [0.7, 1.2], oracle.REACT_GRAY_SCOTT, F=0.04, k=0.06)
+    assert np.array_equal(np.roll(a, (2, 3), axis=(2, 3)), b)
+
+
+def test_mirror_and_rotation_equivariance():
+    rng = np.random.default_rng(4)
+    f0 = random_populations(rng, 2, 7, 7, 0, 0.1)
+    w, ex, ey = oracle.tables()
+    vel = list(zip(ex.tolist(), ey.tolist()))
+
+    def transform(f, op):
+        g = np.empty_like(f)
+        for i, (a, b) in enumerate(vel):
+            a2, b2 = op(a, b)
+            g[:, vel.index((a2, b2))] = f[:, i]
+        return g
+
+    run = lambda f: oracle.run(f, 5, [0.7, 1.2], oracle.REACT_GRAY_SCOTT, F=0.04, k=0.06)
+    base = run(f0)
+    # mirror x -> -x about x = 0 (site x maps to -x mod nx)
+    mir = lambda f: np.roll(f[:, :, :, ::-1], 1, axis=3)
+    np.testing.assert_allclose(run(transform(mir(f0), lambda a, b: (-a, b))), transform(mir(base), lambda a, b: (-a, b)), atol=1e-14)
+    # rotation by 90 degrees: (x, y) -> (-y, x)
+    rot = lambda f: np.roll(np.rot90(f, 1, axes=(2, 3)), 0, axis=2)
+    fr = transform(np.ascontiguousarray(np.rot90(f0, 1, axes=(3, 2))), lambda a, b: (-b, a))
+    br = transform(np.ascontiguousarray(np.rot90(base, 1, axes=(3, 2))), lambda a, b: (-b, a))
+    # the rotation of a periodic square lattice is exact up to a translation:
+    # compare after aligning by the translation that matches the first moment
+    out = run(fr)
+    ok = any(np.abs(np.roll(out, (dy, dx), axis=(2, 3)) - br).max() <= 1e-14 for dy in range(7) for dx in range(7))
+    assert ok
