@@ -1,0 +1,216 @@
+"""Benchmark of the reacting-species D2Q9 lattice Boltzmann step on one MI355X.
+
+Workload timed for the headline line: Gray-Scott (u, v), D2Q9 BGK, 1024 x 1024
+periodic, FP32 storage, tau = (1.0, 0.75), F = 0.04, k = 0.06, central 64 x 64
+square with u = 0.5, v = 0.25 plus U(-0.01, 0.01) noise (seed 0).  One "step"
+is one lattice time step of the whole field (every species, every site):
+collide, react and stream, one fused kernel launch.
+
+The JSON line carries the headline MLUPS per species, the roofline of the
+step kernel (algorithmic bytes: every population read once and written once,
+2 * 9 * sizeof(storage) bytes per species-site-step, over the kernel time
+measured with HIP events on the launch stream), the FP64 oracle timed on the
+host cores, and extra legs: the 4096^2 lattices (working set larger than the
+256 MB Infinity Cache) in FP32 / FP16 / BF16 storage, the batched sweep and
+the continuous-batching server.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, 8 TB/s
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(nspecies, sites, storage_bytes):
+    return 2 * 9 * storage_bytes * nspecies * sites
+
+
+def time_solver(torch, s, steps, warmup):
+    """Warm up, then time exactly `steps` steps between two events on the
+    solver's stream, bracketed by device synchronisation."""
+    s.step(warmup)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(st)
+    s.step(steps)
+    e1.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / 1e3, wall
+
+
+def gs_config(lbrd, workloads, n, storage):
+    extra = dict(rho_ref=(1.0, 0.0)) if storage in ("f16", "bf16") else {}
+    return lbrd.make_config(n, n, 2, tau=workloads.GS_TAU, storage=storage, reaction="gray_scott",
+                            F=workloads.GS_F, k=workloads.GS_K, **extra)
+
+
+def cpu_baseline(workloads, n, budget_s):
+    """The FP64 oracle on the host cores, on a bounded sample: the same
+    1024^2 Gray-Scott field, stepped in chunks until `budget_s` of CPU time."""
+    import oracle
+
+    rho0 = workloads.gray_scott_square(n, n, seed=0)
+    f = oracle.init(rho0)
+    steps = 0
+    chunk = 5
+    t0 = time.perf_counter()
+    while True:
+        f = oracle.run(f, chunk, list(workloads.GS_TAU), oracle.REACT_GRAY_SCOTT, F=workloads.GS_F,
+                       k=workloads.GS_K)
+        steps += chunk
+        el = time.perf_counter() - t0
+        if el >= budget_s or steps >= 4000:
+            break
+    mlups = 2 * n * n * steps / el / 1e6
+    return {"value": round(mlups, 2), "unit": "MLUPS per species", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"Gray-Scott {n}x{n}, FP64 oracle (C, OpenMP), {steps} steps from the benchmark's initial "
+                      f"state, {el:.1f} s"}
+
+
+def hbm_leg(torch, lbrd, workloads, n, storage, steps, warmup):
+    cfg = gs_config(lbrd, workloads, n, storage)
+    s = lbrd.Solver(cfg)
+    s.init(workloads.gray_scott_square(n, n, seed=0))
+    secs, _ = time_solver(torch, s, steps, warmup)
+    b = {"f32": 4, "f16": 2, "bf16": 2, "f64": 8}[storage]
+    sites = n * n
+    per_step = secs / steps
+    gbs = algorithmic_bytes(2, sites, b) / per_step / 1e9
+    out = {"workload": f"gray_scott {n}x{n} {storage}", "steps": steps, "ms_per_step": round(per_step * 1e3, 4),
+           "mlups_per_species": round(2 * sites / per_step / 1e6, 1), "achieved_GBs": round(gbs, 1),
+           "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4), "tuning": s.tuning().as_dict()}
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    return out
+
+
+def batch_leg(torch, lbrd, workloads, steps, warmup, seed=0):
+    insts = workloads.batch_sweep(seed)
+    cfgs = [lbrd.make_config(i.side, i.side, 2, tau=workloads.GS_TAU, storage="f32", reaction="gray_scott",
+                             F=i.F, k=i.k) for i in insts]
+    b = lbrd.Batch(cfgs)
+    t = b.autotune(steps=3)
+    for idx, inst in enumerate(insts):
+        b.init(idx, workloads.batch_initial(inst))
+    b.step(warmup)
+    torch.cuda.synchronize()
+    ms = b.time_steps(steps)
+    species_sites = sum(2 * i.side * i.side for i in insts)
+    mlups = species_sites * steps / (ms / 1e3) / 1e6
+    gbs = species_sites * 72 * steps / (ms / 1e3) / 1e9
+    # the plain single-lattice kernel on the same instances, one after another
+    solo_ms = 0.0
+    solo_steps = 20
+    for inst in insts:
+        s = lbrd.Solver(lbrd.make_config(inst.side, inst.side, 2, tau=workloads.GS_TAU, storage="f32",
+                                         reaction="gray_scott", F=inst.F, k=inst.k))
+        s.set_tuning(graph_steps=0)
+        s.init(workloads.batch_initial(inst))
+        s.step(2)
+        solo_ms += s.time_steps(solo_steps)
+        s.close()
+    solo_mlups = species_sites * solo_steps / (solo_ms / 1e3) / 1e6
+    out = {"workload": f"{len(insts)} Gray-Scott instances, sides {sorted(set(i.side for i in insts))}, FP32",
+           "species_sites": species_sites, "steps": steps, "ms_per_step": round(ms / steps, 4),
+           "mlups_per_species": round(mlups, 1), "achieved_GBs": round(gbs, 1),
+           "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4), "tuning": t.as_dict(),
+           "plain_kernel_one_by_one_mlups_per_species": round(solo_mlups, 1)}
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--extra-steps", type=int, default=300)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_1007_3109_amd import lbrd, workloads
+
+    torch.cuda.set_device(0)
+    n = 1024
+    cfg = gs_config(lbrd, workloads, n, "f32")
+    s = lbrd.Solver(cfg)
+    s.init(workloads.gray_scott_square(n, n, seed=0))
+    log(f"bench: Gray-Scott {n}x{n} f32, warmup {args.warmup}, steps {args.steps}")
+    secs, wall = time_solver(torch, s, args.steps, args.warmup)
+    sites = n * n
+    ms_per_step = secs / args.steps * 1e3
+    value = 2 * sites * args.steps / secs / 1e6
+    bytes_per_launch = algorithmic_bytes(2, sites, 4)
+    achieved = bytes_per_launch / (secs / args.steps) / 1e9
+    _, mass = s.moments()
+    line = {
+        "metric": "MLUPS per species and % HBM roofline; batched p50/p99 solve latency",
+        "value": round(value, 1),
+        "unit": "MLUPS per species",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "gray_scott_1024x1024_f32", "lattice": [n, n], "species": 2, "storage": "f32",
+                   "tau": list(workloads.GS_TAU), "F": workloads.GS_F, "k": workloads.GS_K, "seed": 0,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "note": "1024^2 x 2 species x 9 x 2 buffers x 4 B = 151 MB ping-pong: resident in the 256 MB "
+                             "Infinity Cache; see extra.hbm_4096_* for working sets beyond it"},
+        "wall_s": round(wall, 3),
+        "mass_after": [float(m) for m in mass],
+        "tuning": s.tuning().as_dict(),
+    }
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        log("bench: cpu baseline (oracle)")
+        line["cpu_baseline"] = cpu_baseline(workloads, n, args.cpu_budget)
+    if not args.no_extra:
+        extra = {}
+        for storage in ("f32", "f16", "bf16"):
+            log(f"bench: 4096^2 {storage}")
+            extra[f"hbm_4096_{storage}"] = hbm_leg(torch, lbrd, workloads, 4096, storage, args.extra_steps, 20)
+        log("bench: batched sweep")
+        extra["batched"] = batch_leg(torch, lbrd, workloads, 200, 10)
+        line["extra"] = extra
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,269 @@
+/*
+ * lbrd.h — C ABI of the MI355X (gfx950) reacting-species D2Q9 lattice
+ * Boltzmann library.
+ *
+ * The method (Ayodele, Varnik & Raabe, "Lattice Boltzmann study of pattern
+ * formation in reaction-diffusion systems", Section II.A, second Eq. "relax";
+ * Appendix, Eq. "app1"): for every species s = 1..N and velocity i = 0..8 of
+ * the D2Q9 lattice (weights 4/9, 1/9, 1/36, Eq. "Weights"),
+ *
+ *   f_{i,s}(x + e_i, t + 1) = f_{i,s}(x, t)
+ *                             + (w_i rho_s(x,t) - f_{i,s}(x,t)) / tau_s
+ *                             + w_i R_s(rho_1..rho_N)(x, t),
+ *
+ * with rho_s = sum_i f_{i,s}, the zero-velocity equilibrium w_i rho_s
+ * (Eq. "equili"), periodic boundaries in x and y (Section II.B, Section IV)
+ * and D_s = (tau_s - 1/2) / 3 in lattice units (Section II.A, last sentence).
+ *
+ * Conventions shared by every entry point:
+ *  - Every function returns an int status: LBRD_OK (0) or a negative
+ *    LBRD_E* code; lbrd_strerror() names it.  No C++ exception and no abort
+ *    crosses this boundary.
+ *  - "Device pointer" means memory allocated on the GPU the handle was created
+ *    on (e.g. a torch tensor's data_ptr()); "host pointer" means ordinary CPU
+ *    memory.  The caller owns every buffer it passes; the library owns only
+ *    its opaque host-side handles and never frees caller memory.
+ *  - Work is enqueued on the HIP stream given at creation (NULL = the null
+ *    stream) and is asynchronous unless a host output is requested, in which
+ *    case the call synchronises that stream before returning.
+ *  - A handle must be used by one host thread at a time.
+ *  - Density fields are dense row-major arrays rho[s][y][x] (x fastest);
+ *    population fields are dense f[s][i][y][x] in the velocity numbering
+ *    e_0 = (0,0), e_1..e_4 = (1,0), (0,1), (-1,0), (0,-1),
+ *    e_5..e_8 = (1,1), (-1,1), (-1,-1), (1,-1).
+ *  - The state at time t is the post-streaming, pre-collision f_{i,s}(x, t);
+ *    t counts the steps taken since the last init / set_populations.
+ */
+#ifndef LBRD_H
+#define LBRD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBRD_MAX_SPECIES 4
+
+/* Status codes. */
+#define LBRD_OK 0
+#define LBRD_EINVAL (-1)      /* bad argument (range, enum, null pointer, tau <= 1/2) */
+#define LBRD_ENOMEM (-2)      /* workspace or arena too small                        */
+#define LBRD_EDEVICE (-3)     /* a HIP runtime call failed                            */
+#define LBRD_ENONFINITE (-4)  /* a reduction produced NaN or Inf                      */
+#define LBRD_ESTATE (-5)      /* call out of order (e.g. step before init)           */
+#define LBRD_ENOTFOUND (-6)   /* unknown request ticket                               */
+#define LBRD_ETIMEOUT (-7)    /* wait timed out                                       */
+
+/* Population storage forms. */
+#define LBRD_F64 0            /* double populations, double arithmetic               */
+#define LBRD_F32 1            /* float populations, float arithmetic                 */
+#define LBRD_F16_SHIFTED 2    /* binary16 of f - w_i rho_ref_s, float arithmetic     */
+#define LBRD_BF16_SHIFTED 3   /* bfloat16 of f - w_i rho_ref_s, float arithmetic     */
+
+/* Reaction terms R_s. */
+#define LBRD_REACT_NONE 0        /* R_s = 0                                           */
+#define LBRD_REACT_LINEAR 1      /* R_s = sum_j K[s][j] rho_j + c_s (Section II.B:    */
+                                 /* the decay R_A = -kappa rho_A, Eq. "reac_diff3")   */
+#define LBRD_REACT_GRAY_SCOTT 2  /* N = 2, u = species 0, v = species 1:              */
+                                 /* R_u = -u v^2 + F (1 - u), R_v = u v^2 - (F + k) v */
+                                 /* (Section III, Eqs. "reac_diff10", "reac_diff11"   */
+                                 /* with A_0 = k_1 = 1, F = k_f, k = k_2)             */
+
+/* Element types of density / population arrays crossing the boundary. */
+#define LBRD_DTYPE_F64 0
+#define LBRD_DTYPE_F32 1
+
+typedef struct lbrd_config {
+    int32_t nspecies;     /* N, 1..LBRD_MAX_SPECIES (2 for GRAY_SCOTT)               */
+    int32_t nx, ny;       /* periodic lattice size, each >= 1                          */
+    int32_t storage;      /* LBRD_F64 / LBRD_F32 / LBRD_F16_SHIFTED / LBRD_BF16_SHIFTED */
+    int32_t reaction;     /* LBRD_REACT_*                                              */
+    int32_t reserved;     /* must be 0                                                 */
+    double tau[LBRD_MAX_SPECIES];      /* relaxation times, each > 1/2                 */
+    double rho_ref[LBRD_MAX_SPECIES];  /* storage shift (16-bit forms only)            */
+    double K[LBRD_MAX_SPECIES * LBRD_MAX_SPECIES]; /* LINEAR: K[s*N + j]              */
+    double c[LBRD_MAX_SPECIES];        /* LINEAR: constant source                      */
+    double F, k;                       /* GRAY_SCOTT: feed and kill rates              */
+} lbrd_config;
+
+/* Kernel launch shape.
+ *  vec: sites per lane along x (2 for F64; 2 or 4 for F32; 4 or 8 for the
+ *       16-bit forms).  Single solvers only.
+ *  lanes_x: lanes per row segment, a power of two 1..64 (0 = choose from nx).
+ *       Single solvers only.
+ *  waves: waves (64 lanes) per workgroup: 1, 2 or 4.
+ *  nontemporal: 1 = streaming (non-temporal) loads and stores.
+ *  graph_steps: steps per captured HIP graph (0 = plain launches; else even).
+ *  blocks_per_cu: persistent workgroups per compute unit (1..32); batches only. */
+typedef struct lbrd_tuning {
+    int32_t vec;
+    int32_t lanes_x;
+    int32_t waves;
+    int32_t nontemporal;
+    int32_t graph_steps;
+    int32_t blocks_per_cu;
+    int32_t reserved[2];
+} lbrd_tuning;
+
+const char *lbrd_strerror(int status);
+
+/* Library version string; never NULL. */
+const char *lbrd_version(void);
+
+/* Text of the last LBRD_EDEVICE failure on the calling thread ("" if none). */
+const char *lbrd_last_error(void);
+
+/* ---------------------------------------------------------------- solver -- */
+
+typedef struct lbrd_solver lbrd_solver;
+
+/* Check a configuration without touching the GPU.  LBRD_EINVAL names no field;
+ * every rule is listed on lbrd_config. */
+int lbrd_validate(const lbrd_config *cfg);
+
+/* Bytes of device workspace a solver of this configuration needs (two
+ * population buffers plus reduction scratch).  Host-only. */
+int lbrd_workspace_size(const lbrd_config *cfg, size_t *bytes);
+
+/* Create a solver on the current HIP device.  workspace: device pointer to at
+ * least lbrd_workspace_size() bytes, 256-byte aligned, owned by the caller and
+ * kept alive until lbrd_destroy.  stream: hipStream_t or NULL.
+ * Errors: EINVAL (config, null out, misaligned workspace), ENOMEM (too
+ * small), EDEVICE. */
+int lbrd_create(const lbrd_config *cfg, void *workspace, size_t bytes, void *stream, lbrd_solver **out);
+
+/* Release the handle (NULL is accepted).  Does not free the workspace. */
+int lbrd_destroy(lbrd_solver *h);
+
+/* Initial state f_{i,s}(x, 0) = w_i rho0_s(x) (Eq. "equili"; the paper does
+ * not state the initial populations), t = 0.  rho0: dense [N][ny][nx] of
+ * dtype LBRD_DTYPE_F64/F32, a device pointer if on_device != 0, else a host
+ * pointer (copied before return). */
+int lbrd_init(lbrd_solver *h, const void *rho0, int dtype, int on_device);
+
+/* Set / read the full state as dense f[N][9][ny][nx] (the numbering above).
+ * set: t = 0 afterwards; host or device source.  get: device destination. */
+int lbrd_set_populations(lbrd_solver *h, const void *f, int dtype, int on_device);
+int lbrd_get_populations(lbrd_solver *h, void *f_out, int dtype);
+
+/* Advance nsteps >= 0 time steps, asynchronously on the stream.
+ * ESTATE before init. */
+int lbrd_step(lbrd_solver *h, int64_t nsteps);
+
+/* Densities rho_s(x, t) = sum_i f_{i,s}(x, t) (Section II.A, after Eq.
+ * "relax").  rho_out: device [N][ny][nx] of dtype, or NULL.  mass_out: host
+ * double[N] receiving M_s = sum_x rho_s(x, t) accumulated in FP64 on the GPU
+ * with a fixed reduction order, or NULL; if given, the call synchronises and
+ * returns ENONFINITE when any M_s is NaN or Inf. */
+int lbrd_moments(lbrd_solver *h, void *rho_out, int dtype, double *mass_out);
+
+/* Relative L2 error per species E_s = sqrt(sum_x (ref - rho)^2 / sum_x ref^2)
+ * (Section II.B, the definition of E_rho), FP64 on the GPU.  ref: device
+ * [N][ny][nx] of dtype; err_out: host double[N].  Synchronises. */
+int lbrd_rel_l2(lbrd_solver *h, const void *ref, int dtype, double *err_out);
+
+int lbrd_time(const lbrd_solver *h, int64_t *t);
+
+/* Launch shape in use / override it (validated against the storage form). */
+int lbrd_get_tuning(const lbrd_solver *h, lbrd_tuning *out);
+int lbrd_set_tuning(lbrd_solver *h, const lbrd_tuning *t);
+
+/* Time every valid launch shape on this solver's buffers for `steps` steps
+ * each and keep the fastest; writes it to *chosen if not NULL.  Overwrites
+ * the state: the solver must be (re)initialised afterwards (ESTATE until
+ * then).  cache_path: text file of earlier results keyed by (device, storage,
+ * reaction, N, nx, ny), read and appended; NULL disables the cache. */
+int lbrd_autotune(lbrd_solver *h, int steps, const char *cache_path, lbrd_tuning *chosen);
+
+/* Device time in milliseconds of `nsteps` steps measured with HIP events on
+ * the solver's stream (the state advances).  Synchronises. */
+int lbrd_time_steps(lbrd_solver *h, int64_t nsteps, double *ms);
+
+/* --------------------------------------------------------------- batched -- */
+
+/* Many independent lattices (any sizes, parameters, storage forms and
+ * reactions) advanced together: every step is one persistent launch over the
+ * wave tiles of all instances, and lbrd_batch_step replays HIP graphs of
+ * such launches. */
+typedef struct lbrd_batch lbrd_batch;
+
+int lbrd_batch_workspace_size(const lbrd_config *cfgs, int count, size_t *bytes);
+int lbrd_batch_create(const lbrd_config *cfgs, int count, void *workspace, size_t bytes, void *stream,
+                      lbrd_batch **out);
+int lbrd_batch_destroy(lbrd_batch *b);
+/* Same contracts as lbrd_init / lbrd_moments / lbrd_get_populations for
+ * instance idx (0..count-1). */
+int lbrd_batch_init(lbrd_batch *b, int idx, const void *rho0, int dtype, int on_device);
+int lbrd_batch_moments(lbrd_batch *b, int idx, void *rho_out, int dtype, double *mass_out);
+int lbrd_batch_get_populations(lbrd_batch *b, int idx, void *f_out, int dtype);
+/* Advance every instance by nsteps (ESTATE unless all are initialised). */
+int lbrd_batch_step(lbrd_batch *b, int64_t nsteps);
+/* Persistent-launch shape: blocks_per_cu, waves, nontemporal, graph_steps
+ * (vec and lanes_x are chosen per instance from its size and storage). */
+int lbrd_batch_get_tuning(const lbrd_batch *b, lbrd_tuning *out);
+int lbrd_batch_set_tuning(lbrd_batch *b, const lbrd_tuning *t);
+/* Time the persistent-launch candidates and keep the fastest (state is
+ * overwritten; re-initialise afterwards). */
+int lbrd_batch_autotune(lbrd_batch *b, int steps, lbrd_tuning *chosen);
+int lbrd_batch_time_steps(lbrd_batch *b, int64_t nsteps, double *ms);
+
+/* --------------------------------------------------------------- serving -- */
+
+/* Continuous-batching solve server.  Requests (a config, a host initial
+ * density, a step count) are queued on submit; a worker thread admits them
+ * into a caller-owned device arena as footprint allows, advances all resident
+ * requests together in chunks of persistent batched launches, retires
+ * finished ones (densities and FP64 masses copied to host) and frees their
+ * memory for queued requests. */
+typedef struct lbrd_server lbrd_server;
+
+typedef struct lbrd_server_config {
+    int32_t chunk_steps;   /* steps per scheduling round (>= 1)                   */
+    int32_t max_slots;     /* most requests resident at once (>= 1)               */
+    int32_t max_queue;     /* most requests waiting (>= 1); submit returns ENOMEM beyond */
+    int32_t reserved;
+} lbrd_server_config;
+
+typedef struct lbrd_request_info {
+    int32_t state;         /* 0 queued, 1 resident, 2 done, 3 rejected             */
+    int32_t reserved;
+    double submit_s;       /* seconds on the server clock                          */
+    double admit_s;
+    double done_s;         /* result ready on the host                             */
+    int64_t steps;
+    int64_t footprint;     /* device bytes while resident                          */
+} lbrd_request_info;
+
+typedef struct lbrd_server_stats {
+    int64_t submitted, admitted, completed, rejected;
+    int64_t resident, queued;
+    int64_t species_site_steps;   /* sum over completed requests of N * sites * steps */
+    int64_t arena_bytes, arena_peak_used;
+    double busy_s;                /* wall time with at least one resident request   */
+    double clock_s;               /* server clock now                               */
+} lbrd_server_stats;
+
+/* arena: device pointer, 256-byte aligned, owned by the caller until destroy. */
+int lbrd_server_create(const lbrd_server_config *sc, void *arena, size_t bytes, void *stream, lbrd_server **out);
+/* Stops the worker after finishing resident requests; queued ones are dropped. */
+int lbrd_server_destroy(lbrd_server *s);
+/* rho0_host: host double [N][ny][nx], copied before return.  A request whose
+ * footprint exceeds the whole arena is rejected (ENOMEM, no ticket). */
+int lbrd_server_submit(lbrd_server *s, const lbrd_config *cfg, const double *rho0_host, int64_t nsteps,
+                       int64_t *ticket);
+int lbrd_server_info(lbrd_server *s, int64_t ticket, lbrd_request_info *info);
+/* Block until the request is done or timeout_s passes (ETIMEOUT). */
+int lbrd_server_wait(lbrd_server *s, int64_t ticket, double timeout_s);
+/* Copy a finished request's densities (host double [N][ny][nx], or NULL) and
+ * masses (host double[N], or NULL) and forget the ticket. */
+int lbrd_server_take(lbrd_server *s, int64_t ticket, double *rho_out, double *mass_out, lbrd_request_info *info);
+int lbrd_server_stats_get(lbrd_server *s, lbrd_server_stats *out);
+/* Device bytes a request of this configuration occupies while resident. */
+int lbrd_server_footprint(const lbrd_config *cfg, size_t *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBRD_H */

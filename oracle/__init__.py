@@ -87,6 +87,8 @@ def _load():
             fn.argtypes = [ctypes.c_int] * 3 + [pd, ctypes.c_int, pd, ctypes.c_int, pd, P, P, ctypes.c_int64]
             fn.restype = ctypes.c_int
             getattr(lib, f"orc_moments_{sfx}").argtypes = [ctypes.c_int] * 3 + [P, pd]
+            getattr(lib, f"orc_threads_{sfx}").restype = ctypes.c_int
+            getattr(lib, f"orc_encode_{sfx}").argtypes = [ctypes.c_int] * 4 + [pd, P]
             pf = ctypes.POINTER(ctypes.c_float)
             getattr(lib, f"orc_quantise_{sfx}").argtypes = [ctypes.c_int, pf, pf, ctypes.c_int64]
         _lib = lib
@@ -103,6 +105,11 @@ def _dt(precision: str):
 
 def _ptr(a: np.ndarray, ct):
     return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's step runs on."""
+    return int(_load().orc_threads_f64())
 
 
 def tables(precision: str = "f64"):
@@ -160,6 +167,16 @@ def run(f: np.ndarray, nsteps: int, tau, reaction: int = REACT_NONE, *, K=None, 
         _ptr(rref, ctypes.c_double), _ptr(f, ct), _ptr(work, ct), int(nsteps))
     if rc != 0:
         raise ValueError("oracle rejected its arguments")
+    return f
+
+
+def encode(f: np.ndarray, quant: int, rho_ref) -> np.ndarray:
+    """Populations in the 16-bit shifted storage form (float build):
+    w_i rho_ref_s + Q(f - w_i rho_ref_s); returns a new float32 array."""
+    f = np.array(f, dtype=np.float32, copy=True, order="C")
+    n, _, ny, nx = f.shape
+    rref = np.ascontiguousarray(np.asarray(rho_ref, np.float64).reshape(n))
+    _load().orc_encode_f32(n, nx, ny, quant, _ptr(rref, ctypes.c_double), _ptr(f, ctypes.c_float))
     return f
 
 

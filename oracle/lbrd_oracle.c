@@ -29,6 +29,9 @@
 #include <stddef.h>
 #include <string.h>
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #ifndef REAL
 #define REAL double
@@ -62,6 +65,16 @@ static REAL weight(int i)
     if (i == 0) return (REAL)4 / (REAL)9;
     if (i <= 4) return (REAL)1 / (REAL)9;
     return (REAL)1 / (REAL)36;
+}
+
+/* Threads the parallel step uses (1 without OpenMP). */
+int SFX(orc_threads)(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 /* Expose the tables so the tests can check the lattice isotropy conditions
@@ -153,6 +166,21 @@ static REAL quantise(int quant, REAL g)
 void SFX(orc_quantise)(int quant, const float *in, float *out, int64_t n)
 {
     for (int64_t j = 0; j < n; ++j) out[j] = (float)quantise(quant, (REAL)in[j]);
+}
+
+/* Put populations f [N][9][ny][nx] into the 16-bit shifted storage form in
+ * place: f <- w_i rho_ref_s + Q(f - w_i rho_ref_s), Q the 16-bit rounding. */
+void SFX(orc_encode)(int n, int nx, int ny, int quant, const double *rho_ref, REAL *f)
+{
+    for (int s = 0; s < n; ++s)
+        for (int i = 0; i < 9; ++i) {
+            const REAL shift = weight(i) * (REAL)rho_ref[s];
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    REAL *p = &f[idx(nx, ny, s, i, y, x)];
+                    *p = shift + quantise(quant, *p - shift);
+                }
+        }
 }
 
 /* Initial populations: local equilibrium f_{i,s}(x,0) = w_i rho_s(x,0)

@@ -1,0 +1,602 @@
+// Host side of the lbrd C ABI: validation, layout, solver lifecycle, stepping
+// (plain launches or replayed HIP graphs), read-outs and the autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <mutex>
+#include <new>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "lbrd.h"
+#include "lbrd_internal.h"
+#include "lbrd_util.h"
+
+namespace lbrd {
+
+// ------------------------------------------------------------- errors --
+
+static thread_local std::string g_last_error;
+
+void set_error(const char *where, hipError_t e) {
+    g_last_error = std::string(where) + ": " + hipGetErrorString(e);
+}
+
+// ------------------------------------------------------------- layout --
+
+static int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+// Extra bytes between consecutive planes so that the 9N concurrent streams of
+// a step do not start on the same HBM channel.  LBRD_PLANE_SKEW overrides it.
+static int64_t plane_skew_bytes() {
+    static int64_t v = [] {
+        const char *e = std::getenv("LBRD_PLANE_SKEW");
+        if (e) return (int64_t)std::max(0L, std::atol(e)) / 256 * 256;
+        return (int64_t)768;
+    }();
+    return v;
+}
+
+Layout make_layout(const lbrd_config &c) {
+    Layout L;
+    L.nx = c.nx;
+    L.ny = c.ny;
+    L.ns = c.nspecies;
+    L.esize = storage_bytes(c.storage);
+    L.pitch = round_up(c.nx, 64 / L.esize);
+    const int64_t plane = round_up((int64_t)c.ny * L.pitch * L.esize, 256) + plane_skew_bytes();
+    L.pstride = plane / L.esize;
+    L.buf_bytes = (size_t)round_up(9 * (int64_t)c.nspecies * plane, 4096);
+    return L;
+}
+
+template <class C>
+Params<C> make_params(const lbrd_config &c) {
+    Params<C> p;
+    std::memset(&p, 0, sizeof(p));
+    const int n = c.nspecies;
+    const C w[3] = {C(4) / C(9), C(1) / C(9), C(1) / C(36)};
+    for (int s = 0; s < n; ++s) {
+        p.omega[s] = C(1) / C(c.tau[s]);
+        p.keep[s] = C(1) - p.omega[s];
+        for (int i = 0; i < 9; ++i) {
+            const C wi = i == 0 ? w[0] : (i < 5 ? w[1] : w[2]);
+            const bool shifted = c.storage == LBRD_F16_SHIFTED || c.storage == LBRD_BF16_SHIFTED;
+            p.shift[s][i] = shifted ? wi * C(c.rho_ref[s]) : C(0);
+        }
+    }
+    if (c.reaction == LBRD_REACT_LINEAR) {
+        for (int s = 0; s < n; ++s) {
+            for (int j = 0; j < n; ++j) p.K[s * n + j] = C(c.K[s * n + j]);
+            p.c[s] = C(c.c[s]);
+        }
+    }
+    if (c.reaction == LBRD_REACT_GRAY_SCOTT) {
+        p.F = C(c.F);
+        p.k = C(c.k);
+        p.Fk = p.F + p.k;
+    }
+    return p;
+}
+template Params<float> make_params<float>(const lbrd_config &);
+template Params<double> make_params<double>(const lbrd_config &);
+
+static int ilog2(int v) {
+    int s = 0;
+    while ((1 << s) < v) ++s;
+    return s;
+}
+
+Grid make_grid(const Layout &L, const void *src, void *dst, int vec, int lanes_x) {
+    Grid g;
+    g.src = src;
+    g.dst = dst;
+    g.nx = L.nx;
+    g.ny = L.ny;
+    g.pitch = L.pitch;
+    g.pstride = L.pstride;
+    g.lanes_x = lanes_x;
+    g.lx_shift = ilog2(lanes_x);
+    g.nvec = (L.nx + vec - 1) / vec;
+    g.nseg = (g.nvec + lanes_x - 1) / lanes_x;
+    g.rpw = 64 / lanes_x;
+    g.ntiles = (int64_t)g.nseg * ((L.ny + g.rpw - 1) / g.rpw);
+    return g;
+}
+
+int default_vec(int storage) { return 16 / storage_bytes(storage); }
+
+int default_lanes(int nx, int vec) {
+    const int nvec = (nx + vec - 1) / vec;
+    int l = 1;
+    while (l < nvec && l < 64) l <<= 1;
+    return l;
+}
+
+void fill_batch_inst(BatchInst &bi, const lbrd_config &c, const Layout &L, const void *buf0, const void *buf1,
+                     int vec, int lanes_x) {
+    std::memset(&bi, 0, sizeof(bi));
+    const Grid g = make_grid(L, nullptr, nullptr, vec, lanes_x);
+    bi.buf[0] = buf0;
+    bi.buf[1] = buf1;
+    bi.pitch = L.pitch;
+    bi.pstride = L.pstride;
+    bi.ntiles = g.ntiles;
+    bi.nx = L.nx;
+    bi.ny = L.ny;
+    bi.lanes_x = lanes_x;
+    bi.lx_shift = g.lx_shift;
+    bi.nvec = g.nvec;
+    bi.nseg = g.nseg;
+    bi.rpw = g.rpw;
+    bi.storage = c.storage;
+    bi.variant = variant_of(c);
+    bi.vec = vec;
+    if (c.storage == LBRD_F64) bi.pd = make_params<double>(c);
+    else bi.pf = make_params<float>(c);
+}
+
+int device_cu_count() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return 256;
+    return cus;
+}
+
+int validate_config(const lbrd_config *c) {
+    if (!c) return LBRD_EINVAL;
+    if (c->nspecies < 1 || c->nspecies > LBRD_MAX_SPECIES) return LBRD_EINVAL;
+    if (c->nx < 1 || c->ny < 1) return LBRD_EINVAL;
+    if ((int64_t)c->nx * c->ny > ((int64_t)1 << 31)) return LBRD_EINVAL;
+    if (c->storage < LBRD_F64 || c->storage > LBRD_BF16_SHIFTED) return LBRD_EINVAL;
+    if (c->reaction < LBRD_REACT_NONE || c->reaction > LBRD_REACT_GRAY_SCOTT) return LBRD_EINVAL;
+    if (c->reaction == LBRD_REACT_GRAY_SCOTT && c->nspecies != 2) return LBRD_EINVAL;
+    if (c->reserved != 0) return LBRD_EINVAL;
+    for (int s = 0; s < c->nspecies; ++s) {
+        if (!(c->tau[s] > 0.5) || !std::isfinite(c->tau[s])) return LBRD_EINVAL;
+        if (!std::isfinite(c->rho_ref[s])) return LBRD_EINVAL;
+    }
+    if (c->reaction == LBRD_REACT_LINEAR) {
+        for (int q = 0; q < c->nspecies * c->nspecies; ++q)
+            if (!std::isfinite(c->K[q])) return LBRD_EINVAL;
+        for (int s = 0; s < c->nspecies; ++s)
+            if (!std::isfinite(c->c[s])) return LBRD_EINVAL;
+    }
+    if (c->reaction == LBRD_REACT_GRAY_SCOTT && (!std::isfinite(c->F) || !std::isfinite(c->k))) return LBRD_EINVAL;
+    return LBRD_OK;
+}
+
+// Internal config: NONE runs through the linear kernel with K = 0, c = 0.
+lbrd_config normalise(const lbrd_config &c) {
+    lbrd_config n = c;
+    if (n.reaction == LBRD_REACT_NONE) {
+        std::memset(n.K, 0, sizeof(n.K));
+        std::memset(n.c, 0, sizeof(n.c));
+        n.reaction = LBRD_REACT_LINEAR;
+    }
+    return n;
+}
+
+size_t scratch_bytes() { return (size_t)round_up((kRedBlocks + 1) * kRedSlots * sizeof(double), 4096); }
+
+}  // namespace lbrd
+
+using namespace lbrd;
+
+struct lbrd_solver {
+    lbrd_config cfg;       // normalised
+    Layout L;
+    char *buf[2];
+    double *partials;      // kRedBlocks * kRedSlots
+    double *result;        // kRedSlots
+    hipStream_t stream;
+    hipStream_t capture;   // private stream used only to record graphs
+    int cur = 0;           // buffer holding the current state
+    int64_t t = 0;
+    bool initialised = false;
+    lbrd_tuning tune;
+    alignas(16) unsigned char params[sizeof(Params<double>)];
+    hipGraphExec_t graph[2] = {nullptr, nullptr};   // graph_steps steps starting from buf[0] / buf[1]
+    int graph_steps_built = 0;
+    int device = 0;
+};
+
+namespace {
+
+int fail(const char *where, hipError_t e) {
+    set_error(where, e);
+    return LBRD_EDEVICE;
+}
+
+void drop_graphs(lbrd_solver *h) {
+    for (auto &g : h->graph) {
+        if (g) hipGraphExecDestroy(g);
+        g = nullptr;
+    }
+    h->graph_steps_built = 0;
+}
+
+StepLaunch step_launch(const lbrd_solver *h) {
+    return StepLaunch{h->cfg.storage, variant_of(h->cfg), h->tune.vec, h->tune.waves, h->tune.nontemporal != 0};
+}
+
+hipError_t enqueue_steps(lbrd_solver *h, int from, int64_t n, hipStream_t st) {
+    const StepLaunch sl = step_launch(h);
+    for (int64_t k = 0; k < n; ++k) {
+        const int a = (from + (int)(k & 1)) & 1;
+        const Grid g = make_grid(h->L, h->buf[a], h->buf[a ^ 1], h->tune.vec, h->tune.lanes_x);
+        hipError_t e = launch_step(sl, g, h->params, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t build_graphs(lbrd_solver *h) {
+    drop_graphs(h);
+    const int n = h->tune.graph_steps;
+    for (int from = 0; from < 2; ++from) {
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamBeginCapture(h->capture, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return e;
+        hipError_t le = enqueue_steps(h, from, n, h->capture);
+        e = hipStreamEndCapture(h->capture, &graph);
+        if (le != hipSuccess) {
+            if (graph) hipGraphDestroy(graph);
+            return le;
+        }
+        if (e != hipSuccess) return e;
+        e = hipGraphInstantiate(&h->graph[from], graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (e != hipSuccess) return e;
+    }
+    h->graph_steps_built = n;
+    return hipSuccess;
+}
+
+int check_dtype(int dtype) { return (dtype == LBRD_DTYPE_F64 || dtype == LBRD_DTYPE_F32) ? LBRD_OK : LBRD_EINVAL; }
+
+// Stage a host array in the idle ping-pong buffer (large enough: 9 N b >= 8 N
+// bytes per site for every storage form).
+int stage_host(lbrd_solver *h, const void *host, size_t bytes, const void **dev) {
+    char *stage = h->buf[h->cur ^ 1];
+    if (bytes > h->L.buf_bytes) return LBRD_ENOMEM;
+    hipError_t e = hipMemcpyAsync(stage, host, bytes, hipMemcpyHostToDevice, h->stream);
+    if (e != hipSuccess) return fail("hipMemcpyAsync", e);
+    e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return fail("hipStreamSynchronize", e);
+    *dev = stage;
+    return LBRD_OK;
+}
+
+bool tuning_valid(const lbrd_solver *h, const lbrd_tuning &t) {
+    if (!step_shape_valid(h->cfg.storage, t.vec, t.lanes_x, t.waves)) return false;
+    if (t.graph_steps < 0 || (t.graph_steps & 1) || t.graph_steps > 4096) return false;
+    return t.nontemporal == 0 || t.nontemporal == 1;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lbrd_strerror(int status) {
+    switch (status) {
+        case LBRD_OK: return "ok";
+        case LBRD_EINVAL: return "invalid argument";
+        case LBRD_ENOMEM: return "workspace too small";
+        case LBRD_EDEVICE: return g_last_error.empty() ? "HIP runtime error" : g_last_error.c_str();
+        case LBRD_ENONFINITE: return "non-finite reduction result";
+        case LBRD_ESTATE: return "call out of order (not initialised)";
+        case LBRD_ENOTFOUND: return "unknown ticket";
+        case LBRD_ETIMEOUT: return "timed out";
+        default: return "unknown status";
+    }
+}
+
+const char *lbrd_version(void) { return "lbrd 0.1 gfx950"; }
+
+int lbrd_validate(const lbrd_config *cfg) { return validate_config(cfg); }
+
+int lbrd_workspace_size(const lbrd_config *cfg, size_t *bytes) {
+    int rc = validate_config(cfg);
+    if (rc) return rc;
+    if (!bytes) return LBRD_EINVAL;
+    const Layout L = make_layout(*cfg);
+    *bytes = 2 * L.buf_bytes + scratch_bytes();
+    return LBRD_OK;
+}
+
+int lbrd_create(const lbrd_config *cfg, void *workspace, size_t bytes, void *stream, lbrd_solver **out) {
+    int rc = validate_config(cfg);
+    if (rc) return rc;
+    if (!out || !workspace || ((uintptr_t)workspace & 255)) return LBRD_EINVAL;
+    size_t need = 0;
+    lbrd_workspace_size(cfg, &need);
+    if (bytes < need) return LBRD_ENOMEM;
+    lbrd_solver *h = new (std::nothrow) lbrd_solver();
+    if (!h) return LBRD_ENOMEM;
+    h->cfg = normalise(*cfg);
+    h->L = make_layout(h->cfg);
+    h->buf[0] = static_cast<char *>(workspace);
+    h->buf[1] = h->buf[0] + h->L.buf_bytes;
+    h->partials = reinterpret_cast<double *>(h->buf[1] + h->L.buf_bytes);
+    h->result = h->partials + (size_t)kRedBlocks * kRedSlots;
+    h->stream = static_cast<hipStream_t>(stream);
+    hipGetDevice(&h->device);
+    hipError_t e = hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete h;
+        return fail("hipStreamCreateWithFlags", e);
+    }
+    if (h->cfg.storage == LBRD_F64) {
+        Params<double> p = make_params<double>(h->cfg);
+        std::memcpy(h->params, &p, sizeof(p));
+    } else {
+        Params<float> p = make_params<float>(h->cfg);
+        std::memcpy(h->params, &p, sizeof(p));
+    }
+    std::memset(&h->tune, 0, sizeof(h->tune));
+    h->tune.vec = default_vec(h->cfg.storage);
+    h->tune.lanes_x = default_lanes(h->cfg.nx, h->tune.vec);
+    h->tune.waves = 4;
+    h->tune.nontemporal = 0;
+    h->tune.graph_steps = ((int64_t)h->cfg.nx * h->cfg.ny <= (1 << 18)) ? 32 : 0;
+    *out = h;
+    return LBRD_OK;
+}
+
+int lbrd_destroy(lbrd_solver *h) {
+    if (!h) return LBRD_OK;
+    drop_graphs(h);
+    if (h->capture) hipStreamDestroy(h->capture);
+    delete h;
+    return LBRD_OK;
+}
+
+int lbrd_init(lbrd_solver *h, const void *rho0, int dtype, int on_device) {
+    if (!h || !rho0 || check_dtype(dtype)) return LBRD_EINVAL;
+    const size_t bytes = (size_t)h->cfg.nspecies * h->cfg.nx * h->cfg.ny * (dtype == LBRD_DTYPE_F64 ? 8 : 4);
+    const void *src = rho0;
+    if (!on_device) {
+        int rc = stage_host(h, rho0, bytes, &src);
+        if (rc) return rc;
+    }
+    hipError_t e = launch_init(h->cfg.storage, h->L, h->params, src, dtype, h->buf[h->cur], h->stream);
+    if (e != hipSuccess) return fail("init kernel", e);
+    h->t = 0;
+    h->initialised = true;
+    return LBRD_OK;
+}
+
+int lbrd_set_populations(lbrd_solver *h, const void *f, int dtype, int on_device) {
+    if (!h || !f || check_dtype(dtype)) return LBRD_EINVAL;
+    const size_t bytes = (size_t)h->cfg.nspecies * 9 * h->cfg.nx * h->cfg.ny * (dtype == LBRD_DTYPE_F64 ? 8 : 4);
+    const void *src = f;
+    if (!on_device) {
+        int rc = stage_host(h, f, bytes, &src);
+        if (rc) return rc;
+    }
+    hipError_t e = launch_set_populations(h->cfg.storage, h->L, h->params, src, dtype, h->buf[h->cur], h->stream);
+    if (e != hipSuccess) return fail("set_populations kernel", e);
+    h->t = 0;
+    h->initialised = true;
+    return LBRD_OK;
+}
+
+int lbrd_get_populations(lbrd_solver *h, void *f_out, int dtype) {
+    if (!h || !f_out || check_dtype(dtype)) return LBRD_EINVAL;
+    if (!h->initialised) return LBRD_ESTATE;
+    hipError_t e = launch_get_populations(h->cfg.storage, h->L, h->params, h->buf[h->cur], f_out, dtype, h->stream);
+    return e == hipSuccess ? LBRD_OK : fail("get_populations kernel", e);
+}
+
+int lbrd_step(lbrd_solver *h, int64_t nsteps) {
+    if (!h || nsteps < 0) return LBRD_EINVAL;
+    if (!h->initialised) return LBRD_ESTATE;
+    int64_t left = nsteps;
+    const int gs = h->tune.graph_steps;
+    if (gs > 0 && left >= gs) {
+        if (h->graph_steps_built != gs) {
+            hipError_t e = build_graphs(h);
+            if (e != hipSuccess) {
+                drop_graphs(h);
+                return fail("graph capture", e);
+            }
+        }
+        while (left >= gs) {
+            hipError_t e = hipGraphLaunch(h->graph[h->cur], h->stream);
+            if (e != hipSuccess) return fail("hipGraphLaunch", e);
+            left -= gs;   // an even number of steps: cur is unchanged
+            h->t += gs;
+        }
+    }
+    hipError_t e = enqueue_steps(h, h->cur, left, h->stream);
+    if (e != hipSuccess) return fail("step kernel", e);
+    h->cur ^= (int)(left & 1);
+    h->t += left;
+    return LBRD_OK;
+}
+
+int lbrd_moments(lbrd_solver *h, void *rho_out, int dtype, double *mass_out) {
+    if (!h || (rho_out && check_dtype(dtype))) return LBRD_EINVAL;
+    if (!h->initialised) return LBRD_ESTATE;
+    if (!rho_out && !mass_out) return LBRD_OK;
+    hipError_t e = launch_moments(h->cfg.storage, h->L, h->params, h->buf[h->cur], rho_out, dtype, nullptr, 0,
+                                  h->partials, h->result, h->stream);
+    if (e != hipSuccess) return fail("moments kernel", e);
+    if (!mass_out) return LBRD_OK;
+    double res[kRedSlots];
+    e = hipMemcpyAsync(res, h->result, sizeof(res), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return fail("moments readback", e);
+    int rc = LBRD_OK;
+    for (int s = 0; s < h->cfg.nspecies; ++s) {
+        mass_out[s] = res[s];
+        if (!std::isfinite(res[s])) rc = LBRD_ENONFINITE;
+    }
+    return rc;
+}
+
+int lbrd_rel_l2(lbrd_solver *h, const void *ref, int dtype, double *err_out) {
+    if (!h || !ref || !err_out || check_dtype(dtype)) return LBRD_EINVAL;
+    if (!h->initialised) return LBRD_ESTATE;
+    hipError_t e = launch_moments(h->cfg.storage, h->L, h->params, h->buf[h->cur], nullptr, LBRD_DTYPE_F64, ref,
+                                  dtype, h->partials, h->result, h->stream);
+    if (e != hipSuccess) return fail("moments kernel", e);
+    double res[kRedSlots];
+    e = hipMemcpyAsync(res, h->result, sizeof(res), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return fail("rel_l2 readback", e);
+    int rc = LBRD_OK;
+    for (int s = 0; s < h->cfg.nspecies; ++s) {
+        const double num = res[LBRD_MAX_SPECIES + s], den = res[2 * LBRD_MAX_SPECIES + s];
+        err_out[s] = den > 0 ? std::sqrt(num / den) : std::sqrt(num);
+        if (!std::isfinite(err_out[s])) rc = LBRD_ENONFINITE;
+    }
+    return rc;
+}
+
+int lbrd_time(const lbrd_solver *h, int64_t *t) {
+    if (!h || !t) return LBRD_EINVAL;
+    *t = h->t;
+    return LBRD_OK;
+}
+
+int lbrd_get_tuning(const lbrd_solver *h, lbrd_tuning *out) {
+    if (!h || !out) return LBRD_EINVAL;
+    *out = h->tune;
+    return LBRD_OK;
+}
+
+int lbrd_set_tuning(lbrd_solver *h, const lbrd_tuning *t) {
+    if (!h || !t) return LBRD_EINVAL;
+    lbrd_tuning n = *t;
+    if (n.lanes_x == 0) n.lanes_x = default_lanes(h->cfg.nx, n.vec);
+    std::memset(n.reserved, 0, sizeof(n.reserved));
+    if (!tuning_valid(h, n)) return LBRD_EINVAL;
+    const bool rebuild = n.vec != h->tune.vec || n.lanes_x != h->tune.lanes_x || n.waves != h->tune.waves ||
+                         n.nontemporal != h->tune.nontemporal || n.graph_steps != h->tune.graph_steps;
+    h->tune = n;
+    if (rebuild) drop_graphs(h);
+    return LBRD_OK;
+}
+
+int lbrd_time_steps(lbrd_solver *h, int64_t nsteps, double *ms) {
+    if (!h || !ms || nsteps < 0) return LBRD_EINVAL;
+    if (!h->initialised) return LBRD_ESTATE;
+    hipEvent_t a, b;
+    hipError_t e = hipEventCreate(&a);
+    if (e != hipSuccess) return fail("hipEventCreate", e);
+    e = hipEventCreate(&b);
+    if (e != hipSuccess) {
+        hipEventDestroy(a);
+        return fail("hipEventCreate", e);
+    }
+    int rc = LBRD_OK;
+    e = hipEventRecord(a, h->stream);
+    if (e == hipSuccess) {
+        rc = lbrd_step(h, nsteps);
+        if (rc == LBRD_OK) {
+            e = hipEventRecord(b, h->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(b);
+            float f = 0;
+            if (e == hipSuccess) e = hipEventElapsedTime(&f, a, b);
+            *ms = f;
+        }
+    }
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    if (rc) return rc;
+    return e == hipSuccess ? LBRD_OK : fail("event timing", e);
+}
+
+int lbrd_autotune(lbrd_solver *h, int steps, const char *cache_path, lbrd_tuning *chosen) {
+    if (!h || steps < 2) return LBRD_EINVAL;
+    int dev = 0;
+    hipGetDevice(&dev);
+    hipDeviceProp_t prop;
+    std::string arch = "gfx";
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+    std::ostringstream key;
+    key << arch << " st=" << h->cfg.storage << " v=" << variant_of(h->cfg) << " nx=" << h->cfg.nx
+        << " ny=" << h->cfg.ny;
+    const std::string k = key.str();
+    if (cache_path) {
+        std::ifstream in(cache_path);
+        std::string line;
+        while (std::getline(in, line)) {
+            const size_t bar = line.find('|');
+            if (bar == std::string::npos || line.substr(0, bar) != k) continue;
+            lbrd_tuning t;
+            std::memset(&t, 0, sizeof(t));
+            if (std::sscanf(line.c_str() + bar + 1, "%d %d %d %d %d", &t.vec, &t.lanes_x, &t.waves, &t.nontemporal,
+                            &t.graph_steps) == 5 &&
+                tuning_valid(h, t)) {
+                lbrd_set_tuning(h, &t);
+                h->initialised = false;
+                if (chosen) *chosen = h->tune;
+                return LBRD_OK;
+            }
+        }
+    }
+    // Candidate shapes: every valid vector width, row-segment width up to the
+    // row, waves per workgroup, streaming stores on / off.
+    std::vector<lbrd_tuning> cands;
+    const int vecs[3] = {2, 4, 8};
+    for (int vec : vecs) {
+        const int lmax = default_lanes(h->cfg.nx, vec);
+        for (int lx = std::max(1, lmax / 4); lx <= lmax; lx <<= 1)
+            for (int w : {1, 2, 4})
+                for (int nt = 0; nt < 2; ++nt) {
+                    lbrd_tuning t;
+                    std::memset(&t, 0, sizeof(t));
+                    t.vec = vec;
+                    t.lanes_x = lx;
+                    t.waves = w;
+                    t.nontemporal = nt;
+                    t.graph_steps = h->tune.graph_steps;
+                    if (tuning_valid(h, t)) cands.push_back(t);
+                }
+    }
+    // the state is scratch from here on: fill it with a uniform field
+    h->initialised = true;
+    hipError_t e = hipMemsetAsync(h->buf[0], 0, h->L.buf_bytes, h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(h->buf[1], 0, h->L.buf_bytes, h->stream);
+    if (e != hipSuccess) return fail("autotune clear", e);
+    double best = 1e300;
+    lbrd_tuning best_t = h->tune;
+    for (const lbrd_tuning &t : cands) {
+        lbrd_tuning tt = t;
+        tt.graph_steps = 0;
+        lbrd_set_tuning(h, &tt);
+        double ms = 0;
+        int rc = lbrd_time_steps(h, 2, &ms);   // warm-up
+        if (rc == LBRD_OK) rc = lbrd_time_steps(h, steps, &ms);
+        if (rc != LBRD_OK) continue;
+        if (ms < best) {
+            best = ms;
+            best_t = t;
+        }
+    }
+    lbrd_set_tuning(h, &best_t);
+    h->initialised = false;
+    h->t = 0;
+    if (cache_path) {
+        std::ofstream outf(cache_path, std::ios::app);
+        outf << k << "|" << best_t.vec << " " << best_t.lanes_x << " " << best_t.waves << " " << best_t.nontemporal
+             << " " << best_t.graph_steps << "\n";
+    }
+    if (chosen) *chosen = h->tune;
+    return LBRD_OK;
+}
+
+const char *lbrd_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,259 @@
+// Initialisation, population transfer and read-out kernels, plus the
+// storage dispatch of the step launch.
+#include <hip/hip_runtime.h>
+
+#include "lbrd_device.h"
+
+namespace lbrd {
+
+template <int ST>
+constexpr bool vec_ok_for(int vec) {
+    return ST == kF64 ? vec == 2 : (ST == kF32 ? (vec == 2 || vec == 4) : (vec == 4 || vec == 8));
+}
+
+bool step_shape_valid(int storage, int vec, int lanes_x, int waves) {
+    bool v = false;
+    switch (storage) {
+        case kF64: v = vec_ok_for<kF64>(vec); break;
+        case kF32: v = vec_ok_for<kF32>(vec); break;
+        case kF16: v = vec_ok_for<kF16>(vec); break;
+        case kBF16: v = vec_ok_for<kBF16>(vec); break;
+        default: return false;
+    }
+    const bool pow2 = lanes_x >= 1 && lanes_x <= 64 && (lanes_x & (lanes_x - 1)) == 0;
+    return v && pow2 && (waves == 1 || waves == 2 || waves == 4);
+}
+
+hipError_t launch_step(const StepLaunch &sl, const Grid &g, const void *params, hipStream_t st) {
+    if (g.ntiles <= 0) return hipSuccess;
+    switch (sl.storage) {
+        case kF64: return launch_step_f64(sl, g, params, st);
+        case kF32: return launch_step_f32(sl, g, params, st);
+        case kF16: return launch_step_f16(sl, g, params, st);
+        case kBF16: return launch_step_bf16(sl, g, params, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// ------------------------------------------------- init / populations --
+
+__device__ __forceinline__ int wrap(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+template <class C>
+__device__ __forceinline__ C load_in(const void *p, int dtype, int64_t k) {
+    return dtype == LBRD_DTYPE_F64 ? (C)static_cast<const double *>(p)[k] : (C)static_cast<const float *>(p)[k];
+}
+
+// S_{i,s}(y) = w_i rho0_s(y + e_i): the stored form whose pull gives the
+// equilibrium f_{i,s}(x, 0) = w_i rho0_s(x).
+template <int ST>
+__global__ void k_init(Layout L, Params<typename Traits<ST>::C> p, const void *rho0, int dtype,
+                       typename Traits<ST>::T *dst) {
+    using C = typename Traits<ST>::C;
+    const int64_t sites = (int64_t)L.nx * L.ny;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < sites; k += (int64_t)gridDim.x * blockDim.x) {
+        const int y = (int)(k / L.nx), x = (int)(k % L.nx);
+        for (int s = 0; s < L.ns; ++s) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const int xs = wrap(x + kEx[i], L.nx), ys = wrap(y + kEy[i], L.ny);
+                const C r = load_in<C>(rho0, dtype, ((int64_t)s * L.ny + ys) * L.nx + xs);
+                dst[(int64_t)(s * 9 + i) * L.pstride + (int64_t)y * L.pitch + x] = encode<ST>(wgt<C>(i) * r, p.shift[s][i]);
+            }
+        }
+    }
+}
+
+template <int ST>
+__global__ void k_set_pop(Layout L, Params<typename Traits<ST>::C> p, const void *f, int dtype,
+                          typename Traits<ST>::T *dst) {
+    using C = typename Traits<ST>::C;
+    const int64_t sites = (int64_t)L.nx * L.ny;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < sites; k += (int64_t)gridDim.x * blockDim.x) {
+        const int y = (int)(k / L.nx), x = (int)(k % L.nx);
+        for (int s = 0; s < L.ns; ++s) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const int xs = wrap(x + kEx[i], L.nx), ys = wrap(y + kEy[i], L.ny);
+                const C v = load_in<C>(f, dtype, (((int64_t)s * 9 + i) * L.ny + ys) * L.nx + xs);
+                dst[(int64_t)(s * 9 + i) * L.pstride + (int64_t)y * L.pitch + x] = encode<ST>(v, p.shift[s][i]);
+            }
+        }
+    }
+}
+
+template <int ST>
+__global__ void k_get_pop(Layout L, Params<typename Traits<ST>::C> p, const typename Traits<ST>::T *src, void *f,
+                          int dtype) {
+    using C = typename Traits<ST>::C;
+    const int64_t sites = (int64_t)L.nx * L.ny;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < sites; k += (int64_t)gridDim.x * blockDim.x) {
+        const int y = (int)(k / L.nx), x = (int)(k % L.nx);
+        for (int s = 0; s < L.ns; ++s) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const int xs = wrap(x - kEx[i], L.nx), ys = wrap(y - kEy[i], L.ny);
+                const C v = decode<ST>(src[(int64_t)(s * 9 + i) * L.pstride + (int64_t)ys * L.pitch + xs], p.shift[s][i]);
+                const int64_t o = (((int64_t)s * 9 + i) * L.ny + y) * L.nx + x;
+                if (dtype == LBRD_DTYPE_F64) static_cast<double *>(f)[o] = (double)v;
+                else static_cast<float *>(f)[o] = (float)v;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ moments --
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// rho_s(x) = sum_i f_{i,s}(x) gathered from the pull neighbours, optionally
+// written out, and three FP64 sums per species accumulated per block:
+// sum rho, sum (rho - ref)^2, sum ref^2.
+template <int ST>
+__global__ __launch_bounds__(kRedThreads) void k_moments(Layout L, Params<typename Traits<ST>::C> p,
+                                                         const typename Traits<ST>::T *src, void *rho_out,
+                                                         int dtype, const void *ref, int ref_dtype,
+                                                         double *partials) {
+    using C = typename Traits<ST>::C;
+    double acc[kRedSlots];
+#pragma unroll
+    for (int q = 0; q < kRedSlots; ++q) acc[q] = 0.0;
+    const int64_t sites = (int64_t)L.nx * L.ny;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < sites; k += (int64_t)gridDim.x * blockDim.x) {
+        const int y = (int)(k / L.nx), x = (int)(k % L.nx);
+#pragma unroll
+        for (int s = 0; s < LBRD_MAX_SPECIES; ++s) {
+            if (s >= L.ns) break;
+            C rho = C(0);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const int xs = wrap(x - kEx[i], L.nx), ys = wrap(y - kEy[i], L.ny);
+                rho += decode<ST>(src[(int64_t)(s * 9 + i) * L.pstride + (int64_t)ys * L.pitch + xs], p.shift[s][i]);
+            }
+            const int64_t o = (int64_t)s * sites + k;
+            if (rho_out) {
+                if (dtype == LBRD_DTYPE_F64) static_cast<double *>(rho_out)[o] = (double)rho;
+                else static_cast<float *>(rho_out)[o] = (float)rho;
+            }
+            acc[s] += (double)rho;
+            if (ref) {
+                const double r = ref_dtype == LBRD_DTYPE_F64 ? static_cast<const double *>(ref)[o]
+                                                             : (double)static_cast<const float *>(ref)[o];
+                const double d = r - (double)rho;
+                acc[LBRD_MAX_SPECIES + s] += d * d;
+                acc[2 * LBRD_MAX_SPECIES + s] += r * r;
+            }
+        }
+    }
+    __shared__ double red[kRedThreads / 64][kRedSlots];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int q = 0; q < kRedSlots; ++q) {
+        const double w = wave_sum(acc[q]);
+        if (lane == 0) red[wave][q] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x < kRedSlots) {
+        double t = 0.0;
+        for (int w = 0; w < kRedThreads / 64; ++w) t += red[w][threadIdx.x];
+        partials[(int64_t)blockIdx.x * kRedSlots + threadIdx.x] = t;
+    }
+}
+
+// Second pass: one block sums the per-block partials in a fixed order.
+__global__ __launch_bounds__(kRedThreads) void k_finalize(const double *partials, int nblocks, double *result) {
+    __shared__ double red[kRedThreads / 64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int q = 0; q < kRedSlots; ++q) {
+        double t = 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += kRedThreads) t += partials[(int64_t)b * kRedSlots + q];
+        t = wave_sum(t);
+        if (lane == 0) red[wave] = t;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double u = 0.0;
+            for (int w = 0; w < kRedThreads / 64; ++w) u += red[w];
+            result[q] = u;
+        }
+        __syncthreads();
+    }
+}
+
+template <int ST>
+static hipError_t launch_moments_t(const Layout &L, const void *params, const void *src, void *rho_out, int dtype,
+                                   const void *ref, int ref_dtype, double *partials, double *result,
+                                   hipStream_t st) {
+    using C = typename Traits<ST>::C;
+    using T = typename Traits<ST>::T;
+    const Params<C> &p = *static_cast<const Params<C> *>(params);
+    hipLaunchKernelGGL((k_moments<ST>), dim3(kRedBlocks), dim3(kRedThreads), 0, st, L, p,
+                       static_cast<const T *>(src), rho_out, dtype, ref, ref_dtype, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedThreads), 0, st, partials, kRedBlocks, result);
+    return hipGetLastError();
+}
+
+static unsigned elementwise_blocks(const Layout &L) {
+    const int64_t sites = (int64_t)L.nx * L.ny;
+    int64_t b = (sites + 255) / 256;
+    if (b > 4096) b = 4096;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+#define LBRD_DISPATCH_ST(storage, CALL)              \
+    switch (storage) {                               \
+        case kF64: { constexpr int ST = kF64; CALL; } \
+        case kF32: { constexpr int ST = kF32; CALL; } \
+        case kF16: { constexpr int ST = kF16; CALL; } \
+        case kBF16: { constexpr int ST = kBF16; CALL; } \
+        default: return hipErrorInvalidValue;        \
+    }
+
+hipError_t launch_init(int storage, const Layout &L, const void *params, const void *rho0, int dtype, void *dst,
+                       hipStream_t st) {
+    LBRD_DISPATCH_ST(storage, {
+        using C = typename Traits<ST>::C;
+        using T = typename Traits<ST>::T;
+        hipLaunchKernelGGL((k_init<ST>), dim3(elementwise_blocks(L)), dim3(256), 0, st, L,
+                           *static_cast<const Params<C> *>(params), rho0, dtype, static_cast<T *>(dst));
+        return hipGetLastError();
+    })
+}
+
+hipError_t launch_set_populations(int storage, const Layout &L, const void *params, const void *f, int dtype,
+                                  void *dst, hipStream_t st) {
+    LBRD_DISPATCH_ST(storage, {
+        using C = typename Traits<ST>::C;
+        using T = typename Traits<ST>::T;
+        hipLaunchKernelGGL((k_set_pop<ST>), dim3(elementwise_blocks(L)), dim3(256), 0, st, L,
+                           *static_cast<const Params<C> *>(params), f, dtype, static_cast<T *>(dst));
+        return hipGetLastError();
+    })
+}
+
+hipError_t launch_get_populations(int storage, const Layout &L, const void *params, const void *src, void *f_out,
+                                  int dtype, hipStream_t st) {
+    LBRD_DISPATCH_ST(storage, {
+        using C = typename Traits<ST>::C;
+        using T = typename Traits<ST>::T;
+        hipLaunchKernelGGL((k_get_pop<ST>), dim3(elementwise_blocks(L)), dim3(256), 0, st, L,
+                           *static_cast<const Params<C> *>(params), static_cast<const T *>(src), f_out, dtype);
+        return hipGetLastError();
+    })
+}
+
+hipError_t launch_moments(int storage, const Layout &L, const void *params, const void *src, void *rho_out,
+                          int dtype, const void *ref, int ref_dtype, double *partials, double *result,
+                          hipStream_t st) {
+    LBRD_DISPATCH_ST(storage, {
+        return launch_moments_t<ST>(L, params, src, rho_out, dtype, ref, ref_dtype, partials, result, st);
+    })
+}
+
+}  // namespace lbrd

@@ -1,0 +1,392 @@
+// Host side of batched solving: many independent lattices advanced by one
+// persistent launch per step, with the launches of a chunk replayed from a
+// captured HIP graph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "lbrd.h"
+#include "lbrd_internal.h"
+#include "lbrd_util.h"
+
+using namespace lbrd;
+
+namespace {
+
+int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+struct BatchPlan {
+    size_t hdr_off, inst_off, scratch_off, bufs_off, total;
+    std::vector<size_t> buf_off;   // per instance, first of its two buffers
+};
+
+BatchPlan plan_batch(const lbrd_config *cfgs, int count) {
+    BatchPlan p;
+    p.hdr_off = 0;
+    p.inst_off = 256;
+    p.scratch_off = (size_t)round_up(p.inst_off + sizeof(BatchInst) * (size_t)count, 4096);
+    p.bufs_off = p.scratch_off + scratch_bytes();
+    size_t off = p.bufs_off;
+    for (int i = 0; i < count; ++i) {
+        const Layout L = make_layout(normalise(cfgs[i]));
+        p.buf_off.push_back(off);
+        off += 2 * L.buf_bytes;
+    }
+    p.total = off;
+    return p;
+}
+
+int pick_set(const std::vector<lbrd_config> &cfgs) {
+    bool gs_f32 = true, serve = true;
+    for (const auto &c : cfgs) {
+        const int v = variant_of(c);
+        if (!(c.storage == LBRD_F32 && v == kGS)) gs_f32 = false;
+        if (c.storage == LBRD_F64 || !(v == kGS || v == kLin1)) serve = false;
+    }
+    return gs_f32 ? kBatchGSF32 : (serve ? kBatchServe : kBatchAny);
+}
+
+}  // namespace
+
+struct lbrd_batch {
+    int count = 0;
+    std::vector<lbrd_config> cfg;   // normalised
+    std::vector<Layout> L;
+    std::vector<BatchInst> inst;    // host mirror of the device descriptors
+    std::vector<char> initialised;
+    BatchHeader *d_hdr = nullptr;
+    BatchInst *d_inst = nullptr;
+    double *partials = nullptr, *result = nullptr;
+    hipStream_t stream = nullptr, capture = nullptr;
+    int set = kBatchAny;
+    int cus = 256;
+    int64_t total_tiles = 0;
+    lbrd_tuning tune;
+    bool dirty = true;              // descriptors need uploading
+    hipGraphExec_t graph = nullptr;
+    int graph_steps_built = 0;
+    int64_t t = 0;
+};
+
+namespace {
+
+int fail(const char *where, hipError_t e) {
+    set_error(where, e);
+    return LBRD_EDEVICE;
+}
+
+void drop_graph(lbrd_batch *b) {
+    if (b->graph) hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+    b->graph_steps_built = 0;
+}
+
+int blocks_of(const lbrd_batch *b) {
+    int64_t blocks = (int64_t)b->tune.blocks_per_cu * b->cus;
+    const int64_t need = (b->total_tiles + b->tune.waves - 1) / b->tune.waves;
+    return (int)std::max<int64_t>(1, std::min(blocks, need));
+}
+
+hipError_t upload(lbrd_batch *b, int steps) {
+    bool changed = b->dirty;
+    for (auto &bi : b->inst) {
+        if (bi.steps != steps) changed = true;
+        bi.steps = steps;
+    }
+    if (!changed) return hipSuccess;
+    b->dirty = false;
+    return hipMemcpyAsync(b->d_inst, b->inst.data(), sizeof(BatchInst) * b->inst.size(), hipMemcpyHostToDevice,
+                          b->stream);
+}
+
+hipError_t enqueue(lbrd_batch *b, int n, hipStream_t st) {
+    for (int j = 0; j < n; ++j) {
+        hipError_t e = launch_batch_step(b->d_hdr, b->d_inst, j, blocks_of(b), b->tune.waves, b->tune.nontemporal != 0,
+                                         b->set, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t build_graph(lbrd_batch *b) {
+    drop_graph(b);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t le = enqueue(b, b->tune.graph_steps, b->capture);
+    e = hipStreamEndCapture(b->capture, &g);
+    if (le != hipSuccess) {
+        if (g) hipGraphDestroy(g);
+        return le;
+    }
+    if (e != hipSuccess) return e;
+    e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e == hipSuccess) b->graph_steps_built = b->tune.graph_steps;
+    return e;
+}
+
+bool batch_tuning_valid(const lbrd_tuning &t) {
+    return (t.waves == 1 || t.waves == 2 || t.waves == 4) && t.blocks_per_cu >= 1 && t.blocks_per_cu <= 32 &&
+           (t.nontemporal == 0 || t.nontemporal == 1) && t.graph_steps >= 0 && !(t.graph_steps & 1) &&
+           t.graph_steps <= 4096;
+}
+
+const void *params_of(const lbrd_batch *b, int idx) {
+    const BatchInst &bi = b->inst[idx];
+    return b->cfg[idx].storage == LBRD_F64 ? (const void *)&bi.pd : (const void *)&bi.pf;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbrd_batch_workspace_size(const lbrd_config *cfgs, int count, size_t *bytes) {
+    if (!cfgs || count < 1 || !bytes) return LBRD_EINVAL;
+    for (int i = 0; i < count; ++i)
+        if (int rc = validate_config(&cfgs[i])) return rc;
+    *bytes = plan_batch(cfgs, count).total;
+    return LBRD_OK;
+}
+
+int lbrd_batch_create(const lbrd_config *cfgs, int count, void *workspace, size_t bytes, void *stream,
+                      lbrd_batch **out) {
+    size_t need = 0;
+    if (int rc = lbrd_batch_workspace_size(cfgs, count, &need)) return rc;
+    if (!out || !workspace || ((uintptr_t)workspace & 255)) return LBRD_EINVAL;
+    if (bytes < need) return LBRD_ENOMEM;
+    lbrd_batch *b = new (std::nothrow) lbrd_batch();
+    if (!b) return LBRD_ENOMEM;
+    const BatchPlan p = plan_batch(cfgs, count);
+    char *base = static_cast<char *>(workspace);
+    b->count = count;
+    b->stream = static_cast<hipStream_t>(stream);
+    b->d_hdr = reinterpret_cast<BatchHeader *>(base + p.hdr_off);
+    b->d_inst = reinterpret_cast<BatchInst *>(base + p.inst_off);
+    b->partials = reinterpret_cast<double *>(base + p.scratch_off);
+    b->result = b->partials + (size_t)kRedBlocks * kRedSlots;
+    int64_t tiles = 0;
+    for (int i = 0; i < count; ++i) {
+        const lbrd_config c = normalise(cfgs[i]);
+        const Layout L = make_layout(c);
+        char *b0 = base + p.buf_off[i];
+        const int vec = batch_vec(c.storage);
+        BatchInst bi;
+        fill_batch_inst(bi, c, L, b0, b0 + L.buf_bytes, vec, default_lanes(c.nx, vec));
+        bi.tile_begin = tiles;
+        bi.cur = 0;
+        tiles += bi.ntiles;
+        b->cfg.push_back(c);
+        b->L.push_back(L);
+        b->inst.push_back(bi);
+    }
+    b->initialised.assign(count, 0);
+    b->total_tiles = tiles;
+    b->set = pick_set(b->cfg);
+    b->cus = device_cu_count();
+    std::memset(&b->tune, 0, sizeof(b->tune));
+    b->tune.waves = 4;
+    b->tune.blocks_per_cu = 8;
+    b->tune.graph_steps = 16;
+    BatchHeader h;
+    std::memset(&h, 0, sizeof(h));
+    h.count = count;
+    h.total_tiles = tiles;
+    hipError_t e = hipMemcpyAsync(b->d_hdr, &h, sizeof(h), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete b;
+        return fail("batch create", e);
+    }
+    *out = b;
+    return LBRD_OK;
+}
+
+int lbrd_batch_destroy(lbrd_batch *b) {
+    if (!b) return LBRD_OK;
+    drop_graph(b);
+    if (b->capture) hipStreamDestroy(b->capture);
+    delete b;
+    return LBRD_OK;
+}
+
+int lbrd_batch_init(lbrd_batch *b, int idx, const void *rho0, int dtype, int on_device) {
+    if (!b || idx < 0 || idx >= b->count || !rho0) return LBRD_EINVAL;
+    if (dtype != LBRD_DTYPE_F64 && dtype != LBRD_DTYPE_F32) return LBRD_EINVAL;
+    BatchInst &bi = b->inst[idx];
+    const lbrd_config &c = b->cfg[idx];
+    const void *src = rho0;
+    char *cur = static_cast<char *>(const_cast<void *>(bi.buf[bi.cur]));
+    char *idle = static_cast<char *>(const_cast<void *>(bi.buf[bi.cur ^ 1]));
+    if (!on_device) {
+        const size_t bytes = (size_t)c.nspecies * c.nx * c.ny * (dtype == LBRD_DTYPE_F64 ? 8 : 4);
+        hipError_t e = hipMemcpyAsync(idle, rho0, bytes, hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess) return fail("batch init copy", e);
+        src = idle;
+    }
+    hipError_t e = launch_init(c.storage, b->L[idx], params_of(b, idx), src, dtype, cur, b->stream);
+    if (e != hipSuccess) return fail("batch init kernel", e);
+    b->initialised[idx] = 1;
+    return LBRD_OK;
+}
+
+int lbrd_batch_step(lbrd_batch *b, int64_t nsteps) {
+    if (!b || nsteps < 0) return LBRD_EINVAL;
+    for (char v : b->initialised)
+        if (!v) return LBRD_ESTATE;
+    int64_t left = nsteps;
+    const int gs = b->tune.graph_steps;
+    if (gs > 0 && left >= gs) {
+        hipError_t e = upload(b, gs);
+        if (e != hipSuccess) return fail("batch descriptors", e);
+        if (b->graph_steps_built != gs) {
+            e = build_graph(b);
+            if (e != hipSuccess) {
+                drop_graph(b);
+                return fail("batch graph capture", e);
+            }
+        }
+        while (left >= gs) {
+            e = hipGraphLaunch(b->graph, b->stream);
+            if (e != hipSuccess) return fail("hipGraphLaunch", e);
+            left -= gs;
+            b->t += gs;
+        }
+    }
+    while (left > 0) {
+        const int n = (int)std::min<int64_t>(left, 1 << 20);
+        hipError_t e = upload(b, n);
+        if (e == hipSuccess) e = enqueue(b, n, b->stream);
+        if (e != hipSuccess) return fail("batch step", e);
+        if (n & 1) {
+            for (auto &bi : b->inst) bi.cur ^= 1;
+            b->dirty = true;
+        }
+        left -= n;
+        b->t += n;
+    }
+    return LBRD_OK;
+}
+
+int lbrd_batch_moments(lbrd_batch *b, int idx, void *rho_out, int dtype, double *mass_out) {
+    if (!b || idx < 0 || idx >= b->count) return LBRD_EINVAL;
+    if (rho_out && dtype != LBRD_DTYPE_F64 && dtype != LBRD_DTYPE_F32) return LBRD_EINVAL;
+    if (!b->initialised[idx]) return LBRD_ESTATE;
+    if (!rho_out && !mass_out) return LBRD_OK;
+    const BatchInst &bi = b->inst[idx];
+    hipError_t e = launch_moments(b->cfg[idx].storage, b->L[idx], params_of(b, idx), bi.buf[bi.cur], rho_out, dtype,
+                                  nullptr, 0, b->partials, b->result, b->stream);
+    if (e != hipSuccess) return fail("batch moments", e);
+    if (!mass_out) return LBRD_OK;
+    double res[kRedSlots];
+    e = hipMemcpyAsync(res, b->result, sizeof(res), hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return fail("batch moments readback", e);
+    int rc = LBRD_OK;
+    for (int s = 0; s < b->cfg[idx].nspecies; ++s) {
+        mass_out[s] = res[s];
+        if (!std::isfinite(res[s])) rc = LBRD_ENONFINITE;
+    }
+    return rc;
+}
+
+int lbrd_batch_get_populations(lbrd_batch *b, int idx, void *f_out, int dtype) {
+    if (!b || idx < 0 || idx >= b->count || !f_out) return LBRD_EINVAL;
+    if (dtype != LBRD_DTYPE_F64 && dtype != LBRD_DTYPE_F32) return LBRD_EINVAL;
+    if (!b->initialised[idx]) return LBRD_ESTATE;
+    const BatchInst &bi = b->inst[idx];
+    hipError_t e = launch_get_populations(b->cfg[idx].storage, b->L[idx], params_of(b, idx), bi.buf[bi.cur], f_out,
+                                          dtype, b->stream);
+    return e == hipSuccess ? LBRD_OK : fail("batch get_populations", e);
+}
+
+int lbrd_batch_get_tuning(const lbrd_batch *b, lbrd_tuning *out) {
+    if (!b || !out) return LBRD_EINVAL;
+    *out = b->tune;
+    return LBRD_OK;
+}
+
+int lbrd_batch_set_tuning(lbrd_batch *b, const lbrd_tuning *t) {
+    if (!b || !t) return LBRD_EINVAL;
+    lbrd_tuning n = *t;
+    n.vec = 0;
+    n.lanes_x = 0;
+    std::memset(n.reserved, 0, sizeof(n.reserved));
+    if (!batch_tuning_valid(n)) return LBRD_EINVAL;
+    if (std::memcmp(&n, &b->tune, sizeof(n)) != 0) drop_graph(b);
+    b->tune = n;
+    return LBRD_OK;
+}
+
+int lbrd_batch_time_steps(lbrd_batch *b, int64_t nsteps, double *ms) {
+    if (!b || !ms || nsteps < 0) return LBRD_EINVAL;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return fail("hipEventCreate", hipErrorUnknown);
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return fail("hipEventCreate", hipErrorUnknown);
+    }
+    hipError_t e = hipEventRecord(e0, b->stream);
+    int rc = LBRD_OK;
+    if (e == hipSuccess) {
+        rc = lbrd_batch_step(b, nsteps);
+        if (rc == LBRD_OK) {
+            e = hipEventRecord(e1, b->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float f = 0;
+            if (e == hipSuccess) e = hipEventElapsedTime(&f, e0, e1);
+            *ms = f;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) return rc;
+    return e == hipSuccess ? LBRD_OK : fail("batch timing", e);
+}
+
+int lbrd_batch_autotune(lbrd_batch *b, int steps, lbrd_tuning *chosen) {
+    if (!b || steps < 2) return LBRD_EINVAL;
+    for (int i = 0; i < b->count; ++i) {
+        const BatchInst &bi = b->inst[i];
+        hipError_t e = hipMemsetAsync(const_cast<void *>(bi.buf[0]), 0, b->L[i].buf_bytes, b->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(const_cast<void *>(bi.buf[1]), 0, b->L[i].buf_bytes, b->stream);
+        if (e != hipSuccess) return fail("batch autotune clear", e);
+        b->initialised[i] = 1;
+    }
+    const lbrd_tuning keep = b->tune;
+    lbrd_tuning best = keep;
+    double best_ms = 1e300;
+    for (int bpc : {1, 2, 4, 8, 16})
+        for (int w : {1, 2, 4})
+            for (int nt = 0; nt < 2; ++nt) {
+                lbrd_tuning t = keep;
+                t.blocks_per_cu = bpc;
+                t.waves = w;
+                t.nontemporal = nt;
+                t.graph_steps = 0;
+                if (lbrd_batch_set_tuning(b, &t) != LBRD_OK) continue;
+                double ms = 0;
+                if (lbrd_batch_time_steps(b, 2, &ms) != LBRD_OK) continue;
+                if (lbrd_batch_time_steps(b, steps, &ms) != LBRD_OK) continue;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = t;
+                    best.graph_steps = keep.graph_steps;
+                }
+            }
+    lbrd_batch_set_tuning(b, &best);
+    for (int i = 0; i < b->count; ++i) b->initialised[i] = 0;
+    for (auto &bi : b->inst) bi.cur = 0;
+    b->dirty = true;
+    b->t = 0;
+    if (chosen) *chosen = b->tune;
+    return LBRD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,290 @@
+// Device code of the fused collide-react-stream step (included by the
+// per-storage kernel translation units and the batched kernel).
+//
+// The step is the update of Section II.A (second Eq. "relax"; Appendix Eq.
+// "app1") in "pull" form.  The buffer holds, per plane (s, i) and site y, the
+// post-collision value S_{i,s}(y) that streams to y + e_i; so the state at t
+// is f_{i,s}(x, t) = S_{i,s}(x - e_i).  One step reads, for every site x,
+//   f_{i,s}(x) = S_{i,s}(x - e_i)            (streaming, periodic wrap)
+//   rho_s = sum_i f_{i,s}                    (ascending i)
+//   R_s = R_s(rho_1..rho_N)
+//   S'_{i,s}(x) = f_{i,s} (1 - 1/tau_s) + w_i (rho_s / tau_s + R_s)
+// and stores S' at x.  Every population is read once and written once: the
+// path is bound by HBM bandwidth (about 0.55 flop per byte in FP32), so no
+// matrix cores are involved.
+//
+// Mapping: a wave owns a tile of `rpw` rows x (64 / rpw) lanes; each lane
+// owns `VEC` consecutive sites of one row and moves 16 (or 8) bytes per plane
+// with one vector load and one vector store.  The +-1 shift in x of six of
+// the nine planes is realised in registers: the element that crosses a lane
+// boundary comes from the neighbouring lane by a cross-lane shuffle, and only
+// lanes at a row-segment edge (or at the periodic wrap) load that one element
+// from memory.  Loads stay 16-byte aligned and no LDS staging is needed,
+// because no population is used by two sites.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "lbrd_internal.h"
+
+namespace lbrd {
+
+// ------------------------------------------------------------ storage --
+
+template <int ST>
+struct Traits;
+template <>
+struct Traits<kF64> {
+    using T = double;
+    using C = double;
+};
+template <>
+struct Traits<kF32> {
+    using T = float;
+    using C = float;
+};
+template <>
+struct Traits<kF16> {
+    using T = uint16_t;
+    using C = float;
+};
+template <>
+struct Traits<kBF16> {
+    using T = uint16_t;
+    using C = float;
+};
+
+__device__ __forceinline__ float half_bits_to_float(uint16_t h) {
+    _Float16 x;
+    __builtin_memcpy(&x, &h, 2);
+    return (float)x;
+}
+__device__ __forceinline__ uint16_t float_to_half_bits(float f) {
+    _Float16 x = (_Float16)f;   // round to nearest even
+    uint16_t h;
+    __builtin_memcpy(&h, &x, 2);
+    return h;
+}
+__device__ __forceinline__ float bf16_bits_to_float(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ __forceinline__ uint16_t float_to_bf16_bits(float f) {
+    uint32_t b = __float_as_uint(f);
+    if ((b & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((b >> 16) | 0x40u);   // quiet NaN
+    b += 0x7fffu + ((b >> 16) & 1u);                                              // round to nearest even
+    return (uint16_t)(b >> 16);
+}
+
+template <int ST>
+__device__ __forceinline__ typename Traits<ST>::C decode(typename Traits<ST>::T v, typename Traits<ST>::C shift) {
+    if constexpr (ST == kF16) return half_bits_to_float(v) + shift;
+    else if constexpr (ST == kBF16) return bf16_bits_to_float(v) + shift;
+    else return v;
+}
+template <int ST>
+__device__ __forceinline__ typename Traits<ST>::T encode(typename Traits<ST>::C f, typename Traits<ST>::C shift) {
+    if constexpr (ST == kF16) return float_to_half_bits(f - shift);
+    else if constexpr (ST == kBF16) return float_to_bf16_bits(f - shift);
+    else return f;
+}
+
+// D2Q9 weights w_i (Eq. "Weights") in the compute type.
+template <class C>
+__device__ __forceinline__ constexpr C wgt(int i) {
+    return i == 0 ? C(4) / C(9) : (i < 5 ? C(1) / C(9) : C(1) / C(36));
+}
+
+template <int BYTES>
+struct RawOf;
+template <>
+struct RawOf<16> {
+    typedef uint32_t type __attribute__((ext_vector_type(4)));
+};
+template <>
+struct RawOf<8> {
+    typedef uint32_t type __attribute__((ext_vector_type(2)));
+};
+
+template <class T, int VEC, bool NT>
+__device__ __forceinline__ void load_vec(const T *p, T (&e)[VEC]) {
+    using R = typename RawOf<sizeof(T) * VEC>::type;
+    R r;
+    if constexpr (NT) r = __builtin_nontemporal_load(reinterpret_cast<const R *>(p));
+    else r = *reinterpret_cast<const R *>(p);
+    __builtin_memcpy(e, &r, sizeof(R));
+}
+template <class T, int VEC, bool NT>
+__device__ __forceinline__ void store_vec(T *p, const T (&e)[VEC]) {
+    using R = typename RawOf<sizeof(T) * VEC>::type;
+    R r;
+    __builtin_memcpy(&r, e, sizeof(R));
+    if constexpr (NT) __builtin_nontemporal_store(r, reinterpret_cast<R *>(p));
+    else *reinterpret_cast<R *>(p) = r;
+}
+
+template <int V>
+struct NSpecies {
+    static constexpr int value = V == kGS ? 2 : V + 1;
+};
+
+// Reaction term for one site (Section II.B linear decay; Section III
+// Gray-Scott with A_0 = k_1 = 1).
+template <int V, class C>
+__device__ __forceinline__ void reaction(const Params<C> &p, const C (&rho)[NSpecies<V>::value],
+                                         C (&R)[NSpecies<V>::value]) {
+    constexpr int NS = NSpecies<V>::value;
+    if constexpr (V == kGS) {
+        const C u = rho[0], v = rho[1];
+        const C uvv = u * v * v;
+        R[0] = -uvv + p.F * (C(1) - u);
+        R[1] = uvv - p.Fk * v;
+    } else {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            C acc = C(0);
+#pragma unroll
+            for (int j = 0; j < NS; ++j) acc += p.K[s * NS + j] * rho[j];
+            R[s] = acc + p.c[s];
+        }
+    }
+}
+
+// ---------------------------------------------------------- step tile --
+
+struct TileGeom {
+    int nx, ny;
+    int64_t pitch, pstride;
+    int lx_shift, nvec, nseg, rpw;
+};
+
+// One wave advances one tile by one step.  `lane` is 0..63; every lane of the
+// wave executes this function (lanes outside the lattice compute on clamped
+// addresses and do not store).
+template <int ST, int V, int VEC, bool NT>
+__device__ __forceinline__ void step_tile(const typename Traits<ST>::T *__restrict__ src,
+                                          typename Traits<ST>::T *__restrict__ dst, const TileGeom &g,
+                                          int64_t tile, int lane, const Params<typename Traits<ST>::C> &p) {
+    using T = typename Traits<ST>::T;
+    using C = typename Traits<ST>::C;
+    constexpr int NS = NSpecies<V>::value;
+
+    const int lanes_x = 1 << g.lx_shift;
+    const int sx = (int)(tile % g.nseg);
+    const int ry = (int)(tile / g.nseg);
+    const int vx = lane & (lanes_x - 1);
+    const int y = ry * g.rpw + (lane >> g.lx_shift);
+    const bool row_ok = y < g.ny;
+    const int yc = row_ok ? y : g.ny - 1;
+    const int v = sx * lanes_x + vx;
+    const bool vec_ok = v < g.nvec;
+    const int x0 = (vec_ok ? v : g.nvec - 1) * VEC;
+    const int cnt = min(VEC, g.nx - x0);              // valid sites of this vector
+    const bool last = x0 + VEC >= g.nx;                // holds site nx - 1
+    const bool edge_lo = vx == 0;                      // left neighbour not in this segment
+    const bool edge_hi = (vx == lanes_x - 1) || last;  // right neighbour not in this segment
+    const int ym = yc == 0 ? g.ny - 1 : yc - 1;
+    const int yp = yc + 1 == g.ny ? 0 : yc + 1;
+    const int xprev = x0 == 0 ? g.nx - 1 : x0 - 1;
+    const int xnext = last ? 0 : x0 + VEC;
+
+    // Pull loads: plane (s, i) at row y - e_iy.
+    T raw[NS][9][VEC];
+    T e_lo[NS][9], e_hi[NS][9];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const int row = kEy[i] == 1 ? ym : (kEy[i] == -1 ? yp : yc);
+            const T *rp = src + (int64_t)(s * 9 + i) * g.pstride + (int64_t)row * g.pitch;
+            load_vec<T, VEC, NT>(rp + x0, raw[s][i]);
+            // only the edge lanes issue these single-element loads (exec-masked)
+            e_lo[s][i] = T(0);
+            e_hi[s][i] = T(0);
+            if (kEx[i] == 1) {
+                if (edge_lo) e_lo[s][i] = rp[xprev];
+            }
+            if (kEx[i] == -1) {
+                if (edge_hi) e_hi[s][i] = rp[xnext];
+            }
+        }
+    }
+
+    // Decode and shift along x.
+    C f[NS][9][VEC];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const C sh = p.shift[s][i];
+            C d[VEC];
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) d[j] = decode<ST>(raw[s][i][j], sh);
+            if (kEx[i] == 0) {
+#pragma unroll
+                for (int j = 0; j < VEC; ++j) f[s][i][j] = d[j];
+            } else if (kEx[i] == 1) {
+                const C nb = __shfl_up(d[VEC - 1], 1);
+                const C prev = edge_lo ? decode<ST>(e_lo[s][i], sh) : nb;
+                f[s][i][0] = prev;
+#pragma unroll
+                for (int j = 1; j < VEC; ++j) f[s][i][j] = d[j - 1];
+            } else {
+                const C nb = __shfl_down(d[0], 1);
+                const C next = edge_hi ? decode<ST>(e_hi[s][i], sh) : nb;
+#pragma unroll
+                for (int j = 0; j < VEC - 1; ++j) f[s][i][j] = (last && j == cnt - 1) ? next : d[j + 1];
+                f[s][i][VEC - 1] = next;
+            }
+        }
+    }
+
+    // Collide and react, site by site.
+    T out[NS][9][VEC];
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) {
+        C rho[NS], R[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            C acc = f[s][0][j];
+#pragma unroll
+            for (int i = 1; i < 9; ++i) acc += f[s][i][j];
+            rho[s] = acc;
+        }
+        reaction<V, C>(p, rho, R);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const C a = p.omega[s] * rho[s] + R[s];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const C o = f[s][i][j] * p.keep[s] + wgt<C>(i) * a;
+                out[s][i][j] = encode<ST>(o, p.shift[s][i]);
+            }
+        }
+    }
+
+    if (row_ok && vec_ok) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                store_vec<T, VEC, NT>(dst + (int64_t)(s * 9 + i) * g.pstride + (int64_t)yc * g.pitch + x0,
+                                      out[s][i]);
+    }
+}
+
+// Block index remap so that consecutive tiles land on the same XCD (blocks
+// are dealt to the 8 XCDs round-robin): XCD x gets a contiguous run.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    const int q = nb >> 3, r = nb & 7, x = b & 7;
+    return x * q + min(x, r) + (b >> 3);
+}
+
+template <int ST, int V, int VEC, bool NT>
+__global__ __launch_bounds__(256) void k_step(Grid gr, Params<typename Traits<ST>::C> p) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int waves = blockDim.x >> 6;
+    const int64_t tile = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * waves + wave;
+    if (tile >= gr.ntiles) return;
+    TileGeom g{gr.nx, gr.ny, gr.pitch, gr.pstride, gr.lx_shift, gr.nvec, gr.nseg, gr.rpw};
+    step_tile<ST, V, VEC, NT>(static_cast<const typename Traits<ST>::T *>(gr.src),
+                              static_cast<typename Traits<ST>::T *>(gr.dst), g, tile, lane, p);
+}
+
+}  // namespace lbrd

@@ -1,0 +1,151 @@
+// Internal declarations shared by the lbrd host library and its HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "lbrd.h"
+
+namespace lbrd {
+
+// Velocity numbering of the public ABI: rest, the four axis directions, the
+// four diagonals (the D2Q9 set of Section II.A, Eq. "Weights").
+constexpr int kEx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int kEy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+
+// Storage traits indices (match LBRD_F64 .. LBRD_BF16_SHIFTED).
+enum Storage : int { kF64 = 0, kF32 = 1, kF16 = 2, kBF16 = 3 };
+
+inline int storage_bytes(int st) { return st == kF64 ? 8 : st == kF32 ? 4 : 2; }
+
+// Reaction variants compiled into the step kernel.  NONE runs as LINEAR
+// with K = 0, c = 0, which adds exactly +0 to every population.
+enum Variant : int { kLin1 = 0, kLin2 = 1, kLin3 = 2, kLin4 = 3, kGS = 4, kNumVariants = 5 };
+
+inline int variant_of(const lbrd_config &c) {
+    if (c.reaction == LBRD_REACT_GRAY_SCOTT) return kGS;
+    return c.nspecies - 1;
+}
+
+// Row-major planes f[s][i] of ny rows x `pitch` elements, `pstride` elements
+// apart.  The stored value of plane (s, i) at site y is the post-collision
+// population that streams into y + e_i at the next step.
+struct Layout {
+    int nx = 0, ny = 0, ns = 0, esize = 0;
+    int64_t pitch = 0;     // elements per row (64-byte multiple)
+    int64_t pstride = 0;   // elements per plane (256-byte multiple + skew)
+    size_t buf_bytes = 0;  // one population buffer
+};
+
+Layout make_layout(const lbrd_config &c);
+
+// Arithmetic parameters of one lattice, in the compute type C (double for
+// F64 storage, float otherwise).  Weighted shifts w_i * rho_ref_s are
+// computed on the host in C so host and device agree bit for bit.
+template <class C>
+struct Params {
+    C omega[LBRD_MAX_SPECIES];   // 1 / tau_s
+    C keep[LBRD_MAX_SPECIES];    // 1 - 1 / tau_s
+    C K[LBRD_MAX_SPECIES * LBRD_MAX_SPECIES];
+    C c[LBRD_MAX_SPECIES];
+    C F, k, Fk;                  // Fk = F + k
+    C shift[LBRD_MAX_SPECIES][9];
+};
+
+template <class C>
+Params<C> make_params(const lbrd_config &c);
+
+// Geometry of one step launch over one lattice.
+struct Grid {
+    const void *src;
+    void *dst;
+    int nx, ny;
+    int64_t pitch, pstride;
+    int lanes_x;      // lanes per row segment (power of two, <= 64)
+    int lx_shift;     // log2(lanes_x)
+    int nvec;         // ceil(nx / vec)
+    int nseg;         // ceil(nvec / lanes_x)
+    int rpw;          // rows per wave = 64 / lanes_x
+    int64_t ntiles;   // nseg * ceil(ny / rpw): one tile per wave
+};
+
+Grid make_grid(const Layout &L, const void *src, void *dst, int vec, int lanes_x);
+
+// ------------------------------------------------------------ launchers --
+
+struct StepLaunch {
+    int storage, variant, vec, waves;
+    bool nontemporal;
+};
+
+// One time step of one lattice: src -> dst.  launch_step dispatches to the
+// per-storage instantiations.
+hipError_t launch_step_f64(const StepLaunch &sl, const Grid &g, const void *params, hipStream_t st);
+hipError_t launch_step_f32(const StepLaunch &sl, const Grid &g, const void *params, hipStream_t st);
+hipError_t launch_step_f16(const StepLaunch &sl, const Grid &g, const void *params, hipStream_t st);
+hipError_t launch_step_bf16(const StepLaunch &sl, const Grid &g, const void *params, hipStream_t st);
+hipError_t launch_step(const StepLaunch &sl, const Grid &g, const void *params, hipStream_t st);
+bool step_shape_valid(int storage, int vec, int lanes_x, int waves);
+
+hipError_t launch_init(int storage, const Layout &L, const void *params, const void *rho0, int dtype, void *dst,
+                       hipStream_t st);
+hipError_t launch_set_populations(int storage, const Layout &L, const void *params, const void *f, int dtype,
+                                  void *dst, hipStream_t st);
+hipError_t launch_get_populations(int storage, const Layout &L, const void *params, const void *src, void *f_out,
+                                  int dtype, hipStream_t st);
+// Moments read-out plus FP64 per-block partial sums (mass and, when ref is
+// given, the two sums of the relative L2 error).  partials holds
+// kRedBlocks * kRedSlots doubles; result receives kRedSlots doubles laid out
+// as [sum rho_s | sum (ref - rho)_s^2 | sum ref_s^2], LBRD_MAX_SPECIES each.
+constexpr int kRedBlocks = 512;
+constexpr int kRedSlots = 3 * LBRD_MAX_SPECIES;
+constexpr int kRedThreads = 256;
+hipError_t launch_moments(int storage, const Layout &L, const void *params, const void *src, void *rho_out,
+                          int dtype, const void *ref, int ref_dtype, double *partials, double *result,
+                          hipStream_t st);
+
+// ------------------------------------------------------------- batching --
+
+// Device descriptor of one lattice of a batch, read by the persistent step
+// kernel with wave-uniform loads.  At step j of a chunk the instance reads
+// buf[cur ^ (j & 1)] and writes the other buffer, for j < steps.
+struct alignas(16) BatchInst {
+    const void *buf[2];
+    int64_t pitch, pstride;
+    int64_t tile_begin;   // first global tile index of this instance
+    int64_t ntiles;
+    int32_t nx, ny;
+    int32_t lanes_x, lx_shift, nvec, nseg, rpw;
+    int32_t storage, variant, vec;
+    int32_t cur;          // buffer holding the state at the start of the chunk
+    int32_t steps;        // steps this instance takes in the chunk
+    union {
+        Params<float> pf;
+        Params<double> pd;
+    };
+};
+
+struct alignas(16) BatchHeader {
+    int32_t count;        // instances
+    int32_t pad;
+    int64_t total_tiles;  // sum of ntiles
+};
+
+// Kernel variant sets of the batched step (fewer compiled variants, fewer
+// registers): F32 Gray-Scott only; the serving mix (F32 / F16 / BF16 storage,
+// single-species linear or Gray-Scott); everything.
+enum BatchSet : int { kBatchGSF32 = 0, kBatchServe = 1, kBatchAny = 2 };
+
+// Step j of a chunk for every instance: one persistent launch of `blocks`
+// workgroups of `waves` waves that loop over all tiles.  hdr and inst live in
+// device memory, so a captured graph stays valid when their contents change.
+hipError_t launch_batch_step(const BatchHeader *hdr, const BatchInst *inst, int j, int blocks, int waves,
+                             bool nontemporal, int set, hipStream_t st);
+int batch_vec(int storage);
+void fill_batch_inst(BatchInst &bi, const lbrd_config &c, const Layout &L, const void *buf0, const void *buf1,
+                     int vec, int lanes_x);
+
+int device_cu_count();
+
+}  // namespace lbrd

@@ -1,0 +1,43 @@
+// Host-side launch templates of the step kernel, instantiated once per
+// storage form in its own translation unit (parallel compilation).
+#pragma once
+#include "lbrd_device.h"
+
+namespace lbrd {
+
+template <int ST, int V, int VEC>
+inline hipError_t launch_step_t(const StepLaunch &sl, const Grid &g, const void *params, hipStream_t st) {
+    using C = typename Traits<ST>::C;
+    const Params<C> &p = *static_cast<const Params<C> *>(params);
+    const int64_t nb64 = (g.ntiles + sl.waves - 1) / sl.waves;
+    if (nb64 > 0x7fffffff) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)nb64), block(64 * sl.waves);
+    if (sl.nontemporal) hipLaunchKernelGGL((k_step<ST, V, VEC, true>), grid, block, 0, st, g, p);
+    else hipLaunchKernelGGL((k_step<ST, V, VEC, false>), grid, block, 0, st, g, p);
+    return hipGetLastError();
+}
+
+template <int ST, int V>
+inline hipError_t launch_step_v(const StepLaunch &sl, const Grid &g, const void *params, hipStream_t st) {
+    if constexpr (ST == kF64) {
+        return launch_step_t<ST, V, 2>(sl, g, params, st);
+    } else if constexpr (ST == kF32) {
+        return sl.vec == 2 ? launch_step_t<ST, V, 2>(sl, g, params, st) : launch_step_t<ST, V, 4>(sl, g, params, st);
+    } else {
+        return sl.vec == 4 ? launch_step_t<ST, V, 4>(sl, g, params, st) : launch_step_t<ST, V, 8>(sl, g, params, st);
+    }
+}
+
+template <int ST>
+inline hipError_t launch_step_s(const StepLaunch &sl, const Grid &g, const void *params, hipStream_t st) {
+    switch (sl.variant) {
+        case kLin1: return launch_step_v<ST, kLin1>(sl, g, params, st);
+        case kLin2: return launch_step_v<ST, kLin2>(sl, g, params, st);
+        case kLin3: return launch_step_v<ST, kLin3>(sl, g, params, st);
+        case kLin4: return launch_step_v<ST, kLin4>(sl, g, params, st);
+        case kGS: return launch_step_v<ST, kGS>(sl, g, params, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace lbrd

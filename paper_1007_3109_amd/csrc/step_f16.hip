@@ -1,0 +1,10 @@
+// Step kernels for f16 population storage.
+#include "lbrd_step_launch.h"
+
+namespace lbrd {
+
+hipError_t launch_step_f16(const StepLaunch &sl, const Grid &g, const void *params, hipStream_t st) {
+    return launch_step_s<kF16>(sl, g, params, st);
+}
+
+}  // namespace lbrd

@@ -1,0 +1,147 @@
+"""Batched persistent launches and the continuous-batching server on the GPU.
+
+Every lattice advanced in a batch or by the server must give exactly the
+result of the same lattice advanced alone by the single-lattice kernel with
+the same vector width: the per-site arithmetic is identical and there are no
+atomics, so the comparison is bitwise.  The batch results are also checked
+against the FP64 oracle with the FP32 bar of the parity tests.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from paper_1007_3109_amd import workloads  # noqa: E402
+
+if torch.cuda.is_available():
+    from paper_1007_3109_amd import lbrd  # noqa: E402
+
+BATCH_VEC = {"f64": 2, "f32": 4, "f16": 4, "bf16": 4}
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def solo(cfg, rho0, steps):
+    s = lbrd.Solver(cfg)
+    storage = {v: k for k, v in lbrd.STORAGE.items()}[cfg.storage]
+    s.set_tuning(vec=BATCH_VEC[storage], lanes_x=0, waves=4, graph_steps=0)
+    s.init(rho0).step(steps)
+    return s.moments()[0]
+
+
+def mixed_cases():
+    rng = np.random.default_rng(0)
+    cases = []
+    for j, (side, storage) in enumerate([(48, "f32"), (67, "f32"), (128, "f16"), (33, "bf16"), (200, "f32"),
+                                         (20, "f64"), (96, "f16")]):
+        if j % 3 == 2:
+            cfg = lbrd.make_config(side, side + 3, 1, tau=0.8, storage=storage, reaction="linear", K=[[-0.003]],
+                                   rho_ref=(1.0,))
+            rho0 = workloads.sinusoid(side, side + 3, 0.1, 1)
+        else:
+            F, k = workloads.draw_gs_unstable(rng)
+            cfg = lbrd.make_config(side, side + 3, 2, tau=workloads.GS_TAU, storage=storage, reaction="gray_scott",
+                                   F=F, k=k, rho_ref=(1.0, 0.0))
+            rho0 = workloads.gray_scott_square(side, side + 3, rng=np.random.default_rng(j))
+        cases.append((cfg, rho0))
+    return cases
+
+
+def test_batch_gs_f32_equals_solo_and_oracle():
+    insts = [i for i in workloads.batch_sweep(3, grid=4, sides=(64, 96, 130))]
+    cfgs = [lbrd.make_config(i.side, i.side, 2, tau=workloads.GS_TAU, storage="f32", reaction="gray_scott",
+                             F=i.F, k=i.k) for i in insts]
+    b = lbrd.Batch(cfgs)
+    for idx, inst in enumerate(insts):
+        b.init(idx, workloads.batch_initial(inst))
+    steps = 151
+    b.step(steps)
+    for idx, inst in enumerate(insts):
+        got = b.moments(idx)[0]
+        want = solo(cfgs[idx], workloads.batch_initial(inst), steps)
+        assert torch.equal(got, want), idx
+        if idx % 5 == 0:
+            ref = oracle.solve(workloads.batch_initial(inst), steps, list(workloads.GS_TAU), oracle.REACT_GRAY_SCOTT,
+                               F=inst.F, k=inst.k)
+            assert np.all(oracle.rel_l2(got.cpu().numpy(), ref) <= 1e-5)
+    log(f"batch of {len(insts)} GS f32 lattices: bitwise equal to solo runs")
+
+
+@pytest.mark.parametrize("graph_steps", [0, 8])
+def test_batch_mixed_storage_and_reactions(graph_steps):
+    cases = mixed_cases()
+    b = lbrd.Batch([c for c, _ in cases])
+    b.set_tuning(graph_steps=graph_steps)
+    for idx, (_, rho0) in enumerate(cases):
+        b.init(idx, rho0)
+    b.step(37)
+    b.step(20)
+    for idx, (cfg, rho0) in enumerate(cases):
+        got = b.moments(idx)[0]
+        assert torch.equal(got, solo(cfg, rho0, 57)), idx
+
+
+def test_batch_autotune_then_run():
+    insts = workloads.batch_sweep(1, grid=3, sides=(64, 128))
+    cfgs = [lbrd.make_config(i.side, i.side, 2, tau=workloads.GS_TAU, storage="f32", reaction="gray_scott",
+                             F=i.F, k=i.k) for i in insts]
+    b = lbrd.Batch(cfgs)
+    t = b.autotune(steps=3)
+    assert 1 <= t.blocks_per_cu <= 32 and t.waves in (1, 2, 4)
+    assert lbrd.lib.lbrd_batch_step(b._h, 1) == lbrd.ESTATE
+    for idx, inst in enumerate(insts):
+        b.init(idx, workloads.batch_initial(inst))
+    b.step(40)
+    for idx, inst in enumerate(insts):
+        assert torch.equal(b.moments(idx)[0], solo(cfgs[idx], workloads.batch_initial(inst), 40))
+
+
+def test_server_results_equal_solo_runs():
+    cases = [(c, r) for c, r in mixed_cases() if c.storage != lbrd.STORAGE["f64"]]
+    steps = [130, 64, 300, 1, 77, 250]
+    srv = lbrd.Server(arena_bytes=256 << 20, chunk_steps=64)
+    tickets = []
+    for (cfg, rho0), n in zip(cases, steps):
+        tickets.append(srv.submit(cfg, rho0, n))
+    for t in tickets:
+        srv.wait(t, 120)
+    for t, (cfg, rho0), n in zip(tickets, cases, steps):
+        rho, mass, info = srv.take(t)
+        want = solo(cfg, rho0, n).cpu().numpy()
+        assert np.array_equal(rho, want), t
+        assert info.state == 2 and info.done_s >= info.admit_s >= info.submit_s
+        np.testing.assert_allclose(mass, want.reshape(want.shape[0], -1).sum(axis=1), rtol=1e-12)
+    st = srv.stats()
+    assert st.completed == len(tickets) and st.resident == 0 and st.queued == 0
+    srv.close()
+
+
+def test_server_admission_by_footprint():
+    """An arena that holds about two requests at a time: the others queue and
+    are admitted as memory frees; all finish; the peak stays within the arena."""
+    cfg = lbrd.make_config(256, 256, 2, tau=workloads.GS_TAU, storage="f32", reaction="gray_scott", F=0.04, k=0.06)
+    fp = lbrd.server_footprint(cfg)
+    arena = int(2.5 * fp) + (1 << 20)
+    srv = lbrd.Server(arena_bytes=arena, chunk_steps=50)
+    rho0 = workloads.gray_scott_square(256, 256, seed=0)
+    tickets = [srv.submit(cfg, rho0, 120) for _ in range(6)]
+    for t in tickets:
+        srv.wait(t, 120)
+    outs = [srv.take(t) for t in tickets]
+    for rho, _, info in outs[1:]:
+        assert np.array_equal(rho, outs[0][0])
+    admits = sorted(o[2].admit_s for o in outs)
+    assert admits[-1] > admits[1]            # later requests waited for memory
+    st = srv.stats()
+    assert st.arena_peak_used <= st.arena_bytes and st.arena_peak_used >= 2 * fp
+    big = lbrd.make_config(2048, 2048, 2, tau=workloads.GS_TAU, storage="f32", reaction="gray_scott", F=0.04, k=0.06)
+    with pytest.raises(lbrd.LbrdError) as ei:
+        srv.submit(big, np.zeros((2, 2048, 2048)), 10)
+    assert ei.value.status == lbrd.ENOMEM
+    srv.close()

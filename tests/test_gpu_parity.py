@@ -1,0 +1,292 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle.
+
+Tolerances (relative L2 of rho per species unless stated):
+  * F64 storage: 1e-12 (rounding-order differences only).
+  * F32 storage, linear reactions: 1e-5.
+  * F32 storage, Gray-Scott: 1e-5 where the oracle's own float build stays
+    within 1e-6 of FP64 (the FP32 rounding floor), else 3x that floor.
+  * Population-level checks from random non-equilibrium states: 1e-13
+    (F64) relative to the largest population.
+  * 16-bit shifted storage against the oracle's float build with the same
+    storage rounding: 2e-4 (the two sides round the same stored values, but
+    FMA contraction on the GPU can move a value across a 16-bit rounding
+    boundary; such a flip is one unit in the last place of a stored value,
+    2^-11 (binary16) or 2^-8 (bfloat16) relative, and is diffused afterwards).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from paper_1007_3109_amd import workloads  # noqa: E402
+
+if torch.cuda.is_available():
+    from paper_1007_3109_amd import lbrd  # noqa: E402
+
+
+def gpu_solve(rho0, steps, storage="f32", **cfgkw):
+    n, ny, nx = rho0.shape
+    cfg = lbrd.make_config(nx, ny, n, storage=storage, **cfgkw)
+    s = lbrd.Solver(cfg)
+    s.init(rho0).step(steps)
+    rho, mass = s.moments()
+    return rho.cpu().numpy(), mass, s
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+# ----- config 1: 64 x 64, F64, linear decay, 1000 steps ----------------------
+
+def test_sinusoid_decay_f64_matches_oracle_and_closed_form():
+    rho0 = workloads.sinusoid(64, 64, 0.1, 1)
+    rho, mass, _ = gpu_solve(rho0, 1000, "f64", tau=1.0, reaction="linear", K=[[-1e-3]])
+    ref = oracle.solve(rho0, 1000, 1.0, oracle.REACT_LINEAR, K=[-1e-3])
+    err = oracle.rel_l2(rho, ref)[0]
+    log(f"config1 f64 rel L2 vs oracle {err:.3e}")
+    assert err <= 1e-12
+    lam = (2 + math.cos(2 * math.pi / 64)) / 3
+    exact = (1 - 1e-3) ** 1000 * (1 + 0.1 * lam ** 1000 * np.sin(2 * math.pi * np.arange(64) / 64))
+    assert np.abs(rho[0] - exact[None]).max() <= 1e-12 * exact.max()
+    assert abs(mass[0] - (1 - 1e-3) ** 1000 * 64 * 64) <= 1e-11 * mass[0]
+
+
+# ----- linear reactions in F32 on ragged sizes ------------------------------
+
+@pytest.mark.parametrize("shape", [(45, 67), (1, 1), (3, 1), (7, 5), (130, 33), (64, 64), (17, 257)])
+def test_linear_f32_ragged(shape):
+    ny, nx = shape
+    rng = np.random.default_rng(ny * 1000 + nx)
+    rho0 = rng.uniform(0.5, 1.5, size=(2, ny, nx))
+    K = [[-0.01, 0.0], [0.01, -0.002]]
+    c = [0.001, 0.0]
+    rho, _, _ = gpu_solve(rho0, 200, "f32", tau=(0.8, 1.3), reaction="linear", K=K, c=c)
+    ref = oracle.solve(rho0, 200, [0.8, 1.3], oracle.REACT_LINEAR, K=K, c=c)
+    err = oracle.rel_l2(rho, ref)
+    log(f"linear f32 {shape}: {err}")
+    assert np.all(err <= 1e-5)
+
+
+# ----- population-level exactness from random non-equilibrium states ---------
+
+SHAPES = [(1, 1), (1, 3), (3, 3), (2, 5), (5, 131), (33, 17), (64, 70), (9, 8)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_populations_f64_every_launch_shape(shape):
+    """Random f, every valid (vec, lanes_x, waves) shape: the streamed and
+    collided populations after 7 steps match the oracle."""
+    ny, nx = shape
+    rng = np.random.default_rng(nx + 100 * ny)
+    f0 = rng.uniform(0.0, 0.1, size=(2, 9, ny, nx))
+    kw = dict(F=0.04, k=0.06)
+    ref = oracle.run(f0, 7, [0.7, 1.2], oracle.REACT_GRAY_SCOTT, **kw)
+    cfg = lbrd.make_config(nx, ny, 2, tau=(0.7, 1.2), storage="f64", reaction="gray_scott", **kw)
+    s = lbrd.Solver(cfg)
+    shapes = 0
+    for lx in (1, 2, 4, 8, 16, 32, 64):
+        for waves in (1, 4):
+            for nt in (0, 1):
+                s.set_tuning(vec=2, lanes_x=lx, waves=waves, nontemporal=nt, graph_steps=0)
+                s.set_populations(f0).step(7)
+                got = s.get_populations().cpu().numpy()
+                assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max(), (shape, lx, waves, nt)
+                shapes += 1
+    log(f"populations f64 {shape}: {shapes} launch shapes ok")
+
+
+@pytest.mark.parametrize("storage,vecs", [("f32", (2, 4))])
+def test_populations_f32_vec_variants(storage, vecs):
+    rng = np.random.default_rng(5)
+    ny, nx = 19, 77
+    f0 = rng.uniform(0.0, 0.1, size=(2, 9, ny, nx))
+    ref = oracle.run(f0, 5, [0.7, 1.2], oracle.REACT_GRAY_SCOTT, F=0.04, k=0.06)
+    cfg = lbrd.make_config(nx, ny, 2, tau=(0.7, 1.2), storage=storage, reaction="gray_scott", F=0.04, k=0.06)
+    s = lbrd.Solver(cfg)
+    for vec in vecs:
+        for lx in (4, 16, 32):
+            s.set_tuning(vec=vec, lanes_x=lx, waves=2, graph_steps=0)
+            s.set_populations(f0).step(5)
+            got = s.get_populations().cpu().numpy()
+            assert np.abs(got - ref).max() <= 2e-6 * np.abs(ref).max(), (vec, lx)
+
+
+# ----- Gray-Scott F32 against FP64, with the FP32 rounding floor -------------
+
+@pytest.mark.parametrize("n,steps", [(96, 1000), (130, 300)])
+def test_gray_scott_f32(n, steps):
+    rho0 = workloads.gray_scott_square(n, n - 3, seed=1)
+    kw = dict(F=workloads.GS_F, k=workloads.GS_K)
+    rho, _, _ = gpu_solve(rho0, steps, "f32", tau=workloads.GS_TAU, reaction="gray_scott", **kw)
+    ref = oracle.solve(rho0, steps, list(workloads.GS_TAU), oracle.REACT_GRAY_SCOTT, **kw)
+    floor = oracle.rel_l2(oracle.solve(rho0, steps, list(workloads.GS_TAU), oracle.REACT_GRAY_SCOTT,
+                                       precision="f32", **kw), ref)
+    err = oracle.rel_l2(rho, ref)
+    tol = np.where(floor <= 1e-6, 1e-5, 3 * floor)
+    log(f"GS f32 {n}: err {err} floor {floor}")
+    assert np.all(err <= tol)
+
+
+# ----- 16-bit shifted storage ------------------------------------------------
+
+@pytest.mark.parametrize("storage,quant", [("f16", 1), ("bf16", 2)])
+def test_shifted_storage_matches_emulation(storage, quant):
+    n, steps = 80, 200
+    rho0 = workloads.gray_scott_square(n, n, seed=2)
+    kw = dict(F=workloads.GS_F, k=workloads.GS_K)
+    rho, _, _ = gpu_solve(rho0, steps, storage, tau=workloads.GS_TAU, reaction="gray_scott", rho_ref=(1.0, 0.0), **kw)
+    f = oracle.init(rho0, "f32")
+    f = oracle.encode(f, quant, [1.0, 0.0])
+    emu = oracle.moments(oracle.run(f, steps, list(workloads.GS_TAU), oracle.REACT_GRAY_SCOTT, quant=quant,
+                                    rho_ref=[1.0, 0.0], **kw))
+    ref = oracle.solve(rho0, steps, list(workloads.GS_TAU), oracle.REACT_GRAY_SCOTT, **kw)
+    e_emu = oracle.rel_l2(rho, emu)
+    e_64 = oracle.rel_l2(rho, ref)
+    log(f"{storage}: vs emulation {e_emu}, vs FP64 {e_64}")
+    assert np.all(e_emu <= 2e-4)
+    assert np.all(e_64 <= (5e-3 if storage == "f16" else 5e-2))
+
+
+# ----- read-outs ---------------------------------------------------------------
+
+def test_mass_reduction_and_rel_l2():
+    rng = np.random.default_rng(9)
+    rho0 = rng.uniform(0.0, 2.0, size=(3, 123, 301))
+    cfg = lbrd.make_config(301, 123, 3, tau=(0.6, 0.9, 1.7), storage="f64", reaction="none")
+    s = lbrd.Solver(cfg)
+    s.init(rho0)
+    rho, mass = s.moments()
+    rho = rho.cpu().numpy()
+    assert np.abs(rho - rho0).max() <= 1e-15 * 2
+    np.testing.assert_allclose(mass, oracle.mass(rho), rtol=1e-14)
+    s.step(500)
+    _, m2 = s.moments()
+    np.testing.assert_allclose(m2, mass, rtol=1e-12)
+    ref = torch.tensor(rho0 * 1.01, device="cuda")
+    e = s.rel_l2(ref)
+    mine = oracle.rel_l2(s.moments()[0].cpu().numpy(), rho0 * 1.01)
+    np.testing.assert_allclose(e, mine, rtol=1e-10)
+
+
+def test_f32_mass_conservation_without_reaction():
+    rho0 = workloads.gray_scott_square(256, 256, seed=3)
+    cfg = lbrd.make_config(256, 256, 2, tau=workloads.GS_TAU, storage="f32", reaction="none")
+    s = lbrd.Solver(cfg)
+    s.init(rho0)
+    m0 = s.mass()
+    s.step(2000)
+    m1 = s.mass()
+    drift = np.abs(m1 - m0) / np.abs(m0)
+    log(f"f32 mass drift after 2000 steps: {drift}")
+    assert np.all(drift <= 1e-5)
+
+
+def test_nonfinite_mass_is_reported():
+    rho0 = np.ones((1, 8, 8))
+    rho0[0, 3, 3] = np.nan
+    cfg = lbrd.make_config(8, 8, 1, tau=0.9, storage="f32")
+    s = lbrd.Solver(cfg)
+    s.init(rho0)
+    m = (lbrd.ctypes.c_double * 1)()
+    assert lbrd.lib.lbrd_moments(s._h, None, 0, m) == lbrd.ENONFINITE
+
+
+def test_step_before_init_is_a_state_error():
+    cfg = lbrd.make_config(8, 8, 1, tau=0.9)
+    s = lbrd.Solver(cfg)
+    assert lbrd.lib.lbrd_step(s._h, 1) == lbrd.ESTATE
+    assert lbrd.lib.lbrd_moments(s._h, None, 0, (lbrd.ctypes.c_double * 1)()) == lbrd.ESTATE
+
+
+def test_graph_replay_is_bitwise_identical():
+    rho0 = workloads.gray_scott_square(100, 70, seed=4)
+    kw = dict(tau=workloads.GS_TAU, reaction="gray_scott", F=0.035, k=0.06)
+    cfg = lbrd.make_config(100, 70, 2, storage="f32", **kw)
+    a = lbrd.Solver(cfg)
+    a.set_tuning(graph_steps=0)
+    b = lbrd.Solver(cfg)
+    b.set_tuning(graph_steps=16)
+    a.init(rho0)
+    b.init(rho0)
+    for n in (37, 64, 5, 100):       # graph replays plus odd remainders
+        a.step(n)
+        b.step(n)
+        ra = a.moments()[0]
+        rb = b.moments()[0]
+        assert torch.equal(ra, rb)
+    assert a.time() == b.time() == 206
+
+
+def test_autotune_picks_a_valid_shape(tmp_path):
+    cfg = lbrd.make_config(256, 256, 2, tau=workloads.GS_TAU, storage="f32", reaction="gray_scott", F=0.04, k=0.06)
+    s = lbrd.Solver(cfg)
+    cache = str(tmp_path / "tune.txt")
+    t = s.autotune(steps=4, cache_path=cache)
+    assert t.vec in (2, 4) and t.lanes_x in (16, 32, 64)
+    assert lbrd.lib.lbrd_step(s._h, 1) == lbrd.ESTATE     # state was overwritten
+    rho0 = workloads.gray_scott_square(256, 256, seed=0)
+    s.init(rho0).step(50)
+    ref = oracle.solve(rho0, 50, list(workloads.GS_TAU), oracle.REACT_GRAY_SCOTT, F=0.04, k=0.06)
+    assert np.all(oracle.rel_l2(s.moments()[0].cpu().numpy(), ref) <= 1e-5)
+    # a second solver reads the cached choice
+    s2 = lbrd.Solver(cfg)
+    t2 = s2.autotune(steps=4, cache_path=cache)
+    assert t2.as_dict() == t.as_dict()
+
+
+# ----- full-size checks --------------------------------------------------------
+
+def test_gray_scott_1024_full_field():
+    """The 1024 x 1024 Gray-Scott workload in the launch configuration the
+    benchmark times (default tuning), 100 steps, whole field vs FP64."""
+    rho0 = workloads.gray_scott_square(1024, 1024, seed=0)
+    kw = dict(F=workloads.GS_F, k=workloads.GS_K)
+    rho, _, _ = gpu_solve(rho0, 100, "f32", tau=workloads.GS_TAU, reaction="gray_scott", **kw)
+    ref = oracle.solve(rho0, 100, list(workloads.GS_TAU), oracle.REACT_GRAY_SCOTT, **kw)
+    err = oracle.rel_l2(rho, ref)
+    log(f"GS 1024 f32 100 steps: {err}")
+    assert np.all(err <= 1e-5)
+
+
+def _window_reference(rho0, steps, centre, w, quant=None, **kw):
+    """Oracle on a (w + 2 steps)-wide periodic window around `centre`: after
+    `steps` steps the central w x w block depends only on initial data inside
+    the window (information moves one site per step), so it is exact."""
+    n, ny, nx = rho0.shape
+    h = w // 2 + steps
+    ys = (np.arange(centre[0] - h, centre[0] + h) % ny)
+    xs = (np.arange(centre[1] - h, centre[1] + h) % nx)
+    sub = rho0[:, ys][:, :, xs]
+    if quant is None:
+        r = oracle.solve(sub, steps, list(workloads.GS_TAU), oracle.REACT_GRAY_SCOTT, **kw)
+    else:
+        f = oracle.encode(oracle.init(sub, "f32"), quant, [1.0, 0.0])
+        r = oracle.moments(oracle.run(f, steps, list(workloads.GS_TAU), oracle.REACT_GRAY_SCOTT, quant=quant,
+                                      rho_ref=[1.0, 0.0], **kw))
+    c = steps
+    return r[:, c:c + w, c:c + w], ys[c:c + w], xs[c:c + w]
+
+
+@pytest.mark.parametrize("storage,quant", [("f32", None), ("f16", 1)])
+def test_gray_scott_4096_sampled_windows(storage, quant):
+    """4096 x 4096, the benchmark's launch shape: sampled 32 x 32 windows
+    (including the periodic corner and the perturbed centre) against the
+    oracle computed on their dependence cones."""
+    n, steps = 4096, 60
+    rho0 = workloads.gray_scott_square(n, n, seed=0)
+    kw = dict(F=workloads.GS_F, k=workloads.GS_K)
+    extra = dict(rho_ref=(1.0, 0.0)) if storage != "f32" else {}
+    rho, _, _ = gpu_solve(rho0, steps, storage, tau=workloads.GS_TAU, reaction="gray_scott", **kw, **extra)
+    for centre in [(0, 0), (2048, 2048), (2016, 2080), (4095, 17), (1000, 3000)]:
+        ref, ys, xs = _window_reference(rho0, steps, centre, 32, quant=quant, **kw)
+        got = rho[:, ys][:, :, xs]
+        err = oracle.rel_l2(got, ref)
+        log(f"4096 {storage} window {centre}: {err}")
+        assert np.all(err <= (1e-5 if storage == "f32" else 2e-4))

@@ -58,8 +58,22 @@ def test_storage_emulation_error_scales_with_format():
     r64 = oracle.solve(rho0, 200, [1.0, 0.75], oracle.REACT_GRAY_SCOTT, **kw)
     errs = {}
     for q in (oracle.Q_F16, oracle.Q_BF16):
-        r = oracle.solve(rho0, 200, [1.0, 0.75], oracle.REACT_GRAY_SCOTT, precision="f32",
-                         quant=q, rho_ref=[1.0, 0.0], **kw)
+        f = oracle.encode(oracle.init(rho0, "f32"), q, [1.0, 0.0])
+        r = oracle.moments(oracle.run(f, 200, [1.0, 0.75], oracle.REACT_GRAY_SCOTT, quant=q, rho_ref=[1.0, 0.0], **kw))
         errs[q] = oracle.rel_l2(r, r64)
     assert np.all(errs[oracle.Q_F16] < errs[oracle.Q_BF16])
     assert np.all(errs[oracle.Q_F16] < 1e-2)
+
+
+def test_encode_is_the_storage_rounding():
+    """encode() leaves w_i rho_ref + Q(f - w_i rho_ref): the stored 16-bit value
+    recovered from it is exactly quantise(f - shift)."""
+    rng = np.random.default_rng(4)
+    f = rng.uniform(0, 0.5, size=(2, 9, 3, 5)).astype(np.float32)
+    w, _, _ = oracle.tables("f32")
+    rref = np.array([1.0, 0.25])
+    for q in (oracle.Q_F16, oracle.Q_BF16):
+        g = oracle.encode(f, q, rref)
+        shift = (w[None, :, None, None] * rref.astype(np.float32)[:, None, None, None]).astype(np.float32)
+        want = shift + oracle.quantise(f - shift, q)
+        assert np.array_equal(g, want.astype(np.float32))
