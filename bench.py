@@ -140,6 +140,96 @@ def batch_leg(torch, lbrd, workloads, steps, warmup, seed=0):
     return out
 
 
+def serve_leg(torch, lbrd, workloads, n_requests, pool_gb, steps_range, seed=0, rate=None):
+    """Poisson stream of mixed requests into the continuous-batching server."""
+    import threading
+
+    if rate is None:
+        # offered load near the measured single-kernel throughput: mean work per
+        # request / 8e10 species-site-steps per second, at 85% utilisation
+        e_side2 = (2048 ** 2 - 64 ** 2) / (2 * math.log(32))
+        e_work = 1.5 * e_side2 * (steps_range[0] + steps_range[1]) / 2
+        rate = 0.85 * 8e10 / e_work
+    reqs = workloads.request_stream(n_requests, rate, seed=seed, steps_range=steps_range)
+    cfgs, inits = [], []
+    for r in reqs:
+        if r.reaction == "linear":
+            cfg = lbrd.make_config(r.side, r.side, 1, tau=r.tau, storage=r.storage, reaction="linear", K=[[-r.K]],
+                                   rho_ref=(1.0,))
+        else:
+            cfg = lbrd.make_config(r.side, r.side, 2, tau=r.tau, storage=r.storage, reaction="gray_scott", F=r.F,
+                                   k=r.k, rho_ref=(1.0, 0.0))
+        cfgs.append(cfg)
+        inits.append(workloads.request_initial(r))
+    srv = lbrd.Server(arena_bytes=int(pool_gb * (1 << 30)), chunk_steps=500)
+    tickets = [None] * len(reqs)
+
+    def feeder():
+        t0 = time.perf_counter()
+        for i, r in enumerate(reqs):
+            dt = r.arrival - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            tickets[i] = srv.submit(cfgs[i], inits[i], r.nsteps)
+
+    th = threading.Thread(target=feeder)
+    t0 = time.perf_counter()
+    th.start()
+    th.join()
+    lat, work = [], 0
+    for i, t in enumerate(tickets):
+        srv.wait(t, 600)
+        _, _, info = srv.take(t)
+        lat.append(info.done_s - info.submit_s)
+        work += cfgs[i].nspecies * cfgs[i].nx * cfgs[i].ny * reqs[i].nsteps
+    makespan = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    del srv
+    torch.cuda.empty_cache()
+    # the plain single-lattice kernel on a sample of the same requests
+    solo_work, solo_s = 0, 0.0
+    for i in range(0, len(reqs), max(1, len(reqs) // 12)):
+        s = lbrd.Solver(cfgs[i])
+        s.init(inits[i])
+        n = min(reqs[i].nsteps, 400)
+        s.step(2)
+        solo_s += s.time_steps(n) / 1e3
+        solo_work += cfgs[i].nspecies * cfgs[i].nx * cfgs[i].ny * n
+        s.close()
+    lat = np.array(lat)
+    return {"workload": f"{len(reqs)} requests, Poisson rate {rate:.2f}/s, sides log-uniform [64, 2048], steps "
+                        f"U[{steps_range[0]}, {steps_range[1]}], half linear N=1 / half Gray-Scott, FP32 or F16 "
+                        f"storage, pool {pool_gb} GB",
+            "p50_latency_s": round(float(np.percentile(lat, 50)), 4), "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
+            "mean_latency_s": round(float(lat.mean()), 4), "makespan_s": round(makespan, 3),
+            "aggregate_mlups_per_species": round(work / makespan / 1e6, 1),
+            "busy_mlups_per_species": round(work / max(st.busy_s, 1e-9) / 1e6, 1),
+            "plain_kernel_sample_mlups_per_species": round(solo_work / solo_s / 1e6, 1),
+            "arena_peak_used_gb": round(st.arena_peak_used / 2 ** 30, 3)}
+
+
+def copy_leg(torch, nbytes=1 << 30, reps=20):
+    """Device-to-device copy of a 1 GiB tensor: the achievable HBM rate."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    out = {"bytes_per_copy": 2 * nbytes, "GBs": round(2 * nbytes / sec / 1e9, 1)}
+    del a, b
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -149,6 +239,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--extra-steps", type=int, default=300)
+    ap.add_argument("--legs", default="hbm4096_f32,hbm4096_f16,hbm4096_bf16,batch,serve,copy",
+                    help="extra legs to run (comma list)")
+    ap.add_argument("--serve-requests", type=int, default=120)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
@@ -203,11 +296,20 @@ def main():
         line["cpu_baseline"] = cpu_baseline(workloads, n, args.cpu_budget)
     if not args.no_extra:
         extra = {}
+        legs = [x for x in args.legs.split(",") if x]
         for storage in ("f32", "f16", "bf16"):
-            log(f"bench: 4096^2 {storage}")
-            extra[f"hbm_4096_{storage}"] = hbm_leg(torch, lbrd, workloads, 4096, storage, args.extra_steps, 20)
-        log("bench: batched sweep")
-        extra["batched"] = batch_leg(torch, lbrd, workloads, 200, 10)
+            if f"hbm4096_{storage}" in legs:
+                log(f"bench: 4096^2 {storage}")
+                extra[f"hbm_4096_{storage}"] = hbm_leg(torch, lbrd, workloads, 4096, storage, args.extra_steps, 20)
+        if "batch" in legs:
+            log("bench: batched sweep")
+            extra["batched"] = batch_leg(torch, lbrd, workloads, 200, 10)
+        if "serve" in legs:
+            log("bench: serving")
+            extra["serving"] = serve_leg(torch, lbrd, workloads, args.serve_requests, 16, (1000, 10000))
+        if "copy" in legs:
+            log("bench: copy")
+            extra["copy_1GiB"] = copy_leg(torch)
         line["extra"] = extra
     print(json.dumps(line), flush=True)
 

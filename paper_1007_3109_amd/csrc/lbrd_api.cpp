@@ -377,14 +377,26 @@ int lbrd_init(lbrd_solver *h, const void *rho0, int dtype, int on_device) {
 
 int lbrd_set_populations(lbrd_solver *h, const void *f, int dtype, int on_device) {
     if (!h || !f || check_dtype(dtype)) return LBRD_EINVAL;
-    const size_t bytes = (size_t)h->cfg.nspecies * 9 * h->cfg.nx * h->cfg.ny * (dtype == LBRD_DTYPE_F64 ? 8 : 4);
-    const void *src = f;
-    if (!on_device) {
-        int rc = stage_host(h, f, bytes, &src);
-        if (rc) return rc;
+    const int planes = 9 * h->cfg.nspecies;
+    const size_t plane_bytes = (size_t)h->cfg.nx * h->cfg.ny * (dtype == LBRD_DTYPE_F64 ? 8 : 4);
+    if (on_device) {
+        hipError_t e = launch_set_populations(h->cfg.storage, h->L, h->params, f, dtype, 0, planes, h->buf[h->cur],
+                                              h->stream);
+        if (e != hipSuccess) return fail("set_populations kernel", e);
+    } else {
+        // host source: staged through the idle buffer, as many planes at a time as fit
+        const int per = (int)std::max<size_t>(1, h->L.buf_bytes / plane_bytes);
+        for (int p0 = 0; p0 < planes; p0 += per) {
+            const int p1 = std::min(planes, p0 + per);
+            const void *src = nullptr;
+            int rc = stage_host(h, static_cast<const char *>(f) + p0 * plane_bytes, (p1 - p0) * plane_bytes, &src);
+            if (rc) return rc;
+            hipError_t e = launch_set_populations(h->cfg.storage, h->L, h->params, src, dtype, p0, p1,
+                                                  h->buf[h->cur], h->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+            if (e != hipSuccess) return fail("set_populations kernel", e);
+        }
     }
-    hipError_t e = launch_set_populations(h->cfg.storage, h->L, h->params, src, dtype, h->buf[h->cur], h->stream);
-    if (e != hipSuccess) return fail("set_populations kernel", e);
     h->t = 0;
     h->initialised = true;
     return LBRD_OK;

@@ -58,26 +58,29 @@ __global__ void k_init(Layout L, Params<typename Traits<ST>::C> p, const void *r
             for (int i = 0; i < 9; ++i) {
                 const int xs = wrap(x + kEx[i], L.nx), ys = wrap(y + kEy[i], L.ny);
                 const C r = load_in<C>(rho0, dtype, ((int64_t)s * L.ny + ys) * L.nx + xs);
-                dst[(int64_t)(s * 9 + i) * L.pstride + (int64_t)y * L.pitch + x] = encode<ST>(wgt<C>(i) * r, p.shift[s][i]);
+                // rest population as r - 4 w_1 r - 4 w_5 r so that the nine
+                // equilibrium populations of a site sum to r (see step_tile)
+                const C v = i == 0 ? r - C(4) * (wgt<C>(1) * r) - C(4) * (wgt<C>(5) * r) : wgt<C>(i) * r;
+                dst[(int64_t)(s * 9 + i) * L.pstride + (int64_t)y * L.pitch + x] = encode<ST>(v, p.shift[s][i]);
             }
         }
     }
 }
 
+// Planes [p0, p1) of a dense population array f[s][i][y][x] (f holds only
+// those planes, plane p0 first) into the stored pull form.
 template <int ST>
-__global__ void k_set_pop(Layout L, Params<typename Traits<ST>::C> p, const void *f, int dtype,
+__global__ void k_set_pop(Layout L, Params<typename Traits<ST>::C> p, const void *f, int dtype, int p0, int p1,
                           typename Traits<ST>::T *dst) {
     using C = typename Traits<ST>::C;
     const int64_t sites = (int64_t)L.nx * L.ny;
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < sites; k += (int64_t)gridDim.x * blockDim.x) {
         const int y = (int)(k / L.nx), x = (int)(k % L.nx);
-        for (int s = 0; s < L.ns; ++s) {
-#pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                const int xs = wrap(x + kEx[i], L.nx), ys = wrap(y + kEy[i], L.ny);
-                const C v = load_in<C>(f, dtype, (((int64_t)s * 9 + i) * L.ny + ys) * L.nx + xs);
-                dst[(int64_t)(s * 9 + i) * L.pstride + (int64_t)y * L.pitch + x] = encode<ST>(v, p.shift[s][i]);
-            }
+        for (int q = p0; q < p1; ++q) {
+            const int s = q / 9, i = q % 9;
+            const int xs = wrap(x + kEx[i], L.nx), ys = wrap(y + kEy[i], L.ny);
+            const C v = load_in<C>(f, dtype, ((int64_t)(q - p0) * L.ny + ys) * L.nx + xs);
+            dst[(int64_t)q * L.pstride + (int64_t)y * L.pitch + x] = encode<ST>(v, p.shift[s][i]);
         }
     }
 }
@@ -227,12 +230,12 @@ hipError_t launch_init(int storage, const Layout &L, const void *params, const v
 }
 
 hipError_t launch_set_populations(int storage, const Layout &L, const void *params, const void *f, int dtype,
-                                  void *dst, hipStream_t st) {
+                                  int p0, int p1, void *dst, hipStream_t st) {
     LBRD_DISPATCH_ST(storage, {
         using C = typename Traits<ST>::C;
         using T = typename Traits<ST>::T;
         hipLaunchKernelGGL((k_set_pop<ST>), dim3(elementwise_blocks(L)), dim3(256), 0, st, L,
-                           *static_cast<const Params<C> *>(params), f, dtype, static_cast<T *>(dst));
+                           *static_cast<const Params<C> *>(params), f, dtype, p0, p1, static_cast<T *>(dst));
         return hipGetLastError();
     })
 }

@@ -250,10 +250,18 @@ __device__ __forceinline__ void step_tile(const typename Traits<ST>::T *__restri
         reaction<V, C>(p, rho, R);
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
+            // w_i (rho / tau + R): the rest weight is taken as 1 - 4/9 - 4/36
+            // applied to the value itself, so the nine terms sum to exactly
+            // rho / tau + R up to unbiased rounding (the rounded weights of a
+            // binary format sum to 1 + O(eps), which would add a systematic
+            // mass drift every step).
             const C a = p.omega[s] * rho[s] + R[s];
+            const C e1 = wgt<C>(1) * a, e5 = wgt<C>(5) * a;
+            const C e0 = a - C(4) * e1 - C(4) * e5;
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
-                const C o = f[s][i][j] * p.keep[s] + wgt<C>(i) * a;
+                const C e = i == 0 ? e0 : (i < 5 ? e1 : e5);
+                const C o = f[s][i][j] * p.keep[s] + e;
                 out[s][i][j] = encode<ST>(o, p.shift[s][i]);
             }
         }

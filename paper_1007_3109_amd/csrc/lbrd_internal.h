@@ -90,8 +90,10 @@ bool step_shape_valid(int storage, int vec, int lanes_x, int waves);
 
 hipError_t launch_init(int storage, const Layout &L, const void *params, const void *rho0, int dtype, void *dst,
                        hipStream_t st);
+// Planes [p0, p1) (plane = s * 9 + i) of a dense population array that holds
+// just those planes.
 hipError_t launch_set_populations(int storage, const Layout &L, const void *params, const void *f, int dtype,
-                                  void *dst, hipStream_t st);
+                                  int p0, int p1, void *dst, hipStream_t st);
 hipError_t launch_get_populations(int storage, const Layout &L, const void *params, const void *src, void *f_out,
                                   int dtype, hipStream_t st);
 // Moments read-out plus FP64 per-block partial sums (mass and, when ref is

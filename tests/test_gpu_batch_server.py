@@ -67,9 +67,13 @@ def test_batch_gs_f32_equals_solo_and_oracle():
         want = solo(cfgs[idx], workloads.batch_initial(inst), steps)
         assert torch.equal(got, want), idx
         if idx % 5 == 0:
-            ref = oracle.solve(workloads.batch_initial(inst), steps, list(workloads.GS_TAU), oracle.REACT_GRAY_SCOTT,
-                               F=inst.F, k=inst.k)
-            assert np.all(oracle.rel_l2(got.cpu().numpy(), ref) <= 1e-5)
+            r0 = workloads.batch_initial(inst)
+            kw = dict(F=inst.F, k=inst.k)
+            ref = oracle.solve(r0, steps, list(workloads.GS_TAU), oracle.REACT_GRAY_SCOTT, **kw)
+            floor = oracle.rel_l2(oracle.solve(r0, steps, list(workloads.GS_TAU), oracle.REACT_GRAY_SCOTT,
+                                               precision="f32", **kw), ref)
+            tol = np.where(floor <= 1e-6, 1e-5, 3 * floor)
+            assert np.all(oracle.rel_l2(got.cpu().numpy(), ref) <= tol)
     log(f"batch of {len(insts)} GS f32 lattices: bitwise equal to solo runs")
 
 
