@@ -209,6 +209,71 @@ def serve_leg(torch, lbrd, workloads, n_requests, pool_gb, steps_range, seed=0, 
             "arena_peak_used_gb": round(st.arena_peak_used / 2 ** 30, 3)}
 
 
+def precision_leg(torch, lbrd, workloads, n=4096, steps=10000, check_n=256):
+    """16-bit shifted storage against FP32 storage on the same n^2 Gray-Scott
+    field (same seed), and every storage form against the FP64 oracle on a
+    check_n^2 instance with the same seed, after `steps` steps; FP64 mass drift
+    of each run."""
+    import oracle
+
+    out = {"workload": f"gray_scott {n}x{n}, {steps} steps; oracle check {check_n}x{check_n}, {steps} steps",
+           "rho_ref": [1.0, 0.0]}
+    rho0 = workloads.gray_scott_square(n, n, seed=0)
+    ref_solver = lbrd.Solver(gs_config(lbrd, workloads, n, "f32"))
+    ref_solver.init(rho0)
+    m0 = ref_solver.mass()
+    ref_solver.step(steps)
+    ref_rho, m1 = ref_solver.moments(dtype=torch.float32)
+    out["f32_mass_drift"] = [float(x) for x in (m1 - m0) / m0]
+    ref_solver.close()
+    del ref_solver
+    for st in ("f16", "bf16"):
+        s = lbrd.Solver(gs_config(lbrd, workloads, n, st))
+        s.init(rho0)
+        ma = s.mass()
+        s.step(steps)
+        rho, mb = s.moments(dtype=torch.float32)
+        out[f"{st}_vs_f32_rel_l2"] = [float(x) for x in s.rel_l2(ref_rho)]
+        out[f"{st}_vs_f32_max_abs"] = [float((rho[k] - ref_rho[k]).abs().max()) for k in range(2)]
+        out[f"{st}_mass_drift"] = [float(x) for x in (mb - ma) / ma]
+        s.close()
+        del s, rho
+    del ref_rho
+    torch.cuda.empty_cache()
+    small0 = workloads.gray_scott_square(check_n, check_n, seed=0)
+    t0 = time.perf_counter()
+    ref64 = oracle.solve(small0, steps, list(workloads.GS_TAU), oracle.REACT_GRAY_SCOTT, F=workloads.GS_F,
+                         k=workloads.GS_K)
+    out["oracle_seconds"] = round(time.perf_counter() - t0, 2)
+    ref64_t = torch.tensor(ref64, device="cuda")
+    for st in ("f32", "f16", "bf16"):
+        s = lbrd.Solver(gs_config(lbrd, workloads, check_n, st))
+        s.init(small0).step(steps)
+        rho, _ = s.moments()
+        out[f"{st}_vs_fp64_oracle_rel_l2_{check_n}"] = [float(x) for x in s.rel_l2(ref64_t)]
+        out[f"{st}_vs_fp64_oracle_max_abs_{check_n}"] = [float((rho[k] - ref64_t[k]).abs().max()) for k in range(2)]
+        s.close()
+    return out
+
+
+def config1_leg(torch, lbrd, workloads, steps=1000):
+    """64^2 single species, FP64, linear decay k = 1e-3, tau = 1: launch-bound;
+    plain launches against replayed graphs."""
+    rho0 = workloads.sinusoid(64, 64, 0.1, 1)
+    out = {"workload": "linear decay 64x64 f64, tau 1, k 1e-3"}
+    for gs in (0, 32):
+        s = lbrd.Solver(lbrd.make_config(64, 64, 1, tau=1.0, storage="f64", reaction="linear", K=[[-1e-3]]))
+        s.set_tuning(graph_steps=gs)
+        s.init(rho0)
+        s.step(64)
+        torch.cuda.synchronize()
+        ms = s.time_steps(steps)
+        out[f"graph{gs}_us_per_step"] = round(ms * 1e3 / steps, 3)
+        out[f"graph{gs}_mlups"] = round(64 * 64 * steps / (ms / 1e3) / 1e6, 1)
+        s.close()
+    return out
+
+
 def copy_leg(torch, nbytes=1 << 30, reps=20):
     """Device-to-device copy of a 1 GiB tensor: the achievable HBM rate."""
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -239,7 +304,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--extra-steps", type=int, default=300)
-    ap.add_argument("--legs", default="hbm4096_f32,hbm4096_f16,hbm4096_bf16,batch,serve,copy",
+    ap.add_argument("--legs", default="hbm4096_f32,hbm4096_f16,hbm4096_bf16,batch,serve,config1,copy",
                     help="extra legs to run (comma list)")
     ap.add_argument("--serve-requests", type=int, default=120)
     args = ap.parse_args()
@@ -307,6 +372,12 @@ def main():
         if "serve" in legs:
             log("bench: serving")
             extra["serving"] = serve_leg(torch, lbrd, workloads, args.serve_requests, 16, (1000, 10000))
+        if "precision" in legs:
+            log("bench: precision forms")
+            extra["precision"] = precision_leg(torch, lbrd, workloads)
+        if "config1" in legs:
+            log("bench: 64^2 f64")
+            extra["config1"] = config1_leg(torch, lbrd, workloads)
         if "copy" in legs:
             log("bench: copy")
             extra["copy_1GiB"] = copy_leg(torch)

@@ -200,6 +200,13 @@ int lbrd_batch_moments(lbrd_batch *b, int idx, void *rho_out, int dtype, double 
 int lbrd_batch_get_populations(lbrd_batch *b, int idx, void *f_out, int dtype);
 /* Advance every instance by nsteps (ESTATE unless all are initialised). */
 int lbrd_batch_step(lbrd_batch *b, int64_t nsteps);
+/* Advance instance i by nsteps[i] >= 0 (count entries, host array); all
+ * instances still advance together, each stopping at its own count. */
+int lbrd_batch_advance(lbrd_batch *b, const int64_t *nsteps);
+/* Steps taken by instance idx since its init. */
+int lbrd_batch_time(const lbrd_batch *b, int idx, int64_t *t);
+/* Same contract as lbrd_rel_l2 for instance idx. */
+int lbrd_batch_rel_l2(lbrd_batch *b, int idx, const void *ref, int dtype, double *err_out);
 /* Persistent-launch shape: blocks_per_cu, waves, nontemporal, graph_steps
  * (vec and lanes_x are chosen per instance from its size and storage). */
 int lbrd_batch_get_tuning(const lbrd_batch *b, lbrd_tuning *out);

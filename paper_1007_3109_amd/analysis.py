@@ -173,3 +173,17 @@ def lattice_linearisation(F: float, k: float, Du: float, Dv: float, u: float, v:
 def continuum_growth(F: float, k: float, Du: float, Dv: float, u: float, v: float, q2: float) -> float:
     """max Re eig L(q): growth rate per lattice time step of a Fourier mode."""
     return float(np.max(np.linalg.eigvals(lattice_linearisation(F, k, Du, Dv, u, v, q2)).real))
+
+
+# ----- closed forms used as reference fields ---------------------------------
+
+def point_source_gaussian(L: int, D: float, kappa: float, t: float, x0=None, y0=None) -> np.ndarray:
+    """Infinite-domain solution of the decaying point source, Section II.B,
+    Eq. "reac_diff5": exp(-r^2 / (4 D t)) / (4 pi D t) * exp(-kappa t), on an
+    L x L grid of sites with the source at (x0, y0) (default L // 2)."""
+    x0 = L // 2 if x0 is None else x0
+    y0 = L // 2 if y0 is None else y0
+    x = np.arange(L, dtype=np.float64)[None, :]
+    y = np.arange(L, dtype=np.float64)[:, None]
+    r2 = (x - x0) ** 2 + (y - y0) ** 2
+    return np.exp(-r2 / (4.0 * D * t)) / (4.0 * math.pi * D * t) * math.exp(-kappa * t)

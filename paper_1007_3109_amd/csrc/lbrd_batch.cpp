@@ -58,6 +58,7 @@ struct lbrd_batch {
     std::vector<Layout> L;
     std::vector<BatchInst> inst;    // host mirror of the device descriptors
     std::vector<char> initialised;
+    std::vector<int64_t> tinst;     // steps taken per instance since init
     BatchHeader *d_hdr = nullptr;
     BatchInst *d_inst = nullptr;
     double *partials = nullptr, *result = nullptr;
@@ -185,6 +186,7 @@ int lbrd_batch_create(const lbrd_config *cfgs, int count, void *workspace, size_
         b->inst.push_back(bi);
     }
     b->initialised.assign(count, 0);
+    b->tinst.assign(count, 0);
     b->total_tiles = tiles;
     b->set = pick_set(b->cfg);
     b->cus = device_cu_count();
@@ -233,6 +235,7 @@ int lbrd_batch_init(lbrd_batch *b, int idx, const void *rho0, int dtype, int on_
     hipError_t e = launch_init(c.storage, b->L[idx], params_of(b, idx), src, dtype, cur, b->stream);
     if (e != hipSuccess) return fail("batch init kernel", e);
     b->initialised[idx] = 1;
+    b->tinst[idx] = 0;
     return LBRD_OK;
 }
 
@@ -257,6 +260,7 @@ int lbrd_batch_step(lbrd_batch *b, int64_t nsteps) {
             if (e != hipSuccess) return fail("hipGraphLaunch", e);
             left -= gs;
             b->t += gs;
+            for (auto &t : b->tinst) t += gs;
         }
     }
     while (left > 0) {
@@ -270,8 +274,82 @@ int lbrd_batch_step(lbrd_batch *b, int64_t nsteps) {
         }
         left -= n;
         b->t += n;
+        for (auto &t : b->tinst) t += n;
     }
     return LBRD_OK;
+}
+
+int lbrd_batch_advance(lbrd_batch *b, const int64_t *nsteps) {
+    if (!b || !nsteps) return LBRD_EINVAL;
+    for (int i = 0; i < b->count; ++i) {
+        if (nsteps[i] < 0) return LBRD_EINVAL;
+        if (nsteps[i] > 0 && !b->initialised[i]) return LBRD_ESTATE;
+    }
+    std::vector<int64_t> left(nsteps, nsteps + b->count);
+    const int chunk = b->tune.graph_steps > 0 ? b->tune.graph_steps : 64;
+    for (;;) {
+        int most = 0;
+        for (int i = 0; i < b->count; ++i) {
+            const int n = (int)std::min<int64_t>(left[i], chunk);
+            b->inst[i].steps = n;
+            most = std::max(most, n);
+        }
+        if (most == 0) break;
+        hipError_t e = hipMemcpyAsync(b->d_inst, b->inst.data(), sizeof(BatchInst) * b->inst.size(),
+                                      hipMemcpyHostToDevice, b->stream);
+        if (e != hipSuccess) return fail("batch descriptors", e);
+        b->dirty = false;
+        if (b->tune.graph_steps > 0) {
+            // the captured chunk runs graph_steps launches; instances stop at
+            // their own step limit inside it
+            if (b->graph_steps_built != b->tune.graph_steps) {
+                e = build_graph(b);
+                if (e != hipSuccess) {
+                    drop_graph(b);
+                    return fail("batch graph capture", e);
+                }
+            }
+            e = hipGraphLaunch(b->graph, b->stream);
+        } else {
+            e = enqueue(b, most, b->stream);
+        }
+        if (e != hipSuccess) return fail("batch advance", e);
+        for (int i = 0; i < b->count; ++i) {
+            const int n = b->inst[i].steps;
+            left[i] -= n;
+            b->tinst[i] += n;
+            b->inst[i].cur ^= n & 1;
+        }
+        b->dirty = true;
+    }
+    return LBRD_OK;
+}
+
+int lbrd_batch_time(const lbrd_batch *b, int idx, int64_t *t) {
+    if (!b || !t || idx < 0 || idx >= b->count) return LBRD_EINVAL;
+    *t = b->tinst[idx];
+    return LBRD_OK;
+}
+
+int lbrd_batch_rel_l2(lbrd_batch *b, int idx, const void *ref, int dtype, double *err_out) {
+    if (!b || idx < 0 || idx >= b->count || !ref || !err_out) return LBRD_EINVAL;
+    if (dtype != LBRD_DTYPE_F64 && dtype != LBRD_DTYPE_F32) return LBRD_EINVAL;
+    if (!b->initialised[idx]) return LBRD_ESTATE;
+    const BatchInst &bi = b->inst[idx];
+    hipError_t e = launch_moments(b->cfg[idx].storage, b->L[idx], params_of(b, idx), bi.buf[bi.cur], nullptr,
+                                  LBRD_DTYPE_F64, ref, dtype, b->partials, b->result, b->stream);
+    if (e != hipSuccess) return fail("batch rel_l2", e);
+    double res[kRedSlots];
+    e = hipMemcpyAsync(res, b->result, sizeof(res), hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return fail("batch rel_l2 readback", e);
+    int rc = LBRD_OK;
+    for (int s = 0; s < b->cfg[idx].nspecies; ++s) {
+        const double num = res[LBRD_MAX_SPECIES + s], den = res[2 * LBRD_MAX_SPECIES + s];
+        err_out[s] = den > 0 ? std::sqrt(num / den) : std::sqrt(num);
+        if (!std::isfinite(err_out[s])) rc = LBRD_ENONFINITE;
+    }
+    return rc;
 }
 
 int lbrd_batch_moments(lbrd_batch *b, int idx, void *rho_out, int dtype, double *mass_out) {
@@ -382,6 +460,7 @@ int lbrd_batch_autotune(lbrd_batch *b, int steps, lbrd_tuning *chosen) {
             }
     lbrd_batch_set_tuning(b, &best);
     for (int i = 0; i < b->count; ++i) b->initialised[i] = 0;
+    for (auto &t : b->tinst) t = 0;
     for (auto &bi : b->inst) bi.cur = 0;
     b->dirty = true;
     b->t = 0;

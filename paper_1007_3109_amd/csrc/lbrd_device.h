@@ -156,8 +156,11 @@ struct TileGeom {
 
 // One wave advances one tile by one step.  `lane` is 0..63; every lane of the
 // wave executes this function (lanes outside the lattice compute on clamped
-// addresses and do not store).
-template <int ST, int V, int VEC, bool NT>
+// addresses and do not store).  ROW1: the tile is one row of 64 lanes
+// (lanes_x = 64), so the row and every plane's row base are wave-uniform and
+// live in scalar registers; loads then take a scalar base plus one per-lane
+// offset.
+template <int ST, int V, int VEC, bool NT, bool ROW1 = false>
 __device__ __forceinline__ void step_tile(const typename Traits<ST>::T *__restrict__ src,
                                           typename Traits<ST>::T *__restrict__ dst, const TileGeom &g,
                                           int64_t tile, int lane, const Params<typename Traits<ST>::C> &p) {
@@ -165,11 +168,11 @@ __device__ __forceinline__ void step_tile(const typename Traits<ST>::T *__restri
     using C = typename Traits<ST>::C;
     constexpr int NS = NSpecies<V>::value;
 
-    const int lanes_x = 1 << g.lx_shift;
+    const int lanes_x = ROW1 ? 64 : 1 << g.lx_shift;
     const int sx = (int)(tile % g.nseg);
     const int ry = (int)(tile / g.nseg);
-    const int vx = lane & (lanes_x - 1);
-    const int y = ry * g.rpw + (lane >> g.lx_shift);
+    const int vx = ROW1 ? lane : lane & (lanes_x - 1);
+    const int y = ROW1 ? ry : ry * g.rpw + (lane >> g.lx_shift);
     const bool row_ok = y < g.ny;
     const int yc = row_ok ? y : g.ny - 1;
     const int v = sx * lanes_x + vx;
@@ -193,15 +196,23 @@ __device__ __forceinline__ void step_tile(const typename Traits<ST>::T *__restri
         for (int i = 0; i < 9; ++i) {
             const int row = kEy[i] == 1 ? ym : (kEy[i] == -1 ? yp : yc);
             const T *rp = src + (int64_t)(s * 9 + i) * g.pstride + (int64_t)row * g.pitch;
-            load_vec<T, VEC, NT>(rp + x0, raw[s][i]);
+            // 32-bit byte offset from a (for ROW1 wave-uniform) row base: lets
+            // the compiler use the scalar-base + vector-offset address form
+            load_vec<T, VEC, NT>(reinterpret_cast<const T *>(reinterpret_cast<const char *>(rp) +
+                                                             (uint32_t)x0 * (uint32_t)sizeof(T)),
+                                 raw[s][i]);
             // only the edge lanes issue these single-element loads (exec-masked)
             e_lo[s][i] = T(0);
             e_hi[s][i] = T(0);
             if (kEx[i] == 1) {
-                if (edge_lo) e_lo[s][i] = rp[xprev];
+                if (edge_lo)
+                    e_lo[s][i] = *reinterpret_cast<const T *>(reinterpret_cast<const char *>(rp) +
+                                                              (uint32_t)xprev * (uint32_t)sizeof(T));
             }
             if (kEx[i] == -1) {
-                if (edge_hi) e_hi[s][i] = rp[xnext];
+                if (edge_hi)
+                    e_hi[s][i] = *reinterpret_cast<const T *>(reinterpret_cast<const char *>(rp) +
+                                                              (uint32_t)xnext * (uint32_t)sizeof(T));
             }
         }
     }
@@ -272,8 +283,11 @@ __device__ __forceinline__ void step_tile(const typename Traits<ST>::T *__restri
         for (int s = 0; s < NS; ++s)
 #pragma unroll
             for (int i = 0; i < 9; ++i)
-                store_vec<T, VEC, NT>(dst + (int64_t)(s * 9 + i) * g.pstride + (int64_t)yc * g.pitch + x0,
-                                      out[s][i]);
+                store_vec<T, VEC, NT>(
+                    reinterpret_cast<T *>(reinterpret_cast<char *>(dst + (int64_t)(s * 9 + i) * g.pstride +
+                                                                   (int64_t)yc * g.pitch) +
+                                          (uint32_t)x0 * (uint32_t)sizeof(T)),
+                    out[s][i]);
     }
 }
 
@@ -284,15 +298,15 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
     return x * q + min(x, r) + (b >> 3);
 }
 
-template <int ST, int V, int VEC, bool NT>
+template <int ST, int V, int VEC, bool NT, bool ROW1>
 __global__ __launch_bounds__(256) void k_step(Grid gr, Params<typename Traits<ST>::C> p) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int waves = blockDim.x >> 6;
     const int64_t tile = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * waves + wave;
     if (tile >= gr.ntiles) return;
     TileGeom g{gr.nx, gr.ny, gr.pitch, gr.pstride, gr.lx_shift, gr.nvec, gr.nseg, gr.rpw};
-    step_tile<ST, V, VEC, NT>(static_cast<const typename Traits<ST>::T *>(gr.src),
-                              static_cast<typename Traits<ST>::T *>(gr.dst), g, tile, lane, p);
+    step_tile<ST, V, VEC, NT, ROW1>(static_cast<const typename Traits<ST>::T *>(gr.src),
+                                    static_cast<typename Traits<ST>::T *>(gr.dst), g, tile, lane, p);
 }
 
 }  // namespace lbrd

@@ -12,8 +12,14 @@ inline hipError_t launch_step_t(const StepLaunch &sl, const Grid &g, const void 
     const int64_t nb64 = (g.ntiles + sl.waves - 1) / sl.waves;
     if (nb64 > 0x7fffffff) return hipErrorInvalidValue;
     const dim3 grid((unsigned)nb64), block(64 * sl.waves);
-    if (sl.nontemporal) hipLaunchKernelGGL((k_step<ST, V, VEC, true>), grid, block, 0, st, g, p);
-    else hipLaunchKernelGGL((k_step<ST, V, VEC, false>), grid, block, 0, st, g, p);
+    const bool row1 = g.lanes_x == 64;
+    if (sl.nontemporal) {
+        if (row1) hipLaunchKernelGGL((k_step<ST, V, VEC, true, true>), grid, block, 0, st, g, p);
+        else hipLaunchKernelGGL((k_step<ST, V, VEC, true, false>), grid, block, 0, st, g, p);
+    } else {
+        if (row1) hipLaunchKernelGGL((k_step<ST, V, VEC, false, true>), grid, block, 0, st, g, p);
+        else hipLaunchKernelGGL((k_step<ST, V, VEC, false, false>), grid, block, 0, st, g, p);
+    }
     return hipGetLastError();
 }
 

@@ -102,6 +102,9 @@ SIGNATURES = {
     "lbrd_batch_moments": ([_P, _I, _P, _I, _PD], _I),
     "lbrd_batch_get_populations": ([_P, _I, _P, _I], _I),
     "lbrd_batch_step": ([_P, _I64], _I),
+    "lbrd_batch_advance": ([_P, ctypes.POINTER(_I64)], _I),
+    "lbrd_batch_time": ([_P, _I, ctypes.POINTER(_I64)], _I),
+    "lbrd_batch_rel_l2": ([_P, _I, _P, _I, _PD], _I),
     "lbrd_batch_get_tuning": ([_P, ctypes.POINTER(Tuning)], _I),
     "lbrd_batch_set_tuning": ([_P, ctypes.POINTER(Tuning)], _I),
     "lbrd_batch_autotune": ([_P, _I, ctypes.POINTER(Tuning)], _I),
@@ -357,6 +360,23 @@ class Batch:
 
     def step(self, n: int):
         check(_lib.lbrd_batch_step(self._h, int(n)), "lbrd_batch_step")
+
+    def advance(self, nsteps):
+        """Advance instance i by nsteps[i]."""
+        arr = (_I64 * len(self.cfgs))(*[int(x) for x in nsteps])
+        check(_lib.lbrd_batch_advance(self._h, arr), "lbrd_batch_advance")
+
+    def time(self, idx: int) -> int:
+        t = _I64()
+        check(_lib.lbrd_batch_time(self._h, idx, ctypes.byref(t)), "lbrd_batch_time")
+        return t.value
+
+    def rel_l2(self, idx: int, ref) -> np.ndarray:
+        e = (ctypes.c_double * self.cfgs[idx].nspecies)()
+        st = _lib.lbrd_batch_rel_l2(self._h, idx, _device_ptr(ref), _dtype_code(ref), e)
+        if st not in (OK, ENONFINITE):
+            check(st, "lbrd_batch_rel_l2")
+        return np.array(e[:])
 
     def moments(self, idx: int, dtype=None, mass: bool = True):
         torch = _torch()
