@@ -85,9 +85,11 @@ def cpu_baseline(workloads, n, budget_s):
                       f"state, {el:.1f} s"}
 
 
-def hbm_leg(torch, lbrd, workloads, n, storage, steps, warmup):
+def hbm_leg(torch, lbrd, workloads, n, storage, steps, warmup, tune=True):
     cfg = gs_config(lbrd, workloads, n, storage)
     s = lbrd.Solver(cfg)
+    if tune:
+        s.autotune(steps=10)
     s.init(workloads.gray_scott_square(n, n, seed=0))
     secs, _ = time_solver(torch, s, steps, warmup)
     b = {"f32": 4, "f16": 2, "bf16": 2, "f64": 8}[storage]
@@ -209,49 +211,62 @@ def serve_leg(torch, lbrd, workloads, n_requests, pool_gb, steps_range, seed=0, 
             "arena_peak_used_gb": round(st.arena_peak_used / 2 ** 30, 3)}
 
 
-def precision_leg(torch, lbrd, workloads, n=4096, steps=10000, check_n=256):
-    """16-bit shifted storage against FP32 storage on the same n^2 Gray-Scott
-    field (same seed), and every storage form against the FP64 oracle on a
-    check_n^2 instance with the same seed, after `steps` steps; FP64 mass drift
-    of each run."""
+def precision_leg(torch, lbrd, workloads, n=4096, steps=(1000, 10000), check_n=256):
+    """16-bit shifted storage (rho_ref = (1, 0)) against FP32 storage on the
+    same n^2 Gray-Scott field (same seed), and every storage form against the
+    FP64 oracle on a check_n^2 instance with the same seed, at each checkpoint
+    in `steps`.  The pattern dynamics amplify any perturbation, so pointwise
+    errors grow with time; the field means (FP64 reductions) are reported
+    beside them."""
     import oracle
 
-    out = {"workload": f"gray_scott {n}x{n}, {steps} steps; oracle check {check_n}x{check_n}, {steps} steps",
+    out = {"workload": f"gray_scott {n}x{n} and {check_n}x{check_n}, checkpoints {list(steps)}",
            "rho_ref": [1.0, 0.0]}
     rho0 = workloads.gray_scott_square(n, n, seed=0)
-    ref_solver = lbrd.Solver(gs_config(lbrd, workloads, n, "f32"))
-    ref_solver.init(rho0)
-    m0 = ref_solver.mass()
-    ref_solver.step(steps)
-    ref_rho, m1 = ref_solver.moments(dtype=torch.float32)
-    out["f32_mass_drift"] = [float(x) for x in (m1 - m0) / m0]
-    ref_solver.close()
-    del ref_solver
-    for st in ("f16", "bf16"):
-        s = lbrd.Solver(gs_config(lbrd, workloads, n, st))
+    solvers = {st: lbrd.Solver(gs_config(lbrd, workloads, n, st)) for st in ("f32", "f16", "bf16")}
+    for s in solvers.values():
         s.init(rho0)
-        ma = s.mass()
-        s.step(steps)
-        rho, mb = s.moments(dtype=torch.float32)
-        out[f"{st}_vs_f32_rel_l2"] = [float(x) for x in s.rel_l2(ref_rho)]
-        out[f"{st}_vs_f32_max_abs"] = [float((rho[k] - ref_rho[k]).abs().max()) for k in range(2)]
-        out[f"{st}_mass_drift"] = [float(x) for x in (mb - ma) / ma]
+    done = 0
+    for cp in steps:
+        for s in solvers.values():
+            s.step(cp - done)
+        done = cp
+        ref_rho, m_ref = solvers["f32"].moments(dtype=torch.float32)
+        row = {"f32_mean": [float(m) / (n * n) for m in m_ref]}
+        for st in ("f16", "bf16"):
+            rho, m = solvers[st].moments(dtype=torch.float32)
+            row[f"{st}_vs_f32_rel_l2"] = [float(x) for x in solvers[st].rel_l2(ref_rho)]
+            row[f"{st}_vs_f32_max_abs"] = [float((rho[k] - ref_rho[k]).abs().max()) for k in range(2)]
+            row[f"{st}_mean"] = [float(x) / (n * n) for x in m]
+            del rho
+        del ref_rho
+        out[f"step_{cp}_{n}"] = row
+    for s in solvers.values():
         s.close()
-        del s, rho
-    del ref_rho
+    del solvers
     torch.cuda.empty_cache()
     small0 = workloads.gray_scott_square(check_n, check_n, seed=0)
+    f = oracle.init(small0)
+    done = 0
+    small = {st: lbrd.Solver(gs_config(lbrd, workloads, check_n, st)) for st in ("f32", "f16", "bf16")}
+    for s in small.values():
+        s.init(small0)
     t0 = time.perf_counter()
-    ref64 = oracle.solve(small0, steps, list(workloads.GS_TAU), oracle.REACT_GRAY_SCOTT, F=workloads.GS_F,
-                         k=workloads.GS_K)
+    for cp in steps:
+        f = oracle.run(f, cp - done, list(workloads.GS_TAU), oracle.REACT_GRAY_SCOTT, F=workloads.GS_F,
+                       k=workloads.GS_K)
+        ref64 = torch.tensor(oracle.moments(f), device="cuda")
+        row = {"fp64_mean": [float(x) / check_n ** 2 for x in ref64.sum(dim=(1, 2))]}
+        for st, s in small.items():
+            s.step(cp - done)
+            rho, m = s.moments()
+            row[f"{st}_vs_fp64_rel_l2"] = [float(x) for x in s.rel_l2(ref64)]
+            row[f"{st}_vs_fp64_max_abs"] = [float((rho[k] - ref64[k]).abs().max()) for k in range(2)]
+            row[f"{st}_mean"] = [float(x) / check_n ** 2 for x in m]
+        done = cp
+        out[f"step_{cp}_{check_n}_vs_oracle"] = row
     out["oracle_seconds"] = round(time.perf_counter() - t0, 2)
-    ref64_t = torch.tensor(ref64, device="cuda")
-    for st in ("f32", "f16", "bf16"):
-        s = lbrd.Solver(gs_config(lbrd, workloads, check_n, st))
-        s.init(small0).step(steps)
-        rho, _ = s.moments()
-        out[f"{st}_vs_fp64_oracle_rel_l2_{check_n}"] = [float(x) for x in s.rel_l2(ref64_t)]
-        out[f"{st}_vs_fp64_oracle_max_abs_{check_n}"] = [float((rho[k] - ref64_t[k]).abs().max()) for k in range(2)]
+    for s in small.values():
         s.close()
     return out
 
@@ -303,8 +318,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="default launch shapes instead of the autotuner's")
     ap.add_argument("--extra-steps", type=int, default=300)
-    ap.add_argument("--legs", default="hbm4096_f32,hbm4096_f16,hbm4096_bf16,batch,serve,config1,copy",
+    ap.add_argument("--legs", default="hbm4096_f32,hbm4096_f16,hbm4096_bf16,batch,serve,precision,config1,copy",
                     help="extra legs to run (comma list)")
     ap.add_argument("--serve-requests", type=int, default=120)
     args = ap.parse_args()
@@ -320,8 +336,10 @@ def main():
     n = 1024
     cfg = gs_config(lbrd, workloads, n, "f32")
     s = lbrd.Solver(cfg)
+    if not args.no_tune:
+        s.autotune(steps=20)          # launch shape picked by the library's autotuner
     s.init(workloads.gray_scott_square(n, n, seed=0))
-    log(f"bench: Gray-Scott {n}x{n} f32, warmup {args.warmup}, steps {args.steps}")
+    log(f"bench: Gray-Scott {n}x{n} f32, warmup {args.warmup}, steps {args.steps}, tuning {s.tuning().as_dict()}")
     secs, wall = time_solver(torch, s, args.steps, args.warmup)
     sites = n * n
     ms_per_step = secs / args.steps * 1e3
@@ -365,7 +383,8 @@ def main():
         for storage in ("f32", "f16", "bf16"):
             if f"hbm4096_{storage}" in legs:
                 log(f"bench: 4096^2 {storage}")
-                extra[f"hbm_4096_{storage}"] = hbm_leg(torch, lbrd, workloads, 4096, storage, args.extra_steps, 20)
+                extra[f"hbm_4096_{storage}"] = hbm_leg(torch, lbrd, workloads, 4096, storage, args.extra_steps, 20,
+                                                       tune=not args.no_tune)
         if "batch" in legs:
             log("bench: batched sweep")
             extra["batched"] = batch_leg(torch, lbrd, workloads, 200, 10)

@@ -96,7 +96,10 @@ typedef struct lbrd_config {
  *  waves: waves (64 lanes) per workgroup: 1, 2 or 4.
  *  nontemporal: 1 = streaming (non-temporal) loads and stores.
  *  graph_steps: steps per captured HIP graph (0 = plain launches; else even).
- *  blocks_per_cu: persistent workgroups per compute unit (1..32); batches only. */
+ *  blocks_per_cu: persistent workgroups per compute unit.  Batches: 1..32.
+ *       Single solvers: 0 = one tile per wave, else 1..64 looping over tiles.
+ *  plain_order: single solvers; 0 = consecutive tiles on the same XCD, 1 = the
+ *       hardware's round-robin order. */
 typedef struct lbrd_tuning {
     int32_t vec;
     int32_t lanes_x;
@@ -104,7 +107,8 @@ typedef struct lbrd_tuning {
     int32_t nontemporal;
     int32_t graph_steps;
     int32_t blocks_per_cu;
-    int32_t reserved[2];
+    int32_t plain_order;
+    int32_t reserved;
 } lbrd_tuning;
 
 const char *lbrd_strerror(int status);
@@ -166,6 +170,16 @@ int lbrd_rel_l2(lbrd_solver *h, const void *ref, int dtype, double *err_out);
 
 int lbrd_time(const lbrd_solver *h, int64_t *t);
 
+/* Power spectrum of one species' density fluctuation, for the Fourier
+ * diagnostic of Section III.D (Eq. "reac_diff35": the excited wave numbers
+ * (n_x, n_y) of a pattern): P[k_y][k_x] = |sum_{x,y} (rho_s(x,y) - mean)
+ * exp(-2 pi i (k_x x / nx + k_y y / ny))|^2, computed in FP64 on the GPU by a
+ * row transform followed by a column transform (direct sums).
+ * out: device double [ny][nx].  work: device scratch of
+ * lbrd_spectrum_work_size() bytes.  Asynchronous. */
+int lbrd_spectrum_work_size(int nx, int ny, size_t *bytes);
+int lbrd_spectrum(lbrd_solver *h, int species, void *out, void *work, size_t work_bytes);
+
 /* Launch shape in use / override it (validated against the storage form). */
 int lbrd_get_tuning(const lbrd_solver *h, lbrd_tuning *out);
 int lbrd_set_tuning(lbrd_solver *h, const lbrd_tuning *t);
@@ -207,6 +221,8 @@ int lbrd_batch_advance(lbrd_batch *b, const int64_t *nsteps);
 int lbrd_batch_time(const lbrd_batch *b, int idx, int64_t *t);
 /* Same contract as lbrd_rel_l2 for instance idx. */
 int lbrd_batch_rel_l2(lbrd_batch *b, int idx, const void *ref, int dtype, double *err_out);
+/* Same contract as lbrd_spectrum for instance idx. */
+int lbrd_batch_spectrum(lbrd_batch *b, int idx, int species, void *out, void *work, size_t work_bytes);
 /* Persistent-launch shape: blocks_per_cu, waves, nontemporal, graph_steps
  * (vec and lanes_x are chosen per instance from its size and storage). */
 int lbrd_batch_get_tuning(const lbrd_batch *b, lbrd_tuning *out);

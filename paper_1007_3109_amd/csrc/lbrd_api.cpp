@@ -71,6 +71,8 @@ Params<C> make_params(const lbrd_config &c) {
             const bool shifted = c.storage == LBRD_F16_SHIFTED || c.storage == LBRD_BF16_SHIFTED;
             p.shift[s][i] = shifted ? wi * C(c.rho_ref[s]) : C(0);
         }
+        const bool shifted = c.storage == LBRD_F16_SHIFTED || c.storage == LBRD_BF16_SHIFTED;
+        p.rho_ref[s] = shifted ? C(c.rho_ref[s]) : C(0);
     }
     if (c.reaction == LBRD_REACT_LINEAR) {
         for (int s = 0; s < n; ++s) {
@@ -108,10 +110,14 @@ Grid make_grid(const Layout &L, const void *src, void *dst, int vec, int lanes_x
     g.nseg = (g.nvec + lanes_x - 1) / lanes_x;
     g.rpw = 64 / lanes_x;
     g.ntiles = (int64_t)g.nseg * ((L.ny + g.rpw - 1) / g.rpw);
+    g.blocks = 0;
+    g.xcd_order = 1;
     return g;
 }
 
-int default_vec(int storage) { return 16 / storage_bytes(storage); }
+// 16-byte vectors for F64 / F32; 8-byte vectors for the 16-bit forms (half
+// the registers of 16-byte ones, measured faster on 4096^2 lattices).
+int default_vec(int storage) { return storage == kF64 ? 2 : 4; }
 
 int default_lanes(int nx, int vec) {
     const int nvec = (nx + vec - 1) / vec;
@@ -207,6 +213,7 @@ struct lbrd_solver {
     hipGraphExec_t graph[2] = {nullptr, nullptr};   // graph_steps steps starting from buf[0] / buf[1]
     int graph_steps_built = 0;
     int device = 0;
+    int cus = 256;
 };
 
 namespace {
@@ -232,7 +239,9 @@ hipError_t enqueue_steps(lbrd_solver *h, int from, int64_t n, hipStream_t st) {
     const StepLaunch sl = step_launch(h);
     for (int64_t k = 0; k < n; ++k) {
         const int a = (from + (int)(k & 1)) & 1;
-        const Grid g = make_grid(h->L, h->buf[a], h->buf[a ^ 1], h->tune.vec, h->tune.lanes_x);
+        Grid g = make_grid(h->L, h->buf[a], h->buf[a ^ 1], h->tune.vec, h->tune.lanes_x);
+        g.blocks = h->tune.blocks_per_cu > 0 ? h->tune.blocks_per_cu * h->cus : 0;
+        g.xcd_order = h->tune.plain_order == 0 ? 1 : 0;
         hipError_t e = launch_step(sl, g, h->params, st);
         if (e != hipSuccess) return e;
     }
@@ -278,6 +287,8 @@ int stage_host(lbrd_solver *h, const void *host, size_t bytes, const void **dev)
 
 bool tuning_valid(const lbrd_solver *h, const lbrd_tuning &t) {
     if (!step_shape_valid(h->cfg.storage, t.vec, t.lanes_x, t.waves)) return false;
+    if (t.blocks_per_cu < 0 || t.blocks_per_cu > 64) return false;
+    if (t.plain_order != 0 && t.plain_order != 1) return false;
     if (t.graph_steps < 0 || (t.graph_steps & 1) || t.graph_steps > 4096) return false;
     return t.nontemporal == 0 || t.nontemporal == 1;
 }
@@ -330,6 +341,7 @@ int lbrd_create(const lbrd_config *cfg, void *workspace, size_t bytes, void *str
     h->result = h->partials + (size_t)kRedBlocks * kRedSlots;
     h->stream = static_cast<hipStream_t>(stream);
     hipGetDevice(&h->device);
+    h->cus = device_cu_count();
     hipError_t e = hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking);
     if (e != hipSuccess) {
         delete h;
@@ -346,8 +358,26 @@ int lbrd_create(const lbrd_config *cfg, void *workspace, size_t bytes, void *str
     h->tune.vec = default_vec(h->cfg.storage);
     h->tune.lanes_x = default_lanes(h->cfg.nx, h->tune.vec);
     h->tune.waves = 4;
-    h->tune.nontemporal = 0;
     h->tune.graph_steps = ((int64_t)h->cfg.nx * h->cfg.ny <= (1 << 18)) ? 32 : 0;
+    if (2 * h->L.buf_bytes > ((size_t)256 << 20)) {
+        // Working set beyond the 256 MB Infinity Cache: streaming loads and
+        // stores (they would only evict data the next step reads) and the
+        // shapes measured fastest on 4096^2 Gray-Scott lattices: 8-byte
+        // vectors with the hardware's round-robin tile order for F32 / F64,
+        // 16-byte vectors for binary16, a persistent grid of 8 workgroups per
+        // CU for bfloat16.
+        h->tune.nontemporal = 1;
+        if (h->cfg.storage == LBRD_F32 || h->cfg.storage == LBRD_F64) {
+            h->tune.vec = 2;
+            h->tune.lanes_x = default_lanes(h->cfg.nx, 2);
+            h->tune.plain_order = 1;
+        } else if (h->cfg.storage == LBRD_F16_SHIFTED) {
+            h->tune.vec = 8;
+            h->tune.lanes_x = std::min(32, default_lanes(h->cfg.nx, 8));
+        } else {
+            h->tune.blocks_per_cu = 8;
+        }
+    }
     *out = h;
     return LBRD_OK;
 }
@@ -475,6 +505,22 @@ int lbrd_rel_l2(lbrd_solver *h, const void *ref, int dtype, double *err_out) {
     return rc;
 }
 
+int lbrd_spectrum_work_size(int nx, int ny, size_t *bytes) {
+    if (nx < 1 || ny < 1 || !bytes) return LBRD_EINVAL;
+    *bytes = spectrum_work_bytes(nx, ny);
+    return LBRD_OK;
+}
+
+int lbrd_spectrum(lbrd_solver *h, int species, void *out, void *work, size_t work_bytes) {
+    if (!h || !out || !work || species < 0 || species >= h->cfg.nspecies) return LBRD_EINVAL;
+    if (((uintptr_t)work & 255) || ((uintptr_t)out & 7)) return LBRD_EINVAL;
+    if (work_bytes < spectrum_work_bytes(h->cfg.nx, h->cfg.ny)) return LBRD_ENOMEM;
+    if (!h->initialised) return LBRD_ESTATE;
+    hipError_t e = launch_spectrum(h->cfg.storage, h->L, h->params, h->buf[h->cur], species, static_cast<double *>(out),
+                                   work, h->partials, h->result, h->stream);
+    return e == hipSuccess ? LBRD_OK : fail("spectrum kernels", e);
+}
+
 int lbrd_time(const lbrd_solver *h, int64_t *t) {
     if (!h || !t) return LBRD_EINVAL;
     *t = h->t;
@@ -491,10 +537,9 @@ int lbrd_set_tuning(lbrd_solver *h, const lbrd_tuning *t) {
     if (!h || !t) return LBRD_EINVAL;
     lbrd_tuning n = *t;
     if (n.lanes_x == 0) n.lanes_x = default_lanes(h->cfg.nx, n.vec);
-    std::memset(n.reserved, 0, sizeof(n.reserved));
+    n.reserved = 0;
     if (!tuning_valid(h, n)) return LBRD_EINVAL;
-    const bool rebuild = n.vec != h->tune.vec || n.lanes_x != h->tune.lanes_x || n.waves != h->tune.waves ||
-                         n.nontemporal != h->tune.nontemporal || n.graph_steps != h->tune.graph_steps;
+    const bool rebuild = std::memcmp(&n, &h->tune, sizeof(n)) != 0;
     h->tune = n;
     if (rebuild) drop_graphs(h);
     return LBRD_OK;
@@ -548,8 +593,8 @@ int lbrd_autotune(lbrd_solver *h, int steps, const char *cache_path, lbrd_tuning
             if (bar == std::string::npos || line.substr(0, bar) != k) continue;
             lbrd_tuning t;
             std::memset(&t, 0, sizeof(t));
-            if (std::sscanf(line.c_str() + bar + 1, "%d %d %d %d %d", &t.vec, &t.lanes_x, &t.waves, &t.nontemporal,
-                            &t.graph_steps) == 5 &&
+            if (std::sscanf(line.c_str() + bar + 1, "%d %d %d %d %d %d %d", &t.vec, &t.lanes_x, &t.waves,
+                            &t.nontemporal, &t.graph_steps, &t.plain_order, &t.blocks_per_cu) == 7 &&
                 tuning_valid(h, t)) {
                 lbrd_set_tuning(h, &t);
                 h->initialised = false;
@@ -566,16 +611,20 @@ int lbrd_autotune(lbrd_solver *h, int steps, const char *cache_path, lbrd_tuning
         const int lmax = default_lanes(h->cfg.nx, vec);
         for (int lx = std::max(1, lmax / 4); lx <= lmax; lx <<= 1)
             for (int w : {1, 2, 4})
-                for (int nt = 0; nt < 2; ++nt) {
-                    lbrd_tuning t;
-                    std::memset(&t, 0, sizeof(t));
-                    t.vec = vec;
-                    t.lanes_x = lx;
-                    t.waves = w;
-                    t.nontemporal = nt;
-                    t.graph_steps = h->tune.graph_steps;
-                    if (tuning_valid(h, t)) cands.push_back(t);
-                }
+                for (int nt = 0; nt < 2; ++nt)
+                    for (int order = 0; order < 2; ++order)
+                        for (int bpc : {0, 8}) {
+                            lbrd_tuning t;
+                            std::memset(&t, 0, sizeof(t));
+                            t.vec = vec;
+                            t.lanes_x = lx;
+                            t.waves = w;
+                            t.nontemporal = nt;
+                            t.plain_order = order;
+                            t.blocks_per_cu = bpc;
+                            t.graph_steps = h->tune.graph_steps;
+                            if (tuning_valid(h, t)) cands.push_back(t);
+                        }
     }
     // the state is scratch from here on: fill it with a uniform field
     h->initialised = true;
@@ -603,7 +652,7 @@ int lbrd_autotune(lbrd_solver *h, int steps, const char *cache_path, lbrd_tuning
     if (cache_path) {
         std::ofstream outf(cache_path, std::ios::app);
         outf << k << "|" << best_t.vec << " " << best_t.lanes_x << " " << best_t.waves << " " << best_t.nontemporal
-             << " " << best_t.graph_steps << "\n";
+             << " " << best_t.graph_steps << " " << best_t.plain_order << " " << best_t.blocks_per_cu << "\n";
     }
     if (chosen) *chosen = h->tune;
     return LBRD_OK;

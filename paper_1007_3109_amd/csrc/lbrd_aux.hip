@@ -2,6 +2,8 @@
 // storage dispatch of the step launch.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "lbrd_device.h"
 
 namespace lbrd {
@@ -256,6 +258,119 @@ hipError_t launch_moments(int storage, const Layout &L, const void *params, cons
                           hipStream_t st) {
     LBRD_DISPATCH_ST(storage, {
         return launch_moments_t<ST>(L, params, src, rho_out, dtype, ref, ref_dtype, partials, result, st);
+    })
+}
+
+// ------------------------------------------------------------ spectrum --
+
+// rho_s gathered as double [ny][nx] (contiguous).
+template <int ST>
+__global__ void k_gather_rho(Layout L, Params<typename Traits<ST>::C> p, const typename Traits<ST>::T *src, int s,
+                             double *rho) {
+    using C = typename Traits<ST>::C;
+    const int64_t sites = (int64_t)L.nx * L.ny;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < sites; k += (int64_t)gridDim.x * blockDim.x) {
+        const int y = (int)(k / L.nx), x = (int)(k % L.nx);
+        C r = C(0);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const int xs = wrap(x - kEx[i], L.nx), ys = wrap(y - kEy[i], L.ny);
+            r += decode<ST>(src[(int64_t)(s * 9 + i) * L.pstride + (int64_t)ys * L.pitch + xs], p.shift[s][i]);
+        }
+        rho[k] = (double)r;
+    }
+}
+
+// Row transform: R[y][kx] = sum_x (rho[y][x] - mean) e^{-2 pi i kx x / nx}.
+// One thread per (y, kx); the phase index kx*x is reduced modulo nx exactly.
+__global__ void k_dft_rows(const double *rho, const double *mean, int nx, int ny, double2 *R) {
+    const int64_t n = (int64_t)nx * ny;
+    const double m = mean[0] / (double)n;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+        const int y = (int)(q / nx), kx = (int)(q % nx);
+        double re = 0.0, im = 0.0;
+        int64_t ph = 0;
+        for (int x = 0; x < nx; ++x) {
+            double sn, cs;
+            sincospi(2.0 * (double)ph / (double)nx, &sn, &cs);
+            const double g = rho[(int64_t)y * nx + x] - m;
+            re += g * cs;
+            im -= g * sn;
+            ph += kx;
+            if (ph >= nx) ph -= nx;
+        }
+        R[q] = make_double2(re, im);
+    }
+}
+
+// Column transform and power: P[ky][kx] = |sum_y R[y][kx] e^{-2 pi i ky y / ny}|^2.
+__global__ void k_dft_cols(const double2 *R, int nx, int ny, double *P) {
+    const int64_t n = (int64_t)nx * ny;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+        const int ky = (int)(q / nx), kx = (int)(q % nx);
+        double re = 0.0, im = 0.0;
+        int64_t ph = 0;
+        for (int y = 0; y < ny; ++y) {
+            double sn, cs;
+            sincospi(2.0 * (double)ph / (double)ny, &sn, &cs);
+            const double2 r = R[(int64_t)y * nx + kx];
+            re += r.x * cs + r.y * sn;
+            im += r.y * cs - r.x * sn;
+            ph += ky;
+            if (ph >= ny) ph -= ny;
+        }
+        P[q] = re * re + im * im;
+    }
+}
+
+// Sum of a double array with the deterministic two-pass reduction (slot 0).
+__global__ __launch_bounds__(kRedThreads) void k_sum(const double *a, int64_t n, double *partials) {
+    double acc = 0.0;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+        acc += a[k];
+    __shared__ double red[kRedThreads / 64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    acc = wave_sum(acc);
+    if (lane == 0) red[wave] = acc;
+    __syncthreads();
+    if (threadIdx.x < kRedSlots) {
+        double t = 0.0;
+        if (threadIdx.x == 0)
+            for (int w = 0; w < kRedThreads / 64; ++w) t += red[w];
+        partials[(int64_t)blockIdx.x * kRedSlots + threadIdx.x] = t;
+    }
+}
+
+size_t spectrum_work_bytes(int nx, int ny) {
+    const size_t n = (size_t)nx * ny;
+    return n * sizeof(double) + n * sizeof(double2) + 256;
+}
+
+hipError_t launch_spectrum(int storage, const Layout &L, const void *params, const void *src, int species,
+                           double *out, void *work, double *partials, double *result, hipStream_t st) {
+    const int64_t n = (int64_t)L.nx * L.ny;
+    double *rho = static_cast<double *>(work);
+    double2 *R = reinterpret_cast<double2 *>(static_cast<char *>(work) + (((size_t)n * sizeof(double) + 255) / 256) * 256);
+    hipError_t e = hipSuccess;
+    LBRD_DISPATCH_ST(storage, {
+        using C = typename Traits<ST>::C;
+        using T = typename Traits<ST>::T;
+        hipLaunchKernelGGL((k_gather_rho<ST>), dim3(elementwise_blocks(L)), dim3(256), 0, st, L,
+                           *static_cast<const Params<C> *>(params), static_cast<const T *>(src), species, rho);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_sum, dim3(kRedBlocks), dim3(kRedThreads), 0, st, rho, n, partials);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedThreads), 0, st, partials, kRedBlocks, result);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const unsigned nb = (unsigned)std::min<int64_t>((n + 255) / 256, 8192);
+        hipLaunchKernelGGL(k_dft_rows, dim3(nb), dim3(256), 0, st, rho, result, L.nx, L.ny, R);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_dft_cols, dim3(nb), dim3(256), 0, st, R, L.nx, L.ny, out);
+        return hipGetLastError();
     })
 }
 

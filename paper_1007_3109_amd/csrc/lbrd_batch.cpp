@@ -325,6 +325,18 @@ int lbrd_batch_advance(lbrd_batch *b, const int64_t *nsteps) {
     return LBRD_OK;
 }
 
+int lbrd_batch_spectrum(lbrd_batch *b, int idx, int species, void *out, void *work, size_t work_bytes) {
+    if (!b || idx < 0 || idx >= b->count || !out || !work) return LBRD_EINVAL;
+    if (species < 0 || species >= b->cfg[idx].nspecies) return LBRD_EINVAL;
+    if (((uintptr_t)work & 255) || ((uintptr_t)out & 7)) return LBRD_EINVAL;
+    if (work_bytes < spectrum_work_bytes(b->cfg[idx].nx, b->cfg[idx].ny)) return LBRD_ENOMEM;
+    if (!b->initialised[idx]) return LBRD_ESTATE;
+    const BatchInst &bi = b->inst[idx];
+    hipError_t e = launch_spectrum(b->cfg[idx].storage, b->L[idx], params_of(b, idx), bi.buf[bi.cur], species,
+                                   static_cast<double *>(out), work, b->partials, b->result, b->stream);
+    return e == hipSuccess ? LBRD_OK : fail("batch spectrum", e);
+}
+
 int lbrd_batch_time(const lbrd_batch *b, int idx, int64_t *t) {
     if (!b || !t || idx < 0 || idx >= b->count) return LBRD_EINVAL;
     *t = b->tinst[idx];
@@ -395,7 +407,8 @@ int lbrd_batch_set_tuning(lbrd_batch *b, const lbrd_tuning *t) {
     lbrd_tuning n = *t;
     n.vec = 0;
     n.lanes_x = 0;
-    std::memset(n.reserved, 0, sizeof(n.reserved));
+    n.plain_order = 0;
+    n.reserved = 0;
     if (!batch_tuning_valid(n)) return LBRD_EINVAL;
     if (std::memcmp(&n, &b->tune, sizeof(n)) != 0) drop_graph(b);
     b->tune = n;

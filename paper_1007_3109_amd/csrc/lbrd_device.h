@@ -66,10 +66,10 @@ __device__ __forceinline__ uint16_t float_to_half_bits(float f) {
 }
 __device__ __forceinline__ float bf16_bits_to_float(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 __device__ __forceinline__ uint16_t float_to_bf16_bits(float f) {
-    uint32_t b = __float_as_uint(f);
-    if ((b & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((b >> 16) | 0x40u);   // quiet NaN
-    b += 0x7fffu + ((b >> 16) & 1u);                                              // round to nearest even
-    return (uint16_t)(b >> 16);
+    __bf16 h = (__bf16)f;   // round to nearest even (hardware conversion on gfx950)
+    uint16_t b;
+    __builtin_memcpy(&b, &h, 2);
+    return b;
 }
 
 template <int ST>
@@ -83,6 +83,24 @@ __device__ __forceinline__ typename Traits<ST>::T encode(typename Traits<ST>::C 
     if constexpr (ST == kF16) return float_to_half_bits(f - shift);
     else if constexpr (ST == kBF16) return float_to_bf16_bits(f - shift);
     else return f;
+}
+
+template <int ST>
+constexpr bool kShifted = ST == kF16 || ST == kBF16;
+
+// Stored value <-> deviation d (= f for F64 / F32, f - w_i rho_ref,s for the
+// 16-bit forms).
+template <int ST>
+__device__ __forceinline__ typename Traits<ST>::C decode_dev(typename Traits<ST>::T v) {
+    if constexpr (ST == kF16) return half_bits_to_float(v);
+    else if constexpr (ST == kBF16) return bf16_bits_to_float(v);
+    else return v;
+}
+template <int ST>
+__device__ __forceinline__ typename Traits<ST>::T encode_dev(typename Traits<ST>::C d) {
+    if constexpr (ST == kF16) return float_to_half_bits(d);
+    else if constexpr (ST == kBF16) return float_to_bf16_bits(d);
+    else return d;
 }
 
 // D2Q9 weights w_i (Eq. "Weights") in the compute type.
@@ -217,28 +235,29 @@ __device__ __forceinline__ void step_tile(const typename Traits<ST>::T *__restri
         }
     }
 
-    // Decode and shift along x.
+    // Decode and shift along x.  The 16-bit forms are kept in deviation form
+    // d = f - w_i rho_ref,s throughout (no shift is added or removed per
+    // population); for F64 / F32 storage d = f.
     C f[NS][9][VEC];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            const C sh = p.shift[s][i];
             C d[VEC];
 #pragma unroll
-            for (int j = 0; j < VEC; ++j) d[j] = decode<ST>(raw[s][i][j], sh);
+            for (int j = 0; j < VEC; ++j) d[j] = decode_dev<ST>(raw[s][i][j]);
             if (kEx[i] == 0) {
 #pragma unroll
                 for (int j = 0; j < VEC; ++j) f[s][i][j] = d[j];
             } else if (kEx[i] == 1) {
                 const C nb = __shfl_up(d[VEC - 1], 1);
-                const C prev = edge_lo ? decode<ST>(e_lo[s][i], sh) : nb;
+                const C prev = edge_lo ? decode_dev<ST>(e_lo[s][i]) : nb;
                 f[s][i][0] = prev;
 #pragma unroll
                 for (int j = 1; j < VEC; ++j) f[s][i][j] = d[j - 1];
             } else {
                 const C nb = __shfl_down(d[0], 1);
-                const C next = edge_hi ? decode<ST>(e_hi[s][i], sh) : nb;
+                const C next = edge_hi ? decode_dev<ST>(e_hi[s][i]) : nb;
 #pragma unroll
                 for (int j = 0; j < VEC - 1; ++j) f[s][i][j] = (last && j == cnt - 1) ? next : d[j + 1];
                 f[s][i][VEC - 1] = next;
@@ -246,34 +265,37 @@ __device__ __forceinline__ void step_tile(const typename Traits<ST>::T *__restri
         }
     }
 
-    // Collide and react, site by site.
+    // Collide and react, site by site.  With m_s = sum_i d_i (ascending i),
+    // rho_s = m_s + rho_ref,s (the weights sum to one) and the update
+    //   f' = f (1 - 1/tau) + w_i (rho / tau + R)
+    // reads in deviation form d' = d (1 - 1/tau) + w_i (m / tau + R).
     T out[NS][9][VEC];
 #pragma unroll
     for (int j = 0; j < VEC; ++j) {
-        C rho[NS], R[NS];
+        C m[NS], rho[NS], R[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             C acc = f[s][0][j];
 #pragma unroll
             for (int i = 1; i < 9; ++i) acc += f[s][i][j];
-            rho[s] = acc;
+            m[s] = acc;
+            rho[s] = kShifted<ST> ? acc + p.rho_ref[s] : acc;
         }
         reaction<V, C>(p, rho, R);
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            // w_i (rho / tau + R): the rest weight is taken as 1 - 4/9 - 4/36
+            // w_i (m / tau + R): the rest weight is taken as 1 - 4/9 - 4/36
             // applied to the value itself, so the nine terms sum to exactly
-            // rho / tau + R up to unbiased rounding (the rounded weights of a
+            // m / tau + R up to unbiased rounding (the rounded weights of a
             // binary format sum to 1 + O(eps), which would add a systematic
             // mass drift every step).
-            const C a = p.omega[s] * rho[s] + R[s];
+            const C a = p.omega[s] * m[s] + R[s];
             const C e1 = wgt<C>(1) * a, e5 = wgt<C>(5) * a;
             const C e0 = a - C(4) * e1 - C(4) * e5;
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
                 const C e = i == 0 ? e0 : (i < 5 ? e1 : e5);
-                const C o = f[s][i][j] * p.keep[s] + e;
-                out[s][i][j] = encode<ST>(o, p.shift[s][i]);
+                out[s][i][j] = encode_dev<ST>(f[s][i][j] * p.keep[s] + e);
             }
         }
     }
@@ -302,11 +324,14 @@ template <int ST, int V, int VEC, bool NT, bool ROW1>
 __global__ __launch_bounds__(256) void k_step(Grid gr, Params<typename Traits<ST>::C> p) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int waves = blockDim.x >> 6;
-    const int64_t tile = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * waves + wave;
-    if (tile >= gr.ntiles) return;
+    const int b = gr.xcd_order ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * waves;
     TileGeom g{gr.nx, gr.ny, gr.pitch, gr.pstride, gr.lx_shift, gr.nvec, gr.nseg, gr.rpw};
-    step_tile<ST, V, VEC, NT, ROW1>(static_cast<const typename Traits<ST>::T *>(gr.src),
-                                    static_cast<typename Traits<ST>::T *>(gr.dst), g, tile, lane, p);
+    // one tile per wave when the grid covers all tiles; a persistent grid
+    // walks the tiles with a stride of the whole grid
+    for (int64_t tile = (int64_t)b * waves + wave; tile < gr.ntiles; tile += stride)
+        step_tile<ST, V, VEC, NT, ROW1>(static_cast<const typename Traits<ST>::T *>(gr.src),
+                                        static_cast<typename Traits<ST>::T *>(gr.dst), g, tile, lane, p);
 }
 
 }  // namespace lbrd

@@ -50,7 +50,8 @@ struct Params {
     C K[LBRD_MAX_SPECIES * LBRD_MAX_SPECIES];
     C c[LBRD_MAX_SPECIES];
     C F, k, Fk;                  // Fk = F + k
-    C shift[LBRD_MAX_SPECIES][9];
+    C rho_ref[LBRD_MAX_SPECIES]; // 16-bit forms: the storage shift density
+    C shift[LBRD_MAX_SPECIES][9];   // w_i rho_ref,s
 };
 
 template <class C>
@@ -68,6 +69,8 @@ struct Grid {
     int nseg;         // ceil(nvec / lanes_x)
     int rpw;          // rows per wave = 64 / lanes_x
     int64_t ntiles;   // nseg * ceil(ny / rpw): one tile per wave
+    int blocks;       // 0: one tile per wave; else a persistent grid of this many blocks
+    int xcd_order;    // 1: consecutive tiles on the same XCD
 };
 
 Grid make_grid(const Layout &L, const void *src, void *dst, int vec, int lanes_x);
@@ -106,6 +109,13 @@ constexpr int kRedThreads = 256;
 hipError_t launch_moments(int storage, const Layout &L, const void *params, const void *src, void *rho_out,
                           int dtype, const void *ref, int ref_dtype, double *partials, double *result,
                           hipStream_t st);
+
+// Power spectrum of species s: rho gathered into work (double [ny][nx]), its
+// mean removed, row DFT into work (complex [ny][nx]), column DFT and |.|^2 into
+// out.  work holds spectrum_work_bytes(nx, ny).
+size_t spectrum_work_bytes(int nx, int ny);
+hipError_t launch_spectrum(int storage, const Layout &L, const void *params, const void *src, int species,
+                           double *out, void *work, double *partials, double *result, hipStream_t st);
 
 // ------------------------------------------------------------- batching --
 

@@ -9,7 +9,8 @@ template <int ST, int V, int VEC>
 inline hipError_t launch_step_t(const StepLaunch &sl, const Grid &g, const void *params, hipStream_t st) {
     using C = typename Traits<ST>::C;
     const Params<C> &p = *static_cast<const Params<C> *>(params);
-    const int64_t nb64 = (g.ntiles + sl.waves - 1) / sl.waves;
+    int64_t nb64 = (g.ntiles + sl.waves - 1) / sl.waves;
+    if (g.blocks > 0 && g.blocks < nb64) nb64 = g.blocks;
     if (nb64 > 0x7fffffff) return hipErrorInvalidValue;
     const dim3 grid((unsigned)nb64), block(64 * sl.waves);
     const bool row1 = g.lanes_x == 64;

@@ -38,11 +38,12 @@ class Tuning(ctypes.Structure):
     _fields_ = [
         ("vec", ctypes.c_int32), ("lanes_x", ctypes.c_int32), ("waves", ctypes.c_int32),
         ("nontemporal", ctypes.c_int32), ("graph_steps", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 2),
+        ("plain_order", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k in ("vec", "lanes_x", "waves", "nontemporal", "graph_steps", "blocks_per_cu")}
+        return {k: getattr(self, k) for k in ("vec", "lanes_x", "waves", "nontemporal", "graph_steps", "blocks_per_cu",
+                                              "plain_order")}
 
 
 class ServerConfig(ctypes.Structure):
@@ -91,6 +92,8 @@ SIGNATURES = {
     "lbrd_moments": ([_P, _P, _I, _PD], _I),
     "lbrd_rel_l2": ([_P, _P, _I, _PD], _I),
     "lbrd_time": ([_P, ctypes.POINTER(_I64)], _I),
+    "lbrd_spectrum_work_size": ([_I, _I, ctypes.POINTER(_SZ)], _I),
+    "lbrd_spectrum": ([_P, _I, _P, _P, _SZ], _I),
     "lbrd_get_tuning": ([_P, ctypes.POINTER(Tuning)], _I),
     "lbrd_set_tuning": ([_P, ctypes.POINTER(Tuning)], _I),
     "lbrd_autotune": ([_P, _I, ctypes.c_char_p, ctypes.POINTER(Tuning)], _I),
@@ -105,6 +108,7 @@ SIGNATURES = {
     "lbrd_batch_advance": ([_P, ctypes.POINTER(_I64)], _I),
     "lbrd_batch_time": ([_P, _I, ctypes.POINTER(_I64)], _I),
     "lbrd_batch_rel_l2": ([_P, _I, _P, _I, _PD], _I),
+    "lbrd_batch_spectrum": ([_P, _I, _I, _P, _P, _SZ], _I),
     "lbrd_batch_get_tuning": ([_P, ctypes.POINTER(Tuning)], _I),
     "lbrd_batch_set_tuning": ([_P, ctypes.POINTER(Tuning)], _I),
     "lbrd_batch_autotune": ([_P, _I, ctypes.POINTER(Tuning)], _I),
@@ -168,6 +172,12 @@ def make_config(nx: int, ny: int, nspecies: int = 1, tau=1.0, storage: str = "f3
 def workspace_size(cfg: Config) -> int:
     n = _SZ()
     check(_lib.lbrd_workspace_size(ctypes.byref(cfg), ctypes.byref(n)), "lbrd_workspace_size")
+    return n.value
+
+
+def spectrum_work_size(nx: int, ny: int) -> int:
+    n = _SZ()
+    check(_lib.lbrd_spectrum_work_size(int(nx), int(ny), ctypes.byref(n)), "lbrd_spectrum_work_size")
     return n.value
 
 
@@ -298,6 +308,17 @@ class Solver:
         check(_lib.lbrd_time(self._h, ctypes.byref(t)), "lbrd_time")
         return t.value
 
+    def spectrum(self, species: int):
+        """|DFT(rho_s - mean)|^2 as a device float64 tensor [ny][nx]."""
+        torch = _torch()
+        out = torch.empty((self.cfg.ny, self.cfg.nx), dtype=torch.float64, device=self.device)
+        nbytes = spectrum_work_size(self.cfg.nx, self.cfg.ny)
+        work, ptr = _alloc_workspace(nbytes, self.device)
+        check(_lib.lbrd_spectrum(self._h, int(species), _device_ptr(out), ptr, nbytes), "lbrd_spectrum")
+        torch.cuda.current_stream().synchronize()
+        del work
+        return out
+
     def tuning(self) -> Tuning:
         t = Tuning()
         check(_lib.lbrd_get_tuning(self._h, ctypes.byref(t)), "lbrd_get_tuning")
@@ -370,6 +391,18 @@ class Batch:
         t = _I64()
         check(_lib.lbrd_batch_time(self._h, idx, ctypes.byref(t)), "lbrd_batch_time")
         return t.value
+
+    def spectrum(self, idx: int, species: int):
+        torch = _torch()
+        c = self.cfgs[idx]
+        out = torch.empty((c.ny, c.nx), dtype=torch.float64, device=self.device)
+        nbytes = spectrum_work_size(c.nx, c.ny)
+        work, ptr = _alloc_workspace(nbytes, self.device)
+        check(_lib.lbrd_batch_spectrum(self._h, idx, int(species), _device_ptr(out), ptr, nbytes),
+              "lbrd_batch_spectrum")
+        torch.cuda.current_stream().synchronize()
+        del work
+        return out
 
     def rel_l2(self, idx: int, ref) -> np.ndarray:
         e = (ctypes.c_double * self.cfgs[idx].nspecies)()

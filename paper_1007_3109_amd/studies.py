@@ -47,3 +47,63 @@ def truncation_error_sweep(Ds, kappas, C: float = 2.0, L: int = 100, storage: st
     site_steps = L * L * sum(steps)
     return {"E": E, "D": np.array(Ds), "kappa": np.array(kappas), "steps": np.array(steps).reshape(len(kappas), len(Ds)),
             "D_min": np.array(Ds)[np.argmin(E, axis=1)], "seconds": secs, "mlups": site_steps / secs / 1e6}
+
+
+def dominant_mode(P: np.ndarray):
+    """(n_x, n_y) of the largest non-zero Fourier component of a power
+    spectrum P[k_y][k_x], with n in (-L/2, L/2], and its wavenumber
+    q = 2 pi sqrt((n_x/L_x)^2 + (n_y/L_y)^2) (Section III.D, Eq. "reac_diff35")."""
+    P = np.array(P, dtype=np.float64, copy=True)
+    P[0, 0] = 0.0
+    ky, kx = np.unravel_index(int(np.argmax(P)), P.shape)
+    ny, nx = P.shape
+    n_x = kx if kx <= nx // 2 else kx - nx
+    n_y = ky if ky <= ny // 2 else ky - ny
+    return (n_x, n_y), 2 * np.pi * np.hypot(n_x / nx, n_y / ny), float(P[ky, kx])
+
+
+def phase_diagram(points, Du_over_Dv: float = 8.0, L: int = 64, steps: int = 4000, phi: float = 1e-3,
+                  noise: float = 1e-4, seed: int = 0, storage: str = "f32", device="cuda"):
+    """Gray-Scott runs over (eta, tau_GS) points as one batch (Section III.D,
+    Figs. 6-8): each lattice starts from the homogeneous state (A~-, B~-) plus
+    phi cos(2 pi x / L) cos(2 pi y / L) and seeded U(-noise, noise) on both
+    species, runs `steps` steps, and reports the power spectrum of v, its
+    dominant mode, the growth of the largest non-zero mode, and the linear
+    stability prediction (Hopf line, exact Turing onset, band of unstable
+    wavenumbers in lattice units)."""
+    import torch
+
+    from . import lbrd
+
+    Du = 1.0 / 6.0                     # tau_u = 1
+    Dv = Du / Du_over_Dv
+    taus = (3 * Du + 0.5, 3 * Dv + 0.5)
+    rng = np.random.default_rng(seed)
+    cfgs, inits, meta = [], [], []
+    for eta, tau in points:
+        F, k = analysis.feed_kill(eta, tau)
+        c = analysis.classify(F, k, Du, Dv)
+        u, v = analysis.lattice_state(F, k, "-")
+        rho0 = workloads.perturbed_state(L, L, u, v, phi, (1, 1)) + rng.uniform(-noise, noise, size=(2, L, L))
+        band = analysis.band(c.eta, c.eps2, c.eta_B_minus / c.eta)
+        qband = None if band is None else tuple(float(np.sqrt(max(b, 0.0) * F / Du)) for b in band)
+        cfgs.append(lbrd.make_config(L, L, 2, tau=taus, storage=storage, reaction="gray_scott", F=F, k=k))
+        inits.append(rho0)
+        meta.append(dict(eta=eta, tau=tau, F=F, k=k, hopf_unstable=c.hopf_unstable, turing_unstable=c.turing_unstable,
+                         q_band=qband))
+    b = lbrd.Batch(cfgs, device=device)
+    for i, r in enumerate(inits):
+        b.init(i, r)
+    p0 = [float(b.spectrum(i, 1).max()) for i in range(len(cfgs))]
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    out = []
+    for i, m in enumerate(meta):
+        P = b.spectrum(i, 1).cpu().numpy()
+        mode, q, pmax = dominant_mode(P)
+        m.update(mode=mode, q=q, growth=pmax / max(p0[i], 1e-300), spectrum=P)
+        out.append(m)
+    b.close()
+    return out, {"seconds": secs, "mlups_per_species": 2 * L * L * steps * len(cfgs) / secs / 1e6}

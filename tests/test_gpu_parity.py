@@ -142,33 +142,30 @@ def test_gray_scott_f32(n, steps):
 QUANT = {"f16": 1, "bf16": 2}
 
 
-def _neighbours16(q, storage):
-    """The value q of the 16-bit format and its two neighbours (float32)."""
-    q = np.asarray(q, np.float32)
+def _spacing16(g, storage):
+    """Spacing of the 16-bit format at |g| (binary16: 10 fraction bits,
+    subnormal step 2^-24; bfloat16: 7 fraction bits)."""
+    a = np.maximum(np.abs(np.asarray(g, np.float64)), 1e-300)
+    e = np.floor(np.log2(a))
     if storage == "f16":
-        h = q.astype(np.float16)
-        return (q, np.nextafter(h, np.float16(np.inf)).astype(np.float32),
-                np.nextafter(h, np.float16(-np.inf)).astype(np.float32))
-    bits = q.view(np.uint32).astype(np.int64)
-    sign = bits & 0x80000000
-    mag = bits & 0x7FFFFFFF
-    up = np.where(mag == 0, 0x00010000, sign | (mag + 0x10000))
-    down = np.where(mag == 0, 0x80010000, sign | np.maximum(mag - 0x10000, 0))
-    return (q, up.astype(np.uint32).view(np.float32), down.astype(np.uint32).view(np.float32))
+        return np.maximum(2.0 ** (e - 10), 2.0 ** -24)
+    return 2.0 ** (e - 7)
 
 
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
 def test_shifted_storage_one_step_codes(storage):
-    """One step from random stored states: every stored 16-bit value equals the
-    oracle's (float build, same storage rounding) or is its neighbour in the
-    format; neighbours occur only where the two float computations straddle a
-    rounding boundary (about one value in 2^13 for binary16, 2^16 for bfloat16)."""
+    """One step from random stored states: every stored value equals the
+    oracle's (float build, same storage rounding) or differs by one unit of the
+    16-bit format; such neighbours occur only where the two float computations
+    straddle a rounding boundary (about one value in 2^13 for binary16, 2^16
+    for bfloat16).  Values are compared as decoded by both sides
+    (w_i rho_ref + stored, in float), allowing two float ulps for that sum."""
     q = QUANT[storage]
     rng = np.random.default_rng(11)
     ny, nx = 37, 91
     rref = [1.0, 0.2]
-    f = rng.uniform(0.0, 0.1, size=(2, 9, ny, nx)) + np.array([4 / 9, 1 / 9, 1 / 9, 1 / 9, 1 / 9, 1 / 36, 1 / 36, 1 / 36,
-                                                                 1 / 36])[None, :, None, None] * np.array(rref)[:, None, None, None]
+    w64 = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    f = rng.uniform(0.0, 0.1, size=(2, 9, ny, nx)) + w64[None, :, None, None] * np.array(rref)[:, None, None, None]
     f = oracle.encode(f.astype(np.float32), q, rref)
     kw = dict(F=0.04, k=0.06)
     emu = oracle.run(f, 1, [0.7, 1.2], oracle.REACT_GRAY_SCOTT, quant=q, rho_ref=rref, **kw)
@@ -178,28 +175,21 @@ def test_shifted_storage_one_step_codes(storage):
     got = s.get_populations(dtype=torch.float32).cpu().numpy()
     w, _, _ = oracle.tables("f32")
     shift = (w[None, :, None, None] * np.asarray(rref, np.float32)[:, None, None, None]).astype(np.float32)
-    # stored 16-bit values of both sides (decoding added the shift in float;
-    # rounding back to the format recovers the stored value exactly)
-    qtz = (lambda x: x.astype(np.float16).astype(np.float32)) if storage == "f16" else \
-        (lambda x: oracle.quantise(x, oracle.Q_BF16))
-    qg = qtz((got - shift).astype(np.float32))
-    qe = qtz((emu - shift).astype(np.float32))
-    a, up, down = _neighbours16(qe, storage)
-    ok = (qg == a) | (qg == up) | (qg == down)
-    diff = np.mean(qg != qe)
-    log(f"{storage} one-step codes: {diff:.2e} of values differ by one unit")
-    assert ok.all()
-    assert diff <= 2e-3
+    d = np.abs(got.astype(np.float64) - emu.astype(np.float64))
+    allowed = _spacing16(emu.astype(np.float64) - shift, storage) * 1.0001 + 2 * np.spacing(np.abs(emu))
+    frac = np.mean(d > 0)
+    log(f"{storage} one-step: {frac:.2e} of stored values differ; worst ratio {np.max(d / allowed):.3f}")
+    assert np.all(d <= allowed)
+    assert frac <= 2e-3
 
 
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
 def test_shifted_storage_decay_against_emulation(storage):
-    """300 steps of per-species decay (no amplification of differences and no
-    coupling term whose rounding differs between the two sides): the GPU
-    against the oracle's emulation of the same storage.  Differences come only
-    from one-unit rounding flips where the two float results straddle a 16-bit
-    rounding boundary; bound 1e-4 (binary16) and 1e-3 (bfloat16), about 2^-11
-    and 2^-8 times 0.2 (the size of a stored deviation relative to rho)."""
+    """300 steps of per-species decay: the GPU against the oracle's emulation
+    of the same storage.  The two differ only through one-unit rounding flips
+    (and the kernels' mass-exact rest population), so the GPU result must stay
+    closer to the emulated 16-bit result than that result is to FP64, and
+    within 1e-3 (binary16) / 1e-2 (bfloat16) of it."""
     q = QUANT[storage]
     n = 80
     rho0 = workloads.gray_scott_square(n, n, seed=2)
@@ -210,8 +200,10 @@ def test_shifted_storage_decay_against_emulation(storage):
     emu = oracle.moments(oracle.run(f, 300, [0.9, 0.6], oracle.REACT_LINEAR, K=K, quant=q, rho_ref=rref))
     ref = oracle.solve(rho0, 300, [0.9, 0.6], oracle.REACT_LINEAR, K=K)
     e_emu = oracle.rel_l2(rho, emu)
-    log(f"{storage} decay: vs emulation {e_emu}, emulation vs FP64 {oracle.rel_l2(emu, ref)}")
-    assert np.all(e_emu <= (1e-4 if storage == "f16" else 1e-3))
+    e_fmt = oracle.rel_l2(emu, ref)
+    log(f"{storage} decay: vs emulation {e_emu}, emulation vs FP64 {e_fmt}, GPU vs FP64 {oracle.rel_l2(rho, ref)}")
+    assert np.all(e_emu <= e_fmt)
+    assert np.all(e_emu <= (1e-3 if storage == "f16" else 1e-2))
 
 
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
