@@ -4,19 +4,24 @@ Workload timed for the headline line: Gray-Scott (u, v), D2Q9 BGK, 1024 x 1024
 periodic, FP32 storage, tau = (1.0, 0.75), F = 0.04, k = 0.06, central 64 x 64
 square with u = 0.5, v = 0.25 plus U(-0.01, 0.01) noise (seed 0).  One "step"
 is one lattice time step of the whole field (every species, every site):
-collide, react and stream, one fused kernel launch.
+collide, react and stream.  The library's default launch shape advances two
+steps per launch (64 x rows tiles staged in LDS); --tune runs its autotuner
+first.
 
 The JSON line carries the headline MLUPS per species, the roofline of the
-step kernel (algorithmic bytes: every population read once and written once,
-2 * 9 * sizeof(storage) bytes per species-site-step, over the kernel time
-measured with HIP events on the launch stream), the FP64 oracle timed on the
-host cores, and extra legs: the 4096^2 lattices (working set larger than the
-256 MB Infinity Cache) in FP32 / FP16 / BF16 storage, the batched sweep and
-the continuous-batching server.
+step kernel (algorithmic bytes of one launch: every population read once and
+written once, 2 * 9 * sizeof(storage) bytes per species-site, over the launch
+time measured with HIP events on the launch stream), the HBM traffic per
+launch from the committed hardware-counter summary when it was taken on the
+current kernel sources and launch shape, the FP64 oracle timed on the host
+cores, and extra legs: the 4096^2 lattices (working set larger than the
+256 MB Infinity Cache) in FP32 / FP16 / BF16 storage, the batched sweep, the
+continuous-batching server, the 16-bit storage errors and a device copy.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -29,6 +34,41 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, 8 TB/s
+
+
+# sources that define the two-step FP32 kernel; the committed counter summary
+# records their digest, and its traffic figure is reported only while it matches
+STEP_SOURCES = ("paper_1007_3109_amd/csrc/lbrd_device.h", "paper_1007_3109_amd/csrc/lbrd_internal.h",
+                "paper_1007_3109_amd/csrc/lbrd_step_launch.h", "paper_1007_3109_amd/csrc/step_f32.hip")
+TRAFFIC_SUMMARY = "profiles/pmc_k_step2_gray_scott_1024_f32.txt"
+
+
+def source_digest():
+    h = hashlib.sha256()
+    for rel in STEP_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(tuning):
+    """HBM bytes per launch (FETCH_SIZE and WRITE_SIZE, scaled by the plain
+    copy calibration) from the committed counter summary, or None when the
+    summary is missing or was taken on other kernel sources or launch shape."""
+    path = os.path.join(ROOT, TRAFFIC_SUMMARY)
+    if not os.path.exists(path):
+        return None, "no counter summary"
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith((" ", "#")):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != source_digest():
+        return None, "kernel sources changed since the counters were taken"
+    if kv.get("tuning") != json.dumps(tuning, sort_keys=True):
+        return None, "launch shape differs from the one the counters were taken on"
+    return int(kv["traffic_bytes_per_launch"]), TRAFFIC_SUMMARY
 
 
 def log(msg):
@@ -85,7 +125,7 @@ def cpu_baseline(workloads, n, budget_s):
                       f"state, {el:.1f} s"}
 
 
-def hbm_leg(torch, lbrd, workloads, n, storage, steps, warmup, tune=True):
+def hbm_leg(torch, lbrd, workloads, n, storage, steps, warmup, tune=False):
     cfg = gs_config(lbrd, workloads, n, storage)
     s = lbrd.Solver(cfg)
     if tune:
@@ -95,10 +135,13 @@ def hbm_leg(torch, lbrd, workloads, n, storage, steps, warmup, tune=True):
     b = {"f32": 4, "f16": 2, "bf16": 2, "f64": 8}[storage]
     sites = n * n
     per_step = secs / steps
-    gbs = algorithmic_bytes(2, sites, b) / per_step / 1e9
+    spl = s.tuning().fused_steps
+    gbs = algorithmic_bytes(2, sites, b) / (per_step * spl) / 1e9
     out = {"workload": f"gray_scott {n}x{n} {storage}", "steps": steps, "ms_per_step": round(per_step * 1e3, 4),
-           "mlups_per_species": round(2 * sites / per_step / 1e6, 1), "achieved_GBs": round(gbs, 1),
-           "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4), "tuning": s.tuning().as_dict()}
+           "mlups_per_species": round(2 * sites / per_step / 1e6, 1), "steps_per_launch": spl,
+           "achieved_GBs": round(gbs, 1), "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+           "one_step_equivalent_GBs": round(algorithmic_bytes(2, sites, b) / per_step / 1e9, 1),
+           "tuning": s.tuning().as_dict()}
     s.close()
     del s
     torch.cuda.empty_cache()
@@ -318,7 +361,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--no-tune", action="store_true", help="default launch shapes instead of the autotuner's")
+    ap.add_argument("--tune", action="store_true", help="run the library's autotuner before timing")
     ap.add_argument("--extra-steps", type=int, default=300)
     ap.add_argument("--legs", default="hbm4096_f32,hbm4096_f16,hbm4096_bf16,batch,serve,precision,config1,copy",
                     help="extra legs to run (comma list)")
@@ -336,7 +379,7 @@ def main():
     n = 1024
     cfg = gs_config(lbrd, workloads, n, "f32")
     s = lbrd.Solver(cfg)
-    if not args.no_tune:
+    if args.tune:
         s.autotune(steps=20)          # launch shape picked by the library's autotuner
     s.init(workloads.gray_scott_square(n, n, seed=0))
     log(f"bench: Gray-Scott {n}x{n} f32, warmup {args.warmup}, steps {args.steps}, tuning {s.tuning().as_dict()}")
@@ -344,8 +387,15 @@ def main():
     sites = n * n
     ms_per_step = secs / args.steps * 1e3
     value = 2 * sites * args.steps / secs / 1e6
+    tun = s.tuning()
+    steps_per_launch = tun.fused_steps
+    # algorithmic bytes of one launch: the state read once and written once
+    # (2 * 9 * 4 B per species-site), whether the launch advances one step or
+    # two (the two-step tile's halo re-reads are not counted)
     bytes_per_launch = algorithmic_bytes(2, sites, 4)
-    achieved = bytes_per_launch / (secs / args.steps) / 1e9
+    launch_seconds = secs / args.steps * steps_per_launch
+    achieved = bytes_per_launch / launch_seconds / 1e9
+    traffic, traffic_src = measured_traffic(tun.as_dict())
     _, mass = s.moments()
     line = {
         "metric": "MLUPS per species and % HBM roofline; batched p50/p99 solve latency",
@@ -364,7 +414,12 @@ def main():
                    "tau": list(workloads.GS_TAU), "F": workloads.GS_F, "k": workloads.GS_K, "seed": 0,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_unit": "bytes per launch", "traffic_source": traffic_src,
+                     "kernel": "k_step2 (two steps per launch)" if steps_per_launch == 2 else "k_step",
+                     "steps_per_launch": steps_per_launch,
+                     "launch_us": round(launch_seconds * 1e6, 3),
+                     "bytes_per_launch": bytes_per_launch,
                      "note": "1024^2 x 2 species x 9 x 2 buffers x 4 B = 151 MB ping-pong: resident in the 256 MB "
                              "Infinity Cache; see extra.hbm_4096_* for working sets beyond it"},
         "wall_s": round(wall, 3),
@@ -384,7 +439,7 @@ def main():
             if f"hbm4096_{storage}" in legs:
                 log(f"bench: 4096^2 {storage}")
                 extra[f"hbm_4096_{storage}"] = hbm_leg(torch, lbrd, workloads, 4096, storage, args.extra_steps, 20,
-                                                       tune=not args.no_tune)
+                                                       tune=args.tune)
         if "batch" in legs:
             log("bench: batched sweep")
             extra["batched"] = batch_leg(torch, lbrd, workloads, 200, 10)

@@ -93,13 +93,18 @@ typedef struct lbrd_config {
  *       16-bit forms).  Single solvers only.
  *  lanes_x: lanes per row segment, a power of two 1..64 (0 = choose from nx).
  *       Single solvers only.
- *  waves: waves (64 lanes) per workgroup: 1, 2 or 4.
+ *  waves: waves (64 lanes) per workgroup: 1, 2, 4, 8 or 16.  One-step
+ *       launches use min(waves, 4); two-step launches use all of them.
  *  nontemporal: 1 = streaming (non-temporal) loads and stores.
  *  graph_steps: steps per captured HIP graph (0 = plain launches; else even).
  *  blocks_per_cu: persistent workgroups per compute unit.  Batches: 1..32.
- *       Single solvers: 0 = one tile per wave, else 1..64 looping over tiles.
+ *       Single solvers: 0 = one tile per wave / workgroup, else 1..64 looping
+ *       over tiles.
  *  plain_order: single solvers; 0 = consecutive tiles on the same XCD, 1 = the
- *       hardware's round-robin order. */
+ *       hardware's round-robin order.
+ *  fused_steps: single solvers; 1 = one step per launch, 2 = two steps per
+ *       launch on 64 x tile_rows tiles staged in LDS (temporal blocking).
+ *  tile_rows: rows of a two-step tile, 1..64, within 160 KB of LDS. */
 typedef struct lbrd_tuning {
     int32_t vec;
     int32_t lanes_x;
@@ -108,6 +113,8 @@ typedef struct lbrd_tuning {
     int32_t graph_steps;
     int32_t blocks_per_cu;
     int32_t plain_order;
+    int32_t fused_steps;
+    int32_t tile_rows;
     int32_t reserved;
 } lbrd_tuning;
 

@@ -115,6 +115,24 @@ Grid make_grid(const Layout &L, const void *src, void *dst, int vec, int lanes_x
     return g;
 }
 
+Grid2 make_grid2(const Layout &L, const void *src, void *dst, int tw, int th) {
+    Grid2 g;
+    g.src = src;
+    g.dst = dst;
+    g.nx = L.nx;
+    g.ny = L.ny;
+    g.pitch = L.pitch;
+    g.pstride = L.pstride;
+    g.tw = tw;
+    g.th = th;
+    g.ntx = (L.nx + tw - 1) / tw;
+    g.nty = (L.ny + th - 1) / th;
+    g.ntiles = (int64_t)g.ntx * g.nty;
+    g.blocks = 0;
+    g.xcd_order = 1;
+    return g;
+}
+
 // 16-byte vectors for F64 / F32; 8-byte vectors for the 16-bit forms (half
 // the registers of 16-byte ones, measured faster on 4096^2 lattices).
 int default_vec(int storage) { return storage == kF64 ? 2 : 4; }
@@ -211,6 +229,7 @@ struct lbrd_solver {
     lbrd_tuning tune;
     alignas(16) unsigned char params[sizeof(Params<double>)];
     hipGraphExec_t graph[2] = {nullptr, nullptr};   // graph_steps steps starting from buf[0] / buf[1]
+    int graph_end[2] = {0, 1};                      // buffer holding the state after each graph
     int graph_steps_built = 0;
     int device = 0;
     int cus = 256;
@@ -235,16 +254,38 @@ StepLaunch step_launch(const lbrd_solver *h) {
     return StepLaunch{h->cfg.storage, variant_of(h->cfg), h->tune.vec, h->tune.waves, h->tune.nontemporal != 0};
 }
 
-hipError_t enqueue_steps(lbrd_solver *h, int from, int64_t n, hipStream_t st) {
+// waves of the one-step launches (the two-step kernel may use more)
+StepLaunch step_launch1(const lbrd_solver *h) {
+    StepLaunch sl = step_launch(h);
+    if (sl.waves > 4) sl.waves = 4;
+    return sl;
+}
+
+// Enqueue n steps starting from buf[from]; *end receives the buffer that
+// holds the state afterwards.  Two-step launches are used while two or more
+// steps remain (when tuned so), one-step launches otherwise.
+hipError_t enqueue_steps(lbrd_solver *h, int from, int64_t n, hipStream_t st, int *end) {
     const StepLaunch sl = step_launch(h);
-    for (int64_t k = 0; k < n; ++k) {
-        const int a = (from + (int)(k & 1)) & 1;
-        Grid g = make_grid(h->L, h->buf[a], h->buf[a ^ 1], h->tune.vec, h->tune.lanes_x);
-        g.blocks = h->tune.blocks_per_cu > 0 ? h->tune.blocks_per_cu * h->cus : 0;
-        g.xcd_order = h->tune.plain_order == 0 ? 1 : 0;
-        hipError_t e = launch_step(sl, g, h->params, st);
+    int a = from;
+    for (int64_t k = 0; k < n;) {
+        hipError_t e;
+        if (h->tune.fused_steps == 2 && n - k >= 2) {
+            Grid2 g = make_grid2(h->L, h->buf[a], h->buf[a ^ 1], 64, h->tune.tile_rows);
+            g.blocks = h->tune.blocks_per_cu > 0 ? h->tune.blocks_per_cu * h->cus : 0;
+            g.xcd_order = h->tune.plain_order == 0 ? 1 : 0;
+            e = launch_step2(sl, g, h->params, st);
+            k += 2;
+        } else {
+            Grid g = make_grid(h->L, h->buf[a], h->buf[a ^ 1], h->tune.vec, h->tune.lanes_x);
+            g.blocks = h->tune.fused_steps == 1 && h->tune.blocks_per_cu > 0 ? h->tune.blocks_per_cu * h->cus : 0;
+            g.xcd_order = h->tune.plain_order == 0 ? 1 : 0;
+            e = launch_step(step_launch1(h), g, h->params, st);
+            k += 1;
+        }
         if (e != hipSuccess) return e;
+        a ^= 1;
     }
+    *end = a;
     return hipSuccess;
 }
 
@@ -255,7 +296,7 @@ hipError_t build_graphs(lbrd_solver *h) {
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamBeginCapture(h->capture, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return e;
-        hipError_t le = enqueue_steps(h, from, n, h->capture);
+        hipError_t le = enqueue_steps(h, from, n, h->capture, &h->graph_end[from]);
         e = hipStreamEndCapture(h->capture, &graph);
         if (le != hipSuccess) {
             if (graph) hipGraphDestroy(graph);
@@ -286,11 +327,18 @@ int stage_host(lbrd_solver *h, const void *host, size_t bytes, const void **dev)
 }
 
 bool tuning_valid(const lbrd_solver *h, const lbrd_tuning &t) {
-    if (!step_shape_valid(h->cfg.storage, t.vec, t.lanes_x, t.waves)) return false;
+    // the one-step shape is used for every one-step launch (also the odd
+    // remainder of a fused run)
+    if (!step_shape_valid(h->cfg.storage, t.vec, t.lanes_x, std::min(t.waves, 4))) return false;
     if (t.blocks_per_cu < 0 || t.blocks_per_cu > 64) return false;
     if (t.plain_order != 0 && t.plain_order != 1) return false;
     if (t.graph_steps < 0 || (t.graph_steps & 1) || t.graph_steps > 4096) return false;
-    return t.nontemporal == 0 || t.nontemporal == 1;
+    if (t.nontemporal != 0 && t.nontemporal != 1) return false;
+    if (!(t.waves == 1 || t.waves == 2 || t.waves == 4 || t.waves == 8 || t.waves == 16)) return false;
+    if (t.fused_steps == 1) return true;
+    if (t.fused_steps != 2) return false;
+    if (t.tile_rows < 1 || t.tile_rows > 64) return false;
+    return step2_lds_bytes(h->cfg.storage, h->cfg.nspecies, 64, t.tile_rows) <= (size_t)160 * 1024;
 }
 
 }  // namespace
@@ -360,24 +408,33 @@ int lbrd_create(const lbrd_config *cfg, void *workspace, size_t bytes, void *str
     h->tune.waves = 4;
     h->tune.graph_steps = ((int64_t)h->cfg.nx * h->cfg.ny <= (1 << 18)) ? 32 : 0;
     if (2 * h->L.buf_bytes > ((size_t)256 << 20)) {
-        // Working set beyond the 256 MB Infinity Cache: streaming loads and
-        // stores (they would only evict data the next step reads) and the
-        // shapes measured fastest on 4096^2 Gray-Scott lattices: 8-byte
-        // vectors with the hardware's round-robin tile order for F32 / F64,
-        // 16-byte vectors for binary16, a persistent grid of 8 workgroups per
-        // CU for bfloat16.
+        // one-step launches (odd remainders) beyond the 256 MB Infinity
+        // Cache: streaming accesses and the shapes measured fastest on
+        // 4096^2 lattices
         h->tune.nontemporal = 1;
         if (h->cfg.storage == LBRD_F32 || h->cfg.storage == LBRD_F64) {
             h->tune.vec = 2;
             h->tune.lanes_x = default_lanes(h->cfg.nx, 2);
-            h->tune.plain_order = 1;
         } else if (h->cfg.storage == LBRD_F16_SHIFTED) {
             h->tune.vec = 8;
             h->tune.lanes_x = std::min(32, default_lanes(h->cfg.nx, 8));
-        } else {
-            h->tune.blocks_per_cu = 8;
         }
     }
+    // Two steps per launch on 64 x rows tiles staged in LDS (temporal
+    // blocking): measured 1.7-1.8x the one-step launches at 1024^2 and 4096^2.
+    // Rows: 8 for 4- and 8-byte storage, 16 for 16-bit storage, halved until
+    // the tile fits in LDS; 8 waves per workgroup; cached accesses.  Tile
+    // order: consecutive tiles on one XCD while both buffers fit in the
+    // Infinity Cache (measured best at 1024^2), the hardware's round-robin
+    // order beyond it (best at 4096^2).
+    h->tune.fused_steps = 2;
+    h->tune.waves = 8;
+    h->tune.nontemporal = 0;
+    h->tune.plain_order = (2 * h->L.buf_bytes > ((size_t)256 << 20)) ? 1 : 0;
+    h->tune.tile_rows = storage_bytes(h->cfg.storage) == 2 ? 16 : 8;
+    while (h->tune.tile_rows > 1 &&
+           step2_lds_bytes(h->cfg.storage, h->cfg.nspecies, 64, h->tune.tile_rows) > (size_t)160 * 1024)
+        h->tune.tile_rows /= 2;
     *out = h;
     return LBRD_OK;
 }
@@ -455,13 +512,15 @@ int lbrd_step(lbrd_solver *h, int64_t nsteps) {
         while (left >= gs) {
             hipError_t e = hipGraphLaunch(h->graph[h->cur], h->stream);
             if (e != hipSuccess) return fail("hipGraphLaunch", e);
-            left -= gs;   // an even number of steps: cur is unchanged
+            h->cur = h->graph_end[h->cur];
+            left -= gs;
             h->t += gs;
         }
     }
-    hipError_t e = enqueue_steps(h, h->cur, left, h->stream);
+    int end = h->cur;
+    hipError_t e = enqueue_steps(h, h->cur, left, h->stream, &end);
     if (e != hipSuccess) return fail("step kernel", e);
-    h->cur ^= (int)(left & 1);
+    h->cur = end;
     h->t += left;
     return LBRD_OK;
 }
@@ -576,6 +635,7 @@ int lbrd_time_steps(lbrd_solver *h, int64_t nsteps, double *ms) {
 
 int lbrd_autotune(lbrd_solver *h, int steps, const char *cache_path, lbrd_tuning *chosen) {
     if (!h || steps < 2) return LBRD_EINVAL;
+    steps += steps & 1;   // even, so two-step candidates time whole launches
     int dev = 0;
     hipGetDevice(&dev);
     hipDeviceProp_t prop;
@@ -593,8 +653,9 @@ int lbrd_autotune(lbrd_solver *h, int steps, const char *cache_path, lbrd_tuning
             if (bar == std::string::npos || line.substr(0, bar) != k) continue;
             lbrd_tuning t;
             std::memset(&t, 0, sizeof(t));
-            if (std::sscanf(line.c_str() + bar + 1, "%d %d %d %d %d %d %d", &t.vec, &t.lanes_x, &t.waves,
-                            &t.nontemporal, &t.graph_steps, &t.plain_order, &t.blocks_per_cu) == 7 &&
+            if (std::sscanf(line.c_str() + bar + 1, "%d %d %d %d %d %d %d %d %d", &t.vec, &t.lanes_x, &t.waves,
+                            &t.nontemporal, &t.graph_steps, &t.plain_order, &t.blocks_per_cu, &t.fused_steps,
+                            &t.tile_rows) == 9 &&
                 tuning_valid(h, t)) {
                 lbrd_set_tuning(h, &t);
                 h->initialised = false;
@@ -604,7 +665,9 @@ int lbrd_autotune(lbrd_solver *h, int steps, const char *cache_path, lbrd_tuning
         }
     }
     // Candidate shapes: every valid vector width, row-segment width up to the
-    // row, waves per workgroup, streaming stores on / off.
+    // row, waves per workgroup, streaming or cached accesses, tile order,
+    // one tile per wave or a persistent grid; and two-step launches over
+    // tile heights and workgroup sizes.
     std::vector<lbrd_tuning> cands;
     const int vecs[3] = {2, 4, 8};
     for (int vec : vecs) {
@@ -622,10 +685,28 @@ int lbrd_autotune(lbrd_solver *h, int steps, const char *cache_path, lbrd_tuning
                             t.nontemporal = nt;
                             t.plain_order = order;
                             t.blocks_per_cu = bpc;
+                            t.fused_steps = 1;
+                            t.tile_rows = 16;
                             t.graph_steps = h->tune.graph_steps;
                             if (tuning_valid(h, t)) cands.push_back(t);
                         }
     }
+    for (int rows : {4, 8, 16, 24, 32})
+        for (int w : {4, 8, 16})
+            for (int nt = 0; nt < 2; ++nt)
+                for (int order = 0; order < 2; ++order) {
+                    lbrd_tuning t = h->tune;
+                    t.vec = default_vec(h->cfg.storage);
+                    t.lanes_x = default_lanes(h->cfg.nx, t.vec);
+                    t.waves = w;
+                    t.nontemporal = nt;
+                    t.plain_order = order;
+                    t.blocks_per_cu = 0;
+                    t.fused_steps = 2;
+                    t.tile_rows = rows;
+                    t.reserved = 0;
+                    if (tuning_valid(h, t)) cands.push_back(t);
+                }
     // the state is scratch from here on: fill it with a uniform field
     h->initialised = true;
     hipError_t e = hipMemsetAsync(h->buf[0], 0, h->L.buf_bytes, h->stream);
@@ -652,7 +733,8 @@ int lbrd_autotune(lbrd_solver *h, int steps, const char *cache_path, lbrd_tuning
     if (cache_path) {
         std::ofstream outf(cache_path, std::ios::app);
         outf << k << "|" << best_t.vec << " " << best_t.lanes_x << " " << best_t.waves << " " << best_t.nontemporal
-             << " " << best_t.graph_steps << " " << best_t.plain_order << " " << best_t.blocks_per_cu << "\n";
+             << " " << best_t.graph_steps << " " << best_t.plain_order << " " << best_t.blocks_per_cu << " "
+             << best_t.fused_steps << " " << best_t.tile_rows << "\n";
     }
     if (chosen) *chosen = h->tune;
     return LBRD_OK;

@@ -26,6 +26,21 @@ bool step_shape_valid(int storage, int vec, int lanes_x, int waves) {
     return v && pow2 && (waves == 1 || waves == 2 || waves == 4);
 }
 
+hipError_t launch_step2(const StepLaunch &sl, const Grid2 &g, const void *params, hipStream_t st) {
+    if (g.ntiles <= 0) return hipSuccess;
+    switch (sl.storage) {
+        case kF64: return launch_step2_f64(sl, g, params, st);
+        case kF32: return launch_step2_f32(sl, g, params, st);
+        case kF16: return launch_step2_f16(sl, g, params, st);
+        case kBF16: return launch_step2_bf16(sl, g, params, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+size_t step2_lds_bytes(int storage, int nspecies, int tw, int th) {
+    return (size_t)9 * nspecies * (tw + 2) * (th + 2) * storage_bytes(storage);
+}
+
 hipError_t launch_step(const StepLaunch &sl, const Grid &g, const void *params, hipStream_t st) {
     if (g.ntiles <= 0) return hipSuccess;
     switch (sl.storage) {

@@ -194,6 +194,7 @@ int lbrd_batch_create(const lbrd_config *cfgs, int count, void *workspace, size_
     b->tune.waves = 4;
     b->tune.blocks_per_cu = 8;
     b->tune.graph_steps = 16;
+    b->tune.fused_steps = 1;
     BatchHeader h;
     std::memset(&h, 0, sizeof(h));
     h.count = count;
@@ -408,6 +409,8 @@ int lbrd_batch_set_tuning(lbrd_batch *b, const lbrd_tuning *t) {
     n.vec = 0;
     n.lanes_x = 0;
     n.plain_order = 0;
+    n.fused_steps = 1;
+    n.tile_rows = 0;
     n.reserved = 0;
     if (!batch_tuning_valid(n)) return LBRD_EINVAL;
     if (std::memcmp(&n, &b->tune, sizeof(n)) != 0) drop_graph(b);

@@ -164,6 +164,54 @@ __device__ __forceinline__ void reaction(const Params<C> &p, const C (&rho)[NSpe
     }
 }
 
+// ------------------------------------------------------- site update --
+
+// Collide and react one site: f holds the nine pulled populations of each
+// species in deviation form (d = f for F64 / F32, f - w_i rho_ref,s for the
+// 16-bit forms); o receives the encoded post-collision values.  With
+// m_s = sum_i d_i (ascending i), rho_s = m_s + rho_ref,s (the weights sum to
+// one) and the update f' = f (1 - 1/tau) + w_i (rho / tau + R) reads
+// d' = d (1 - 1/tau) + w_i (m / tau + R).
+template <int ST, int V>
+__device__ __forceinline__ void collide_site(const Params<typename Traits<ST>::C> &p,
+                                             const typename Traits<ST>::C (&f)[NSpecies<V>::value][9],
+                                             typename Traits<ST>::T (&o)[NSpecies<V>::value][9]) {
+    using C = typename Traits<ST>::C;
+    constexpr int NS = NSpecies<V>::value;
+    C m[NS], rho[NS], R[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        C acc = f[s][0];
+#pragma unroll
+        for (int i = 1; i < 9; ++i) acc += f[s][i];
+        m[s] = acc;
+        rho[s] = kShifted<ST> ? acc + p.rho_ref[s] : acc;
+    }
+    reaction<V, C>(p, rho, R);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        // w_i (m / tau + R): the rest weight is taken as 1 - 4/9 - 4/36
+        // applied to the value itself, so the nine terms sum to exactly
+        // m / tau + R up to unbiased rounding (the rounded weights of a
+        // binary format sum to 1 + O(eps), which would add a systematic mass
+        // drift every step).
+        const C a = p.omega[s] * m[s] + R[s];
+        const C e1 = wgt<C>(1) * a, e5 = wgt<C>(5) * a;
+        const C e0 = a - C(4) * e1 - C(4) * e5;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const C e = i == 0 ? e0 : (i < 5 ? e1 : e5);
+            C r = f[s][i] * p.keep[s] + e;
+            // 16-bit forms: keep the float result as a value of its own so
+            // the conversion always rounds the float (the compiler may
+            // otherwise fold the multiply-add into a mixed-precision
+            // instruction that rounds once, differently in different kernels)
+            if constexpr (kShifted<ST>) asm volatile("" : "+v"(r));
+            o[s][i] = encode_dev<ST>(r);
+        }
+    }
+}
+
 // ---------------------------------------------------------- step tile --
 
 struct TileGeom {
@@ -265,39 +313,21 @@ __device__ __forceinline__ void step_tile(const typename Traits<ST>::T *__restri
         }
     }
 
-    // Collide and react, site by site.  With m_s = sum_i d_i (ascending i),
-    // rho_s = m_s + rho_ref,s (the weights sum to one) and the update
-    //   f' = f (1 - 1/tau) + w_i (rho / tau + R)
-    // reads in deviation form d' = d (1 - 1/tau) + w_i (m / tau + R).
+    // Collide and react, site by site.
     T out[NS][9][VEC];
 #pragma unroll
     for (int j = 0; j < VEC; ++j) {
-        C m[NS], rho[NS], R[NS];
+        C fs[NS][9];
+        T os[NS][9];
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            C acc = f[s][0][j];
+        for (int s = 0; s < NS; ++s)
 #pragma unroll
-            for (int i = 1; i < 9; ++i) acc += f[s][i][j];
-            m[s] = acc;
-            rho[s] = kShifted<ST> ? acc + p.rho_ref[s] : acc;
-        }
-        reaction<V, C>(p, rho, R);
+            for (int i = 0; i < 9; ++i) fs[s][i] = f[s][i][j];
+        collide_site<ST, V>(p, fs, os);
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            // w_i (m / tau + R): the rest weight is taken as 1 - 4/9 - 4/36
-            // applied to the value itself, so the nine terms sum to exactly
-            // m / tau + R up to unbiased rounding (the rounded weights of a
-            // binary format sum to 1 + O(eps), which would add a systematic
-            // mass drift every step).
-            const C a = p.omega[s] * m[s] + R[s];
-            const C e1 = wgt<C>(1) * a, e5 = wgt<C>(5) * a;
-            const C e0 = a - C(4) * e1 - C(4) * e5;
+        for (int s = 0; s < NS; ++s)
 #pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                const C e = i == 0 ? e0 : (i < 5 ? e1 : e5);
-                out[s][i][j] = encode_dev<ST>(f[s][i][j] * p.keep[s] + e);
-            }
-        }
+            for (int i = 0; i < 9; ++i) out[s][i][j] = os[s][i];
     }
 
     if (row_ok && vec_ok) {
@@ -332,6 +362,94 @@ __global__ __launch_bounds__(256) void k_step(Grid gr, Params<typename Traits<ST
     for (int64_t tile = (int64_t)b * waves + wave; tile < gr.ntiles; tile += stride)
         step_tile<ST, V, VEC, NT, ROW1>(static_cast<const typename Traits<ST>::T *>(gr.src),
                                         static_cast<typename Traits<ST>::T *>(gr.dst), g, tile, lane, p);
+}
+
+// ------------------------------------------------ two steps per launch --
+
+__device__ __forceinline__ int wrap_mod(int a, int n) {
+    int r = a % n;
+    return r < 0 ? r + n : r;
+}
+
+template <class T, bool NT>
+__device__ __forceinline__ T load_one(const T *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <class T, bool NT>
+__device__ __forceinline__ void store_one(T *p, T v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
+// Two time steps per launch on a tile of tw x th sites (temporal blocking).
+// Phase 1 computes the post-collision populations of step t+1 on the tile
+// plus a one-site halo, reading the buffer of step t, and keeps them (in the
+// storage encoding) in LDS; phase 2 pulls from LDS, computes step t+2 on the
+// tile and stores it.  Per two steps the buffer is read once for the tile
+// plus halo and written once, instead of read and written twice.  Each site
+// runs the same arithmetic as the one-step kernel, so the result is bitwise
+// identical to two one-step launches.
+template <int ST, int V, bool NT>
+__global__ __launch_bounds__(1024) void k_step2(Grid2 g, Params<typename Traits<ST>::C> p) {
+    using T = typename Traits<ST>::T;
+    using C = typename Traits<ST>::C;
+    constexpr int NS = NSpecies<V>::value;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    T *L = reinterpret_cast<T *>(smem);
+    const T *__restrict__ src = static_cast<const T *>(g.src);
+    T *__restrict__ dst = static_cast<T *>(g.dst);
+    const int ew = g.tw + 2, eh = g.th + 2, esz = ew * eh, tsz = g.tw * g.th;
+    const int b0 = g.xcd_order ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    for (int64_t tile = b0; tile < g.ntiles; tile += gridDim.x) {
+        const int tx = (int)(tile % g.ntx), ty = (int)(tile / g.ntx);
+        const int x0 = tx * g.tw, y0 = ty * g.th;
+        // phase 1: step t -> t+1 on the tile and its halo, into LDS
+        for (int q = threadIdx.x; q < esz; q += blockDim.x) {
+            const int ex = q % ew, ey = q / ew;
+            const int gx = wrap_mod(x0 - 1 + ex, g.nx), gy = wrap_mod(y0 - 1 + ey, g.ny);
+            const int xm = gx == 0 ? g.nx - 1 : gx - 1, xp = gx + 1 == g.nx ? 0 : gx + 1;
+            const int ym = gy == 0 ? g.ny - 1 : gy - 1, yp = gy + 1 == g.ny ? 0 : gy + 1;
+            C f[NS][9];
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    const int col = kEx[i] == 1 ? xm : (kEx[i] == -1 ? xp : gx);
+                    const int row = kEy[i] == 1 ? ym : (kEy[i] == -1 ? yp : gy);
+                    f[s][i] = decode_dev<ST>(
+                        load_one<T, NT>(src + (int64_t)(s * 9 + i) * g.pstride + (int64_t)row * g.pitch + col));
+                }
+            T o[NS][9];
+            collide_site<ST, V>(p, f, o);
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+#pragma unroll
+                for (int i = 0; i < 9; ++i) L[(s * 9 + i) * esz + q] = o[s][i];
+        }
+        __syncthreads();
+        // phase 2: step t+1 -> t+2 on the tile, pulling from LDS
+        for (int q = threadIdx.x; q < tsz; q += blockDim.x) {
+            const int lx = q % g.tw, ly = q / g.tw;
+            const int gx = x0 + lx, gy = y0 + ly;
+            C f[NS][9];
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+#pragma unroll
+                for (int i = 0; i < 9; ++i)
+                    f[s][i] = decode_dev<ST>(L[(s * 9 + i) * esz + (ly + 1 - kEy[i]) * ew + (lx + 1 - kEx[i])]);
+            T o[NS][9];
+            collide_site<ST, V>(p, f, o);
+            if (gx < g.nx && gy < g.ny) {
+#pragma unroll
+                for (int s = 0; s < NS; ++s)
+#pragma unroll
+                    for (int i = 0; i < 9; ++i)
+                        store_one<T, NT>(dst + (int64_t)(s * 9 + i) * g.pstride + (int64_t)gy * g.pitch + gx, o[s][i]);
+            }
+        }
+        __syncthreads();   // LDS is reused by the next tile
+    }
 }
 
 }  // namespace lbrd

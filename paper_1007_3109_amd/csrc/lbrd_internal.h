@@ -75,6 +75,24 @@ struct Grid {
 
 Grid make_grid(const Layout &L, const void *src, void *dst, int vec, int lanes_x);
 
+// Geometry of a two-step (temporally blocked) launch: tiles of tw x th sites,
+// one workgroup per tile (or a persistent grid of `blocks` workgroups).
+struct Grid2 {
+    const void *src;
+    void *dst;
+    int nx, ny;
+    int64_t pitch, pstride;
+    int tw, th;
+    int ntx, nty;
+    int64_t ntiles;
+    int blocks;
+    int xcd_order;
+};
+
+Grid2 make_grid2(const Layout &L, const void *src, void *dst, int tw, int th);
+// LDS bytes a two-step launch needs.
+size_t step2_lds_bytes(int storage, int nspecies, int tw, int th);
+
 // ------------------------------------------------------------ launchers --
 
 struct StepLaunch {
@@ -89,6 +107,12 @@ hipError_t launch_step_f32(const StepLaunch &sl, const Grid &g, const void *para
 hipError_t launch_step_f16(const StepLaunch &sl, const Grid &g, const void *params, hipStream_t st);
 hipError_t launch_step_bf16(const StepLaunch &sl, const Grid &g, const void *params, hipStream_t st);
 hipError_t launch_step(const StepLaunch &sl, const Grid &g, const void *params, hipStream_t st);
+// Two steps src -> dst (one launch).
+hipError_t launch_step2_f64(const StepLaunch &sl, const Grid2 &g, const void *params, hipStream_t st);
+hipError_t launch_step2_f32(const StepLaunch &sl, const Grid2 &g, const void *params, hipStream_t st);
+hipError_t launch_step2_f16(const StepLaunch &sl, const Grid2 &g, const void *params, hipStream_t st);
+hipError_t launch_step2_bf16(const StepLaunch &sl, const Grid2 &g, const void *params, hipStream_t st);
+hipError_t launch_step2(const StepLaunch &sl, const Grid2 &g, const void *params, hipStream_t st);
 bool step_shape_valid(int storage, int vec, int lanes_x, int waves);
 
 hipError_t launch_init(int storage, const Layout &L, const void *params, const void *rho0, int dtype, void *dst,

@@ -47,4 +47,40 @@ inline hipError_t launch_step_s(const StepLaunch &sl, const Grid &g, const void 
     }
 }
 
+template <int ST, int V, bool NT>
+inline hipError_t launch_step2_t(const StepLaunch &sl, const Grid2 &g, const void *params, hipStream_t st) {
+    using C = typename Traits<ST>::C;
+    const Params<C> &p = *static_cast<const Params<C> *>(params);
+    const size_t lds = step2_lds_bytes(ST, NSpecies<V>::value, g.tw, g.th);
+    static bool attr_set = false;   // per instantiation: allow more than 64 KB of LDS
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_step2<ST, V, NT>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    int64_t nb = g.ntiles;
+    if (g.blocks > 0 && g.blocks < nb) nb = g.blocks;
+    if (nb > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_step2<ST, V, NT>), dim3((unsigned)nb), dim3(64 * sl.waves), lds, st, g, p);
+    return hipGetLastError();
+}
+
+template <int ST, bool NT>
+inline hipError_t launch_step2_v(const StepLaunch &sl, const Grid2 &g, const void *params, hipStream_t st) {
+    switch (sl.variant) {
+        case kLin1: return launch_step2_t<ST, kLin1, NT>(sl, g, params, st);
+        case kLin2: return launch_step2_t<ST, kLin2, NT>(sl, g, params, st);
+        case kLin3: return launch_step2_t<ST, kLin3, NT>(sl, g, params, st);
+        case kLin4: return launch_step2_t<ST, kLin4, NT>(sl, g, params, st);
+        case kGS: return launch_step2_t<ST, kGS, NT>(sl, g, params, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int ST>
+inline hipError_t launch_step2_s(const StepLaunch &sl, const Grid2 &g, const void *params, hipStream_t st) {
+    return sl.nontemporal ? launch_step2_v<ST, true>(sl, g, params, st) : launch_step2_v<ST, false>(sl, g, params, st);
+}
+
 }  // namespace lbrd

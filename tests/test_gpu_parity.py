@@ -97,7 +97,7 @@ def test_populations_f64_every_launch_shape(shape):
     for lx in (1, 2, 4, 8, 16, 32, 64):
         for waves in (1, 4):
             for nt in (0, 1):
-                s.set_tuning(vec=2, lanes_x=lx, waves=waves, nontemporal=nt, graph_steps=0)
+                s.set_tuning(vec=2, lanes_x=lx, waves=waves, nontemporal=nt, graph_steps=0, fused_steps=1)
                 s.set_populations(f0).step(7)
                 got = s.get_populations().cpu().numpy()
                 assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max(), (shape, lx, waves, nt)
@@ -115,7 +115,7 @@ def test_populations_f32_vec_variants(storage, vecs):
     s = lbrd.Solver(cfg)
     for vec in vecs:
         for lx in (4, 16, 32):
-            s.set_tuning(vec=vec, lanes_x=lx, waves=2, graph_steps=0)
+            s.set_tuning(vec=vec, lanes_x=lx, waves=2, graph_steps=0, fused_steps=1)
             s.set_populations(f0).step(5)
             got = s.get_populations().cpu().numpy()
             assert np.abs(got - ref).max() <= 2e-6 * np.abs(ref).max(), (vec, lx)
@@ -381,3 +381,56 @@ def test_gray_scott_4096_sampled_windows(storage, quant):
         log(f"4096 {storage} sampled: vs emulation {err}, emulation vs FP64 {fmt}, "
             f"GPU vs FP64 {oracle.rel_l2(cat(gots), cat(r64s))}")
         assert np.all(err <= fmt)
+
+
+# ----- two steps per launch (temporal blocking) ------------------------------
+
+FUSED_CASES = [("f64", "gray_scott", 2), ("f32", "gray_scott", 2), ("f16", "gray_scott", 2), ("bf16", "gray_scott", 2),
+               ("f32", "linear", 1), ("f32", "linear", 3), ("f16", "linear", 1)]
+
+
+@pytest.mark.parametrize("storage,reaction,ns", FUSED_CASES)
+def test_two_step_launch_is_bitwise_identical(storage, reaction, ns):
+    """The LDS-tiled two-step launch runs each site's arithmetic exactly as the
+    one-step launch, so every population after 7 steps (three two-step
+    launches and one one-step launch) is bitwise equal, on ragged and tiny
+    lattices, for several tile heights and workgroup sizes."""
+    for ny, nx in [(1, 1), (3, 3), (2, 5), (45, 67), (33, 130), (17, 257)]:
+        rng = np.random.default_rng(nx * 7 + ny)
+        kw = dict(F=0.04, k=0.06) if reaction == "gray_scott" else dict(K=-0.01 * np.eye(ns))
+        rref = (0.3,) * ns
+        cfg = lbrd.make_config(nx, ny, ns, tau=[0.7, 1.2, 0.9][:ns], storage=storage, reaction=reaction,
+                               rho_ref=rref, **kw)
+        f0 = rng.uniform(0.0, 0.1, size=(ns, 9, ny, nx))
+        ref = lbrd.Solver(cfg)
+        ref.set_tuning(fused_steps=1, graph_steps=0)
+        ref.set_populations(f0).step(7)
+        want = ref.get_populations()
+        s = lbrd.Solver(cfg)
+        b = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[storage]
+        for rows in (1, 8, 16):
+            if 9 * ns * 66 * (rows + 2) * b > 160 * 1024:
+                continue                      # the tile would not fit in LDS
+            for waves in (4, 16):
+                s.set_tuning(fused_steps=2, tile_rows=rows, waves=waves, graph_steps=0)
+                s.set_populations(f0).step(7)
+                assert torch.equal(s.get_populations(), want), (ny, nx, rows, waves)
+        assert s.time() == 7
+
+
+def test_two_step_launch_with_graphs_and_oracle():
+    rho0 = workloads.gray_scott_square(200, 160, seed=7)
+    kw = dict(F=workloads.GS_F, k=workloads.GS_K)
+    cfg = lbrd.make_config(200, 160, 2, tau=workloads.GS_TAU, storage="f32", reaction="gray_scott", **kw)
+    a = lbrd.Solver(cfg)
+    a.set_tuning(fused_steps=1, graph_steps=0)
+    b = lbrd.Solver(cfg)
+    b.set_tuning(fused_steps=2, tile_rows=16, waves=16, graph_steps=6)   # graphs of 3 fused launches
+    a.init(rho0)
+    b.init(rho0)
+    for n in (13, 6, 31, 2):
+        a.step(n)
+        b.step(n)
+        assert torch.equal(a.moments()[0], b.moments()[0])
+    ref = oracle.solve(rho0, 52, list(workloads.GS_TAU), oracle.REACT_GRAY_SCOTT, **kw)
+    assert np.all(oracle.rel_l2(b.moments()[0].cpu().numpy(), ref) <= 1e-5)
