@@ -4,7 +4,7 @@ Workload timed for the headline line: Gray-Scott (u, v), D2Q9 BGK, 1024 x 1024
 periodic, FP32 storage, tau = (1.0, 0.75), F = 0.04, k = 0.06, central 64 x 64
 square with u = 0.5, v = 0.25 plus U(-0.01, 0.01) noise (seed 0).  One "step"
 is one lattice time step of the whole field (every species, every site):
-collide, react and stream.  The library's default launch shape advances two
+collide, react and stream.  The library's default launch shape advances four
 steps per launch (64 x rows tiles staged in LDS); --tune runs its autotuner
 first.
 
@@ -40,7 +40,7 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, 8 TB/s
 # records their digest, and its traffic figure is reported only while it matches
 STEP_SOURCES = ("paper_1007_3109_amd/csrc/lbrd_device.h", "paper_1007_3109_amd/csrc/lbrd_internal.h",
                 "paper_1007_3109_amd/csrc/lbrd_step_launch.h", "paper_1007_3109_amd/csrc/step_f32.hip")
-TRAFFIC_SUMMARY = "profiles/pmc_k_step2_gray_scott_1024_f32.txt"
+TRAFFIC_SUMMARY = "profiles/pmc_k_stepT_gray_scott_1024_f32.txt"
 
 
 def source_digest():
@@ -390,8 +390,8 @@ def main():
     tun = s.tuning()
     steps_per_launch = tun.fused_steps
     # algorithmic bytes of one launch: the state read once and written once
-    # (2 * 9 * 4 B per species-site), whether the launch advances one step or
-    # two (the two-step tile's halo re-reads are not counted)
+    # (2 * 9 * 4 B per species-site), whatever the number of steps the launch
+    # advances (the tile halo's re-reads are not counted)
     bytes_per_launch = algorithmic_bytes(2, sites, 4)
     launch_seconds = secs / args.steps * steps_per_launch
     achieved = bytes_per_launch / launch_seconds / 1e9
@@ -416,7 +416,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "traffic_unit": "bytes per launch", "traffic_source": traffic_src,
-                     "kernel": "k_step2 (two steps per launch)" if steps_per_launch == 2 else "k_step",
+                     "kernel": (f"k_stepT ({steps_per_launch} steps per launch, {tun.tile_cols} x {tun.tile_rows} "
+                                f"tiles in LDS)") if steps_per_launch > 1 else "k_step (one step per launch)",
                      "steps_per_launch": steps_per_launch,
                      "launch_us": round(launch_seconds * 1e6, 3),
                      "bytes_per_launch": bytes_per_launch,

@@ -102,9 +102,17 @@ typedef struct lbrd_config {
  *       over tiles.
  *  plain_order: single solvers; 0 = consecutive tiles on the same XCD, 1 = the
  *       hardware's round-robin order.
- *  fused_steps: single solvers; 1 = one step per launch, 2 = two steps per
- *       launch on 64 x tile_rows tiles staged in LDS (temporal blocking).
- *  tile_rows: rows of a two-step tile, 1..64, within 160 KB of LDS. */
+ *  fused_steps: single solvers; 1 = one step per launch; T = 2, 3 or 4 =
+ *       T steps per launch on tile_cols x tile_rows tiles staged in LDS
+ *       (temporal blocking; a remainder of 2 .. T-1 steps runs as one shorter
+ *       launch on the same tiles, a single remaining step as a one-step
+ *       launch).  Results are bitwise identical for every setting.
+ *  tile_rows, tile_cols: multi-step tile, rows 1..64 and columns 8..512; the
+ *       region (tile_cols + 2(T-1)) x (tile_rows + 2(T-1)) x 9 N populations
+ *       must fit in 160 KB of LDS and, for T >= 3, the second phase's region
+ *       (two sites smaller per axis) must not exceed the workgroup's
+ *       register budget (64 * waves threads x 1..4 sites, fewer for more
+ *       species or FP64).  Ignored when fused_steps = 1. */
 typedef struct lbrd_tuning {
     int32_t vec;
     int32_t lanes_x;
@@ -115,7 +123,7 @@ typedef struct lbrd_tuning {
     int32_t plain_order;
     int32_t fused_steps;
     int32_t tile_rows;
-    int32_t reserved;
+    int32_t tile_cols;
 } lbrd_tuning;
 
 const char *lbrd_strerror(int status);

@@ -115,8 +115,8 @@ Grid make_grid(const Layout &L, const void *src, void *dst, int vec, int lanes_x
     return g;
 }
 
-Grid2 make_grid2(const Layout &L, const void *src, void *dst, int tw, int th) {
-    Grid2 g;
+GridT make_gridT(const Layout &L, const void *src, void *dst, int tw, int th, int steps) {
+    GridT g;
     g.src = src;
     g.dst = dst;
     g.nx = L.nx;
@@ -130,6 +130,8 @@ Grid2 make_grid2(const Layout &L, const void *src, void *dst, int tw, int th) {
     g.ntiles = (int64_t)g.ntx * g.nty;
     g.blocks = 0;
     g.xcd_order = 1;
+    g.steps = steps;
+    g.bytes = L.buf_bytes < ((size_t)1 << 32) ? (uint32_t)L.buf_bytes : 0;   // 0: too large, launch refused
     return g;
 }
 
@@ -254,7 +256,7 @@ StepLaunch step_launch(const lbrd_solver *h) {
     return StepLaunch{h->cfg.storage, variant_of(h->cfg), h->tune.vec, h->tune.waves, h->tune.nontemporal != 0};
 }
 
-// waves of the one-step launches (the two-step kernel may use more)
+// waves of the one-step launches (the multi-step kernel may use more)
 StepLaunch step_launch1(const lbrd_solver *h) {
     StepLaunch sl = step_launch(h);
     if (sl.waves > 4) sl.waves = 4;
@@ -262,22 +264,26 @@ StepLaunch step_launch1(const lbrd_solver *h) {
 }
 
 // Enqueue n steps starting from buf[from]; *end receives the buffer that
-// holds the state afterwards.  Two-step launches are used while two or more
-// steps remain (when tuned so), one-step launches otherwise.
+// holds the state afterwards.  With fused_steps = T >= 2, launches of T steps
+// run while T or more steps remain, then one launch of the 2 .. T-1 left (same
+// tiles), then a one-step launch for a single remaining step.
 hipError_t enqueue_steps(lbrd_solver *h, int from, int64_t n, hipStream_t st, int *end) {
     const StepLaunch sl = step_launch(h);
+    const int T = h->tune.fused_steps;
     int a = from;
     for (int64_t k = 0; k < n;) {
         hipError_t e;
-        if (h->tune.fused_steps == 2 && n - k >= 2) {
-            Grid2 g = make_grid2(h->L, h->buf[a], h->buf[a ^ 1], 64, h->tune.tile_rows);
+        const int64_t left = n - k;
+        if (T >= 2 && left >= 2) {
+            const int m = left < T ? (int)left : T;
+            GridT g = make_gridT(h->L, h->buf[a], h->buf[a ^ 1], h->tune.tile_cols, h->tune.tile_rows, m);
             g.blocks = h->tune.blocks_per_cu > 0 ? h->tune.blocks_per_cu * h->cus : 0;
             g.xcd_order = h->tune.plain_order == 0 ? 1 : 0;
-            e = launch_step2(sl, g, h->params, st);
-            k += 2;
+            e = launch_stepT(sl, g, h->params, st);
+            k += m;
         } else {
             Grid g = make_grid(h->L, h->buf[a], h->buf[a ^ 1], h->tune.vec, h->tune.lanes_x);
-            g.blocks = h->tune.fused_steps == 1 && h->tune.blocks_per_cu > 0 ? h->tune.blocks_per_cu * h->cus : 0;
+            g.blocks = T == 1 && h->tune.blocks_per_cu > 0 ? h->tune.blocks_per_cu * h->cus : 0;
             g.xcd_order = h->tune.plain_order == 0 ? 1 : 0;
             e = launch_step(step_launch1(h), g, h->params, st);
             k += 1;
@@ -326,6 +332,12 @@ int stage_host(lbrd_solver *h, const void *host, size_t bytes, const void **dev)
     return LBRD_OK;
 }
 
+// The multi-step kernel addresses a buffer with 32-bit byte offsets.
+bool multi_step_possible(const lbrd_solver *h) {
+    return h->L.buf_bytes < ((size_t)1 << 32) &&
+           (int64_t)h->L.pitch * storage_bytes(h->cfg.storage) < ((int64_t)1 << 24);
+}
+
 bool tuning_valid(const lbrd_solver *h, const lbrd_tuning &t) {
     // the one-step shape is used for every one-step launch (also the odd
     // remainder of a fused run)
@@ -336,9 +348,10 @@ bool tuning_valid(const lbrd_solver *h, const lbrd_tuning &t) {
     if (t.nontemporal != 0 && t.nontemporal != 1) return false;
     if (!(t.waves == 1 || t.waves == 2 || t.waves == 4 || t.waves == 8 || t.waves == 16)) return false;
     if (t.fused_steps == 1) return true;
-    if (t.fused_steps != 2) return false;
+    if (!multi_step_possible(h)) return false;
+    if (t.fused_steps < 2 || t.fused_steps > kMaxFusedSteps) return false;
     if (t.tile_rows < 1 || t.tile_rows > 64) return false;
-    return step2_lds_bytes(h->cfg.storage, h->cfg.nspecies, 64, t.tile_rows) <= (size_t)160 * 1024;
+    return stepT_shape_fits(h->cfg.storage, h->cfg.nspecies, t.tile_cols, t.tile_rows, t.fused_steps, t.waves);
 }
 
 }  // namespace
@@ -420,21 +433,31 @@ int lbrd_create(const lbrd_config *cfg, void *workspace, size_t bytes, void *str
             h->tune.lanes_x = std::min(32, default_lanes(h->cfg.nx, 8));
         }
     }
-    // Two steps per launch on 64 x rows tiles staged in LDS (temporal
-    // blocking): measured 1.7-1.8x the one-step launches at 1024^2 and 4096^2.
-    // Rows: 8 for 4- and 8-byte storage, 16 for 16-bit storage, halved until
-    // the tile fits in LDS; 8 waves per workgroup; cached accesses.  Tile
-    // order: consecutive tiles on one XCD while both buffers fit in the
-    // Infinity Cache (measured best at 1024^2), the hardware's round-robin
-    // order beyond it (best at 4096^2).
-    h->tune.fused_steps = 2;
-    h->tune.waves = 8;
-    h->tune.nontemporal = 0;
-    h->tune.plain_order = (2 * h->L.buf_bytes > ((size_t)256 << 20)) ? 1 : 0;
-    h->tune.tile_rows = storage_bytes(h->cfg.storage) == 2 ? 16 : 8;
-    while (h->tune.tile_rows > 1 &&
-           step2_lds_bytes(h->cfg.storage, h->cfg.nspecies, 64, h->tune.tile_rows) > (size_t)160 * 1024)
-        h->tune.tile_rows /= 2;
+    // Four steps per launch on 64 x rows tiles staged in LDS (temporal
+    // blocking): measured 2.4x (1024^2) and 2.7x (4096^2, FP32) the one-step
+    // launches.  Rows: 4 while both buffers fit in the 256 MB Infinity Cache,
+    // 8 beyond it; halved (then fewer steps per launch) until the shape fits
+    // in LDS and the register budget; 8 waves per workgroup; cached accesses.
+    // Tile order: consecutive tiles on one XCD inside the Infinity Cache, the
+    // hardware's round-robin order beyond it (each measured best there).
+    // Buffers of 4 GiB or more keep one-step launches.
+    const bool in_cache = 2 * h->L.buf_bytes <= ((size_t)256 << 20);
+    h->tune.tile_cols = 64;
+    h->tune.tile_rows = in_cache ? 4 : 8;
+    h->tune.fused_steps = 1;
+    if (multi_step_possible(h)) {
+        h->tune.waves = 8;
+        h->tune.nontemporal = 0;
+        h->tune.plain_order = in_cache ? 0 : 1;
+        for (int ts = kMaxFusedSteps; ts >= 2 && h->tune.fused_steps == 1; --ts) {
+            for (int rows = h->tune.tile_rows; rows >= 1; rows /= 2)
+                if (stepT_shape_fits(h->cfg.storage, h->cfg.nspecies, 64, rows, ts, 8)) {
+                    h->tune.fused_steps = ts;
+                    h->tune.tile_rows = rows;
+                    break;
+                }
+        }
+    }
     *out = h;
     return LBRD_OK;
 }
@@ -596,7 +619,6 @@ int lbrd_set_tuning(lbrd_solver *h, const lbrd_tuning *t) {
     if (!h || !t) return LBRD_EINVAL;
     lbrd_tuning n = *t;
     if (n.lanes_x == 0) n.lanes_x = default_lanes(h->cfg.nx, n.vec);
-    n.reserved = 0;
     if (!tuning_valid(h, n)) return LBRD_EINVAL;
     const bool rebuild = std::memcmp(&n, &h->tune, sizeof(n)) != 0;
     h->tune = n;
@@ -635,7 +657,7 @@ int lbrd_time_steps(lbrd_solver *h, int64_t nsteps, double *ms) {
 
 int lbrd_autotune(lbrd_solver *h, int steps, const char *cache_path, lbrd_tuning *chosen) {
     if (!h || steps < 2) return LBRD_EINVAL;
-    steps += steps & 1;   // even, so two-step candidates time whole launches
+    steps = (steps + 11) / 12 * 12;   // whole launches for every step count 1 .. 4
     int dev = 0;
     hipGetDevice(&dev);
     hipDeviceProp_t prop;
@@ -653,9 +675,9 @@ int lbrd_autotune(lbrd_solver *h, int steps, const char *cache_path, lbrd_tuning
             if (bar == std::string::npos || line.substr(0, bar) != k) continue;
             lbrd_tuning t;
             std::memset(&t, 0, sizeof(t));
-            if (std::sscanf(line.c_str() + bar + 1, "%d %d %d %d %d %d %d %d %d", &t.vec, &t.lanes_x, &t.waves,
+            if (std::sscanf(line.c_str() + bar + 1, "%d %d %d %d %d %d %d %d %d %d", &t.vec, &t.lanes_x, &t.waves,
                             &t.nontemporal, &t.graph_steps, &t.plain_order, &t.blocks_per_cu, &t.fused_steps,
-                            &t.tile_rows) == 9 &&
+                            &t.tile_rows, &t.tile_cols) == 10 &&
                 tuning_valid(h, t)) {
                 lbrd_set_tuning(h, &t);
                 h->initialised = false;
@@ -666,8 +688,8 @@ int lbrd_autotune(lbrd_solver *h, int steps, const char *cache_path, lbrd_tuning
     }
     // Candidate shapes: every valid vector width, row-segment width up to the
     // row, waves per workgroup, streaming or cached accesses, tile order,
-    // one tile per wave or a persistent grid; and two-step launches over
-    // tile heights and workgroup sizes.
+    // one tile per wave or a persistent grid; and multi-step launches over
+    // steps per launch, tile widths and heights and workgroup sizes.
     std::vector<lbrd_tuning> cands;
     const int vecs[3] = {2, 4, 8};
     for (int vec : vecs) {
@@ -686,27 +708,28 @@ int lbrd_autotune(lbrd_solver *h, int steps, const char *cache_path, lbrd_tuning
                             t.plain_order = order;
                             t.blocks_per_cu = bpc;
                             t.fused_steps = 1;
-                            t.tile_rows = 16;
                             t.graph_steps = h->tune.graph_steps;
                             if (tuning_valid(h, t)) cands.push_back(t);
                         }
     }
-    for (int rows : {4, 8, 16, 24, 32})
-        for (int w : {4, 8, 16})
-            for (int nt = 0; nt < 2; ++nt)
-                for (int order = 0; order < 2; ++order) {
-                    lbrd_tuning t = h->tune;
-                    t.vec = default_vec(h->cfg.storage);
-                    t.lanes_x = default_lanes(h->cfg.nx, t.vec);
-                    t.waves = w;
-                    t.nontemporal = nt;
-                    t.plain_order = order;
-                    t.blocks_per_cu = 0;
-                    t.fused_steps = 2;
-                    t.tile_rows = rows;
-                    t.reserved = 0;
-                    if (tuning_valid(h, t)) cands.push_back(t);
-                }
+    for (int ts = 2; ts <= kMaxFusedSteps; ++ts)
+        for (int cols : {64, 128})
+            for (int rows : {4, 8, 16, 24, 32})
+                for (int w : {4, 8, 16})
+                    for (int nt = 0; nt < 2; ++nt)
+                        for (int order = 0; order < 2; ++order) {
+                            lbrd_tuning t = h->tune;
+                            t.vec = default_vec(h->cfg.storage);
+                            t.lanes_x = default_lanes(h->cfg.nx, t.vec);
+                            t.waves = w;
+                            t.nontemporal = nt;
+                            t.plain_order = order;
+                            t.blocks_per_cu = 0;
+                            t.fused_steps = ts;
+                            t.tile_rows = rows;
+                            t.tile_cols = cols;
+                            if (tuning_valid(h, t)) cands.push_back(t);
+                        }
     // the state is scratch from here on: fill it with a uniform field
     h->initialised = true;
     hipError_t e = hipMemsetAsync(h->buf[0], 0, h->L.buf_bytes, h->stream);
@@ -734,7 +757,7 @@ int lbrd_autotune(lbrd_solver *h, int steps, const char *cache_path, lbrd_tuning
         std::ofstream outf(cache_path, std::ios::app);
         outf << k << "|" << best_t.vec << " " << best_t.lanes_x << " " << best_t.waves << " " << best_t.nontemporal
              << " " << best_t.graph_steps << " " << best_t.plain_order << " " << best_t.blocks_per_cu << " "
-             << best_t.fused_steps << " " << best_t.tile_rows << "\n";
+             << best_t.fused_steps << " " << best_t.tile_rows << " " << best_t.tile_cols << "\n";
     }
     if (chosen) *chosen = h->tune;
     return LBRD_OK;

@@ -26,19 +26,37 @@ bool step_shape_valid(int storage, int vec, int lanes_x, int waves) {
     return v && pow2 && (waves == 1 || waves == 2 || waves == 4);
 }
 
-hipError_t launch_step2(const StepLaunch &sl, const Grid2 &g, const void *params, hipStream_t st) {
+hipError_t launch_stepT(const StepLaunch &sl, const GridT &g, const void *params, hipStream_t st) {
     if (g.ntiles <= 0) return hipSuccess;
+    // 32-bit byte offsets: the whole buffer below 4 GiB, a row pitch below
+    // 16 MiB (24-bit multiplies)
+    if ((int64_t)g.pitch * storage_bytes(sl.storage) >= (1 << 24) || g.bytes == 0) return hipErrorInvalidValue;
     switch (sl.storage) {
-        case kF64: return launch_step2_f64(sl, g, params, st);
-        case kF32: return launch_step2_f32(sl, g, params, st);
-        case kF16: return launch_step2_f16(sl, g, params, st);
-        case kBF16: return launch_step2_bf16(sl, g, params, st);
+        case kF64: return launch_stepT_f64(sl, g, params, st);
+        case kF32: return launch_stepT_f32(sl, g, params, st);
+        case kF16: return launch_stepT_f16(sl, g, params, st);
+        case kBF16: return launch_stepT_bf16(sl, g, params, st);
         default: return hipErrorInvalidValue;
     }
 }
 
-size_t step2_lds_bytes(int storage, int nspecies, int tw, int th) {
-    return (size_t)9 * nspecies * (tw + 2) * (th + 2) * storage_bytes(storage);
+size_t stepT_lds_bytes(int storage, int nspecies, int tw, int th, int steps) {
+    const int h = steps - 1;
+    return (size_t)9 * nspecies * (tw + 2 * h) * (th + 2 * h) * storage_bytes(storage);
+}
+
+int stepT_sites_per_thread(int tw, int th, int steps, int waves) {
+    if (steps <= 2) return 0;
+    const int64_t middle = (int64_t)(tw + 2 * (steps - 1) - 2) * (th + 2 * (steps - 1) - 2);
+    return (int)((middle + 64 * waves - 1) / (64 * waves));
+}
+
+bool stepT_shape_fits(int storage, int nspecies, int tw, int th, int steps, int waves) {
+    if (steps < 2 || steps > kMaxFusedSteps || (tw != 64 && tw != 128) || th < 1 || waves < 1 || waves > 16)
+        return false;
+    if (stepT_lds_bytes(storage, nspecies, tw, th, steps) > (size_t)160 * 1024) return false;
+    const int k = stepT_sites_per_thread(tw, th, steps, waves);
+    return k <= 1 || (k == 2 && waves <= 8);
 }
 
 hipError_t launch_step(const StepLaunch &sl, const Grid &g, const void *params, hipStream_t st) {

@@ -411,7 +411,7 @@ int lbrd_batch_set_tuning(lbrd_batch *b, const lbrd_tuning *t) {
     n.plain_order = 0;
     n.fused_steps = 1;
     n.tile_rows = 0;
-    n.reserved = 0;
+    n.tile_cols = 0;
     if (!batch_tuning_valid(n)) return LBRD_EINVAL;
     if (std::memcmp(&n, &b->tune, sizeof(n)) != 0) drop_graph(b);
     b->tune = n;

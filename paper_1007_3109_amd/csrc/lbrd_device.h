@@ -364,88 +364,173 @@ __global__ __launch_bounds__(256) void k_step(Grid gr, Params<typename Traits<ST
                                         static_cast<typename Traits<ST>::T *>(gr.dst), g, tile, lane, p);
 }
 
-// ------------------------------------------------ two steps per launch --
+// ------------------------------------------- several steps per launch --
 
 __device__ __forceinline__ int wrap_mod(int a, int n) {
     int r = a % n;
     return r < 0 ? r + n : r;
 }
 
-template <class T, bool NT>
-__device__ __forceinline__ T load_one(const T *p) {
-    if constexpr (NT) return __builtin_nontemporal_load(p);
-    else return *p;
+// Raw buffer access with a 32-bit byte offset split into a per-lane part
+// (voffset) and a wave-uniform part (soffset, the plane): the hardware adds
+// them to the descriptor's base, so no 64-bit address arithmetic is spent per
+// population.  Accesses beyond the descriptor's byte range read 0 and do not
+// write.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
 }
-template <class T, bool NT>
-__device__ __forceinline__ void store_one(T *p, T v) {
-    if constexpr (NT) __builtin_nontemporal_store(v, p);
-    else *p = v;
+template <class T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    if constexpr (sizeof(T) == 8) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    else if constexpr (sizeof(T) == 4) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    else return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+}
+template <class T>
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, T v) {
+    if constexpr (sizeof(T) == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(typename RawOf<8>::type, v), r, voff, soff, 0);
+    else if constexpr (sizeof(T) == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
+    else
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, voff, soff, 0);
 }
 
-// Two time steps per launch on a tile of tw x th sites (temporal blocking).
-// Phase 1 computes the post-collision populations of step t+1 on the tile
-// plus a one-site halo, reading the buffer of step t, and keeps them (in the
-// storage encoding) in LDS; phase 2 pulls from LDS, computes step t+2 on the
-// tile and stores it.  Per two steps the buffer is read once for the tile
-// plus halo and written once, instead of read and written twice.  Each site
-// runs the same arithmetic as the one-step kernel, so the result is bitwise
-// identical to two one-step launches.
-template <int ST, int V, bool NT>
-__global__ __launch_bounds__(1024) void k_step2(Grid2 g, Params<typename Traits<ST>::C> p) {
+// a * b for a, b below 2^24 (one full-rate multiply)
+__device__ __forceinline__ uint32_t mul24(int a, uint32_t b) { return (uint32_t)__umul24((uint32_t)a, b); }
+
+// LDS layout of the multi-step region: row-interleaved planes, element
+// (plane P, column x, row y) at y * (9 N) * EW + P * EW + x, with EW the
+// region width.  A site's 9 N pulled inputs then sit at compile-time offsets
+// from one address (its lower-left neighbour), and consecutive lanes touch
+// consecutive words.
+template <int ST, int NS, int EW>
+__device__ __forceinline__ void gather_lds(const typename Traits<ST>::T *L, int lx, int ly,
+                                           typename Traits<ST>::C (&f)[NS][9]) {
+    constexpr int RS = 9 * NS * EW;
+    const typename Traits<ST>::T *b = L + (ly - 1) * RS + (lx - 1);
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f[s][i] = decode_dev<ST>(b[(1 - kEy[i]) * RS + (s * 9 + i) * EW + (1 - kEx[i])]);
+}
+template <int ST, int NS, int EW>
+__device__ __forceinline__ void put_lds(typename Traits<ST>::T *L, int lx, int ly,
+                                        const typename Traits<ST>::T (&o)[NS][9]) {
+    constexpr int RS = 9 * NS * EW;
+    typename Traits<ST>::T *b = L + ly * RS + lx;
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int i = 0; i < 9; ++i) b[(s * 9 + i) * EW] = o[s][i];
+}
+
+// TS time steps per launch on a tile of TW x th sites (temporal blocking).
+// The workgroup keeps a (TW + 2h) x (th + 2h) region in LDS, h = TS - 1.
+// Phase 1 reads step t from the source buffer (pulling across the region's
+// edge), collides, and writes the post-collision values of step t+1 on the
+// whole region to LDS.  Each middle phase j = 2 .. TS-1 advances the region
+// shrunk by j-1 sites on every side, in place: every thread first pulls the
+// inputs of its sites into registers (MAXK sites, 1 or 2), the workgroup
+// synchronises, then the threads collide and overwrite LDS.  The last phase
+// pulls from LDS, collides on the tile itself and stores step t+TS.  Per TS
+// steps the buffer is read once (tile plus an h+1 halo) and written once.
+// Every site runs the arithmetic of the one-step kernel on the same encoded
+// inputs, so the result is bitwise identical to TS one-step launches.
+// Requires the buffer to span less than 4 GiB (32-bit byte offsets).
+template <int ST, int V, int TS, int MAXK, int TW>
+__global__ __launch_bounds__(MAXK == 1 ? 1024 : 512) void k_stepT(GridT g, Params<typename Traits<ST>::C> p) {
     using T = typename Traits<ST>::T;
     using C = typename Traits<ST>::C;
     constexpr int NS = NSpecies<V>::value;
+    constexpr int H = TS - 1;
+    constexpr int EW = TW + 2 * H;
+    constexpr uint32_t B = sizeof(T);
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     T *L = reinterpret_cast<T *>(smem);
-    const T *__restrict__ src = static_cast<const T *>(g.src);
-    T *__restrict__ dst = static_cast<T *>(g.dst);
-    const int ew = g.tw + 2, eh = g.th + 2, esz = ew * eh, tsz = g.tw * g.th;
+    const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(g.src, g.bytes);
+    const __amdgpu_buffer_rsrc_t rd = buffer_rsrc(g.dst, g.bytes);
+    const int nx = g.nx, ny = g.ny, th = g.th;
+    const int eh = th + 2 * H, esz = EW * eh, tsz = TW * th;
+    const uint32_t pitch_b = (uint32_t)g.pitch * B, pstride_b = (uint32_t)g.pstride * B;
+    const bool one_wrap = nx >= TW + H && ny >= th + H;   // the region wraps at most once per axis
+    const int nthr = blockDim.x;
+    const int dx = nthr % EW, dy = nthr / EW;
+    const int ex0 = (int)threadIdx.x % EW, ey0 = (int)threadIdx.x / EW;
     const int b0 = g.xcd_order ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     for (int64_t tile = b0; tile < g.ntiles; tile += gridDim.x) {
         const int tx = (int)(tile % g.ntx), ty = (int)(tile / g.ntx);
-        const int x0 = tx * g.tw, y0 = ty * g.th;
-        // phase 1: step t -> t+1 on the tile and its halo, into LDS
-        for (int q = threadIdx.x; q < esz; q += blockDim.x) {
-            const int ex = q % ew, ey = q / ew;
-            const int gx = wrap_mod(x0 - 1 + ex, g.nx), gy = wrap_mod(y0 - 1 + ey, g.ny);
-            const int xm = gx == 0 ? g.nx - 1 : gx - 1, xp = gx + 1 == g.nx ? 0 : gx + 1;
-            const int ym = gy == 0 ? g.ny - 1 : gy - 1, yp = gy + 1 == g.ny ? 0 : gy + 1;
-            C f[NS][9];
-#pragma unroll
-            for (int s = 0; s < NS; ++s)
-#pragma unroll
-                for (int i = 0; i < 9; ++i) {
-                    const int col = kEx[i] == 1 ? xm : (kEx[i] == -1 ? xp : gx);
-                    const int row = kEy[i] == 1 ? ym : (kEy[i] == -1 ? yp : gy);
-                    f[s][i] = decode_dev<ST>(
-                        load_one<T, NT>(src + (int64_t)(s * 9 + i) * g.pstride + (int64_t)row * g.pitch + col));
-                }
-            T o[NS][9];
-            collide_site<ST, V>(p, f, o);
-#pragma unroll
-            for (int s = 0; s < NS; ++s)
-#pragma unroll
-                for (int i = 0; i < 9; ++i) L[(s * 9 + i) * esz + q] = o[s][i];
-        }
-        __syncthreads();
-        // phase 2: step t+1 -> t+2 on the tile, pulling from LDS
-        for (int q = threadIdx.x; q < tsz; q += blockDim.x) {
-            const int lx = q % g.tw, ly = q / g.tw;
-            const int gx = x0 + lx, gy = y0 + ly;
+        const int x0 = tx * TW, y0 = ty * th;
+        // phase 1: step t -> t+1 on the whole region, from the source buffer
+        int ex = ex0, ey = ey0;
+        for (int q = threadIdx.x; q < esz; q += nthr) {
+            int gx = x0 - H + ex, gy = y0 - H + ey;
+            if (one_wrap) {
+                gx += gx < 0 ? nx : 0;
+                gx -= gx >= nx ? nx : 0;
+                gy += gy < 0 ? ny : 0;
+                gy -= gy >= ny ? ny : 0;
+            } else {
+                gx = wrap_mod(gx, nx);
+                gy = wrap_mod(gy, ny);
+            }
+            // byte offsets of columns x-1, x, x+1 and rows y-1, y, y+1
+            const uint32_t cx[3] = {(uint32_t)(gx == 0 ? nx - 1 : gx - 1) * B, (uint32_t)gx * B,
+                                    (uint32_t)(gx + 1 == nx ? 0 : gx + 1) * B};
+            const uint32_t ry[3] = {mul24(gy == 0 ? ny - 1 : gy - 1, pitch_b), mul24(gy, pitch_b),
+                                    mul24(gy + 1 == ny ? 0 : gy + 1, pitch_b)};
             C f[NS][9];
 #pragma unroll
             for (int s = 0; s < NS; ++s)
 #pragma unroll
                 for (int i = 0; i < 9; ++i)
-                    f[s][i] = decode_dev<ST>(L[(s * 9 + i) * esz + (ly + 1 - kEy[i]) * ew + (lx + 1 - kEx[i])]);
+                    f[s][i] = decode_dev<ST>(buf_load<T>(rs, ry[1 - kEy[i]] + cx[1 - kEx[i]], (uint32_t)(s * 9 + i) * pstride_b));
             T o[NS][9];
             collide_site<ST, V>(p, f, o);
-            if (gx < g.nx && gy < g.ny) {
+            put_lds<ST, NS, EW>(L, ex, ey, o);
+            ex += dx;
+            ey += dy;
+            if (ex >= EW) {
+                ex -= EW;
+                ++ey;
+            }
+        }
+        __syncthreads();
+        // middle phases: step t+j-1 -> t+j on the region shrunk by j-1, in LDS
+#pragma unroll
+        for (int j = 2; j < TS; ++j) {
+            const int rw = EW - 2 * (j - 1), rsz = rw * (eh - 2 * (j - 1));
+            C f[MAXK][NS][9];
+#pragma unroll
+            for (int k = 0; k < MAXK; ++k) {
+                const int q = threadIdx.x + k * nthr;
+                if (q < rsz) gather_lds<ST, NS, EW>(L, q % rw + j - 1, q / rw + j - 1, f[k]);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < MAXK; ++k) {
+                const int q = threadIdx.x + k * nthr;
+                if (q < rsz) {
+                    T o[NS][9];
+                    collide_site<ST, V>(p, f[k], o);
+                    put_lds<ST, NS, EW>(L, q % rw + j - 1, q / rw + j - 1, o);
+                }
+            }
+            __syncthreads();
+        }
+        // last phase: step t+TS-1 -> t+TS on the tile, to the destination buffer
+        for (int q = threadIdx.x; q < tsz; q += nthr) {
+            const int lx = q % TW, ly = q / TW;
+            const int gx = x0 + lx, gy = y0 + ly;
+            C f[NS][9];
+            gather_lds<ST, NS, EW>(L, lx + H, ly + H, f);
+            T o[NS][9];
+            collide_site<ST, V>(p, f, o);
+            if (gx < nx && gy < ny) {
+                const uint32_t off = mul24(gy, pitch_b) + (uint32_t)gx * B;
 #pragma unroll
                 for (int s = 0; s < NS; ++s)
 #pragma unroll
-                    for (int i = 0; i < 9; ++i)
-                        store_one<T, NT>(dst + (int64_t)(s * 9 + i) * g.pstride + (int64_t)gy * g.pitch + gx, o[s][i]);
+                    for (int i = 0; i < 9; ++i) buf_store<T>(rd, off, (uint32_t)(s * 9 + i) * pstride_b, o[s][i]);
             }
         }
         __syncthreads();   // LDS is reused by the next tile

@@ -75,9 +75,10 @@ struct Grid {
 
 Grid make_grid(const Layout &L, const void *src, void *dst, int vec, int lanes_x);
 
-// Geometry of a two-step (temporally blocked) launch: tiles of tw x th sites,
-// one workgroup per tile (or a persistent grid of `blocks` workgroups).
-struct Grid2 {
+// Geometry of a launch that advances `steps` time steps (temporal blocking):
+// tiles of tw x th sites, one workgroup per tile (or a persistent grid of
+// `blocks` workgroups).
+struct GridT {
     const void *src;
     void *dst;
     int nx, ny;
@@ -87,11 +88,22 @@ struct Grid2 {
     int64_t ntiles;
     int blocks;
     int xcd_order;
+    int steps;        // 2 .. kMaxFusedSteps
+    uint32_t bytes;   // bytes of one buffer (less than 4 GiB)
 };
 
-Grid2 make_grid2(const Layout &L, const void *src, void *dst, int tw, int th);
-// LDS bytes a two-step launch needs.
-size_t step2_lds_bytes(int storage, int nspecies, int tw, int th);
+constexpr int kMaxFusedSteps = 4;
+
+GridT make_gridT(const Layout &L, const void *src, void *dst, int tw, int th, int steps);
+// LDS bytes of a launch of `steps` steps on tw x th tiles.
+size_t stepT_lds_bytes(int storage, int nspecies, int tw, int th, int steps);
+// Sites per thread that the middle phases of a multi-step launch hold in
+// registers: the largest middle region over the workgroup's threads, rounded
+// up (0 for two steps, which have no middle phase).  Launch shapes that need
+// more than 2 are rejected; 2 needs at most 8 waves (a 512-thread register
+// budget).
+int stepT_sites_per_thread(int tw, int th, int steps, int waves);
+bool stepT_shape_fits(int storage, int nspecies, int tw, int th, int steps, int waves);
 
 // ------------------------------------------------------------ launchers --
 
@@ -107,12 +119,12 @@ hipError_t launch_step_f32(const StepLaunch &sl, const Grid &g, const void *para
 hipError_t launch_step_f16(const StepLaunch &sl, const Grid &g, const void *params, hipStream_t st);
 hipError_t launch_step_bf16(const StepLaunch &sl, const Grid &g, const void *params, hipStream_t st);
 hipError_t launch_step(const StepLaunch &sl, const Grid &g, const void *params, hipStream_t st);
-// Two steps src -> dst (one launch).
-hipError_t launch_step2_f64(const StepLaunch &sl, const Grid2 &g, const void *params, hipStream_t st);
-hipError_t launch_step2_f32(const StepLaunch &sl, const Grid2 &g, const void *params, hipStream_t st);
-hipError_t launch_step2_f16(const StepLaunch &sl, const Grid2 &g, const void *params, hipStream_t st);
-hipError_t launch_step2_bf16(const StepLaunch &sl, const Grid2 &g, const void *params, hipStream_t st);
-hipError_t launch_step2(const StepLaunch &sl, const Grid2 &g, const void *params, hipStream_t st);
+// g.steps time steps src -> dst in one launch.
+hipError_t launch_stepT_f64(const StepLaunch &sl, const GridT &g, const void *params, hipStream_t st);
+hipError_t launch_stepT_f32(const StepLaunch &sl, const GridT &g, const void *params, hipStream_t st);
+hipError_t launch_stepT_f16(const StepLaunch &sl, const GridT &g, const void *params, hipStream_t st);
+hipError_t launch_stepT_bf16(const StepLaunch &sl, const GridT &g, const void *params, hipStream_t st);
+hipError_t launch_stepT(const StepLaunch &sl, const GridT &g, const void *params, hipStream_t st);
 bool step_shape_valid(int storage, int vec, int lanes_x, int waves);
 
 hipError_t launch_init(int storage, const Layout &L, const void *params, const void *rho0, int dtype, void *dst,

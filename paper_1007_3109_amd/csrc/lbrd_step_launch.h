@@ -47,14 +47,14 @@ inline hipError_t launch_step_s(const StepLaunch &sl, const Grid &g, const void 
     }
 }
 
-template <int ST, int V, bool NT>
-inline hipError_t launch_step2_t(const StepLaunch &sl, const Grid2 &g, const void *params, hipStream_t st) {
+template <int ST, int V, int TS, int MAXK, int TW>
+inline hipError_t launch_stepT_t(const StepLaunch &sl, const GridT &g, const void *params, hipStream_t st) {
     using C = typename Traits<ST>::C;
     const Params<C> &p = *static_cast<const Params<C> *>(params);
-    const size_t lds = step2_lds_bytes(ST, NSpecies<V>::value, g.tw, g.th);
+    const size_t lds = stepT_lds_bytes(ST, NSpecies<V>::value, TW, g.th, TS);
     static bool attr_set = false;   // per instantiation: allow more than 64 KB of LDS
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_step2<ST, V, NT>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_stepT<ST, V, TS, MAXK, TW>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
         attr_set = true;
@@ -62,25 +62,45 @@ inline hipError_t launch_step2_t(const StepLaunch &sl, const Grid2 &g, const voi
     int64_t nb = g.ntiles;
     if (g.blocks > 0 && g.blocks < nb) nb = g.blocks;
     if (nb > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_step2<ST, V, NT>), dim3((unsigned)nb), dim3(64 * sl.waves), lds, st, g, p);
+    hipLaunchKernelGGL((k_stepT<ST, V, TS, MAXK, TW>), dim3((unsigned)nb), dim3(64 * sl.waves), lds, st, g, p);
     return hipGetLastError();
 }
 
-template <int ST, bool NT>
-inline hipError_t launch_step2_v(const StepLaunch &sl, const Grid2 &g, const void *params, hipStream_t st) {
-    switch (sl.variant) {
-        case kLin1: return launch_step2_t<ST, kLin1, NT>(sl, g, params, st);
-        case kLin2: return launch_step2_t<ST, kLin2, NT>(sl, g, params, st);
-        case kLin3: return launch_step2_t<ST, kLin3, NT>(sl, g, params, st);
-        case kLin4: return launch_step2_t<ST, kLin4, NT>(sl, g, params, st);
-        case kGS: return launch_step2_t<ST, kGS, NT>(sl, g, params, st);
+template <int ST, int V, int TW>
+inline hipError_t launch_stepT_n(const StepLaunch &sl, const GridT &g, const void *params, hipStream_t st) {
+    static_assert(kMaxFusedSteps == 4, "instantiate every step count");
+    const bool two = stepT_sites_per_thread(TW, g.th, g.steps, sl.waves) == 2;
+    switch (g.steps) {
+        case 2: return launch_stepT_t<ST, V, 2, 1, TW>(sl, g, params, st);
+        case 3: return two ? launch_stepT_t<ST, V, 3, 2, TW>(sl, g, params, st)
+                           : launch_stepT_t<ST, V, 3, 1, TW>(sl, g, params, st);
+        case 4: return two ? launch_stepT_t<ST, V, 4, 2, TW>(sl, g, params, st)
+                           : launch_stepT_t<ST, V, 4, 1, TW>(sl, g, params, st);
         default: return hipErrorInvalidValue;
     }
 }
 
+template <int ST, int V>
+inline hipError_t launch_stepT_w(const StepLaunch &sl, const GridT &g, const void *params, hipStream_t st) {
+    if (!stepT_shape_fits(ST, NSpecies<V>::value, g.tw, g.th, g.steps, sl.waves)) return hipErrorInvalidValue;
+    switch (g.tw) {
+        case 64: return launch_stepT_n<ST, V, 64>(sl, g, params, st);
+        case 128: return launch_stepT_n<ST, V, 128>(sl, g, params, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// The multi-step kernel uses cached accesses whatever sl.nontemporal says.
 template <int ST>
-inline hipError_t launch_step2_s(const StepLaunch &sl, const Grid2 &g, const void *params, hipStream_t st) {
-    return sl.nontemporal ? launch_step2_v<ST, true>(sl, g, params, st) : launch_step2_v<ST, false>(sl, g, params, st);
+inline hipError_t launch_stepT_s(const StepLaunch &sl, const GridT &g, const void *params, hipStream_t st) {
+    switch (sl.variant) {
+        case kLin1: return launch_stepT_w<ST, kLin1>(sl, g, params, st);
+        case kLin2: return launch_stepT_w<ST, kLin2>(sl, g, params, st);
+        case kLin3: return launch_stepT_w<ST, kLin3>(sl, g, params, st);
+        case kLin4: return launch_stepT_w<ST, kLin4>(sl, g, params, st);
+        case kGS: return launch_stepT_w<ST, kGS>(sl, g, params, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace lbrd

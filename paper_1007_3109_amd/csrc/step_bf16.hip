@@ -7,8 +7,8 @@ hipError_t launch_step_bf16(const StepLaunch &sl, const Grid &g, const void *par
     return launch_step_s<kBF16>(sl, g, params, st);
 }
 
-hipError_t launch_step2_bf16(const StepLaunch &sl, const Grid2 &g, const void *params, hipStream_t st) {
-    return launch_step2_s<kBF16>(sl, g, params, st);
+hipError_t launch_stepT_bf16(const StepLaunch &sl, const GridT &g, const void *params, hipStream_t st) {
+    return launch_stepT_s<kBF16>(sl, g, params, st);
 }
 
 }  // namespace lbrd

@@ -7,8 +7,8 @@ hipError_t launch_step_f16(const StepLaunch &sl, const Grid &g, const void *para
     return launch_step_s<kF16>(sl, g, params, st);
 }
 
-hipError_t launch_step2_f16(const StepLaunch &sl, const Grid2 &g, const void *params, hipStream_t st) {
-    return launch_step2_s<kF16>(sl, g, params, st);
+hipError_t launch_stepT_f16(const StepLaunch &sl, const GridT &g, const void *params, hipStream_t st) {
+    return launch_stepT_s<kF16>(sl, g, params, st);
 }
 
 }  // namespace lbrd

@@ -20,7 +20,6 @@ from paper_1007_3109_amd import workloads  # noqa: E402
 if torch.cuda.is_available():
     from paper_1007_3109_amd import lbrd  # noqa: E402
 
-BATCH_VEC = {"f64": 2, "f32": 4, "f16": 4, "bf16": 4}
 
 
 def log(msg):
@@ -28,9 +27,10 @@ def log(msg):
 
 
 def solo(cfg, rho0, steps):
+    """A single solver with its default launch shape (several steps per
+    launch): the batched and served results must equal it bitwise."""
     s = lbrd.Solver(cfg)
-    storage = {v: k for k, v in lbrd.STORAGE.items()}[cfg.storage]
-    s.set_tuning(vec=BATCH_VEC[storage], lanes_x=0, waves=4, graph_steps=0)
+    s.set_tuning(graph_steps=0)
     s.init(rho0).step(steps)
     return s.moments()[0]
 

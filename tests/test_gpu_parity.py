@@ -383,23 +383,43 @@ def test_gray_scott_4096_sampled_windows(storage, quant):
         assert np.all(err <= fmt)
 
 
-# ----- two steps per launch (temporal blocking) ------------------------------
+# ----- several steps per launch (temporal blocking) -------------------------
 
 FUSED_CASES = [("f64", "gray_scott", 2), ("f32", "gray_scott", 2), ("f16", "gray_scott", 2), ("bf16", "gray_scott", 2),
-               ("f32", "linear", 1), ("f32", "linear", 3), ("f16", "linear", 1)]
+               ("f32", "linear", 1), ("f32", "linear", 3), ("f16", "linear", 1), ("f64", "linear", 4)]
+
+
+def multi_step_shape_fits(b, ns, cols, rows, steps, waves):
+    """The documented limits of a multi-step launch shape: 64 or 128 columns,
+    the LDS region (cols + 2h) x (rows + 2h) x 9 ns values (h = steps - 1)
+    within 160 KB, and the second phase's region (two sites smaller per axis)
+    within 1 site per thread, or 2 with at most 8 waves."""
+    if cols not in (64, 128):
+        return False
+    h = steps - 1
+    if 9 * ns * (cols + 2 * h) * (rows + 2 * h) * b > 160 * 1024:
+        return False
+    if steps == 2:
+        return True
+    k = -(-((cols + 2 * h - 2) * (rows + 2 * h - 2)) // (64 * waves))
+    return k <= 1 or (k == 2 and waves <= 8)
 
 
 @pytest.mark.parametrize("storage,reaction,ns", FUSED_CASES)
-def test_two_step_launch_is_bitwise_identical(storage, reaction, ns):
-    """The LDS-tiled two-step launch runs each site's arithmetic exactly as the
-    one-step launch, so every population after 7 steps (three two-step
-    launches and one one-step launch) is bitwise equal, on ragged and tiny
-    lattices, for several tile heights and workgroup sizes."""
+def test_multi_step_launch_is_bitwise_identical(storage, reaction, ns):
+    """The LDS-tiled multi-step launch runs each site's arithmetic exactly as
+    the one-step launch, so every population after 7 steps (T-step launches, a
+    shorter launch for a remainder of 2 .. T-1, a one-step launch for a single
+    remaining step) is bitwise equal, on ragged and tiny lattices, for 2, 3 and
+    4 steps per launch, both tile widths, several heights and workgroup
+    sizes.  Shapes beyond the documented limits are rejected with EINVAL."""
+    b = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[storage]
+    ran = 0
     for ny, nx in [(1, 1), (3, 3), (2, 5), (45, 67), (33, 130), (17, 257)]:
         rng = np.random.default_rng(nx * 7 + ny)
         kw = dict(F=0.04, k=0.06) if reaction == "gray_scott" else dict(K=-0.01 * np.eye(ns))
         rref = (0.3,) * ns
-        cfg = lbrd.make_config(nx, ny, ns, tau=[0.7, 1.2, 0.9][:ns], storage=storage, reaction=reaction,
+        cfg = lbrd.make_config(nx, ny, ns, tau=[0.7, 1.2, 0.9, 0.8][:ns], storage=storage, reaction=reaction,
                                rho_ref=rref, **kw)
         f0 = rng.uniform(0.0, 0.1, size=(ns, 9, ny, nx))
         ref = lbrd.Solver(cfg)
@@ -407,25 +427,34 @@ def test_two_step_launch_is_bitwise_identical(storage, reaction, ns):
         ref.set_populations(f0).step(7)
         want = ref.get_populations()
         s = lbrd.Solver(cfg)
-        b = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[storage]
-        for rows in (1, 8, 16):
-            if 9 * ns * 66 * (rows + 2) * b > 160 * 1024:
-                continue                      # the tile would not fit in LDS
-            for waves in (4, 16):
-                s.set_tuning(fused_steps=2, tile_rows=rows, waves=waves, graph_steps=0)
-                s.set_populations(f0).step(7)
-                assert torch.equal(s.get_populations(), want), (ny, nx, rows, waves)
+        for steps in (2, 3, 4):
+            for cols, rows in ((64, 1), (64, 8), (64, 16), (128, 2), (128, 8)):
+                for waves in (4, 8, 16):
+                    if not multi_step_shape_fits(b, ns, cols, rows, steps, waves):
+                        with pytest.raises(lbrd.LbrdError):
+                            s.set_tuning(fused_steps=steps, tile_cols=cols, tile_rows=rows, waves=waves,
+                                         graph_steps=0)
+                        continue
+                    s.set_tuning(fused_steps=steps, tile_cols=cols, tile_rows=rows, waves=waves, graph_steps=0)
+                    s.set_populations(f0).step(7)
+                    assert torch.equal(s.get_populations(), want), (ny, nx, steps, cols, rows, waves)
+                    ran += 1
         assert s.time() == 7
+        for cols in (32, 96, 256):                    # widths the kernel does not take
+            with pytest.raises(lbrd.LbrdError):
+                s.set_tuning(fused_steps=2, tile_cols=cols, tile_rows=2, waves=4, graph_steps=0)
+    log(f"multi-step {storage} {reaction} N={ns}: {ran} shapes bitwise equal")
+    assert ran >= 30
 
 
-def test_two_step_launch_with_graphs_and_oracle():
+def test_multi_step_launch_with_graphs_and_oracle():
     rho0 = workloads.gray_scott_square(200, 160, seed=7)
     kw = dict(F=workloads.GS_F, k=workloads.GS_K)
     cfg = lbrd.make_config(200, 160, 2, tau=workloads.GS_TAU, storage="f32", reaction="gray_scott", **kw)
     a = lbrd.Solver(cfg)
     a.set_tuning(fused_steps=1, graph_steps=0)
     b = lbrd.Solver(cfg)
-    b.set_tuning(fused_steps=2, tile_rows=16, waves=16, graph_steps=6)   # graphs of 3 fused launches
+    b.set_tuning(fused_steps=3, tile_rows=8, tile_cols=64, waves=8, graph_steps=8)   # 3 + 3 + 2 per graph
     a.init(rho0)
     b.init(rho0)
     for n in (13, 6, 31, 2):
