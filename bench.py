@@ -161,7 +161,9 @@ def batch_leg(torch, lbrd, workloads, steps, warmup, seed=0):
     ms = b.time_steps(steps)
     species_sites = sum(2 * i.side * i.side for i in insts)
     mlups = species_sites * steps / (ms / 1e3) / 1e6
-    gbs = species_sites * 72 * steps / (ms / 1e3) / 1e9
+    spl = t.fused_steps
+    # per launch: the state of every instance read once and written once
+    gbs = species_sites * 72 * steps / spl / (ms / 1e3) / 1e9
     # the plain single-lattice kernel on the same instances, one after another
     solo_ms = 0.0
     solo_steps = 20
@@ -176,8 +178,9 @@ def batch_leg(torch, lbrd, workloads, steps, warmup, seed=0):
     solo_mlups = species_sites * solo_steps / (solo_ms / 1e3) / 1e6
     out = {"workload": f"{len(insts)} Gray-Scott instances, sides {sorted(set(i.side for i in insts))}, FP32",
            "species_sites": species_sites, "steps": steps, "ms_per_step": round(ms / steps, 4),
-           "mlups_per_species": round(mlups, 1), "achieved_GBs": round(gbs, 1),
-           "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4), "tuning": t.as_dict(),
+           "mlups_per_species": round(mlups, 1), "steps_per_launch": spl, "achieved_GBs": round(gbs, 1),
+           "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4), "one_step_equivalent_GBs": round(gbs * spl, 1),
+           "tuning": t.as_dict(),
            "plain_kernel_one_by_one_mlups_per_species": round(solo_mlups, 1)}
     b.close()
     del b
@@ -190,11 +193,12 @@ def serve_leg(torch, lbrd, workloads, n_requests, pool_gb, steps_range, seed=0, 
     import threading
 
     if rate is None:
-        # offered load near the measured single-kernel throughput: mean work per
-        # request / 8e10 species-site-steps per second, at 85% utilisation
+        # offered load near the server's measured throughput (about 2e11
+        # species-site-steps per second with four steps per launch): mean work
+        # per request / 2e11, at 85% utilisation
         e_side2 = (2048 ** 2 - 64 ** 2) / (2 * math.log(32))
         e_work = 1.5 * e_side2 * (steps_range[0] + steps_range[1]) / 2
-        rate = 0.85 * 8e10 / e_work
+        rate = 0.85 * 2e11 / e_work
     reqs = workloads.request_stream(n_requests, rate, seed=seed, steps_range=steps_range)
     cfgs, inits = [], []
     for r in reqs:
@@ -443,7 +447,7 @@ def main():
                                                        tune=args.tune)
         if "batch" in legs:
             log("bench: batched sweep")
-            extra["batched"] = batch_leg(torch, lbrd, workloads, 200, 10)
+            extra["batched"] = batch_leg(torch, lbrd, workloads, 2000, 32)
         if "serve" in legs:
             log("bench: serving")
             extra["serving"] = serve_leg(torch, lbrd, workloads, args.serve_requests, 16, (1000, 10000))

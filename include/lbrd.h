@@ -107,12 +107,12 @@ typedef struct lbrd_config {
  *       (temporal blocking; a remainder of 2 .. T-1 steps runs as one shorter
  *       launch on the same tiles, a single remaining step as a one-step
  *       launch).  Results are bitwise identical for every setting.
- *  tile_rows, tile_cols: multi-step tile, rows 1..64 and columns 8..512; the
+ *  tile_rows, tile_cols: multi-step tile, rows 1..64 and columns 64 or 128; the
  *       region (tile_cols + 2(T-1)) x (tile_rows + 2(T-1)) x 9 N populations
  *       must fit in 160 KB of LDS and, for T >= 3, the second phase's region
- *       (two sites smaller per axis) must not exceed the workgroup's
- *       register budget (64 * waves threads x 1..4 sites, fewer for more
- *       species or FP64).  Ignored when fused_steps = 1. */
+ *       (two sites smaller per axis) must not exceed 64 * waves threads x 1
+ *       site, or x 4 sites with at most 8 waves.  Ignored when
+ *       fused_steps = 1. */
 typedef struct lbrd_tuning {
     int32_t vec;
     int32_t lanes_x;

@@ -56,7 +56,7 @@ bool stepT_shape_fits(int storage, int nspecies, int tw, int th, int steps, int 
         return false;
     if (stepT_lds_bytes(storage, nspecies, tw, th, steps) > (size_t)160 * 1024) return false;
     const int k = stepT_sites_per_thread(tw, th, steps, waves);
-    return k <= 1 || (k == 2 && waves <= 8);
+    return k <= 1 || (k <= 4 && waves <= 8);
 }
 
 hipError_t launch_step(const StepLaunch &sl, const Grid &g, const void *params, hipStream_t st) {

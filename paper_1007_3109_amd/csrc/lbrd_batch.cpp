@@ -71,6 +71,7 @@ struct lbrd_batch {
     hipGraphExec_t graph = nullptr;
     int graph_steps_built = 0;
     int64_t t = 0;
+    bool multi_ok = false;          // every instance can take multi-step launches
 };
 
 namespace {
@@ -86,10 +87,39 @@ void drop_graph(lbrd_batch *b) {
     b->graph_steps_built = 0;
 }
 
-int blocks_of(const lbrd_batch *b) {
+int steps_per_launch(const lbrd_batch *b) { return b->tune.fused_steps; }
+
+int64_t blocks_of(const lbrd_batch *b) {
+    if (steps_per_launch(b) > 1) {
+        // one workgroup per tile, or a persistent grid of blocks_per_cu per CU
+        const int64_t need = b->total_tiles;
+        if (b->tune.blocks_per_cu == 0) return std::max<int64_t>(1, need);
+        return std::max<int64_t>(1, std::min<int64_t>((int64_t)b->tune.blocks_per_cu * b->cus, need));
+    }
     int64_t blocks = (int64_t)b->tune.blocks_per_cu * b->cus;
     const int64_t need = (b->total_tiles + b->tune.waves - 1) / b->tune.waves;
-    return (int)std::max<int64_t>(1, std::min(blocks, need));
+    return std::max<int64_t>(1, std::min(blocks, need));
+}
+
+// Tile every instance for the current launch kind and lay the tiles out one
+// instance after another; the header follows on the batch stream.
+hipError_t retile(lbrd_batch *b) {
+    int64_t tiles = 0;
+    for (int i = 0; i < b->count; ++i) {
+        BatchInst &bi = b->inst[i];
+        set_batch_tiling(bi, b->L[i], steps_per_launch(b), b->tune.tile_rows);
+        bi.tile_begin = tiles;
+        tiles += bi.ntiles;
+    }
+    b->total_tiles = tiles;
+    b->dirty = true;
+    BatchHeader h;
+    std::memset(&h, 0, sizeof(h));
+    h.count = b->count;
+    h.total_tiles = tiles;
+    hipError_t e = hipMemcpyAsync(b->d_hdr, &h, sizeof(h), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    return e;
 }
 
 hipError_t upload(lbrd_batch *b, int steps) {
@@ -104,10 +134,15 @@ hipError_t upload(lbrd_batch *b, int steps) {
                           b->stream);
 }
 
-hipError_t enqueue(lbrd_batch *b, int n, hipStream_t st) {
-    for (int j = 0; j < n; ++j) {
-        hipError_t e = launch_batch_step(b->d_hdr, b->d_inst, j, blocks_of(b), b->tune.waves, b->tune.nontemporal != 0,
-                                         b->set, st);
+// Enqueue the launches j = 0 .. launches-1 of a chunk.
+hipError_t enqueue(lbrd_batch *b, int64_t launches, hipStream_t st) {
+    const int ts = steps_per_launch(b);
+    for (int64_t j = 0; j < launches; ++j) {
+        hipError_t e =
+            ts > 1 ? launch_batch_stepT(b->d_hdr, b->d_inst, (int)j, blocks_of(b), b->tune.waves, ts, b->tune.tile_rows,
+                                        b->set, st)
+                   : launch_batch_step(b->d_hdr, b->d_inst, (int)j, (int)blocks_of(b), b->tune.waves,
+                                       b->tune.nontemporal != 0, b->set, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -118,7 +153,7 @@ hipError_t build_graph(lbrd_batch *b) {
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
-    hipError_t le = enqueue(b, b->tune.graph_steps, b->capture);
+    hipError_t le = enqueue(b, launches_for(b->tune.graph_steps, steps_per_launch(b)), b->capture);
     e = hipStreamEndCapture(b->capture, &g);
     if (le != hipSuccess) {
         if (g) hipGraphDestroy(g);
@@ -131,10 +166,18 @@ hipError_t build_graph(lbrd_batch *b) {
     return e;
 }
 
-bool batch_tuning_valid(const lbrd_tuning &t) {
-    return (t.waves == 1 || t.waves == 2 || t.waves == 4) && t.blocks_per_cu >= 1 && t.blocks_per_cu <= 32 &&
-           (t.nontemporal == 0 || t.nontemporal == 1) && t.graph_steps >= 0 && !(t.graph_steps & 1) &&
-           t.graph_steps <= 4096;
+bool batch_tuning_valid(const lbrd_batch *b, const lbrd_tuning &t) {
+    if (t.nontemporal != 0 && t.nontemporal != 1) return false;
+    if (t.graph_steps < 0 || t.graph_steps > 4096) return false;
+    if (t.fused_steps == 1)
+        return (t.waves == 1 || t.waves == 2 || t.waves == 4) && t.blocks_per_cu >= 1 && t.blocks_per_cu <= 32 &&
+               !(t.graph_steps & 1);
+    // multi-step launches: an even number of launches per captured chunk, so
+    // every instance ends a chunk in the buffer it started from
+    if (!b->multi_ok || t.fused_steps < 2 || t.fused_steps > kMaxFusedSteps) return false;
+    if (t.graph_steps % (2 * t.fused_steps)) return false;
+    if (t.blocks_per_cu < 0 || t.blocks_per_cu > 32) return false;
+    return stepT_shape_fits(kF32, 2, 64, t.tile_rows, t.fused_steps, t.waves);
 }
 
 const void *params_of(const lbrd_batch *b, int idx) {
@@ -170,7 +213,6 @@ int lbrd_batch_create(const lbrd_config *cfgs, int count, void *workspace, size_
     b->d_inst = reinterpret_cast<BatchInst *>(base + p.inst_off);
     b->partials = reinterpret_cast<double *>(base + p.scratch_off);
     b->result = b->partials + (size_t)kRedBlocks * kRedSlots;
-    int64_t tiles = 0;
     for (int i = 0; i < count; ++i) {
         const lbrd_config c = normalise(cfgs[i]);
         const Layout L = make_layout(c);
@@ -178,29 +220,34 @@ int lbrd_batch_create(const lbrd_config *cfgs, int count, void *workspace, size_
         const int vec = batch_vec(c.storage);
         BatchInst bi;
         fill_batch_inst(bi, c, L, b0, b0 + L.buf_bytes, vec, default_lanes(c.nx, vec));
-        bi.tile_begin = tiles;
         bi.cur = 0;
-        tiles += bi.ntiles;
         b->cfg.push_back(c);
         b->L.push_back(L);
         b->inst.push_back(bi);
     }
     b->initialised.assign(count, 0);
     b->tinst.assign(count, 0);
-    b->total_tiles = tiles;
     b->set = pick_set(b->cfg);
     b->cus = device_cu_count();
+    b->multi_ok = b->set != kBatchAny;
+    for (int i = 0; i < count; ++i)
+        if (!batch_multi_ok(b->L[i], b->cfg[i].storage)) b->multi_ok = false;
     std::memset(&b->tune, 0, sizeof(b->tune));
-    b->tune.waves = 4;
-    b->tune.blocks_per_cu = 8;
-    b->tune.graph_steps = 16;
-    b->tune.fused_steps = 1;
-    BatchHeader h;
-    std::memset(&h, 0, sizeof(h));
-    h.count = count;
-    h.total_tiles = tiles;
-    hipError_t e = hipMemcpyAsync(b->d_hdr, &h, sizeof(h), hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (b->multi_ok) {
+        // four steps per launch on 64 x 8 tiles, one workgroup of 8 waves per
+        // tile (the single-lattice default beyond the Infinity Cache)
+        b->tune.fused_steps = 4;
+        b->tune.tile_rows = 8;
+        b->tune.waves = 8;
+        b->tune.blocks_per_cu = 0;
+        b->tune.graph_steps = 32;
+    } else {
+        b->tune.fused_steps = 1;
+        b->tune.waves = 4;
+        b->tune.blocks_per_cu = 8;
+        b->tune.graph_steps = 16;
+    }
+    hipError_t e = retile(b);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
     if (e != hipSuccess) {
         delete b;
@@ -266,10 +313,11 @@ int lbrd_batch_step(lbrd_batch *b, int64_t nsteps) {
     }
     while (left > 0) {
         const int n = (int)std::min<int64_t>(left, 1 << 20);
+        const int64_t launches = launches_for(n, steps_per_launch(b));
         hipError_t e = upload(b, n);
-        if (e == hipSuccess) e = enqueue(b, n, b->stream);
+        if (e == hipSuccess) e = enqueue(b, launches, b->stream);
         if (e != hipSuccess) return fail("batch step", e);
-        if (n & 1) {
+        if (launches & 1) {
             for (auto &bi : b->inst) bi.cur ^= 1;
             b->dirty = true;
         }
@@ -287,7 +335,8 @@ int lbrd_batch_advance(lbrd_batch *b, const int64_t *nsteps) {
         if (nsteps[i] > 0 && !b->initialised[i]) return LBRD_ESTATE;
     }
     std::vector<int64_t> left(nsteps, nsteps + b->count);
-    const int chunk = b->tune.graph_steps > 0 ? b->tune.graph_steps : 64;
+    const int ts = steps_per_launch(b);
+    const int chunk = b->tune.graph_steps > 0 ? b->tune.graph_steps : 64 * ts;
     for (;;) {
         int most = 0;
         for (int i = 0; i < b->count; ++i) {
@@ -312,14 +361,14 @@ int lbrd_batch_advance(lbrd_batch *b, const int64_t *nsteps) {
             }
             e = hipGraphLaunch(b->graph, b->stream);
         } else {
-            e = enqueue(b, most, b->stream);
+            e = enqueue(b, launches_for(most, ts), b->stream);
         }
         if (e != hipSuccess) return fail("batch advance", e);
         for (int i = 0; i < b->count; ++i) {
             const int n = b->inst[i].steps;
             left[i] -= n;
             b->tinst[i] += n;
-            b->inst[i].cur ^= n & 1;
+            b->inst[i].cur ^= (int)(launches_for(n, ts) & 1);
         }
         b->dirty = true;
     }
@@ -409,12 +458,17 @@ int lbrd_batch_set_tuning(lbrd_batch *b, const lbrd_tuning *t) {
     n.vec = 0;
     n.lanes_x = 0;
     n.plain_order = 0;
-    n.fused_steps = 1;
-    n.tile_rows = 0;
-    n.tile_cols = 0;
-    if (!batch_tuning_valid(n)) return LBRD_EINVAL;
-    if (std::memcmp(&n, &b->tune, sizeof(n)) != 0) drop_graph(b);
+    if (n.fused_steps == 1) n.tile_rows = 0;
+    n.tile_cols = n.fused_steps > 1 ? 64 : 0;
+    if (!batch_tuning_valid(b, n)) return LBRD_EINVAL;
+    if (std::memcmp(&n, &b->tune, sizeof(n)) == 0) return LBRD_OK;
+    const bool tiling = n.fused_steps != b->tune.fused_steps || n.tile_rows != b->tune.tile_rows;
+    drop_graph(b);
     b->tune = n;
+    if (tiling) {
+        hipError_t e = retile(b);
+        if (e != hipSuccess) return fail("batch retile", e);
+    }
     return LBRD_OK;
 }
 
@@ -454,26 +508,50 @@ int lbrd_batch_autotune(lbrd_batch *b, int steps, lbrd_tuning *chosen) {
         b->initialised[i] = 1;
     }
     const lbrd_tuning keep = b->tune;
-    lbrd_tuning best = keep;
-    double best_ms = 1e300;
+    steps = (steps + 11) / 12 * 12;   // whole launches for every step count 1 .. 4
+    // candidates: persistent one-step launches over blocks per CU, waves and
+    // streaming accesses; multi-step launches over steps per launch, tile
+    // heights and workgroup sizes (one workgroup per tile)
+    std::vector<lbrd_tuning> cands;
     for (int bpc : {1, 2, 4, 8, 16})
         for (int w : {1, 2, 4})
             for (int nt = 0; nt < 2; ++nt) {
                 lbrd_tuning t = keep;
+                t.fused_steps = 1;
+                t.tile_rows = 0;
                 t.blocks_per_cu = bpc;
                 t.waves = w;
                 t.nontemporal = nt;
-                t.graph_steps = 0;
-                if (lbrd_batch_set_tuning(b, &t) != LBRD_OK) continue;
-                double ms = 0;
-                if (lbrd_batch_time_steps(b, 2, &ms) != LBRD_OK) continue;
-                if (lbrd_batch_time_steps(b, steps, &ms) != LBRD_OK) continue;
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    best = t;
-                    best.graph_steps = keep.graph_steps;
-                }
+                cands.push_back(t);
             }
+    if (b->multi_ok)
+        for (int ts = 2; ts <= kMaxFusedSteps; ++ts)
+            for (int rows : {4, 8, 16})
+                for (int w : {4, 8, 16}) {
+                    lbrd_tuning t = keep;
+                    t.fused_steps = ts;
+                    t.tile_rows = rows;
+                    t.blocks_per_cu = 0;
+                    t.waves = w;
+                    t.nontemporal = 0;
+                    cands.push_back(t);
+                }
+    lbrd_tuning best = keep;
+    double best_ms = 1e300;
+    for (lbrd_tuning t : cands) {
+        t.graph_steps = 0;
+        if (lbrd_batch_set_tuning(b, &t) != LBRD_OK) continue;
+        double ms = 0;
+        if (lbrd_batch_time_steps(b, 2, &ms) != LBRD_OK) continue;
+        if (lbrd_batch_time_steps(b, steps, &ms) != LBRD_OK) continue;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = t;
+            // the caller's chunk length, rounded up to an even number of launches
+            const int unit = best.fused_steps > 1 ? 2 * best.fused_steps : 2;
+            best.graph_steps = keep.graph_steps > 0 ? (keep.graph_steps + unit - 1) / unit * unit : 0;
+        }
+    }
     lbrd_batch_set_tuning(b, &best);
     for (int i = 0; i < b->count; ++i) b->initialised[i] = 0;
     for (auto &t : b->tinst) t = 0;

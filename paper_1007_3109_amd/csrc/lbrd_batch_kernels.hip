@@ -83,6 +83,141 @@ __global__ __launch_bounds__(256) void k_batch_step(const BatchHeader *__restric
     }
 }
 
+// ------------------------------------------- several steps per launch --
+
+template <int ST, int V, int TS, int MAXK>
+__device__ __forceinline__ void batch_tileT(const BatchInst &bi, int j, int64_t local, int m, unsigned char *smem) {
+    using T = typename Traits<ST>::T;
+    const int in = bi.cur ^ (j & 1);
+    TileT t;
+    t.src = buffer_rsrc(bi.buf[in], bi.bytes);
+    t.dst = buffer_rsrc(bi.buf[in ^ 1], bi.bytes);
+    t.nx = bi.nx;
+    t.ny = bi.ny;
+    t.th = bi.mt_th;
+    t.pitch_b = (uint32_t)bi.pitch * (uint32_t)sizeof(T);
+    t.pstride_b = (uint32_t)bi.pstride * (uint32_t)sizeof(T);
+    const int tx = (int)(local % bi.mt_ntx), ty = (int)(local / bi.mt_ntx);
+    if constexpr (ST == kF64)
+        stepT_tile<ST, V, TS, MAXK, 64, true>(t, bi.pd, tx * 64, ty * bi.mt_th, m, reinterpret_cast<T *>(smem));
+    else
+        stepT_tile<ST, V, TS, MAXK, 64, true>(t, bi.pf, tx * 64, ty * bi.mt_th, m, reinterpret_cast<T *>(smem));
+}
+
+template <int ST, int TS, int MAXK>
+__device__ __forceinline__ void batch_tileT_serve(const BatchInst &bi, int j, int64_t local, int m,
+                                                  unsigned char *smem) {
+    if (bi.variant == kGS) batch_tileT<ST, kGS, TS, MAXK>(bi, j, local, m, smem);
+    else batch_tileT<ST, kLin1, TS, MAXK>(bi, j, local, m, smem);
+}
+
+// Launch j of a chunk, TS steps per launch: every workgroup walks the global
+// list of 64 x rows tiles; the owning instance is found by binary search over
+// tile_begin (workgroup-uniform).  Instance i takes m = min(TS, steps_i - j TS)
+// steps on its tiles when m > 0; its buffers alternate once per launch.
+template <int SET, int TS, int MAXK>
+__global__ __launch_bounds__(MAXK == 1 ? 1024 : 512) void k_batch_stepT(const BatchHeader *__restrict__ hdr,
+                                                                        const BatchInst *__restrict__ inst, int j) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const int count = hdr->count;
+    const int64_t total = hdr->total_tiles;
+    int hint = 0;
+    for (int64_t t = xcd_remap(blockIdx.x, gridDim.x); t < total; t += gridDim.x) {
+        int lo = inst[hint].tile_begin <= t ? hint : 0, hi = count - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (inst[mid].tile_begin <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        hint = lo;
+        const BatchInst &bi = inst[lo];
+        const int64_t done = (int64_t)j * TS;
+        if (done >= bi.steps) continue;
+        const int m = (int)(bi.steps - done < TS ? bi.steps - done : TS);
+        const int64_t local = t - bi.tile_begin;
+        if constexpr (SET == kBatchGSF32) {
+            batch_tileT<kF32, kGS, TS, MAXK>(bi, j, local, m, smem);
+        } else {
+            switch (bi.storage) {
+                case kF32: batch_tileT_serve<kF32, TS, MAXK>(bi, j, local, m, smem); break;
+                case kF16: batch_tileT_serve<kF16, TS, MAXK>(bi, j, local, m, smem); break;
+                default: batch_tileT_serve<kBF16, TS, MAXK>(bi, j, local, m, smem); break;
+            }
+        }
+    }
+}
+
+template <int SET, int TS, int MAXK>
+static hipError_t launch_setT(const BatchHeader *hdr, const BatchInst *inst, int j, int64_t blocks, int waves,
+                              size_t lds, hipStream_t st) {
+    static bool attr_set = false;   // per instantiation: allow more than 64 KB of LDS
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch_stepT<SET, TS, MAXK>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_batch_stepT<SET, TS, MAXK>), dim3((unsigned)blocks), dim3(64 * waves), lds, st, hdr, inst,
+                       j);
+    return hipGetLastError();
+}
+
+template <int SET, int TS>
+static hipError_t launch_setT_k(const BatchHeader *hdr, const BatchInst *inst, int j, int64_t blocks, int waves,
+                                int rows, size_t lds, hipStream_t st) {
+    switch (stepT_sites_per_thread(64, rows, TS, waves)) {
+        case 0:
+        case 1: return launch_setT<SET, TS, 1>(hdr, inst, j, blocks, waves, lds, st);
+        case 2: return launch_setT<SET, TS, 2>(hdr, inst, j, blocks, waves, lds, st);
+        case 3: return launch_setT<SET, TS, 3>(hdr, inst, j, blocks, waves, lds, st);
+        case 4: return launch_setT<SET, TS, 4>(hdr, inst, j, blocks, waves, lds, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int SET>
+static hipError_t launch_setT_n(const BatchHeader *hdr, const BatchInst *inst, int j, int64_t blocks, int waves,
+                                int ts, int rows, size_t lds, hipStream_t st) {
+    switch (ts) {
+        case 2: return launch_setT<SET, 2, 1>(hdr, inst, j, blocks, waves, lds, st);
+        case 3: return launch_setT_k<SET, 3>(hdr, inst, j, blocks, waves, rows, lds, st);
+        case 4: return launch_setT_k<SET, 4>(hdr, inst, j, blocks, waves, rows, lds, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_batch_stepT(const BatchHeader *hdr, const BatchInst *inst, int j, int64_t blocks, int waves, int ts,
+                              int rows, int set, hipStream_t st) {
+    // LDS of the largest member of either set: Gray-Scott in FP32
+    if (!stepT_shape_fits(kF32, 2, 64, rows, ts, waves) || blocks < 1 || blocks > 0x7fffffff)
+        return hipErrorInvalidValue;
+    const size_t lds = stepT_lds_bytes(kF32, 2, 64, rows, ts);
+    switch (set) {
+        case kBatchGSF32: return launch_setT_n<kBatchGSF32>(hdr, inst, j, blocks, waves, ts, rows, lds, st);
+        case kBatchServe: return launch_setT_n<kBatchServe>(hdr, inst, j, blocks, waves, ts, rows, lds, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+bool batch_multi_ok(const Layout &L, int storage) {
+    return L.buf_bytes < ((size_t)1 << 32) && (int64_t)L.pitch * storage_bytes(storage) < ((int64_t)1 << 24);
+}
+
+void set_batch_tiling(BatchInst &bi, const Layout &L, int ts, int rows) {
+    if (ts > 1) {
+        bi.mt_th = rows;
+        bi.mt_ntx = (L.nx + 63) / 64;
+        bi.ntiles = (int64_t)bi.mt_ntx * ((L.ny + rows - 1) / rows);
+        bi.bytes = (uint32_t)L.buf_bytes;
+    } else {
+        bi.mt_th = 0;
+        bi.mt_ntx = 0;
+        bi.ntiles = make_grid(L, nullptr, nullptr, bi.vec, bi.lanes_x).ntiles;
+        bi.bytes = 0;
+    }
+
+}
+
 template <int SET>
 static hipError_t launch_set(const BatchHeader *hdr, const BatchInst *inst, int j, int blocks, int waves, bool nt,
                              hipStream_t st) {

@@ -424,116 +424,168 @@ __device__ __forceinline__ void put_lds(typename Traits<ST>::T *L, int lx, int l
         for (int i = 0; i < 9; ++i) b[(s * 9 + i) * EW] = o[s][i];
 }
 
-// TS time steps per launch on a tile of TW x th sites (temporal blocking).
+// Geometry of one lattice as the multi-step tile reads it.
+struct TileT {
+    __amdgpu_buffer_rsrc_t src, dst;
+    int nx, ny, th;
+    uint32_t pitch_b, pstride_b;   // row and plane strides in bytes
+};
+
+// TS time steps on one tile of TW x th sites whose lower-left site is
+// (x0, y0) (temporal blocking; called by every thread of the workgroup).
 // The workgroup keeps a (TW + 2h) x (th + 2h) region in LDS, h = TS - 1.
 // Phase 1 reads step t from the source buffer (pulling across the region's
 // edge), collides, and writes the post-collision values of step t+1 on the
-// whole region to LDS.  Each middle phase j = 2 .. TS-1 advances the region
+// whole region to LDS.  Each middle phase j = 2 .. m-1 advances the region
 // shrunk by j-1 sites on every side, in place: every thread first pulls the
-// inputs of its sites into registers (MAXK sites, 1 or 2), the workgroup
+// inputs of its sites into registers (MAXK sites, 1 to 4), the workgroup
 // synchronises, then the threads collide and overwrite LDS.  The last phase
-// pulls from LDS, collides on the tile itself and stores step t+TS.  Per TS
-// steps the buffer is read once (tile plus an h+1 halo) and written once.
-// Every site runs the arithmetic of the one-step kernel on the same encoded
-// inputs, so the result is bitwise identical to TS one-step launches.
-// Requires the buffer to span less than 4 GiB (32-bit byte offsets).
-template <int ST, int V, int TS, int MAXK, int TW>
-__global__ __launch_bounds__(MAXK == 1 ? 1024 : 512) void k_stepT(GridT g, Params<typename Traits<ST>::C> p) {
+// pulls from LDS, collides on the tile itself and stores step t+m.  Per m
+// steps the buffer is read once (tile plus a halo) and written once.  Every
+// site runs the arithmetic of the one-step kernel on the same encoded inputs,
+// so the result is bitwise identical to m one-step launches.  m = TS unless
+// VARM, where 1 <= m <= TS is a workgroup-uniform runtime count (m = 1 reads
+// and writes the buffers directly).  Byte offsets are 32-bit: the buffer
+// spans less than 4 GiB.
+template <int ST, int V, int TS, int MAXK, int TW, bool VARM>
+__device__ __forceinline__ void stepT_tile(const TileT &g, const Params<typename Traits<ST>::C> &p, int x0, int y0,
+                                           int m, typename Traits<ST>::T *L) {
     using T = typename Traits<ST>::T;
     using C = typename Traits<ST>::C;
     constexpr int NS = NSpecies<V>::value;
     constexpr int H = TS - 1;
     constexpr int EW = TW + 2 * H;
     constexpr uint32_t B = sizeof(T);
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    T *L = reinterpret_cast<T *>(smem);
-    const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(g.src, g.bytes);
-    const __amdgpu_buffer_rsrc_t rd = buffer_rsrc(g.dst, g.bytes);
     const int nx = g.nx, ny = g.ny, th = g.th;
-    const int eh = th + 2 * H, esz = EW * eh, tsz = TW * th;
-    const uint32_t pitch_b = (uint32_t)g.pitch * B, pstride_b = (uint32_t)g.pstride * B;
-    const bool one_wrap = nx >= TW + H && ny >= th + H;   // the region wraps at most once per axis
+    const int tsz = TW * th;
     const int nthr = blockDim.x;
-    const int dx = nthr % EW, dy = nthr / EW;
-    const int ex0 = (int)threadIdx.x % EW, ey0 = (int)threadIdx.x / EW;
-    const int b0 = g.xcd_order ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    for (int64_t tile = b0; tile < g.ntiles; tile += gridDim.x) {
-        const int tx = (int)(tile % g.ntx), ty = (int)(tile / g.ntx);
-        const int x0 = tx * TW, y0 = ty * th;
-        // phase 1: step t -> t+1 on the whole region, from the source buffer
-        int ex = ex0, ey = ey0;
-        for (int q = threadIdx.x; q < esz; q += nthr) {
-            int gx = x0 - H + ex, gy = y0 - H + ey;
-            if (one_wrap) {
-                gx += gx < 0 ? nx : 0;
-                gx -= gx >= nx ? nx : 0;
-                gy += gy < 0 ? ny : 0;
-                gy -= gy >= ny ? ny : 0;
-            } else {
-                gx = wrap_mod(gx, nx);
-                gy = wrap_mod(gy, ny);
-            }
-            // byte offsets of columns x-1, x, x+1 and rows y-1, y, y+1
-            const uint32_t cx[3] = {(uint32_t)(gx == 0 ? nx - 1 : gx - 1) * B, (uint32_t)gx * B,
-                                    (uint32_t)(gx + 1 == nx ? 0 : gx + 1) * B};
-            const uint32_t ry[3] = {mul24(gy == 0 ? ny - 1 : gy - 1, pitch_b), mul24(gy, pitch_b),
-                                    mul24(gy + 1 == ny ? 0 : gy + 1, pitch_b)};
-            C f[NS][9];
-#pragma unroll
-            for (int s = 0; s < NS; ++s)
-#pragma unroll
-                for (int i = 0; i < 9; ++i)
-                    f[s][i] = decode_dev<ST>(buf_load<T>(rs, ry[1 - kEy[i]] + cx[1 - kEx[i]], (uint32_t)(s * 9 + i) * pstride_b));
-            T o[NS][9];
-            collide_site<ST, V>(p, f, o);
-            put_lds<ST, NS, EW>(L, ex, ey, o);
-            ex += dx;
-            ey += dy;
-            if (ex >= EW) {
-                ex -= EW;
-                ++ey;
-            }
-        }
-        __syncthreads();
-        // middle phases: step t+j-1 -> t+j on the region shrunk by j-1, in LDS
-#pragma unroll
-        for (int j = 2; j < TS; ++j) {
-            const int rw = EW - 2 * (j - 1), rsz = rw * (eh - 2 * (j - 1));
-            C f[MAXK][NS][9];
-#pragma unroll
-            for (int k = 0; k < MAXK; ++k) {
-                const int q = threadIdx.x + k * nthr;
-                if (q < rsz) gather_lds<ST, NS, EW>(L, q % rw + j - 1, q / rw + j - 1, f[k]);
-            }
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < MAXK; ++k) {
-                const int q = threadIdx.x + k * nthr;
-                if (q < rsz) {
-                    T o[NS][9];
-                    collide_site<ST, V>(p, f[k], o);
-                    put_lds<ST, NS, EW>(L, q % rw + j - 1, q / rw + j - 1, o);
-                }
-            }
-            __syncthreads();
-        }
-        // last phase: step t+TS-1 -> t+TS on the tile, to the destination buffer
+    if constexpr (!VARM) m = TS;
+    if (VARM && m == 1) {
+        // a single step: pull from the source buffer, store to the destination
         for (int q = threadIdx.x; q < tsz; q += nthr) {
-            const int lx = q % TW, ly = q / TW;
-            const int gx = x0 + lx, gy = y0 + ly;
-            C f[NS][9];
-            gather_lds<ST, NS, EW>(L, lx + H, ly + H, f);
-            T o[NS][9];
-            collide_site<ST, V>(p, f, o);
+            const int gx = x0 + q % TW, gy = y0 + q / TW;
             if (gx < nx && gy < ny) {
-                const uint32_t off = mul24(gy, pitch_b) + (uint32_t)gx * B;
+                const uint32_t cx[3] = {(uint32_t)(gx == 0 ? nx - 1 : gx - 1) * B, (uint32_t)gx * B,
+                                        (uint32_t)(gx + 1 == nx ? 0 : gx + 1) * B};
+                const uint32_t ry[3] = {mul24(gy == 0 ? ny - 1 : gy - 1, g.pitch_b), mul24(gy, g.pitch_b),
+                                        mul24(gy + 1 == ny ? 0 : gy + 1, g.pitch_b)};
+                C f[NS][9];
 #pragma unroll
                 for (int s = 0; s < NS; ++s)
 #pragma unroll
-                    for (int i = 0; i < 9; ++i) buf_store<T>(rd, off, (uint32_t)(s * 9 + i) * pstride_b, o[s][i]);
+                    for (int i = 0; i < 9; ++i)
+                        f[s][i] = decode_dev<ST>(
+                            buf_load<T>(g.src, ry[1 - kEy[i]] + cx[1 - kEx[i]], (uint32_t)(s * 9 + i) * g.pstride_b));
+                T o[NS][9];
+                collide_site<ST, V>(p, f, o);
+#pragma unroll
+                for (int s = 0; s < NS; ++s)
+#pragma unroll
+                    for (int i = 0; i < 9; ++i)
+                        buf_store<T>(g.dst, ry[1] + cx[1], (uint32_t)(s * 9 + i) * g.pstride_b, o[s][i]);
             }
         }
-        __syncthreads();   // LDS is reused by the next tile
+        return;
+    }
+    const int eh = th + 2 * H, esz = EW * eh;
+    const bool one_wrap = nx >= TW + H && ny >= th + H;   // the region wraps at most once per axis
+    // phase 1: step t -> t+1 on the whole region, from the source buffer
+    const int dx = nthr % EW, dy = nthr / EW;
+    int ex = (int)threadIdx.x % EW, ey = (int)threadIdx.x / EW;
+    for (int q = threadIdx.x; q < esz; q += nthr) {
+        int gx = x0 - H + ex, gy = y0 - H + ey;
+        if (one_wrap) {
+            gx += gx < 0 ? nx : 0;
+            gx -= gx >= nx ? nx : 0;
+            gy += gy < 0 ? ny : 0;
+            gy -= gy >= ny ? ny : 0;
+        } else {
+            gx = wrap_mod(gx, nx);
+            gy = wrap_mod(gy, ny);
+        }
+        // byte offsets of columns x-1, x, x+1 and rows y-1, y, y+1
+        const uint32_t cx[3] = {(uint32_t)(gx == 0 ? nx - 1 : gx - 1) * B, (uint32_t)gx * B,
+                                (uint32_t)(gx + 1 == nx ? 0 : gx + 1) * B};
+        const uint32_t ry[3] = {mul24(gy == 0 ? ny - 1 : gy - 1, g.pitch_b), mul24(gy, g.pitch_b),
+                                mul24(gy + 1 == ny ? 0 : gy + 1, g.pitch_b)};
+        C f[NS][9];
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                f[s][i] = decode_dev<ST>(
+                    buf_load<T>(g.src, ry[1 - kEy[i]] + cx[1 - kEx[i]], (uint32_t)(s * 9 + i) * g.pstride_b));
+        T o[NS][9];
+        collide_site<ST, V>(p, f, o);
+        put_lds<ST, NS, EW>(L, ex, ey, o);
+        ex += dx;
+        ey += dy;
+        if (ex >= EW) {
+            ex -= EW;
+            ++ey;
+        }
+    }
+    __syncthreads();
+    // middle phases: step t+j-1 -> t+j on the region shrunk by j-1, in LDS
+#pragma unroll
+    for (int j = 2; j < TS; ++j) {
+        if (VARM && j >= m) break;
+        const int rw = EW - 2 * (j - 1), rsz = rw * (eh - 2 * (j - 1));
+        C f[MAXK][NS][9];
+#pragma unroll
+        for (int k = 0; k < MAXK; ++k) {
+            const int q = threadIdx.x + k * nthr;
+            if (q < rsz) gather_lds<ST, NS, EW>(L, q % rw + j - 1, q / rw + j - 1, f[k]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < MAXK; ++k) {
+            const int q = threadIdx.x + k * nthr;
+            if (q < rsz) {
+                T o[NS][9];
+                collide_site<ST, V>(p, f[k], o);
+                put_lds<ST, NS, EW>(L, q % rw + j - 1, q / rw + j - 1, o);
+            }
+        }
+        __syncthreads();
+    }
+    // last phase: step t+m-1 -> t+m on the tile, to the destination buffer
+    for (int q = threadIdx.x; q < tsz; q += nthr) {
+        const int lx = q % TW, ly = q / TW;
+        const int gx = x0 + lx, gy = y0 + ly;
+        C f[NS][9];
+        gather_lds<ST, NS, EW>(L, lx + H, ly + H, f);
+        T o[NS][9];
+        collide_site<ST, V>(p, f, o);
+        if (gx < nx && gy < ny) {
+            const uint32_t off = mul24(gy, g.pitch_b) + (uint32_t)gx * B;
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+#pragma unroll
+                for (int i = 0; i < 9; ++i) buf_store<T>(g.dst, off, (uint32_t)(s * 9 + i) * g.pstride_b, o[s][i]);
+        }
+    }
+    __syncthreads();   // LDS is reused by the next tile
+}
+
+// TS steps per launch over one lattice: one workgroup per tile (or a
+// persistent grid walking the tiles).
+template <int ST, int V, int TS, int MAXK, int TW>
+__global__ __launch_bounds__(MAXK == 1 ? 1024 : 512) void k_stepT(GridT g, Params<typename Traits<ST>::C> p) {
+    using T = typename Traits<ST>::T;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    TileT t;
+    t.src = buffer_rsrc(g.src, g.bytes);
+    t.dst = buffer_rsrc(g.dst, g.bytes);
+    t.nx = g.nx;
+    t.ny = g.ny;
+    t.th = g.th;
+    t.pitch_b = (uint32_t)g.pitch * (uint32_t)sizeof(T);
+    t.pstride_b = (uint32_t)g.pstride * (uint32_t)sizeof(T);
+    const int b0 = g.xcd_order ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    for (int64_t tile = b0; tile < g.ntiles; tile += gridDim.x) {
+        const int tx = (int)(tile % g.ntx), ty = (int)(tile / g.ntx);
+        stepT_tile<ST, V, TS, MAXK, TW, false>(t, p, tx * TW, ty * g.th, TS, reinterpret_cast<T *>(smem));
     }
 }
 

@@ -7,6 +7,7 @@
 //   2. advances every resident request by min(chunk, steps left) with a
 //      replayed graph of persistent batched launches (per-slot step limits
 //      live in device descriptors, so the graph is reused across rounds);
+//      rounds of the serving mix advance four steps per launch on LDS tiles;
 //   3. enqueues the density read-out of requests that finish in this round
 //      and records an event;
 //   4. while the GPU works on that round, retires the previous round's
@@ -132,7 +133,7 @@ struct lbrd_server {
     bool failed = false;
     int64_t next_id = 1;
     int cus = 256;
-    hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};   // per kernel set
+    hipGraphExec_t graph[4] = {nullptr, nullptr, nullptr, nullptr};   // per kernel set; [3]: multi-step serve
     std::chrono::steady_clock::time_point t0;
     lbrd_server_stats stats;
     double busy_since = -1;
@@ -156,31 +157,40 @@ void mark_busy(lbrd_server *s) {
 
 int blocks_for(const lbrd_server *s) { return 8 * s->cus; }
 
-hipError_t enqueue_chunk(lbrd_server *s, int set, hipStream_t st) {
-    for (int j = 0; j < s->sc.chunk_steps; ++j) {
-        hipError_t e = launch_batch_step(s->d_hdr, s->d_inst, j, blocks_for(s), 4, false, set, st);
+// Multi-step rounds (the serving mix, every request below 4 GiB per buffer):
+// four steps per launch on 64 x 4 tiles, a persistent grid of 8-wave
+// workgroups, four per CU.
+constexpr int kServeSteps = 4, kServeRows = 4, kServeWaves = 8, kServeBlocksPerCu = 4;
+
+hipError_t enqueue_chunk(lbrd_server *s, int set, bool multi, hipStream_t st) {
+    const int64_t launches = launches_for(s->sc.chunk_steps, multi ? kServeSteps : 1);
+    for (int64_t j = 0; j < launches; ++j) {
+        hipError_t e = multi ? launch_batch_stepT(s->d_hdr, s->d_inst, (int)j, (int64_t)kServeBlocksPerCu * s->cus,
+                                                  kServeWaves, kServeSteps, kServeRows, set, st)
+                             : launch_batch_step(s->d_hdr, s->d_inst, (int)j, blocks_for(s), 4, false, set, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
-hipError_t run_chunk(lbrd_server *s, int set) {
-    if (!s->graph[set]) {
+hipError_t run_chunk(lbrd_server *s, int set, bool multi) {
+    const int slot = multi ? 3 : set;
+    if (!s->graph[slot]) {
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamBeginCapture(s->capture, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return e;
-        hipError_t le = enqueue_chunk(s, set, s->capture);
+        hipError_t le = enqueue_chunk(s, set, multi, s->capture);
         e = hipStreamEndCapture(s->capture, &g);
         if (le != hipSuccess) {
             if (g) hipGraphDestroy(g);
             return le;
         }
         if (e != hipSuccess) return e;
-        e = hipGraphInstantiate(&s->graph[set], g, nullptr, nullptr, 0);
+        e = hipGraphInstantiate(&s->graph[slot], g, nullptr, nullptr, 0);
         hipGraphDestroy(g);
         if (e != hipSuccess) return e;
     }
-    return hipGraphLaunch(s->graph[set], s->stream);
+    return hipGraphLaunch(s->graph[slot], s->stream);
 }
 
 char *slot_buf(lbrd_server *s, const Request &r, int which) {
@@ -314,17 +324,22 @@ void worker_loop(lbrd_server *s) {
             int64_t tiles = 0;
             bool serve = true;
             for (Request *rp : resp) {
+                const int v = variant_of(rp->cfg);
+                if (rp->cfg.storage == LBRD_F64 || !(v == kGS || v == kLin1)) serve = false;
+                if (!batch_multi_ok(rp->L, rp->cfg.storage)) serve = false;
+            }
+            const int ts = serve ? kServeSteps : 1;
+            for (Request *rp : resp) {
                 Request &r = *rp;
                 const int vec = batch_vec(r.cfg.storage);
                 BatchInst bi;
                 fill_batch_inst(bi, r.cfg, r.L, slot_buf(s, r, 0), slot_buf(s, r, 1), vec, default_lanes(r.cfg.nx, vec));
+                set_batch_tiling(bi, r.L, ts, kServeRows);
                 bi.tile_begin = tiles;
                 bi.cur = r.cur;
                 bi.steps = (int)std::min<int64_t>(r.left, s->sc.chunk_steps);
                 tiles += bi.ntiles;
                 inst.push_back(bi);
-                const int v = variant_of(r.cfg);
-                if (r.cfg.storage == LBRD_F64 || !(v == kGS || v == kLin1)) serve = false;
             }
             BatchHeader h;
             std::memset(&h, 0, sizeof(h));
@@ -333,12 +348,12 @@ void worker_loop(lbrd_server *s) {
             err = hipMemcpyAsync(s->d_inst, inst.data(), sizeof(BatchInst) * inst.size(), hipMemcpyHostToDevice,
                                  s->stream);
             if (err == hipSuccess) err = hipMemcpyAsync(s->d_hdr, &h, sizeof(h), hipMemcpyHostToDevice, s->stream);
-            if (err == hipSuccess) err = run_chunk(s, serve ? kBatchServe : kBatchAny);
+            if (err == hipSuccess) err = run_chunk(s, serve ? kBatchServe : kBatchAny, serve);
             for (size_t q = 0; q < res.size() && err == hipSuccess; ++q) {
                 Request &r = *resp[q];
                 const int taken = inst[q].steps;
                 r.left -= taken;
-                r.cur ^= taken & 1;
+                r.cur ^= (int)(launches_for(taken, ts) & 1);
                 if (r.left == 0) {
                     err = launch_moments(r.cfg.storage, r.L, params_blob(r, blob), slot_buf(s, r, r.cur),
                                          slot_rho(s, r), LBRD_DTYPE_F64, nullptr, 0, s->partials, slot_result(s, r),

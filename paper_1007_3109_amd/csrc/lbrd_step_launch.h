@@ -66,16 +66,25 @@ inline hipError_t launch_stepT_t(const StepLaunch &sl, const GridT &g, const voi
     return hipGetLastError();
 }
 
+template <int ST, int V, int TS, int TW>
+inline hipError_t launch_stepT_k(const StepLaunch &sl, const GridT &g, const void *params, hipStream_t st) {
+    switch (stepT_sites_per_thread(TW, g.th, TS, sl.waves)) {
+        case 0:
+        case 1: return launch_stepT_t<ST, V, TS, 1, TW>(sl, g, params, st);
+        case 2: return launch_stepT_t<ST, V, TS, 2, TW>(sl, g, params, st);
+        case 3: return launch_stepT_t<ST, V, TS, 3, TW>(sl, g, params, st);
+        case 4: return launch_stepT_t<ST, V, TS, 4, TW>(sl, g, params, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <int ST, int V, int TW>
 inline hipError_t launch_stepT_n(const StepLaunch &sl, const GridT &g, const void *params, hipStream_t st) {
     static_assert(kMaxFusedSteps == 4, "instantiate every step count");
-    const bool two = stepT_sites_per_thread(TW, g.th, g.steps, sl.waves) == 2;
     switch (g.steps) {
         case 2: return launch_stepT_t<ST, V, 2, 1, TW>(sl, g, params, st);
-        case 3: return two ? launch_stepT_t<ST, V, 3, 2, TW>(sl, g, params, st)
-                           : launch_stepT_t<ST, V, 3, 1, TW>(sl, g, params, st);
-        case 4: return two ? launch_stepT_t<ST, V, 4, 2, TW>(sl, g, params, st)
-                           : launch_stepT_t<ST, V, 4, 1, TW>(sl, g, params, st);
+        case 3: return launch_stepT_k<ST, V, 3, TW>(sl, g, params, st);
+        case 4: return launch_stepT_k<ST, V, 4, TW>(sl, g, params, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -53,11 +53,24 @@ def mixed_cases():
     return cases
 
 
-def test_batch_gs_f32_equals_solo_and_oracle():
+@pytest.mark.parametrize("mode", ["default", "one-step", "three-step"])
+def test_batch_gs_f32_equals_solo_and_oracle(mode):
+    """The batched Gray-Scott FP32 job (default: four steps per launch on LDS
+    tiles, graphs of 32 steps; also persistent one-step launches and three
+    steps per launch) equals solo runs bitwise after 151 steps (graph replays
+    plus a ragged remainder) and the FP64 oracle within the FP32 floor."""
     insts = [i for i in workloads.batch_sweep(3, grid=4, sides=(64, 96, 130))]
     cfgs = [lbrd.make_config(i.side, i.side, 2, tau=workloads.GS_TAU, storage="f32", reaction="gray_scott",
                              F=i.F, k=i.k) for i in insts]
     b = lbrd.Batch(cfgs)
+    t = b.tuning()
+    assert t.fused_steps == 4 and t.tile_rows == 8 and t.graph_steps == 32
+    if mode == "one-step":
+        b.set_tuning(fused_steps=1, waves=4, blocks_per_cu=8, graph_steps=16)
+    elif mode == "three-step":
+        b.set_tuning(fused_steps=3, tile_rows=4, waves=8, graph_steps=18)
+        with pytest.raises(lbrd.LbrdError):
+            b.set_tuning(graph_steps=16)        # not an even number of three-step launches
     for idx, inst in enumerate(insts):
         b.init(idx, workloads.batch_initial(inst))
     steps = 151
@@ -74,7 +87,35 @@ def test_batch_gs_f32_equals_solo_and_oracle():
                                                precision="f32", **kw), ref)
             tol = np.where(floor <= 1e-6, 1e-5, 3 * floor)
             assert np.all(oracle.rel_l2(got.cpu().numpy(), ref) <= tol)
-    log(f"batch of {len(insts)} GS f32 lattices: bitwise equal to solo runs")
+    log(f"batch of {len(insts)} GS f32 lattices ({mode}): bitwise equal to solo runs")
+
+
+def serve_mix_cases():
+    """F32 / F16 / BF16 storage, single-species decay or Gray-Scott: the
+    serving mix, which batches with several steps per launch."""
+    return [(c, r) for c, r in mixed_cases() if c.storage != lbrd.STORAGE["f64"]]
+
+
+@pytest.mark.parametrize("ts,graph_steps", [(4, 0), (4, 16), (3, 12), (2, 4)])
+def test_batch_multi_step_advance_equals_solo(ts, graph_steps):
+    """Per-instance step counts (lbrd_batch_advance) on the serving mix with
+    T steps per launch: counts that are not multiples of T end with a shorter
+    launch (down to a single step), instances with 0 steps stay put, and every
+    instance equals its solo run bitwise."""
+    cases = serve_mix_cases()
+    b = lbrd.Batch([c for c, _ in cases])
+    b.set_tuning(fused_steps=ts, tile_rows=4, waves=8, blocks_per_cu=0, graph_steps=graph_steps)
+    for idx, (_, rho0) in enumerate(cases):
+        b.init(idx, rho0)
+    counts = [1, 2, 3, 0, 5, 23][:len(cases)]
+    b.advance(counts)
+    more = [7, 0, 1, 4, 30, 2][:len(cases)]
+    b.advance(more)
+    b.step(9)
+    for idx, (cfg, rho0) in enumerate(cases):
+        n = counts[idx] + more[idx] + 9
+        assert b.time(idx) == n
+        assert torch.equal(b.moments(idx)[0], solo(cfg, rho0, n)), (idx, n)
 
 
 @pytest.mark.parametrize("graph_steps", [0, 8])
@@ -97,7 +138,11 @@ def test_batch_autotune_then_run():
                              F=i.F, k=i.k) for i in insts]
     b = lbrd.Batch(cfgs)
     t = b.autotune(steps=3)
-    assert 1 <= t.blocks_per_cu <= 32 and t.waves in (1, 2, 4)
+    if t.fused_steps == 1:
+        assert 1 <= t.blocks_per_cu <= 32 and t.waves in (1, 2, 4)
+    else:
+        assert 2 <= t.fused_steps <= 4 and t.tile_rows in (4, 8, 16) and t.graph_steps % (2 * t.fused_steps) == 0
+    log(f"batch autotune chose {t.as_dict()}")
     assert lbrd.lib.lbrd_batch_step(b._h, 1) == lbrd.ESTATE
     for idx, inst in enumerate(insts):
         b.init(idx, workloads.batch_initial(inst))
@@ -107,7 +152,10 @@ def test_batch_autotune_then_run():
 
 
 def test_server_results_equal_solo_runs():
-    cases = [(c, r) for c, r in mixed_cases() if c.storage != lbrd.STORAGE["f64"]]
+    """The serving mix (four steps per launch inside the server's rounds):
+    request lengths that are not multiples of the chunk or of four, including
+    a single step, equal their solo runs bitwise."""
+    cases = serve_mix_cases()
     steps = [130, 64, 300, 1, 77, 250]
     srv = lbrd.Server(arena_bytes=256 << 20, chunk_steps=64)
     tickets = []
