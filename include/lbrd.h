@@ -107,10 +107,11 @@ typedef struct lbrd_config {
  *       (temporal blocking; a remainder of 2 .. T-1 steps runs as one shorter
  *       launch on the same tiles, a single remaining step as a one-step
  *       launch).  Results are bitwise identical for every setting.
- *  tile_rows, tile_cols: multi-step tile, rows 1..64 and columns 64 or 128; the
- *       region (tile_cols + 2(T-1)) x (tile_rows + 2(T-1)) x 9 N populations
- *       must fit in 160 KB of LDS and, for T >= 3, the second phase's region
- *       (two sites smaller per axis) must not exceed 64 * waves threads x 1
+ *  tile_rows, tile_cols: multi-step tile, rows 1..64 and columns 64 or 128.
+ *       With h = T-1 and w = tile_cols + 2h, the LDS region of tile_rows + 2h
+ *       rows of 9 N w populations (each row padded by fewer than 256 bytes)
+ *       must fit in 160 KB, and for T >= 3 the second phase's
+ *       w x (tile_rows + 2h - 2) sites must not exceed 64 * waves threads x 1
  *       site, or x 4 sites with at most 8 waves.  Ignored when
  *       fused_steps = 1. */
 typedef struct lbrd_tuning {

@@ -435,20 +435,20 @@ int lbrd_create(const lbrd_config *cfg, void *workspace, size_t bytes, void *str
     }
     // Four steps per launch on 64 x rows tiles staged in LDS (temporal
     // blocking): measured 2.4x (1024^2) and 2.7x (4096^2, FP32) the one-step
-    // launches.  Rows: 4 while both buffers fit in the 256 MB Infinity Cache,
-    // 8 beyond it; halved (then fewer steps per launch) until the shape fits
-    // in LDS and the register budget; 8 waves per workgroup; cached accesses.
-    // Tile order: consecutive tiles on one XCD inside the Infinity Cache, the
-    // hardware's round-robin order beyond it (each measured best there).
-    // Buffers of 4 GiB or more keep one-step launches.
+    // launches.  Rows: 4 while both buffers fit in the 256 MB Infinity Cache;
+    // beyond it 8 for 4- and 8-byte storage, 24 for the 16-bit forms (taller
+    // tiles re-read fewer halo rows); halved (then fewer steps per launch)
+    // until the shape fits in LDS and the register budget.  8 waves per
+    // workgroup, cached accesses, consecutive tiles on one XCD (each measured
+    // best).  Buffers of 4 GiB or more keep one-step launches.
     const bool in_cache = 2 * h->L.buf_bytes <= ((size_t)256 << 20);
     h->tune.tile_cols = 64;
-    h->tune.tile_rows = in_cache ? 4 : 8;
+    h->tune.tile_rows = in_cache ? 4 : (storage_bytes(h->cfg.storage) == 2 ? 24 : 8);
     h->tune.fused_steps = 1;
     if (multi_step_possible(h)) {
         h->tune.waves = 8;
         h->tune.nontemporal = 0;
-        h->tune.plain_order = in_cache ? 0 : 1;
+        h->tune.plain_order = 0;
         for (int ts = kMaxFusedSteps; ts >= 2 && h->tune.fused_steps == 1; --ts) {
             for (int rows = h->tune.tile_rows; rows >= 1; rows /= 2)
                 if (stepT_shape_fits(h->cfg.storage, h->cfg.nspecies, 64, rows, ts, 8)) {

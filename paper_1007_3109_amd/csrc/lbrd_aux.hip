@@ -42,12 +42,13 @@ hipError_t launch_stepT(const StepLaunch &sl, const GridT &g, const void *params
 
 size_t stepT_lds_bytes(int storage, int nspecies, int tw, int th, int steps) {
     const int h = steps - 1;
-    return (size_t)9 * nspecies * (tw + 2 * h) * (th + 2 * h) * storage_bytes(storage);
+    const int b = storage_bytes(storage);
+    return (size_t)(th + 2 * h) * stepT_row_stride(nspecies, tw + 2 * h, b) * b;
 }
 
 int stepT_sites_per_thread(int tw, int th, int steps, int waves) {
     if (steps <= 2) return 0;
-    const int64_t middle = (int64_t)(tw + 2 * (steps - 1) - 2) * (th + 2 * (steps - 1) - 2);
+    const int64_t middle = (int64_t)(tw + 2 * (steps - 1)) * (th + 2 * (steps - 1) - 2);
     return (int)((middle + 64 * waves - 1) / (64 * waves));
 }
 

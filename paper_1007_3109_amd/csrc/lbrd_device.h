@@ -399,14 +399,14 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, uint32_t vof
 __device__ __forceinline__ uint32_t mul24(int a, uint32_t b) { return (uint32_t)__umul24((uint32_t)a, b); }
 
 // LDS layout of the multi-step region: row-interleaved planes, element
-// (plane P, column x, row y) at y * (9 N) * EW + P * EW + x, with EW the
-// region width.  A site's 9 N pulled inputs then sit at compile-time offsets
-// from one address (its lower-left neighbour), and consecutive lanes touch
-// consecutive words.
+// (plane P, column x, row y) at y * RS + P * EW + x, with EW the region width
+// and RS = stepT_row_stride (9 N EW plus bank padding).  A site's 9 N pulled
+// inputs then sit at compile-time offsets from one address (its lower-left
+// neighbour), and consecutive lanes touch consecutive banks.
 template <int ST, int NS, int EW>
 __device__ __forceinline__ void gather_lds(const typename Traits<ST>::T *L, int lx, int ly,
                                            typename Traits<ST>::C (&f)[NS][9]) {
-    constexpr int RS = 9 * NS * EW;
+    constexpr int RS = stepT_row_stride(NS, EW, (int)sizeof(typename Traits<ST>::T));
     const typename Traits<ST>::T *b = L + (ly - 1) * RS + (lx - 1);
 #pragma unroll
     for (int s = 0; s < NS; ++s)
@@ -416,7 +416,7 @@ __device__ __forceinline__ void gather_lds(const typename Traits<ST>::T *L, int 
 template <int ST, int NS, int EW>
 __device__ __forceinline__ void put_lds(typename Traits<ST>::T *L, int lx, int ly,
                                         const typename Traits<ST>::T (&o)[NS][9]) {
-    constexpr int RS = 9 * NS * EW;
+    constexpr int RS = stepT_row_stride(NS, EW, (int)sizeof(typename Traits<ST>::T));
     typename Traits<ST>::T *b = L + ly * RS + lx;
 #pragma unroll
     for (int s = 0; s < NS; ++s)
@@ -526,25 +526,28 @@ __device__ __forceinline__ void stepT_tile(const TileT &g, const Params<typename
         }
     }
     __syncthreads();
-    // middle phases: step t+j-1 -> t+j on the region shrunk by j-1, in LDS
+    // middle phases: step t+j-1 -> t+j on the region shrunk by j-1, in LDS.
+    // Threads walk whole region rows (all EW columns, the same order as phase
+    // 1, so the bank padding holds) and skip the columns outside the shrunk
+    // region.
 #pragma unroll
     for (int j = 2; j < TS; ++j) {
         if (VARM && j >= m) break;
-        const int rw = EW - 2 * (j - 1), rsz = rw * (eh - 2 * (j - 1));
+        const int rsz = EW * (eh - 2 * (j - 1));
         C f[MAXK][NS][9];
 #pragma unroll
         for (int k = 0; k < MAXK; ++k) {
-            const int q = threadIdx.x + k * nthr;
-            if (q < rsz) gather_lds<ST, NS, EW>(L, q % rw + j - 1, q / rw + j - 1, f[k]);
+            const int q = threadIdx.x + k * nthr, lx = q % EW;
+            if (q < rsz && lx >= j - 1 && lx < EW - (j - 1)) gather_lds<ST, NS, EW>(L, lx, q / EW + j - 1, f[k]);
         }
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < MAXK; ++k) {
-            const int q = threadIdx.x + k * nthr;
-            if (q < rsz) {
+            const int q = threadIdx.x + k * nthr, lx = q % EW;
+            if (q < rsz && lx >= j - 1 && lx < EW - (j - 1)) {
                 T o[NS][9];
                 collide_site<ST, V>(p, f[k], o);
-                put_lds<ST, NS, EW>(L, q % rw + j - 1, q / rw + j - 1, o);
+                put_lds<ST, NS, EW>(L, lx, q / EW + j - 1, o);
             }
         }
         __syncthreads();

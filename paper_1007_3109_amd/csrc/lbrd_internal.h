@@ -95,11 +95,22 @@ struct GridT {
 constexpr int kMaxFusedSteps = 4;
 
 GridT make_gridT(const Layout &L, const void *src, void *dst, int tw, int th, int steps);
+// LDS row stride (elements) of the multi-step region of width ew with 9 N
+// planes of `bytes`-byte elements: 9 N ew rounded up so that stride - ew is a
+// multiple of 256 bytes (64 banks of 4 bytes).  Consecutive sites in
+// row-major order over the region then fall in consecutive banks even where a
+// wave's sites wrap to the next row: no bank conflicts.
+__host__ __device__ constexpr int stepT_row_stride(int nspecies, int ew, int bytes) {
+    const int unit = 256 / bytes;
+    const int base = 9 * nspecies * ew;
+    return base + ((ew - base) % unit + unit) % unit;
+}
 // LDS bytes of a launch of `steps` steps on tw x th tiles.
 size_t stepT_lds_bytes(int storage, int nspecies, int tw, int th, int steps);
 // Sites per thread that the middle phases of a multi-step launch hold in
-// registers: the largest middle region over the workgroup's threads, rounded
-// up (0 for two steps, which have no middle phase).  Launch shapes that need
+// registers: the largest middle region (all tw + 2h columns of the rows it
+// spans) over the workgroup's threads, rounded up (0 for two steps, which have
+// no middle phase).  Launch shapes that need
 // more than 4 are rejected; 2 to 4 need at most 8 waves (a 512-thread
 // register budget).
 int stepT_sites_per_thread(int tw, int th, int steps, int waves);

@@ -390,18 +390,22 @@ FUSED_CASES = [("f64", "gray_scott", 2), ("f32", "gray_scott", 2), ("f16", "gray
 
 
 def multi_step_shape_fits(b, ns, cols, rows, steps, waves):
-    """The documented limits of a multi-step launch shape: 64 or 128 columns,
-    the LDS region (cols + 2h) x (rows + 2h) x 9 ns values (h = steps - 1)
-    within 160 KB, and the second phase's region (two sites smaller per axis)
-    within 1 site per thread, or 4 with at most 8 waves."""
+    """The documented limits of a multi-step launch shape: 64 or 128 columns;
+    the LDS region of rows + 2h rows (h = steps - 1), each row 9 ns (cols + 2h)
+    values padded to a multiple of 256 bytes beyond cols + 2h, within 160 KB;
+    and the second phase's rows (rows + 2h - 2 rows of cols + 2h sites) within
+    1 site per thread, or 4 with at most 8 waves."""
     if cols not in (64, 128):
         return False
     h = steps - 1
-    if 9 * ns * (cols + 2 * h) * (rows + 2 * h) * b > 160 * 1024:
+    ew = cols + 2 * h
+    unit = 256 // b
+    stride = 9 * ns * ew + (ew - 9 * ns * ew) % unit
+    if (rows + 2 * h) * stride * b > 160 * 1024:
         return False
     if steps == 2:
         return True
-    k = -(-((cols + 2 * h - 2) * (rows + 2 * h - 2)) // (64 * waves))
+    k = -(-(ew * (rows + 2 * h - 2)) // (64 * waves))
     return k <= 1 or (k <= 4 and waves <= 8)
 
 
