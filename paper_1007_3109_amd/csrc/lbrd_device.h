@@ -488,41 +488,70 @@ __device__ __forceinline__ void stepT_tile(const TileT &g, const Params<typename
         return;
     }
     const int eh = th + 2 * H, esz = EW * eh;
-    const bool one_wrap = nx >= TW + H && ny >= th + H;   // the region wraps at most once per axis
     // phase 1: step t -> t+1 on the whole region, from the source buffer
     const int dx = nthr % EW, dy = nthr / EW;
     int ex = (int)threadIdx.x % EW, ey = (int)threadIdx.x / EW;
-    for (int q = threadIdx.x; q < esz; q += nthr) {
-        int gx = x0 - H + ex, gy = y0 - H + ey;
-        if (one_wrap) {
-            gx += gx < 0 ? nx : 0;
-            gx -= gx >= nx ? nx : 0;
-            gy += gy < 0 ? ny : 0;
-            gy -= gy >= ny ? ny : 0;
-        } else {
-            gx = wrap_mod(gx, nx);
-            gy = wrap_mod(gy, ny);
+    if (x0 >= H + 1 && x0 + TW + H + 1 <= nx && y0 >= H + 1 && y0 + th + H + 1 <= ny) {
+        // Interior tile: the pulled region does not wrap.  The lane's byte
+        // offset from the region's lower-left site is advanced incrementally;
+        // the plane and the pull shift -e_i go into the wave-uniform offset.
+        const uint32_t base = mul24(y0 - H, g.pitch_b) + (uint32_t)(x0 - H) * B;
+        const uint32_t step = (uint32_t)dy * g.pitch_b + (uint32_t)dx * B, wrap = g.pitch_b - (uint32_t)EW * B;
+        uint32_t rel = mul24(ey, g.pitch_b) + (uint32_t)ex * B;
+        for (int q = threadIdx.x; q < esz; q += nthr) {
+            C f[NS][9];
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+#pragma unroll
+                for (int i = 0; i < 9; ++i)
+                    f[s][i] = decode_dev<ST>(buf_load<T>(
+                        g.src, rel, (uint32_t)(s * 9 + i) * g.pstride_b + base - kEy[i] * g.pitch_b - kEx[i] * B));
+            T o[NS][9];
+            collide_site<ST, V>(p, f, o);
+            put_lds<ST, NS, EW>(L, ex, ey, o);
+            ex += dx;
+            ey += dy;
+            rel += step;
+            if (ex >= EW) {
+                ex -= EW;
+                ++ey;
+                rel += wrap;
+            }
         }
-        // byte offsets of columns x-1, x, x+1 and rows y-1, y, y+1
-        const uint32_t cx[3] = {(uint32_t)(gx == 0 ? nx - 1 : gx - 1) * B, (uint32_t)gx * B,
-                                (uint32_t)(gx + 1 == nx ? 0 : gx + 1) * B};
-        const uint32_t ry[3] = {mul24(gy == 0 ? ny - 1 : gy - 1, g.pitch_b), mul24(gy, g.pitch_b),
-                                mul24(gy + 1 == ny ? 0 : gy + 1, g.pitch_b)};
-        C f[NS][9];
+    } else {
+        const bool one_wrap = nx >= TW + H && ny >= th + H;   // the region wraps at most once per axis
+        for (int q = threadIdx.x; q < esz; q += nthr) {
+            int gx = x0 - H + ex, gy = y0 - H + ey;
+            if (one_wrap) {
+                gx += gx < 0 ? nx : 0;
+                gx -= gx >= nx ? nx : 0;
+                gy += gy < 0 ? ny : 0;
+                gy -= gy >= ny ? ny : 0;
+            } else {
+                gx = wrap_mod(gx, nx);
+                gy = wrap_mod(gy, ny);
+            }
+            // byte offsets of columns x-1, x, x+1 and rows y-1, y, y+1
+            const uint32_t cx[3] = {(uint32_t)(gx == 0 ? nx - 1 : gx - 1) * B, (uint32_t)gx * B,
+                                    (uint32_t)(gx + 1 == nx ? 0 : gx + 1) * B};
+            const uint32_t ry[3] = {mul24(gy == 0 ? ny - 1 : gy - 1, g.pitch_b), mul24(gy, g.pitch_b),
+                                    mul24(gy + 1 == ny ? 0 : gy + 1, g.pitch_b)};
+            C f[NS][9];
 #pragma unroll
-        for (int s = 0; s < NS; ++s)
+            for (int s = 0; s < NS; ++s)
 #pragma unroll
-            for (int i = 0; i < 9; ++i)
-                f[s][i] = decode_dev<ST>(
-                    buf_load<T>(g.src, ry[1 - kEy[i]] + cx[1 - kEx[i]], (uint32_t)(s * 9 + i) * g.pstride_b));
-        T o[NS][9];
-        collide_site<ST, V>(p, f, o);
-        put_lds<ST, NS, EW>(L, ex, ey, o);
-        ex += dx;
-        ey += dy;
-        if (ex >= EW) {
-            ex -= EW;
-            ++ey;
+                for (int i = 0; i < 9; ++i)
+                    f[s][i] = decode_dev<ST>(
+                        buf_load<T>(g.src, ry[1 - kEy[i]] + cx[1 - kEx[i]], (uint32_t)(s * 9 + i) * g.pstride_b));
+            T o[NS][9];
+            collide_site<ST, V>(p, f, o);
+            put_lds<ST, NS, EW>(L, ex, ey, o);
+            ex += dx;
+            ey += dy;
+            if (ex >= EW) {
+                ex -= EW;
+                ++ey;
+            }
         }
     }
     __syncthreads();

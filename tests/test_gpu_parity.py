@@ -414,12 +414,13 @@ def test_multi_step_launch_is_bitwise_identical(storage, reaction, ns):
     """The LDS-tiled multi-step launch runs each site's arithmetic exactly as
     the one-step launch, so every population after 7 steps (T-step launches, a
     shorter launch for a remainder of 2 .. T-1, a one-step launch for a single
-    remaining step) is bitwise equal, on ragged and tiny lattices, for 2, 3 and
+    remaining step) is bitwise equal, on ragged and tiny lattices and on one
+    with interior tiles (whose pulled region does not wrap), for 2, 3 and
     4 steps per launch, both tile widths, several heights and workgroup
     sizes.  Shapes beyond the documented limits are rejected with EINVAL."""
     b = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[storage]
     ran = 0
-    for ny, nx in [(1, 1), (3, 3), (2, 5), (45, 67), (33, 130), (17, 257)]:
+    for ny, nx in [(1, 1), (3, 3), (2, 5), (45, 67), (33, 130), (17, 257), (70, 300)]:
         rng = np.random.default_rng(nx * 7 + ny)
         kw = dict(F=0.04, k=0.06) if reaction == "gray_scott" else dict(K=-0.01 * np.eye(ns))
         rref = (0.3,) * ns
