@@ -258,6 +258,26 @@ def serve_leg(torch, lbrd, workloads, n_requests, pool_gb, steps_range, seed=0, 
             "arena_peak_used_gb": round(st.arena_peak_used / 2 ** 30, 3)}
 
 
+def rescaling_leg(torch, steps=400000):
+    """Section IV length-rescaling study at paper scale (Figs. 11, 12): the
+    Turing-regime point eta = 2.016933, tau_GS = 2.7303 on boxes of side 128 ..
+    512 with diffusivities (L / 128)^2 (0.03, 0.015), 400000 steps (the
+    paper's t), plus control boxes of twice the side with unscaled
+    diffusivities; one batch."""
+    from paper_1007_3109_amd import studies
+
+    sizes = [128, 192, 256, 384, 512]
+    r = studies.rescaling_study(sizes, 128, (0.03, 0.015), 2.016933, 2.7303, steps, start="cos")
+    out = {"workload": f"Gray-Scott eta 2.016933 tau 2.7303, sides {sizes} with D scaled as L^2, {steps} steps, "
+                       f"controls at twice the side with unscaled D",
+           "stripe_count": {str(L): round(r["sizes"][L]["n"], 2) for L in sizes},
+           "q_max_L": {str(L): round(r["sizes"][L]["qL"], 2) for L in sizes},
+           "control_stripe_count": {f"{a}->{b}": round(c["n"], 2) for (a, b), c in r["control_modes"].items()},
+           "seconds": round(r["seconds"], 3), "mlups_per_species": round(r["mlups_per_species"], 1)}
+    torch.cuda.empty_cache()
+    return out
+
+
 def precision_leg(torch, lbrd, workloads, n=4096, steps=(1000, 10000), check_n=256):
     """16-bit shifted storage (rho_ref = (1, 0)) against FP32 storage on the
     same n^2 Gray-Scott field (same seed), and every storage form against the
@@ -367,7 +387,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--tune", action="store_true", help="run the library's autotuner before timing")
     ap.add_argument("--extra-steps", type=int, default=300)
-    ap.add_argument("--legs", default="hbm4096_f32,hbm4096_f16,hbm4096_bf16,batch,serve,precision,config1,copy",
+    ap.add_argument("--legs", default="hbm4096_f32,hbm4096_f16,hbm4096_bf16,batch,serve,precision,rescaling,config1,copy",
                     help="extra legs to run (comma list)")
     ap.add_argument("--serve-requests", type=int, default=120)
     args = ap.parse_args()
@@ -454,6 +474,9 @@ def main():
         if "precision" in legs:
             log("bench: precision forms")
             extra["precision"] = precision_leg(torch, lbrd, workloads)
+        if "rescaling" in legs:
+            log("bench: rescaling study")
+            extra["rescaling"] = rescaling_leg(torch)
         if "config1" in legs:
             log("bench: 64^2 f64")
             extra["config1"] = config1_leg(torch, lbrd, workloads)

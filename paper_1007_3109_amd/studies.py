@@ -6,6 +6,18 @@ Gaussian, Eq. "reac_diff5", over a grid of diffusivities D_A and decay rates
 kappa, each lattice taken to the same diffusion extent D t = C.  All lattices
 run together in one batch (FP64 storage by default); E_rho is reduced on the
 device in FP64.
+
+phase_diagram: Gray-Scott runs over (eta, tau_GS) points from the perturbed
+homogeneous state (Section III.D, Figs. 6-8), with the power spectrum of v
+computed on the device and the dominant mode set against the linear-stability
+band.
+
+rescaling_study: the length-rescaling test of Section IV (Figs. 10-12): the
+same dimensionless (eta, tau_GS, eps) on boxes of side L with every
+diffusivity scaled as (L / L_ref)^2 and the start scaled with the box; the
+pattern should be the same up to the scale factor (equal stripe or spot
+count, q_max L constant, block-averaged fields and normalised profiles
+alike), which a control run with unscaled diffusivities does not show.
 """
 from __future__ import annotations
 
@@ -107,3 +119,97 @@ def phase_diagram(points, Du_over_Dv: float = 8.0, L: int = 64, steps: int = 400
         out.append(m)
     b.close()
     return out, {"seconds": secs, "mlups_per_species": 2 * L * L * steps * len(cfgs) / secs / 1e6}
+
+
+def _block_average(a: np.ndarray, b: int) -> np.ndarray:
+    n, L, _ = a.shape
+    return a.reshape(n, L // b, b, L // b, b).mean(axis=(2, 4))
+
+
+def _rel_l2(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    d = (a - b).reshape(a.shape[0], -1)
+    r = b.reshape(b.shape[0], -1)
+    return np.sqrt((d * d).sum(axis=1) / np.maximum((r * r).sum(axis=1), 1e-300))
+
+
+def _profile(v: np.ndarray, frac: float, points: int) -> np.ndarray:
+    """v along the row y = round(frac L), resampled (periodic linear
+    interpolation) at `points` equally spaced positions x / L in [0, 1)."""
+    L = v.shape[1]
+    row = v[int(round(frac * L)) % v.shape[0]]
+    xs = np.arange(points) * L / points
+    i0 = np.floor(xs).astype(int)
+    w = xs - i0
+    return (1 - w) * row[i0 % L] + w * row[(i0 + 1) % L]
+
+
+def rescaling_study(sizes, L_ref: int, D_ref, eta: float, tau: float, steps: int, start: str = "box",
+                    box_ref: int = 20, phi: float = 1e-3, control: bool = True, profile_y: float = 0.85,
+                    profile_points: int = 200, storage: str = "f32", device="cuda"):
+    """Section IV: Gray-Scott at fixed (eta, tau_GS) (so F and k fixed) on
+    boxes of side L in `sizes`, with (D_u, D_v) = (L / L_ref)^2 D_ref.  Start
+    "box": the trivial state with a central square of side box_ref L / L_ref at
+    u = 0.5, v = 0.25 (Figs. 9, 10); start "cos": the B~- state plus
+    phi cos(2 pi x / L) cos(2 pi y / L) on both species (Figs. 7, 11).  All
+    lattices run `steps` steps in one batch.  With control=True every size
+    that is twice another also runs with the smaller size's diffusivities.
+
+    Returns per size: the initial and final densities (host, FP64), the
+    dominant mode (n_x, n_y) of v, its length n (the stripe count), q_max and
+    q_max L (Eq. "reac_diff35"), the profile of v along y = profile_y L
+    resampled at profile_points positions x / L; for each pair (L, 2L): the
+    relative L2 gap between the 2 x 2 block average of the 2L field and the L
+    field (rescaled run, and control run), and the control run's mode."""
+    import torch
+
+    from . import lbrd
+
+    sizes = sorted(int(L) for L in sizes)
+    F, k = analysis.feed_kill(eta, tau)
+    runs = []                                  # (L, D, is_control)
+    for L in sizes:
+        lam = L / L_ref
+        runs.append((L, (lam * lam * D_ref[0], lam * lam * D_ref[1]), False))
+    if control:
+        for L in sizes:
+            if 2 * L in sizes:
+                lam = L / L_ref
+                runs.append((2 * L, (lam * lam * D_ref[0], lam * lam * D_ref[1]), True))
+    cfgs, inits = [], []
+    for L, D, _ in runs:
+        taus = (3 * D[0] + 0.5, 3 * D[1] + 0.5)          # D = (tau - 1/2) / 3
+        cfgs.append(lbrd.make_config(L, L, 2, tau=taus, storage=storage, reaction="gray_scott", F=F, k=k))
+        if start == "box":
+            inits.append(workloads.gs_box(L, int(round(box_ref * L / L_ref))))
+        else:
+            u, v = analysis.lattice_state(F, k, "-")
+            inits.append(workloads.perturbed_state(L, L, u, v, phi, (1, 1)))
+    b = lbrd.Batch(cfgs, device=device)
+    for i, r in enumerate(inits):
+        b.init(i, r)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    fields, per_size, control_modes = {}, {}, {}
+    for i, (L, D, is_ctrl) in enumerate(runs):
+        rho = b.moments(i)[0].cpu().numpy()
+        fields[(L, is_ctrl)] = rho
+        mode, q, _ = dominant_mode(b.spectrum(i, 1).cpu().numpy())
+        if is_ctrl:
+            control_modes[(L // 2, L)] = dict(D=D, mode=mode, n=float(np.hypot(*mode)), q_max=q, qL=q * L)
+            continue
+        per_size[L] = dict(D=D, mode=mode, n=float(np.hypot(*mode)), q_max=q, qL=q * L,
+                           profile=_profile(rho[1], profile_y, profile_points), rho=rho, v=rho[1], init=inits[i])
+    b.close()
+    gaps, control_gaps = {}, {}
+    for L in sizes:
+        if 2 * L in sizes:
+            coarse = fields[(L, False)]
+            gaps[(L, 2 * L)] = _rel_l2(_block_average(fields[(2 * L, False)], 2), coarse)
+            if control:
+                control_gaps[(L, 2 * L)] = _rel_l2(_block_average(fields[(2 * L, True)], 2), coarse)
+    site_steps = sum(2 * L * L for L, _, _ in runs) * steps
+    return {"F": F, "k": k, "sizes": per_size, "gaps": gaps, "control_gaps": control_gaps,
+            "control_modes": control_modes, "seconds": secs, "mlups_per_species": site_steps / secs / 1e6}

@@ -70,6 +70,18 @@ def gray_scott_square(nx: int, ny: int | None = None, seed: int = 0, noise: floa
     return rho
 
 
+def gs_box(side: int, box: int, u_in: float = 0.5, v_in: float = 0.25) -> np.ndarray:
+    """Noiseless Gray-Scott start [2][side][side]: u = 1, v = 0 with a central
+    box x box square at (u_in, v_in) (the finite perturbation of the trivial
+    state of Section IV, Fig. 9), rows and columns [side/2 - box/2, +box)."""
+    rho = np.zeros((2, side, side))
+    rho[0] = 1.0
+    lo = side // 2 - box // 2
+    rho[0, lo:lo + box, lo:lo + box] = u_in
+    rho[1, lo:lo + box, lo:lo + box] = v_in
+    return rho
+
+
 def perturbed_state(nx: int, ny: int, u: float, v: float, amp: float, mode=(1, 1)) -> np.ndarray:
     """Homogeneous (u, v) plus amp * cos(2 pi mx x/nx) cos(2 pi my y/ny) on both
     species (the small-amplitude start of Section III.D)."""

@@ -87,3 +87,35 @@ def test_phase_diagram_signs_and_band():
     ref = oracle.solve(rho0, 1500, taus, oracle.REACT_GRAY_SCOTT, F=F, k=k)
     floor = oracle.rel_l2(oracle.solve(rho0, 1500, taus, oracle.REACT_GRAY_SCOTT, precision="f32", F=F, k=k), ref)
     assert np.all(oracle.rel_l2(got, ref) <= np.maximum(1e-5, 3 * floor))
+
+
+def test_rescaling_study_keeps_stripe_count():
+    """Section IV (Figs. 11, 12): at the Turing-regime point eta = 2.016933,
+    tau_GS = 2.7303 (D_u / D_v = 2), boxes of side 64 .. 256 with both
+    diffusivities scaled as (L / 64)^2 and the cos(2 pi x / L) cos(2 pi y / L)
+    start keep the stripe count |n| of the dominant mode (q_max L constant
+    within 15 %), while a box twice as large with the smaller box's
+    diffusivities doubles it.  The smallest lattice equals the FP64 oracle
+    within the FP32 rounding floor."""
+    from paper_1007_3109_amd import studies
+
+    sizes = [64, 96, 128, 192, 256]
+    res = studies.rescaling_study(sizes, 64, (0.03, 0.015), 2.016933, 2.7303, 20000, start="cos")
+    ns = {L: res["sizes"][L]["n"] for L in sizes}
+    print(f"rescaling: stripe counts {ns}, control {[(k, c['n']) for k, c in res['control_modes'].items()]}, "
+          f"{res['seconds']:.2f} s", flush=True)
+    med = float(np.median(list(ns.values())))
+    assert med > 6                                    # a developed pattern, not the start's mode 1
+    for L in sizes:
+        assert abs(ns[L] - med) <= 0.15 * med, (L, ns)
+    for (L, L2), c in res["control_modes"].items():
+        assert abs(c["n"] - 2 * ns[L]) <= 0.25 * 2 * ns[L], (L, L2, c["n"], ns[L])
+    # parity of the batched lattice with the oracle (2000 steps, smallest box)
+    short = studies.rescaling_study([64, 128], 64, (0.03, 0.015), 2.016933, 2.7303, 2000, start="cos", control=False)
+    d = short["sizes"][64]
+    taus = [oracle.tau_from_diffusivity(x) for x in d["D"]]
+    kw = dict(F=short["F"], k=short["k"])
+    ref = oracle.solve(d["init"], 2000, taus, oracle.REACT_GRAY_SCOTT, **kw)
+    floor = oracle.rel_l2(oracle.solve(d["init"], 2000, taus, oracle.REACT_GRAY_SCOTT, precision="f32", **kw), ref)
+    tol = np.where(floor <= 1e-6, 1e-5, 3 * floor)
+    assert np.all(oracle.rel_l2(d["rho"], ref) <= tol), (oracle.rel_l2(d["rho"], ref), floor)
