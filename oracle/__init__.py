@@ -82,13 +82,14 @@ def _load():
             pd = ctypes.POINTER(ctypes.c_double)
             pi = ctypes.POINTER(ctypes.c_int)
             getattr(lib, f"orc_tables_{sfx}").argtypes = [P, pi, pi]
-            getattr(lib, f"orc_init_{sfx}").argtypes = [ctypes.c_int] * 3 + [pd, P]
+            getattr(lib, f"orc_init_{sfx}").argtypes = [ctypes.c_int] * 3 + [pd, pd, P]
             fn = getattr(lib, f"orc_run_{sfx}")
-            fn.argtypes = [ctypes.c_int] * 3 + [pd, ctypes.c_int, pd, ctypes.c_int, pd, P, P, ctypes.c_int64]
+            fn.argtypes = [ctypes.c_int] * 3 + [pd, ctypes.c_int, pd, ctypes.c_int, pd, pd, P, P, ctypes.c_int64]
+            getattr(lib, f"orc_eq_coefs_{sfx}").argtypes = [pd, P]
             fn.restype = ctypes.c_int
             getattr(lib, f"orc_moments_{sfx}").argtypes = [ctypes.c_int] * 3 + [P, pd]
             getattr(lib, f"orc_threads_{sfx}").restype = ctypes.c_int
-            getattr(lib, f"orc_encode_{sfx}").argtypes = [ctypes.c_int] * 4 + [pd, P]
+            getattr(lib, f"orc_encode_{sfx}").argtypes = [ctypes.c_int] * 4 + [pd, pd, P]
             pf = ctypes.POINTER(ctypes.c_float)
             getattr(lib, f"orc_quantise_{sfx}").argtypes = [ctypes.c_int, pf, pf, ctypes.c_int64]
         _lib = lib
@@ -122,13 +123,37 @@ def tables(precision: str = "f64"):
     return w, ex, ey
 
 
-def init(rho0: np.ndarray, precision: str = "f64") -> np.ndarray:
-    """Equilibrium populations f_{i,s} = w_i rho0_s, shape [N][9][ny][nx]."""
+def _velocity(u):
+    """None, or the 2 components of the equilibrium velocity as a C array."""
+    if u is None:
+        return None
+    a = np.ascontiguousarray(np.asarray(u, np.float64).reshape(2))
+    return a
+
+
+def _uptr(a):
+    return None if a is None else _ptr(a, ctypes.c_double)
+
+
+def eq_coefs(u=None, precision: str = "f64") -> np.ndarray:
+    """The oracle's equilibrium coefficients c_i(u) of Eq. "Maxwellian"
+    (f^eq_i = c_i rho; c_i = w_i when u is None or zero)."""
+    npdt, ct = _dt(precision)
+    c = np.zeros(9, npdt)
+    ua = _velocity(u)
+    getattr(_load(), f"orc_eq_coefs_{precision}")(_uptr(ua), _ptr(c, ct))
+    return c
+
+
+def init(rho0: np.ndarray, precision: str = "f64", u=None) -> np.ndarray:
+    """Equilibrium populations f_{i,s} = c_i(u) rho0_s (c_i = w_i without a
+    velocity), shape [N][9][ny][nx]."""
     rho0 = np.ascontiguousarray(rho0, dtype=np.float64)
     n, ny, nx = rho0.shape
     npdt, ct = _dt(precision)
     f = np.zeros((n, 9, ny, nx), npdt)
-    getattr(_load(), f"orc_init_{precision}")(n, nx, ny, _ptr(rho0, ctypes.c_double), _ptr(f, ct))
+    ua = _velocity(u)
+    getattr(_load(), f"orc_init_{precision}")(n, nx, ny, _ptr(rho0, ctypes.c_double), _uptr(ua), _ptr(f, ct))
     return f
 
 
@@ -143,13 +168,14 @@ def _params(reaction: int, n: int, K=None, c=None, F=None, k=None) -> np.ndarray
 
 
 def run(f: np.ndarray, nsteps: int, tau, reaction: int = REACT_NONE, *, K=None, c=None, F=None, k=None,
-        quant: int = Q_NONE, rho_ref=None) -> np.ndarray:
+        quant: int = Q_NONE, rho_ref=None, u=None) -> np.ndarray:
     """Advance populations f [N][9][ny][nx] by nsteps; returns a new array.
 
     The dtype of f selects the build (float64: the oracle proper; float32: the
     rounding-floor / storage-emulation build).  ``quant`` (float32 only) rounds
     every stored population to binary16 or bfloat16 after subtracting
-    w_i * rho_ref[s], the 16-bit shifted storage form.
+    c_i * rho_ref[s], the 16-bit shifted storage form.  ``u`` is the
+    equilibrium velocity of Eq. "Maxwellian" (None: the paper's u = 0).
     """
     f = np.array(f, copy=True, order="C")
     precision = {np.dtype(np.float64): "f64", np.dtype(np.float32): "f32"}[f.dtype]
@@ -162,21 +188,23 @@ def run(f: np.ndarray, nsteps: int, tau, reaction: int = REACT_NONE, *, K=None, 
     if quant != Q_NONE and precision != "f32":
         raise ValueError("storage emulation runs in the float build")
     work = np.empty_like(f)
+    ua = _velocity(u)
     rc = getattr(_load(), f"orc_run_{precision}")(
         n, nx, ny, _ptr(tau, ctypes.c_double), reaction, _ptr(params, ctypes.c_double), quant,
-        _ptr(rref, ctypes.c_double), _ptr(f, ct), _ptr(work, ct), int(nsteps))
+        _ptr(rref, ctypes.c_double), _uptr(ua), _ptr(f, ct), _ptr(work, ct), int(nsteps))
     if rc != 0:
         raise ValueError("oracle rejected its arguments")
     return f
 
 
-def encode(f: np.ndarray, quant: int, rho_ref) -> np.ndarray:
+def encode(f: np.ndarray, quant: int, rho_ref, u=None) -> np.ndarray:
     """Populations in the 16-bit shifted storage form (float build):
-    w_i rho_ref_s + Q(f - w_i rho_ref_s); returns a new float32 array."""
+    c_i rho_ref_s + Q(f - c_i rho_ref_s); returns a new float32 array."""
     f = np.array(f, dtype=np.float32, copy=True, order="C")
     n, _, ny, nx = f.shape
     rref = np.ascontiguousarray(np.asarray(rho_ref, np.float64).reshape(n))
-    _load().orc_encode_f32(n, nx, ny, quant, _ptr(rref, ctypes.c_double), _ptr(f, ctypes.c_float))
+    ua = _velocity(u)
+    _load().orc_encode_f32(n, nx, ny, quant, _ptr(rref, ctypes.c_double), _uptr(ua), _ptr(f, ctypes.c_float))
     return f
 
 
@@ -226,6 +254,6 @@ def tau_from_diffusivity(D: float) -> float:
 
 def solve(rho0: np.ndarray, nsteps: int, tau, reaction: int = REACT_NONE, precision: str = "f64", **kw):
     """Convenience: equilibrium init, nsteps of the update, density read-out."""
-    f = init(rho0, precision)
+    f = init(rho0, precision, kw.get("u"))
     f = run(f, nsteps, tau, reaction, **kw)
     return moments(f)

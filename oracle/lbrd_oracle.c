@@ -19,11 +19,14 @@
  *
  * The update is written in "push" form, exactly as the paper writes it:
  *     f_{i,s}(x + e_i, t + 1) = f_{i,s}(x, t)
- *                               + (w_i rho_s(x,t) - f_{i,s}(x,t)) / tau_s
+ *                               + (f^eq_{i,s}(x,t) - f_{i,s}(x,t)) / tau_s
  *                               + w_i R_s(rho_1..rho_N)(x, t)
  * with rho_s = sum_i f_{i,s} (Section II.A, the sentence after Eq. "relax"),
  * f^eq_{i,s} = w_i rho_s (Eq. "equili"), periodic wrap in x and y
- * (Section II.B and Section IV), lattice units dx = dt = 1.
+ * (Section II.B and Section IV), lattice units dx = dt = 1.  With a
+ * prescribed uniform velocity u the equilibrium is the low-Mach Maxwellian
+ * of Eq. "Maxwellian", f^eq_{i,s} = c_i(u) rho_s (the paper's runs have
+ * u = 0, which gives c_i = w_i exactly).
  */
 #include <stdint.h>
 #include <stddef.h>
@@ -65,6 +68,27 @@ static REAL weight(int i)
     if (i == 0) return (REAL)4 / (REAL)9;
     if (i <= 4) return (REAL)1 / (REAL)9;
     return (REAL)1 / (REAL)36;
+}
+
+/* Equilibrium coefficient of Eq. "Maxwellian" with c_s^2 = 1/3 (Section
+ * II.A): f^eq_i = c_i rho with
+ *     c_i = w_i [1 + (e_i.u) / c_s^2 + (e_i.u)^2 / (2 c_s^4) - (u.u) / (2 c_s^2)].
+ * u = NULL or u = (0, 0) returns w_i itself (Eq. "equili"). */
+static REAL eq_coef(int i, const double *u)
+{
+    const REAL w = weight(i);
+    if (!u || (u[0] == 0.0 && u[1] == 0.0)) return w;
+    const REAL ux = (REAL)u[0], uy = (REAL)u[1];
+    const REAL cs2 = (REAL)1 / (REAL)3;
+    const REAL eu = (REAL)EX[i] * ux + (REAL)EY[i] * uy;
+    const REAL uu = ux * ux + uy * uy;
+    return w * ((REAL)1 + eu / cs2 + eu * eu / ((REAL)2 * cs2 * cs2) - uu / ((REAL)2 * cs2));
+}
+
+/* Expose the equilibrium coefficients c_i(u) (for the tests). */
+void SFX(orc_eq_coefs)(const double *u, REAL *c)
+{
+    for (int i = 0; i < 9; ++i) c[i] = eq_coef(i, u);
 }
 
 /* Threads the parallel step uses (1 without OpenMP). */
@@ -169,12 +193,13 @@ void SFX(orc_quantise)(int quant, const float *in, float *out, int64_t n)
 }
 
 /* Put populations f [N][9][ny][nx] into the 16-bit shifted storage form in
- * place: f <- w_i rho_ref_s + Q(f - w_i rho_ref_s), Q the 16-bit rounding. */
-void SFX(orc_encode)(int n, int nx, int ny, int quant, const double *rho_ref, REAL *f)
+ * place: f <- c_i rho_ref_s + Q(f - c_i rho_ref_s), Q the 16-bit rounding,
+ * c_i the equilibrium coefficient (w_i when u = 0). */
+void SFX(orc_encode)(int n, int nx, int ny, int quant, const double *rho_ref, const double *u, REAL *f)
 {
     for (int s = 0; s < n; ++s)
         for (int i = 0; i < 9; ++i) {
-            const REAL shift = weight(i) * (REAL)rho_ref[s];
+            const REAL shift = eq_coef(i, u) * (REAL)rho_ref[s];
             for (int y = 0; y < ny; ++y)
                 for (int x = 0; x < nx; ++x) {
                     REAL *p = &f[idx(nx, ny, s, i, y, x)];
@@ -183,23 +208,24 @@ void SFX(orc_encode)(int n, int nx, int ny, int quant, const double *rho_ref, RE
         }
 }
 
-/* Initial populations: local equilibrium f_{i,s}(x,0) = w_i rho_s(x,0)
- * (Eq. "equili"; the paper does not state the initial populations, this is
- * the reading used throughout).  rho0 is [N][ny][nx]. */
-void SFX(orc_init)(int n, int nx, int ny, const double *rho0, REAL *f)
+/* Initial populations: local equilibrium f_{i,s}(x,0) = c_i rho_s(x,0)
+ * (Eq. "equili", or Eq. "Maxwellian" with velocity u; the paper does not
+ * state the initial populations, this is the reading used throughout).
+ * rho0 is [N][ny][nx]; u is NULL or 2 values. */
+void SFX(orc_init)(int n, int nx, int ny, const double *rho0, const double *u, REAL *f)
 {
     for (int s = 0; s < n; ++s)
         for (int i = 0; i < 9; ++i)
             for (int y = 0; y < ny; ++y)
                 for (int x = 0; x < nx; ++x)
                     f[idx(nx, ny, s, i, y, x)] =
-                        weight(i) * (REAL)rho0[((size_t)s * ny + y) * nx + x];
+                        eq_coef(i, u) * (REAL)rho0[((size_t)s * ny + y) * nx + x];
 }
 
 /* One time step t -> t+1 of the update equation, push form, f -> fn. */
 static void step_once(int n, int nx, int ny, const double *tau, int kind,
                       const double *params, int quant, const double *rho_ref,
-                      const REAL *f, REAL *fn)
+                      const double *u, const REAL *f, REAL *fn)
 {
 #pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; ++y) {
@@ -216,10 +242,11 @@ static void step_once(int n, int nx, int ny, const double *tau, int kind,
                 for (int i = 0; i < 9; ++i) {
                     const REAL fi = f[idx(nx, ny, s, i, y, x)];
                     const REAL wi = weight(i);
-                    REAL g = fi + (wi * rho[s] - fi) / (REAL)tau[s] + wi * R[s];
+                    const REAL ci = eq_coef(i, u);
+                    REAL g = fi + (ci * rho[s] - fi) / (REAL)tau[s] + wi * R[s];
                     if (quant != ORC_Q_NONE) {
-                        /* storage form: g - w_i rho_ref,s rounded to 16 bits */
-                        const REAL shift = wi * (REAL)rho_ref[s];
+                        /* storage form: g - c_i rho_ref,s rounded to 16 bits */
+                        const REAL shift = ci * (REAL)rho_ref[s];
                         g = shift + quantise(quant, g - shift);
                     }
                     int xd = x + EX[i], yd = y + EY[i];
@@ -235,16 +262,17 @@ static void step_once(int n, int nx, int ny, const double *tau, int kind,
 }
 
 /* Advance f (in place, [N][9][ny][nx]) by nsteps.  work is a caller buffer
- * of the same size.  Returns 0, or -1 on bad arguments. */
+ * of the same size; u is NULL (no advection) or the 2 components of the
+ * equilibrium velocity.  Returns 0, or -1 on bad arguments. */
 int SFX(orc_run)(int n, int nx, int ny, const double *tau, int kind,
                  const double *params, int quant, const double *rho_ref,
-                 REAL *f, REAL *work, int64_t nsteps)
+                 const double *u, REAL *f, REAL *work, int64_t nsteps)
 {
     if (n < 1 || n > ORC_MAX_SPECIES || nx < 1 || ny < 1 || nsteps < 0) return -1;
     if (kind == ORC_REACT_GRAY_SCOTT && n != 2) return -1;
     REAL *a = f, *b = work;
     for (int64_t t = 0; t < nsteps; ++t) {
-        step_once(n, nx, ny, tau, kind, params, quant, rho_ref, a, b);
+        step_once(n, nx, ny, tau, kind, params, quant, rho_ref, u, a, b);
         REAL *tmp = a;
         a = b;
         b = tmp;

@@ -32,11 +32,22 @@ def golden(name: str = "paper_values.txt") -> dict:
     return out
 
 
-def propagator(q, taus, J, w, ex, ey) -> np.ndarray:
+def maxwellian_coefs(u, w, ex, ey) -> np.ndarray:
+    """c_i(u) = w_i [1 + 3 e_i.u + 9/2 (e_i.u)^2 - 3/2 u.u]: Eq. "Maxwellian"
+    with c_s^2 = 1/3, written out with the constants folded (independent of the
+    oracle's own expression)."""
+    ux, uy = u
+    eu = np.asarray(ex, float) * ux + np.asarray(ey, float) * uy
+    return np.asarray(w, float) * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * (ux * ux + uy * uy))
+
+
+def propagator(q, taus, J, w, ex, ey, ceq=None) -> np.ndarray:
     """One-step Fourier propagator P(q) of the update for a linear reaction
-    R_s = sum_r J[s][r] rho_r (9N x 9N, species-major, velocity index i)."""
+    R_s = sum_r J[s][r] rho_r (9N x 9N, species-major, velocity index i); the
+    equilibrium is ceq_i rho (ceq = w without a velocity)."""
     qx, qy = q
     n = len(taus)
+    ceq = w if ceq is None else ceq
     P = np.zeros((9 * n, 9 * n), complex)
     for s in range(n):
         om = 1.0 / taus[s]
@@ -45,7 +56,7 @@ def propagator(q, taus, J, w, ex, ey) -> np.ndarray:
             ph = np.exp(-1j * (qx * ex[i] + qy * ey[i]))
             P[row, row] += ph * (1.0 - om)
             for j in range(9):
-                P[row, 9 * s + j] += ph * w[i] * om
+                P[row, 9 * s + j] += ph * ceq[i] * om
             for r in range(n):
                 for j in range(9):
                     P[row, 9 * r + j] += ph * w[i] * J[s][r]

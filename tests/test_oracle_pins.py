@@ -14,7 +14,7 @@ import pytest
 
 import oracle
 from paper_1007_3109_amd import analysis, workloads
-from pins import gaussian_point_source, golden, gs_jacobian, gs_reaction, propagator, source_vector
+from pins import gaussian_point_source, golden, gs_jacobian, gs_reaction, maxwellian_coefs, propagator, source_vector
 
 G = golden()
 
@@ -158,6 +158,73 @@ def test_linear_reaction_fourier_propagator(shape):
                 if mx == 0 and my == 0:
                     v = v + source_vector(c, w, ex, ey, nx * ny)
             assert np.abs(v - Fn[:, my, mx]).max() <= 1e-12 * scale
+
+
+# ----- advective equilibrium (Eq. "Maxwellian" with a uniform velocity) -------
+
+VELOCITIES = [(0.1, -0.05), (-0.2, 0.0), (0.03, 0.17)]
+
+
+@pytest.mark.parametrize("u", VELOCITIES)
+def test_maxwellian_equilibrium_moments(u):
+    """The oracle's c_i(u) carry the moments of the low-Mach Maxwellian on
+    D2Q9: sum c_i = 1, sum c_i e_i = u, sum c_i e_i e_i^T = c_s^2 I + u u^T
+    (c_s^2 = 1/3), up to FP64 rounding (1e-15); u = 0 gives the weights
+    themselves."""
+    c = oracle.eq_coefs(u)
+    w, ex, ey = oracle.tables()
+    E = np.stack([ex, ey]).astype(float)
+    assert abs(c.sum() - 1.0) <= 1e-15
+    assert np.allclose(E @ c, u, rtol=0, atol=1e-15)
+    second = (E * c) @ E.T
+    assert np.allclose(second, np.eye(2) / 3 + np.outer(u, u), rtol=0, atol=1e-15)
+    assert np.array_equal(oracle.eq_coefs(None), w) and np.array_equal(oracle.eq_coefs((0.0, 0.0)), w)
+    assert np.allclose(c, maxwellian_coefs(u, w, ex, ey), rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("u", VELOCITIES[:2])
+def test_advective_linear_fourier_propagator(u):
+    """With a velocity in the equilibrium every Fourier mode still evolves by
+    the 9N x 9N one-step matrix, now with c_i(u) in place of w_i in the
+    equilibrium (the source keeps w_i): random non-equilibrium populations,
+    two species with a linear reaction, to 1e-12."""
+    ny, nx = 5, 7
+    rng = np.random.default_rng(11)
+    taus = [0.7, 1.1]
+    K = np.array([[-0.04, 0.01], [0.02, -0.03]])
+    f0 = random_populations(rng, 2, ny, nx)
+    nsteps = 6
+    f = oracle.run(f0, nsteps, taus, oracle.REACT_LINEAR, K=K, u=u)
+    w, ex, ey = oracle.tables()
+    ceq = maxwellian_coefs(u, w, ex, ey)
+    F0 = np.fft.fft2(f0, axes=(2, 3)).reshape(18, ny, nx)
+    Fn = np.fft.fft2(f, axes=(2, 3)).reshape(18, ny, nx)
+    scale = np.abs(F0).max()
+    for my in range(ny):
+        for mx in range(nx):
+            P = propagator((2 * math.pi * mx / nx, 2 * math.pi * my / ny), taus, K, w, ex, ey, ceq)
+            v = np.linalg.matrix_power(P, nsteps) @ F0[:, my, mx]
+            assert np.abs(v - Fn[:, my, mx]).max() <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("u", VELOCITIES)
+def test_advection_moves_centre_of_mass_by_u(u):
+    """Without reaction the first moment of the equilibrium is rho u, so the
+    total momentum stays M u through every collision and streaming: the centre
+    of mass of a blob moves by exactly u per step, for any tau.  Gaussian blob
+    on a 160 x 160 box (tails below 1e-25 at the edges), 60 steps."""
+    L, n = 160, 60
+    x = np.arange(L)[None, :] - L / 2
+    y = np.arange(L)[:, None] - L / 2
+    rho0 = (1.0 + 0.0 * x + 0.0 * y) * np.exp(-(x * x + y * y) / 18.0)
+    rho0 = rho0[None]
+    for tau in (0.6, 1.3):
+        rho = oracle.solve(rho0, n, [tau], oracle.REACT_NONE, u=u)
+        M = rho.sum()
+        cx = (rho[0] * x).sum() / M
+        cy = (rho[0] * y).sum() / M
+        assert abs(cx - n * u[0]) <= 1e-10 and abs(cy - n * u[1]) <= 1e-10, (tau, cx, cy)
+        assert abs(M - rho0.sum()) <= 1e-11 * M
 
 
 # ----- pin 5: mass invariants ------------------------------------------------
