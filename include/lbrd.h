@@ -59,8 +59,9 @@ extern "C" {
 /* Population storage forms. */
 #define LBRD_F64 0            /* double populations, double arithmetic               */
 #define LBRD_F32 1            /* float populations, float arithmetic                 */
-#define LBRD_F16_SHIFTED 2    /* binary16 of f - w_i rho_ref_s, float arithmetic     */
-#define LBRD_BF16_SHIFTED 3   /* bfloat16 of f - w_i rho_ref_s, float arithmetic     */
+#define LBRD_F16_SHIFTED 2    /* binary16 of f - c_i rho_ref_s, float arithmetic     */
+#define LBRD_BF16_SHIFTED 3   /* bfloat16 of f - c_i rho_ref_s, float arithmetic     */
+                              /* (c_i = w_i, or c_i(u) with an advection velocity)   */
 
 /* Reaction terms R_s. */
 #define LBRD_REACT_NONE 0        /* R_s = 0                                           */
@@ -86,6 +87,16 @@ typedef struct lbrd_config {
     double K[LBRD_MAX_SPECIES * LBRD_MAX_SPECIES]; /* LINEAR: K[s*N + j]              */
     double c[LBRD_MAX_SPECIES];        /* LINEAR: constant source                      */
     double F, k;                       /* GRAY_SCOTT: feed and kill rates              */
+    double u[2];                       /* advection velocity (lattice units) of the    */
+                                       /* equilibrium, the same for every species:     */
+                                       /* f^eq_i = c_i rho with the low-Mach Maxwellian */
+                                       /* c_i = w_i [1 + 3 e_i.u + 9/2 (e_i.u)^2       */
+                                       /*            - 3/2 u.u] (Section II.A, Eq.     */
+                                       /* "Maxwellian", c_s^2 = 1/3); (0, 0) is the    */
+                                       /* paper's pure reaction-diffusion.  Non-zero u */
+                                       /* needs u.u < 1/3 and GRAY_SCOTT, or N = 1 with */
+                                       /* LINEAR or NONE; otherwise LBRD_EINVAL.  The  */
+                                       /* source term keeps w_i R_s.                   */
 } lbrd_config;
 
 /* Kernel launch shape.

@@ -63,13 +63,25 @@ Params<C> make_params(const lbrd_config &c) {
     std::memset(&p, 0, sizeof(p));
     const int n = c.nspecies;
     const C w[3] = {C(4) / C(9), C(1) / C(9), C(1) / C(36)};
+    // equilibrium coefficients: the weights, or the low-Mach Maxwellian
+    // c_i = w_i [1 + 3 e.u + 9/2 (e.u)^2 - 3/2 u.u] evaluated in double
+    p.adv = (c.u[0] != 0.0 || c.u[1] != 0.0) ? 1 : 0;
+    for (int i = 0; i < 9; ++i) {
+        const C wi = i == 0 ? w[0] : (i < 5 ? w[1] : w[2]);
+        if (!p.adv) {
+            p.ceq[i] = wi;
+        } else {
+            const double wd = i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+            const double eu = kEx[i] * c.u[0] + kEy[i] * c.u[1], uu = c.u[0] * c.u[0] + c.u[1] * c.u[1];
+            p.ceq[i] = C(wd * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu));
+        }
+    }
     for (int s = 0; s < n; ++s) {
         p.omega[s] = C(1) / C(c.tau[s]);
         p.keep[s] = C(1) - p.omega[s];
         for (int i = 0; i < 9; ++i) {
-            const C wi = i == 0 ? w[0] : (i < 5 ? w[1] : w[2]);
             const bool shifted = c.storage == LBRD_F16_SHIFTED || c.storage == LBRD_BF16_SHIFTED;
-            p.shift[s][i] = shifted ? wi * C(c.rho_ref[s]) : C(0);
+            p.shift[s][i] = shifted ? p.ceq[i] * C(c.rho_ref[s]) : C(0);
         }
         const bool shifted = c.storage == LBRD_F16_SHIFTED || c.storage == LBRD_BF16_SHIFTED;
         p.rho_ref[s] = shifted ? C(c.rho_ref[s]) : C(0);
@@ -197,6 +209,12 @@ int validate_config(const lbrd_config *c) {
             if (!std::isfinite(c->c[s])) return LBRD_EINVAL;
     }
     if (c->reaction == LBRD_REACT_GRAY_SCOTT && (!std::isfinite(c->F) || !std::isfinite(c->k))) return LBRD_EINVAL;
+    if (!std::isfinite(c->u[0]) || !std::isfinite(c->u[1])) return LBRD_EINVAL;
+    if (c->u[0] != 0.0 || c->u[1] != 0.0) {
+        // advective variants: Gray-Scott, or one species with a linear (or no) reaction
+        if (!(c->reaction == LBRD_REACT_GRAY_SCOTT || c->nspecies == 1)) return LBRD_EINVAL;
+        if (!(c->u[0] * c->u[0] + c->u[1] * c->u[1] < 1.0 / 3.0)) return LBRD_EINVAL;
+    }
     return LBRD_OK;
 }
 

@@ -94,9 +94,17 @@ __global__ void k_init(Layout L, Params<typename Traits<ST>::C> p, const void *r
             for (int i = 0; i < 9; ++i) {
                 const int xs = wrap(x + kEx[i], L.nx), ys = wrap(y + kEy[i], L.ny);
                 const C r = load_in<C>(rho0, dtype, ((int64_t)s * L.ny + ys) * L.nx + xs);
-                // rest population as r - 4 w_1 r - 4 w_5 r so that the nine
-                // equilibrium populations of a site sum to r (see step_tile)
-                const C v = i == 0 ? r - C(4) * (wgt<C>(1) * r) - C(4) * (wgt<C>(5) * r) : wgt<C>(i) * r;
+                // rest population as r minus the moving ones, so that the
+                // nine equilibrium populations of a site sum to r (see
+                // collide_site)
+                C v;
+                if (p.adv) {
+                    C moving = C(0);
+                    for (int j = 1; j < 9; ++j) moving += p.ceq[j] * r;
+                    v = i == 0 ? r - moving : p.ceq[i] * r;
+                } else {
+                    v = i == 0 ? r - C(4) * (wgt<C>(1) * r) - C(4) * (wgt<C>(5) * r) : wgt<C>(i) * r;
+                }
                 dst[(int64_t)(s * 9 + i) * L.pstride + (int64_t)y * L.pitch + x] = encode<ST>(v, p.shift[s][i]);
             }
         }

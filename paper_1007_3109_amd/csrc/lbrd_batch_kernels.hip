@@ -29,6 +29,8 @@ __device__ __forceinline__ void batch_tile_var(const BatchInst &bi, int j, int64
         case kLin2: batch_tile<ST, kLin2, NT>(bi, j, local, lane); break;
         case kLin3: batch_tile<ST, kLin3, NT>(bi, j, local, lane); break;
         case kLin4: batch_tile<ST, kLin4, NT>(bi, j, local, lane); break;
+        case kAdvLin1: batch_tile<ST, kAdvLin1, NT>(bi, j, local, lane); break;
+        case kAdvGS: batch_tile<ST, kAdvGS, NT>(bi, j, local, lane); break;
         default: batch_tile<ST, kGS, NT>(bi, j, local, lane); break;
     }
 }

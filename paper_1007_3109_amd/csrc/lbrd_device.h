@@ -137,9 +137,15 @@ __device__ __forceinline__ void store_vec(T *p, const T (&e)[VEC]) {
     else *reinterpret_cast<R *>(p) = r;
 }
 
+// The reaction of a variant without its advection, and whether it advects.
+template <int V>
+constexpr int kReactionOf = V == kAdvLin1 ? kLin1 : (V == kAdvGS ? kGS : V);
+template <int V>
+constexpr bool kAdvective = V == kAdvLin1 || V == kAdvGS;
+
 template <int V>
 struct NSpecies {
-    static constexpr int value = V == kGS ? 2 : V + 1;
+    static constexpr int value = kReactionOf<V> == kGS ? 2 : kReactionOf<V> + 1;
 };
 
 // Reaction term for one site (Section II.B linear decay; Section III
@@ -148,7 +154,7 @@ template <int V, class C>
 __device__ __forceinline__ void reaction(const Params<C> &p, const C (&rho)[NSpecies<V>::value],
                                          C (&R)[NSpecies<V>::value]) {
     constexpr int NS = NSpecies<V>::value;
-    if constexpr (V == kGS) {
+    if constexpr (kReactionOf<V> == kGS) {
         const C u = rho[0], v = rho[1];
         const C uvv = u * v * v;
         R[0] = -uvv + p.F * (C(1) - u);
@@ -167,10 +173,11 @@ __device__ __forceinline__ void reaction(const Params<C> &p, const C (&rho)[NSpe
 // ------------------------------------------------------- site update --
 
 // Collide and react one site: f holds the nine pulled populations of each
-// species in deviation form (d = f for F64 / F32, f - w_i rho_ref,s for the
+// species in deviation form (d = f for F64 / F32, f - c_i rho_ref,s for the
 // 16-bit forms); o receives the encoded post-collision values.  With
-// m_s = sum_i d_i (ascending i), rho_s = m_s + rho_ref,s (the weights sum to
-// one) and the update f' = f (1 - 1/tau) + w_i (rho / tau + R) reads
+// m_s = sum_i d_i (ascending i), rho_s = m_s + rho_ref,s (the c_i sum to
+// one) and the update f' = f (1 - 1/tau) + c_i rho / tau + w_i R reads
+// d' = d (1 - 1/tau) + c_i m / tau + w_i R; without advection c_i = w_i and
 // d' = d (1 - 1/tau) + w_i (m / tau + R).
 template <int ST, int V>
 __device__ __forceinline__ void collide_site(const Params<typename Traits<ST>::C> &p,
@@ -188,6 +195,29 @@ __device__ __forceinline__ void collide_site(const Params<typename Traits<ST>::C
         rho[s] = kShifted<ST> ? acc + p.rho_ref[s] : acc;
     }
     reaction<V, C>(p, rho, R);
+    if constexpr (kAdvective<V>) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            // c_i m / tau + w_i R for the moving populations; the rest
+            // population takes what makes the nine terms sum to m / tau + R
+            const C om = p.omega[s] * m[s];
+            const C a = om + R[s];
+            C e[9], moving = C(0);
+#pragma unroll
+            for (int i = 1; i < 9; ++i) {
+                e[i] = p.ceq[i] * om + wgt<C>(i) * R[s];
+                moving += e[i];
+            }
+            e[0] = a - moving;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                C r = f[s][i] * p.keep[s] + e[i];
+                if constexpr (kShifted<ST>) asm volatile("" : "+v"(r));
+                o[s][i] = encode_dev<ST>(r);
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         // w_i (m / tau + R): the rest weight is taken as 1 - 4/9 - 4/36

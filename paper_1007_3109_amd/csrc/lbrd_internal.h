@@ -20,12 +20,15 @@ enum Storage : int { kF64 = 0, kF32 = 1, kF16 = 2, kBF16 = 3 };
 inline int storage_bytes(int st) { return st == kF64 ? 8 : st == kF32 ? 4 : 2; }
 
 // Reaction variants compiled into the step kernel.  NONE runs as LINEAR
-// with K = 0, c = 0, which adds exactly +0 to every population.
-enum Variant : int { kLin1 = 0, kLin2 = 1, kLin3 = 2, kLin4 = 3, kGS = 4, kNumVariants = 5 };
+// with K = 0, c = 0, which adds exactly +0 to every population.  The
+// advective variants carry an equilibrium velocity (one species linear, or
+// Gray-Scott).
+enum Variant : int { kLin1 = 0, kLin2 = 1, kLin3 = 2, kLin4 = 3, kGS = 4, kAdvLin1 = 5, kAdvGS = 6, kNumVariants = 7 };
 
 inline int variant_of(const lbrd_config &c) {
-    if (c.reaction == LBRD_REACT_GRAY_SCOTT) return kGS;
-    return c.nspecies - 1;
+    const bool adv = c.u[0] != 0.0 || c.u[1] != 0.0;
+    if (c.reaction == LBRD_REACT_GRAY_SCOTT) return adv ? kAdvGS : kGS;
+    return adv ? kAdvLin1 : c.nspecies - 1;
 }
 
 // Row-major planes f[s][i] of ny rows x `pitch` elements, `pstride` elements
@@ -51,7 +54,9 @@ struct Params {
     C c[LBRD_MAX_SPECIES];
     C F, k, Fk;                  // Fk = F + k
     C rho_ref[LBRD_MAX_SPECIES]; // 16-bit forms: the storage shift density
-    C shift[LBRD_MAX_SPECIES][9];   // w_i rho_ref,s
+    C shift[LBRD_MAX_SPECIES][9];   // c_i rho_ref,s
+    C ceq[9];                    // equilibrium coefficients c_i (w_i without a velocity)
+    int32_t adv;                 // 1: c_i carry an advection velocity
 };
 
 template <class C>

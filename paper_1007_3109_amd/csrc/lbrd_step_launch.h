@@ -43,6 +43,8 @@ inline hipError_t launch_step_s(const StepLaunch &sl, const Grid &g, const void 
         case kLin3: return launch_step_v<ST, kLin3>(sl, g, params, st);
         case kLin4: return launch_step_v<ST, kLin4>(sl, g, params, st);
         case kGS: return launch_step_v<ST, kGS>(sl, g, params, st);
+        case kAdvLin1: return launch_step_v<ST, kAdvLin1>(sl, g, params, st);
+        case kAdvGS: return launch_step_v<ST, kAdvGS>(sl, g, params, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -108,6 +110,8 @@ inline hipError_t launch_stepT_s(const StepLaunch &sl, const GridT &g, const voi
         case kLin3: return launch_stepT_w<ST, kLin3>(sl, g, params, st);
         case kLin4: return launch_stepT_w<ST, kLin4>(sl, g, params, st);
         case kGS: return launch_stepT_w<ST, kGS>(sl, g, params, st);
+        case kAdvLin1: return launch_stepT_w<ST, kAdvLin1>(sl, g, params, st);
+        case kAdvGS: return launch_stepT_w<ST, kAdvGS>(sl, g, params, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -30,7 +30,7 @@ class Config(ctypes.Structure):
         ("storage", ctypes.c_int32), ("reaction", ctypes.c_int32), ("reserved", ctypes.c_int32),
         ("tau", ctypes.c_double * MAX_SPECIES), ("rho_ref", ctypes.c_double * MAX_SPECIES),
         ("K", ctypes.c_double * (MAX_SPECIES * MAX_SPECIES)), ("c", ctypes.c_double * MAX_SPECIES),
-        ("F", ctypes.c_double), ("k", ctypes.c_double),
+        ("F", ctypes.c_double), ("k", ctypes.c_double), ("u", ctypes.c_double * 2),
     ]
 
 
@@ -147,7 +147,7 @@ def check(status: int, where: str) -> int:
 
 
 def make_config(nx: int, ny: int, nspecies: int = 1, tau=1.0, storage: str = "f32", reaction: str = "none",
-                K=None, c=None, F: float = 0.0, k: float = 0.0, rho_ref=None) -> Config:
+                K=None, c=None, F: float = 0.0, k: float = 0.0, rho_ref=None, u=None) -> Config:
     cfg = Config()
     cfg.nspecies, cfg.nx, cfg.ny = nspecies, nx, ny
     cfg.storage = STORAGE[storage]
@@ -167,6 +167,8 @@ def make_config(nx: int, ny: int, nspecies: int = 1, tau=1.0, storage: str = "f3
         for s, v in enumerate(np.asarray(c, np.float64).reshape(-1)[:nspecies]):
             cfg.c[s] = float(v)
     cfg.F, cfg.k = float(F), float(k)
+    if u is not None:
+        cfg.u[0], cfg.u[1] = (float(x) for x in u)
     return cfg
 
 

@@ -6,6 +6,7 @@ import ctypes
 import re
 from pathlib import Path
 
+import numpy as np
 import pytest
 
 from paper_1007_3109_amd import lbrd
@@ -47,6 +48,8 @@ def gs(nx=32, ny=32, **kw):
     lambda c: c.tau.__setitem__(0, 0.5),            # tau must exceed 1/2
     lambda c: c.tau.__setitem__(1, float("nan")),
     lambda c: setattr(c, "F", float("inf")),
+    lambda c: c.u.__setitem__(0, float("nan")),
+    lambda c: (c.u.__setitem__(0, 0.5), c.u.__setitem__(1, 0.35)),   # u.u >= 1/3
 ])
 def test_invalid_configs_rejected(mutate):
     c = gs()
@@ -55,6 +58,20 @@ def test_invalid_configs_rejected(mutate):
     assert lbrd.validate(c) == lbrd.EINVAL
     n = ctypes.c_size_t()
     assert lbrd.lib.lbrd_workspace_size(ctypes.byref(c), ctypes.byref(n)) == lbrd.EINVAL
+
+
+def test_advection_velocity_validation():
+    """A velocity in the equilibrium is accepted for Gray-Scott and for one
+    species (linear or no reaction) with u.u < 1/3; a multi-species linear
+    system with a velocity is rejected."""
+    assert lbrd.validate(gs(u=(0.1, -0.05))) == lbrd.OK
+    assert lbrd.validate(lbrd.make_config(8, 8, 1, tau=0.8, reaction="linear", K=[[-0.01]], u=(0.2, 0.0))) == lbrd.OK
+    assert lbrd.validate(lbrd.make_config(8, 8, 1, tau=0.8, u=(0.0, -0.3))) == lbrd.OK
+    two = lbrd.make_config(8, 8, 2, tau=0.8, reaction="linear", K=-0.01 * np.eye(2))
+    assert lbrd.validate(two) == lbrd.OK
+    two.u[0] = 0.1
+    assert lbrd.validate(two) == lbrd.EINVAL
+    assert lbrd.validate(gs(u=(0.4, 0.42))) == lbrd.EINVAL
 
 
 def test_workspace_size_covers_two_padded_buffers():

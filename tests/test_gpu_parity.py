@@ -227,6 +227,75 @@ def test_shifted_storage_gray_scott(storage):
     assert np.all(oracle.rel_l2(rho, ref) <= (1e-2 if storage == "f16" else 1e-1))
 
 
+# ----- advective equilibrium (Eq. "Maxwellian" with a uniform velocity) -------
+
+@pytest.mark.parametrize("shape", [(1, 1), (3, 5), (33, 70)])
+def test_advective_populations_f64(shape):
+    """Random non-equilibrium populations, Gray-Scott with an equilibrium
+    velocity, every launch kind (one step per launch and T = 2..4 per launch):
+    the populations after 7 steps match the oracle to 1e-13 of the largest,
+    and the one-species linear variant likewise."""
+    ny, nx = shape
+    rng = np.random.default_rng(5 + nx)
+    u = (0.12, -0.07)
+    for ns, reaction, kw in [(2, "gray_scott", dict(F=0.04, k=0.06)), (1, "linear", dict(K=[[-0.02]]))]:
+        f0 = rng.uniform(0.0, 0.1, size=(ns, 9, ny, nx))
+        taus = [0.7, 1.2][:ns]
+        okw = dict(kw)
+        if reaction == "linear":
+            okw = dict(K=np.array(kw["K"]))
+        ref = oracle.run(f0, 7, taus, oracle.REACT_GRAY_SCOTT if ns == 2 else oracle.REACT_LINEAR, u=u, **okw)
+        cfg = lbrd.make_config(nx, ny, ns, tau=taus, storage="f64", reaction=reaction, u=u, **kw)
+        s = lbrd.Solver(cfg)
+        for fused in (1, 2, 3, 4):
+            s.set_tuning(fused_steps=fused, tile_cols=64, tile_rows=4, waves=8, graph_steps=0)
+            s.set_populations(f0).step(7)
+            got = s.get_populations().cpu().numpy()
+            assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max(), (shape, ns, fused)
+
+
+def test_advected_gray_scott_f32_and_drift():
+    """Gray-Scott FP32 with u = (0.1, 0.05) from the square start: the FP64
+    oracle within the FP32 floor after 300 steps, and a blob without reaction
+    moves its centre of mass by u per step (FP64 storage, 1e-9)."""
+    u = (0.1, 0.05)
+    rho0 = workloads.gray_scott_square(96, 96, seed=4)
+    kw = dict(F=workloads.GS_F, k=workloads.GS_K)
+    rho, _, _ = gpu_solve(rho0, 300, "f32", tau=workloads.GS_TAU, reaction="gray_scott", u=u, **kw)
+    ref = oracle.solve(rho0, 300, list(workloads.GS_TAU), oracle.REACT_GRAY_SCOTT, u=u, **kw)
+    floor = oracle.rel_l2(oracle.solve(rho0, 300, list(workloads.GS_TAU), oracle.REACT_GRAY_SCOTT, precision="f32",
+                                       u=u, **kw), ref)
+    tol = np.where(floor <= 1e-6, 1e-5, 3 * floor)
+    err = oracle.rel_l2(rho, ref)
+    log(f"advected GS f32: rel L2 {err}, FP32 floor {floor}")
+    assert np.all(err <= tol)
+    L, n = 160, 60
+    x = np.arange(L)[None, :] - L / 2
+    y = np.arange(L)[:, None] - L / 2
+    blob = np.exp(-(x * x + y * y) / 18.0)[None]
+    got, mass, _ = gpu_solve(blob, n, "f64", tau=0.9, reaction="none", u=u)
+    M = got.sum()
+    assert abs((got[0] * x).sum() / M - n * u[0]) <= 1e-9 and abs((got[0] * y).sum() / M - n * u[1]) <= 1e-9
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_advective_shifted_storage(storage):
+    """16-bit shifted storage with a velocity (shift c_i(u) rho_ref): the GPU
+    stays closer to the oracle's emulation of the same storage than that
+    emulation is to FP64 (single-species decay, 200 steps)."""
+    q = QUANT[storage]
+    u = (-0.08, 0.11)
+    rho0 = workloads.sinusoid(64, 48, 0.1, 2)
+    rref = [1.0]
+    rho, _, _ = gpu_solve(rho0, 200, storage, tau=0.8, reaction="linear", K=[[-0.001]], rho_ref=rref, u=u)
+    f = oracle.encode(oracle.init(rho0, "f32", u), q, rref, u)
+    emu = oracle.moments(oracle.run(f, 200, [0.8], oracle.REACT_LINEAR, K=[[-0.001]], quant=q, rho_ref=rref, u=u))
+    ref = oracle.solve(rho0, 200, [0.8], oracle.REACT_LINEAR, K=[[-0.001]], u=u)
+    e_emu, e_fmt = oracle.rel_l2(rho, emu), oracle.rel_l2(emu, ref)
+    log(f"advective {storage}: vs emulation {e_emu}, emulation vs FP64 {e_fmt}")
+    assert np.all(e_emu <= e_fmt)
+
+
 # ----- read-outs ---------------------------------------------------------------
 
 def test_mass_reduction_and_rel_l2():
@@ -386,7 +455,8 @@ def test_gray_scott_4096_sampled_windows(storage, quant):
 # ----- several steps per launch (temporal blocking) -------------------------
 
 FUSED_CASES = [("f64", "gray_scott", 2), ("f32", "gray_scott", 2), ("f16", "gray_scott", 2), ("bf16", "gray_scott", 2),
-               ("f32", "linear", 1), ("f32", "linear", 3), ("f16", "linear", 1), ("f64", "linear", 4)]
+               ("f32", "linear", 1), ("f32", "linear", 3), ("f16", "linear", 1), ("f64", "linear", 4),
+               ("f32", "gray_scott_advected", 2), ("bf16", "linear_advected", 1)]
 
 
 def multi_step_shape_fits(b, ns, cols, rows, steps, waves):
@@ -422,10 +492,12 @@ def test_multi_step_launch_is_bitwise_identical(storage, reaction, ns):
     ran = 0
     for ny, nx in [(1, 1), (3, 3), (2, 5), (45, 67), (33, 130), (17, 257), (70, 300)]:
         rng = np.random.default_rng(nx * 7 + ny)
-        kw = dict(F=0.04, k=0.06) if reaction == "gray_scott" else dict(K=-0.01 * np.eye(ns))
+        kw = dict(F=0.04, k=0.06) if reaction.startswith("gray_scott") else dict(K=-0.01 * np.eye(ns))
+        if reaction.endswith("_advected"):
+            kw["u"] = (0.09, -0.13)
         rref = (0.3,) * ns
-        cfg = lbrd.make_config(nx, ny, ns, tau=[0.7, 1.2, 0.9, 0.8][:ns], storage=storage, reaction=reaction,
-                               rho_ref=rref, **kw)
+        cfg = lbrd.make_config(nx, ny, ns, tau=[0.7, 1.2, 0.9, 0.8][:ns], storage=storage,
+                               reaction=reaction.replace("_advected", ""), rho_ref=rref, **kw)
         f0 = rng.uniform(0.0, 0.1, size=(ns, 9, ny, nx))
         ref = lbrd.Solver(cfg)
         ref.set_tuning(fused_steps=1, graph_steps=0)
