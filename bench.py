@@ -36,7 +36,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, 8 TB/s
 
 
-# sources that define the two-step FP32 kernel; the committed counter summary
+# sources that define the multi-step FP32 kernel; the committed counter summary
 # records their digest, and its traffic figure is reported only while it matches
 STEP_SOURCES = ("paper_1007_3109_amd/csrc/lbrd_device.h", "paper_1007_3109_amd/csrc/lbrd_internal.h",
                 "paper_1007_3109_amd/csrc/lbrd_step_launch.h", "paper_1007_3109_amd/csrc/step_f32.hip")

@@ -105,15 +105,17 @@ typedef struct lbrd_config {
  *  lanes_x: lanes per row segment, a power of two 1..64 (0 = choose from nx).
  *       Single solvers only.
  *  waves: waves (64 lanes) per workgroup: 1, 2, 4, 8 or 16.  One-step
- *       launches use min(waves, 4); two-step launches use all of them.
+ *       launches use min(waves, 4); multi-step launches use all of them.
  *  nontemporal: 1 = streaming (non-temporal) loads and stores.
- *  graph_steps: steps per captured HIP graph (0 = plain launches; else even).
- *  blocks_per_cu: persistent workgroups per compute unit.  Batches: 1..32.
+ *  graph_steps: steps per captured HIP graph (0 = plain launches; else even;
+ *       batches with T steps per launch: a multiple of 2T).
+ *  blocks_per_cu: persistent workgroups per compute unit.  Batches: 1..32
+ *       (one-step) or 0..32 (multi-step, 0 = one workgroup per tile).
  *       Single solvers: 0 = one tile per wave / workgroup, else 1..64 looping
  *       over tiles.
  *  plain_order: single solvers; 0 = consecutive tiles on the same XCD, 1 = the
  *       hardware's round-robin order.
- *  fused_steps: single solvers; 1 = one step per launch; T = 2, 3 or 4 =
+ *  fused_steps: 1 = one step per launch; T = 2, 3 or 4 =
  *       T steps per launch on tile_cols x tile_rows tiles staged in LDS
  *       (temporal blocking; a remainder of 2 .. T-1 steps runs as one shorter
  *       launch on the same tiles, a single remaining step as a one-step
@@ -250,12 +252,21 @@ int lbrd_batch_time(const lbrd_batch *b, int idx, int64_t *t);
 int lbrd_batch_rel_l2(lbrd_batch *b, int idx, const void *ref, int dtype, double *err_out);
 /* Same contract as lbrd_spectrum for instance idx. */
 int lbrd_batch_spectrum(lbrd_batch *b, int idx, int species, void *out, void *work, size_t work_bytes);
-/* Persistent-launch shape: blocks_per_cu, waves, nontemporal, graph_steps
- * (vec and lanes_x are chosen per instance from its size and storage). */
+/* Launch shape of a batch.  Batches whose instances are all Gray-Scott FP32,
+ * or all from the serving mix (one-species linear or Gray-Scott without a
+ * velocity, in FP32 / F16 / BF16 storage, each buffer below 4 GiB), take
+ * fused_steps = T in 2..4 on 64 x tile_rows tiles (default 4 steps on 64 x 8
+ * tiles, 8 waves, blocks_per_cu 0 = one workgroup per tile, graph_steps 32):
+ * launch j advances each instance by min(T, its steps left in the chunk), and
+ * graph_steps must be a multiple of 2T.  Other batches use persistent
+ * one-step launches: fused_steps = 1, waves 1/2/4, blocks_per_cu 1..32,
+ * nontemporal, even graph_steps (vec and lanes_x are chosen per instance).
+ * Results are bitwise identical for every shape. */
 int lbrd_batch_get_tuning(const lbrd_batch *b, lbrd_tuning *out);
 int lbrd_batch_set_tuning(lbrd_batch *b, const lbrd_tuning *t);
-/* Time the persistent-launch candidates and keep the fastest (state is
- * overwritten; re-initialise afterwards). */
+/* Time the launch-shape candidates (one-step persistent shapes and, where
+ * allowed, multi-step shapes) and keep the fastest (state is overwritten;
+ * re-initialise afterwards). */
 int lbrd_batch_autotune(lbrd_batch *b, int steps, lbrd_tuning *chosen);
 int lbrd_batch_time_steps(lbrd_batch *b, int64_t nsteps, double *ms);
 
