@@ -483,6 +483,14 @@ def main():
         if "copy" in legs:
             log("bench: copy")
             extra["copy_1GiB"] = copy_leg(torch)
+            # the same launch's algorithmic rate against a plain device copy
+            # measured in this process (read + write of 1 GiB)
+            copy = extra["copy_1GiB"]["GBs"]
+            line["roofline"]["copy_GBs"] = copy
+            line["roofline"]["frac_of_copy"] = round(line["roofline"]["achieved"] / copy, 4)
+            for key in ("hbm_4096_f32", "hbm_4096_f16", "hbm_4096_bf16", "batched"):
+                if key in extra:
+                    extra[key]["frac_of_copy"] = round(extra[key]["achieved_GBs"] / copy, 4)
         line["extra"] = extra
     print(json.dumps(line), flush=True)
 
