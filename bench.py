@@ -330,11 +330,28 @@ def precision_leg(torch, lbrd, workloads, n=4096, steps=(1000, 10000), check_n=2
             row[f"{st}_vs_fp64_rel_l2"] = [float(x) for x in s.rel_l2(ref64)]
             row[f"{st}_vs_fp64_max_abs"] = [float((rho[k] - ref64[k]).abs().max()) for k in range(2)]
             row[f"{st}_mean"] = [float(x) / check_n ** 2 for x in m]
+            m64 = oracle.mass(oracle.moments(f))
+            row[f"{st}_mass_rel_diff_vs_fp64"] = [float(abs(a - b) / abs(b)) for a, b in zip(m, m64)]
         done = cp
         out[f"step_{cp}_{check_n}_vs_oracle"] = row
     out["oracle_seconds"] = round(time.perf_counter() - t0, 2)
     for s in small.values():
         s.close()
+    # FP64 mass drift of each storage form without reaction (the update
+    # conserves mass exactly in real arithmetic): 1024^2, two species, the
+    # Gray-Scott start, 2000 steps
+    drift = {}
+    start = workloads.gray_scott_square(1024, 1024, seed=0)
+    for st in ("f64", "f32", "f16", "bf16"):
+        extra = dict(rho_ref=(1.0, 0.0)) if st in ("f16", "bf16") else {}
+        s = lbrd.Solver(lbrd.make_config(1024, 1024, 2, tau=workloads.GS_TAU, storage=st, reaction="none", **extra))
+        s.init(start)
+        _, m0 = s.moments()
+        s.step(2000)
+        _, m1 = s.moments()
+        drift[st] = [float(abs(b - a) / abs(a)) for a, b in zip(m0, m1)]
+        s.close()
+    out["mass_drift_no_reaction_1024_2000_steps"] = drift
     return out
 
 
