@@ -132,6 +132,31 @@ def test_batch_mixed_storage_and_reactions(graph_steps):
         assert torch.equal(got, solo(cfg, rho0, 57)), idx
 
 
+def test_batch_with_advected_instances_equals_solo():
+    """Instances with an equilibrium velocity batch through the persistent
+    one-step kernel (any variant): advected Gray-Scott in FP32, an advected
+    single species in F16, and a plain Gray-Scott lattice; each equals its
+    solo run bitwise, also with per-instance step counts."""
+    rng = np.random.default_rng(9)
+    F, k = workloads.draw_gs_unstable(rng)
+    cases = [
+        (lbrd.make_config(70, 50, 2, tau=workloads.GS_TAU, storage="f32", reaction="gray_scott", F=F, k=k,
+                          u=(0.1, -0.04)), workloads.gray_scott_square(70, 50, rng=np.random.default_rng(1))),
+        (lbrd.make_config(64, 33, 1, tau=0.8, storage="f16", reaction="linear", K=[[-0.002]], rho_ref=(1.0,),
+                          u=(-0.05, 0.12)), workloads.sinusoid(64, 33, 0.1, 2)),
+        (lbrd.make_config(96, 96, 2, tau=workloads.GS_TAU, storage="f32", reaction="gray_scott", F=F, k=k),
+         workloads.gray_scott_square(96, 96, rng=np.random.default_rng(2))),
+    ]
+    b = lbrd.Batch([c for c, _ in cases])
+    assert b.tuning().fused_steps == 1
+    for idx, (_, rho0) in enumerate(cases):
+        b.init(idx, rho0)
+    counts = [41, 17, 30]
+    b.advance(counts)
+    for idx, (cfg, rho0) in enumerate(cases):
+        assert torch.equal(b.moments(idx)[0], solo(cfg, rho0, counts[idx])), idx
+
+
 def test_batch_autotune_then_run():
     insts = workloads.batch_sweep(1, grid=3, sides=(64, 128))
     cfgs = [lbrd.make_config(i.side, i.side, 2, tau=workloads.GS_TAU, storage="f32", reaction="gray_scott",
@@ -171,6 +196,26 @@ def test_server_results_equal_solo_runs():
         np.testing.assert_allclose(mass, want.reshape(want.shape[0], -1).sum(axis=1), rtol=1e-12)
     st = srv.stats()
     assert st.completed == len(tickets) and st.resident == 0 and st.queued == 0
+    srv.close()
+
+
+def test_server_with_an_advected_request_equals_solo():
+    """A request with an equilibrium velocity sends its rounds through the
+    one-step kernel of the any-variant set; results still equal solo runs."""
+    cfg_a = lbrd.make_config(80, 60, 2, tau=workloads.GS_TAU, storage="f32", reaction="gray_scott",
+                             F=workloads.GS_F, k=workloads.GS_K, u=(0.07, 0.03))
+    cfg_b = lbrd.make_config(48, 48, 1, tau=0.9, storage="f32", reaction="linear", K=[[-0.001]])
+    r_a = workloads.gray_scott_square(80, 60, seed=5)
+    r_b = workloads.sinusoid(48, 48, 0.1, 1)
+    srv = lbrd.Server(arena_bytes=64 << 20, chunk_steps=40)
+    ta = srv.submit(cfg_a, r_a, 97)
+    tb = srv.submit(cfg_b, r_b, 55)
+    for t in (ta, tb):
+        srv.wait(t, 120)
+    for t, cfg, r0, n in ((ta, cfg_a, r_a, 97), (tb, cfg_b, r_b, 55)):
+        rho, _, info = srv.take(t)
+        assert info.state == 2
+        assert np.array_equal(rho, solo(cfg, r0, n).cpu().numpy()), t
     srv.close()
 
 
