@@ -106,7 +106,8 @@ typedef struct lbrd_config {
  *       Single solvers only.
  *  waves: waves (64 lanes) per workgroup: 1, 2, 4, 8 or 16.  One-step
  *       launches use min(waves, 4); multi-step launches use all of them.
- *  nontemporal: 1 = streaming (non-temporal) loads and stores.
+ *  nontemporal: 1 = streaming (non-temporal) accesses: loads and stores of
+ *       one-step launches, the result stores of multi-step launches.
  *  graph_steps: steps per captured HIP graph (0 = plain launches; else even;
  *       batches with T steps per launch: a multiple of 2T).
  *  blocks_per_cu: persistent workgroups per compute unit.  Batches: 1..32

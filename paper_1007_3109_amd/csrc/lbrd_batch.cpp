@@ -116,6 +116,7 @@ hipError_t retile(lbrd_batch *b) {
     BatchHeader h;
     std::memset(&h, 0, sizeof(h));
     h.count = b->count;
+    h.nt_store = steps_per_launch(b) > 1 ? b->tune.nontemporal : 0;
     h.total_tiles = tiles;
     hipError_t e = hipMemcpyAsync(b->d_hdr, &h, sizeof(h), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
@@ -235,12 +236,16 @@ int lbrd_batch_create(const lbrd_config *cfgs, int count, void *workspace, size_
     std::memset(&b->tune, 0, sizeof(b->tune));
     if (b->multi_ok) {
         // four steps per launch on 64 x 8 tiles, one workgroup of 8 waves per
-        // tile (the single-lattice default beyond the Infinity Cache)
+        // tile, streaming stores when the buffers exceed the Infinity Cache
+        // (the single-lattice defaults beyond it)
+        size_t bytes = 0;
+        for (const Layout &L : b->L) bytes += 2 * L.buf_bytes;
         b->tune.fused_steps = 4;
         b->tune.tile_rows = 8;
         b->tune.waves = 8;
         b->tune.blocks_per_cu = 0;
         b->tune.graph_steps = 32;
+        b->tune.nontemporal = bytes > ((size_t)256 << 20) ? 1 : 0;
     } else {
         b->tune.fused_steps = 1;
         b->tune.waves = 4;
@@ -462,7 +467,8 @@ int lbrd_batch_set_tuning(lbrd_batch *b, const lbrd_tuning *t) {
     n.tile_cols = n.fused_steps > 1 ? 64 : 0;
     if (!batch_tuning_valid(b, n)) return LBRD_EINVAL;
     if (std::memcmp(&n, &b->tune, sizeof(n)) == 0) return LBRD_OK;
-    const bool tiling = n.fused_steps != b->tune.fused_steps || n.tile_rows != b->tune.tile_rows;
+    const bool tiling = n.fused_steps != b->tune.fused_steps || n.tile_rows != b->tune.tile_rows ||
+                        n.nontemporal != b->tune.nontemporal;
     drop_graph(b);
     b->tune = n;
     if (tiling) {
@@ -527,15 +533,16 @@ int lbrd_batch_autotune(lbrd_batch *b, int steps, lbrd_tuning *chosen) {
     if (b->multi_ok)
         for (int ts = 2; ts <= kMaxFusedSteps; ++ts)
             for (int rows : {4, 8, 16})
-                for (int w : {4, 8, 16}) {
-                    lbrd_tuning t = keep;
-                    t.fused_steps = ts;
-                    t.tile_rows = rows;
-                    t.blocks_per_cu = 0;
-                    t.waves = w;
-                    t.nontemporal = 0;
-                    cands.push_back(t);
-                }
+                for (int w : {4, 8, 16})
+                    for (int nt = 0; nt < 2; ++nt) {
+                        lbrd_tuning t = keep;
+                        t.fused_steps = ts;
+                        t.tile_rows = rows;
+                        t.blocks_per_cu = 0;
+                        t.waves = w;
+                        t.nontemporal = nt;
+                        cands.push_back(t);
+                    }
     lbrd_tuning best = keep;
     double best_ms = 1e300;
     for (lbrd_tuning t : cands) {

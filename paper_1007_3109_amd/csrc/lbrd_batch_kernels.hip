@@ -88,7 +88,8 @@ __global__ __launch_bounds__(256) void k_batch_step(const BatchHeader *__restric
 // ------------------------------------------- several steps per launch --
 
 template <int ST, int V, int TS, int MAXK>
-__device__ __forceinline__ void batch_tileT(const BatchInst &bi, int j, int64_t local, int m, unsigned char *smem) {
+__device__ __forceinline__ void batch_tileT(const BatchInst &bi, int j, int64_t local, int m, int nt_store,
+                                            unsigned char *smem) {
     using T = typename Traits<ST>::T;
     const int in = bi.cur ^ (j & 1);
     TileT t;
@@ -99,6 +100,7 @@ __device__ __forceinline__ void batch_tileT(const BatchInst &bi, int j, int64_t 
     t.th = bi.mt_th;
     t.pitch_b = (uint32_t)bi.pitch * (uint32_t)sizeof(T);
     t.pstride_b = (uint32_t)bi.pstride * (uint32_t)sizeof(T);
+    t.nt_store = nt_store;
     const int tx = (int)(local % bi.mt_ntx), ty = (int)(local / bi.mt_ntx);
     if constexpr (ST == kF64)
         stepT_tile<ST, V, TS, MAXK, 64, true>(t, bi.pd, tx * 64, ty * bi.mt_th, m, reinterpret_cast<T *>(smem));
@@ -107,10 +109,10 @@ __device__ __forceinline__ void batch_tileT(const BatchInst &bi, int j, int64_t 
 }
 
 template <int ST, int TS, int MAXK>
-__device__ __forceinline__ void batch_tileT_serve(const BatchInst &bi, int j, int64_t local, int m,
+__device__ __forceinline__ void batch_tileT_serve(const BatchInst &bi, int j, int64_t local, int m, int nt_store,
                                                   unsigned char *smem) {
-    if (bi.variant == kGS) batch_tileT<ST, kGS, TS, MAXK>(bi, j, local, m, smem);
-    else batch_tileT<ST, kLin1, TS, MAXK>(bi, j, local, m, smem);
+    if (bi.variant == kGS) batch_tileT<ST, kGS, TS, MAXK>(bi, j, local, m, nt_store, smem);
+    else batch_tileT<ST, kLin1, TS, MAXK>(bi, j, local, m, nt_store, smem);
 }
 
 // Launch j of a chunk, TS steps per launch: every workgroup walks the global
@@ -121,7 +123,7 @@ template <int SET, int TS, int MAXK>
 __global__ __launch_bounds__(MAXK == 1 ? 1024 : 512) void k_batch_stepT(const BatchHeader *__restrict__ hdr,
                                                                         const BatchInst *__restrict__ inst, int j) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    const int count = hdr->count;
+    const int count = hdr->count, nt_store = hdr->nt_store;
     const int64_t total = hdr->total_tiles;
     int hint = 0;
     for (int64_t t = xcd_remap(blockIdx.x, gridDim.x); t < total; t += gridDim.x) {
@@ -138,12 +140,12 @@ __global__ __launch_bounds__(MAXK == 1 ? 1024 : 512) void k_batch_stepT(const Ba
         const int m = (int)(bi.steps - done < TS ? bi.steps - done : TS);
         const int64_t local = t - bi.tile_begin;
         if constexpr (SET == kBatchGSF32) {
-            batch_tileT<kF32, kGS, TS, MAXK>(bi, j, local, m, smem);
+            batch_tileT<kF32, kGS, TS, MAXK>(bi, j, local, m, nt_store, smem);
         } else {
             switch (bi.storage) {
-                case kF32: batch_tileT_serve<kF32, TS, MAXK>(bi, j, local, m, smem); break;
-                case kF16: batch_tileT_serve<kF16, TS, MAXK>(bi, j, local, m, smem); break;
-                default: batch_tileT_serve<kBF16, TS, MAXK>(bi, j, local, m, smem); break;
+                case kF32: batch_tileT_serve<kF32, TS, MAXK>(bi, j, local, m, nt_store, smem); break;
+                case kF16: batch_tileT_serve<kF16, TS, MAXK>(bi, j, local, m, nt_store, smem); break;
+                default: batch_tileT_serve<kBF16, TS, MAXK>(bi, j, local, m, nt_store, smem); break;
             }
         }
     }

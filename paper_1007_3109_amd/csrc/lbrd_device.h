@@ -415,14 +415,16 @@ __device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, u
     else if constexpr (sizeof(T) == 4) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
     else return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
 }
-template <class T>
+// NT: a streaming (non-temporal) store, cache policy bit "nt".
+template <class T, bool NT = false>
 __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, T v) {
+    constexpr int aux = NT ? 2 : 0;
     if constexpr (sizeof(T) == 8)
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(typename RawOf<8>::type, v), r, voff, soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(typename RawOf<8>::type, v), r, voff, soff, aux);
     else if constexpr (sizeof(T) == 4)
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, aux);
     else
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, voff, soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, voff, soff, aux);
 }
 
 // a * b for a, b below 2^24 (one full-rate multiply)
@@ -459,6 +461,7 @@ struct TileT {
     __amdgpu_buffer_rsrc_t src, dst;
     int nx, ny, th;
     uint32_t pitch_b, pstride_b;   // row and plane strides in bytes
+    int nt_store;                  // 1: streaming stores of the result (working set beyond the caches)
 };
 
 // TS time steps on one tile of TW x th sites whose lower-left site is
@@ -621,10 +624,18 @@ __device__ __forceinline__ void stepT_tile(const TileT &g, const Params<typename
         collide_site<ST, V>(p, f, o);
         if (gx < nx && gy < ny) {
             const uint32_t off = mul24(gy, g.pitch_b) + (uint32_t)gx * B;
+            if (g.nt_store) {
 #pragma unroll
-            for (int s = 0; s < NS; ++s)
+                for (int s = 0; s < NS; ++s)
 #pragma unroll
-                for (int i = 0; i < 9; ++i) buf_store<T>(g.dst, off, (uint32_t)(s * 9 + i) * g.pstride_b, o[s][i]);
+                    for (int i = 0; i < 9; ++i)
+                        buf_store<T, true>(g.dst, off, (uint32_t)(s * 9 + i) * g.pstride_b, o[s][i]);
+            } else {
+#pragma unroll
+                for (int s = 0; s < NS; ++s)
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) buf_store<T>(g.dst, off, (uint32_t)(s * 9 + i) * g.pstride_b, o[s][i]);
+            }
         }
     }
     __syncthreads();   // LDS is reused by the next tile
@@ -644,6 +655,7 @@ __global__ __launch_bounds__(MAXK == 1 ? 1024 : 512) void k_stepT(GridT g, Param
     t.th = g.th;
     t.pitch_b = (uint32_t)g.pitch * (uint32_t)sizeof(T);
     t.pstride_b = (uint32_t)g.pstride * (uint32_t)sizeof(T);
+    t.nt_store = g.nt_store;
     const int b0 = g.xcd_order ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     for (int64_t tile = b0; tile < g.ntiles; tile += gridDim.x) {
         const int tx = (int)(tile % g.ntx), ty = (int)(tile / g.ntx);

@@ -95,6 +95,7 @@ struct GridT {
     int xcd_order;
     int steps;        // 2 .. kMaxFusedSteps
     uint32_t bytes;   // bytes of one buffer (less than 4 GiB)
+    int nt_store;     // 1: streaming (non-temporal) stores of the result
 };
 
 constexpr int kMaxFusedSteps = 4;
@@ -195,7 +196,7 @@ struct alignas(16) BatchInst {
 
 struct alignas(16) BatchHeader {
     int32_t count;        // instances
-    int32_t pad;
+    int32_t nt_store;     // multi-step launches: 1 = streaming stores of the results
     int64_t total_tiles;  // sum of ntiles
 };
 

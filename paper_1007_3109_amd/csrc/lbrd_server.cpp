@@ -345,6 +345,10 @@ void worker_loop(lbrd_server *s) {
             std::memset(&h, 0, sizeof(h));
             h.count = (int)inst.size();
             h.total_tiles = tiles;
+            // streaming stores once the resident buffers exceed the Infinity Cache
+            size_t bytes = 0;
+            for (Request *rp : resp) bytes += 2 * rp->L.buf_bytes;
+            h.nt_store = serve && bytes > ((size_t)256 << 20) ? 1 : 0;
             err = hipMemcpyAsync(s->d_inst, inst.data(), sizeof(BatchInst) * inst.size(), hipMemcpyHostToDevice,
                                  s->stream);
             if (err == hipSuccess) err = hipMemcpyAsync(s->d_hdr, &h, sizeof(h), hipMemcpyHostToDevice, s->stream);

@@ -96,15 +96,15 @@ def serve_mix_cases():
     return [(c, r) for c, r in mixed_cases() if c.storage != lbrd.STORAGE["f64"]]
 
 
-@pytest.mark.parametrize("ts,graph_steps", [(4, 0), (4, 16), (3, 12), (2, 4)])
-def test_batch_multi_step_advance_equals_solo(ts, graph_steps):
+@pytest.mark.parametrize("ts,graph_steps,nt", [(4, 0, 0), (4, 16, 1), (3, 12, 0), (2, 4, 1)])
+def test_batch_multi_step_advance_equals_solo(ts, graph_steps, nt):
     """Per-instance step counts (lbrd_batch_advance) on the serving mix with
     T steps per launch: counts that are not multiples of T end with a shorter
     launch (down to a single step), instances with 0 steps stay put, and every
     instance equals its solo run bitwise."""
     cases = serve_mix_cases()
     b = lbrd.Batch([c for c, _ in cases])
-    b.set_tuning(fused_steps=ts, tile_rows=4, waves=8, blocks_per_cu=0, graph_steps=graph_steps)
+    b.set_tuning(fused_steps=ts, tile_rows=4, waves=8, blocks_per_cu=0, graph_steps=graph_steps, nontemporal=nt)
     for idx, (_, rho0) in enumerate(cases):
         b.init(idx, rho0)
     counts = [1, 2, 3, 0, 5, 23][:len(cases)]

@@ -542,7 +542,8 @@ def test_multi_step_launch_is_bitwise_identical(storage, reaction, ns):
                             s.set_tuning(fused_steps=steps, tile_cols=cols, tile_rows=rows, waves=waves,
                                          graph_steps=0)
                         continue
-                    s.set_tuning(fused_steps=steps, tile_cols=cols, tile_rows=rows, waves=waves, graph_steps=0)
+                    s.set_tuning(fused_steps=steps, tile_cols=cols, tile_rows=rows, waves=waves, graph_steps=0,
+                                 nontemporal=int(waves == 16))
                     s.set_populations(f0).step(7)
                     assert torch.equal(s.get_populations(), want), (ny, nx, steps, cols, rows, waves)
                     ran += 1
