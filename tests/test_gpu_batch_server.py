@@ -90,6 +90,36 @@ def test_batch_gs_f32_equals_solo_and_oracle(mode):
     log(f"batch of {len(insts)} GS f32 lattices ({mode}): bitwise equal to solo runs")
 
 
+def test_full_size_sweep_batch_sampled():
+    """The benchmark's batched workload at full size (256 Gray-Scott instances,
+    sides 128..512, seed 0, default launch shape: four steps per launch,
+    graphs of 32 steps): after 70 steps (two graph replays and a ragged
+    remainder) a sample of instances equals their solo runs bitwise, and the
+    smallest sampled lattice equals the FP64 oracle within the FP32 floor."""
+    insts = workloads.batch_sweep(0)
+    cfgs = [lbrd.make_config(i.side, i.side, 2, tau=workloads.GS_TAU, storage="f32", reaction="gray_scott",
+                             F=i.F, k=i.k) for i in insts]
+    b = lbrd.Batch(cfgs)
+    for idx, inst in enumerate(insts):
+        b.init(idx, workloads.batch_initial(inst))
+    steps = 70
+    b.step(steps)
+    sample = [0, 37, 101, 128, 200, 255]
+    for idx in sample:
+        got = b.moments(idx)[0]
+        assert torch.equal(got, solo(cfgs[idx], workloads.batch_initial(insts[idx]), steps)), idx
+    small = min(sample, key=lambda i: insts[i].side)
+    r0 = workloads.batch_initial(insts[small])
+    kw = dict(F=insts[small].F, k=insts[small].k)
+    ref = oracle.solve(r0, steps, list(workloads.GS_TAU), oracle.REACT_GRAY_SCOTT, **kw)
+    floor = oracle.rel_l2(oracle.solve(r0, steps, list(workloads.GS_TAU), oracle.REACT_GRAY_SCOTT, precision="f32",
+                                       **kw), ref)
+    tol = np.where(floor <= 1e-6, 1e-5, 3 * floor)
+    assert np.all(oracle.rel_l2(b.moments(small)[0].cpu().numpy(), ref) <= tol)
+    log(f"full-size sweep batch: {len(insts)} instances, sampled {sample} bitwise equal to solo runs")
+    b.close()
+
+
 def serve_mix_cases():
     """F32 / F16 / BF16 storage, single-species decay or Gray-Scott: the
     serving mix, which batches with several steps per launch."""
