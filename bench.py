@@ -424,12 +424,16 @@ def main():
         s.autotune(steps=20)          # launch shape picked by the library's autotuner
     rho0 = workloads.gray_scott_square(n, n, seed=0)
     # initial state from host memory (FP64 densities over PCIe, then the
-    # equilibrium kernel): outside the timed region, reported beside it
-    torch.cuda.synchronize()
-    t_init = time.perf_counter()
-    s.init(rho0)
-    torch.cuda.synchronize()
-    init_ms = (time.perf_counter() - t_init) * 1e3
+    # equilibrium kernel): outside the timed region, reported beside it.  The
+    # first call also loads the library's code object; the second is timed.
+    init_ms = []
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t_init = time.perf_counter()
+        s.init(rho0)
+        torch.cuda.synchronize()
+        init_ms.append((time.perf_counter() - t_init) * 1e3)
+    first_init_ms, init_ms = init_ms
     log(f"bench: Gray-Scott {n}x{n} f32, warmup {args.warmup}, steps {args.steps}, tuning {s.tuning().as_dict()}")
     secs, wall = time_solver(torch, s, args.steps, args.warmup)
     sites = n * n
@@ -473,6 +477,7 @@ def main():
                              "Infinity Cache; see extra.hbm_4096_* for working sets beyond it"},
         "wall_s": round(wall, 3),
         "init_from_host_ms": round(init_ms, 3),
+        "first_init_from_host_ms": round(first_init_ms, 3),
         "host_inclusive_mlups_per_species": round(2 * sites * args.steps / (secs + init_ms / 1e3) / 1e6, 1),
         "mass_after": [float(m) for m in mass],
         "tuning": s.tuning().as_dict(),
