@@ -249,6 +249,22 @@ def test_server_with_an_advected_request_equals_solo():
     srv.close()
 
 
+def test_server_destroy_with_queued_requests():
+    """Destroying a server finishes the resident request and drops the queued
+    ones: the call returns promptly and the resident work stays consistent."""
+    import time
+
+    cfg = lbrd.make_config(128, 128, 2, tau=workloads.GS_TAU, storage="f32", reaction="gray_scott", F=0.04, k=0.06)
+    fp = lbrd.server_footprint(cfg)
+    srv = lbrd.Server(arena_bytes=int(1.5 * fp) + (4 << 20), chunk_steps=100)
+    rho0 = workloads.gray_scott_square(128, 128, seed=1)
+    tickets = [srv.submit(cfg, rho0, 2000) for _ in range(5)]
+    assert len(set(tickets)) == 5
+    t0 = time.perf_counter()
+    srv.close()
+    assert time.perf_counter() - t0 < 30
+
+
 def test_server_admission_by_footprint():
     """An arena that holds about two requests at a time: the others queue and
     are admitted as memory frees; all finish; the peak stays within the arena."""
