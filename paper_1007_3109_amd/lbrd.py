@@ -128,6 +128,11 @@ SIGNATURES = {
 def _load() -> ctypes.CDLL:
     if not _LIB_PATH.exists():
         raise ImportError(f"{_LIB_PATH} is not built: run __graft_entry__.build() (hipcc, gfx950)")
+    # Device memory and streams come from torch, so the library must bind to the
+    # HIP runtime torch carries.  Loading the library first would map the
+    # system HIP runtime as well: two runtimes in one process, and the second
+    # sees neither torch's allocations nor (once torch holds it) the device.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(str(_LIB_PATH))
     for name, (args, res) in SIGNATURES.items():
         fn = getattr(lib, name)

@@ -117,3 +117,21 @@ def test_null_handles_are_rejected():
     assert lbrd.lib.lbrd_create(ctypes.byref(c), None, 1 << 30, None, ctypes.byref(out)) == lbrd.EINVAL
     assert lbrd.lib.lbrd_create(ctypes.byref(c), 0x1001, 1 << 30, None, ctypes.byref(out)) == lbrd.EINVAL
     assert lbrd.lib.lbrd_create(ctypes.byref(c), 0x1000, 16, None, ctypes.byref(out)) == lbrd.ENOMEM
+
+
+def test_binding_shares_torchs_hip_runtime():
+    """Importing the binding before torch must not map a second HIP runtime:
+    device pointers and streams come from torch, so the library has to bind to
+    the runtime torch loads (a second runtime sees neither)."""
+    import ast
+    import subprocess
+    import sys
+    code = ("from paper_1007_3109_amd import lbrd\n"
+            "import torch\n"
+            "maps = open('/proc/self/maps').read().split('\\n')\n"
+            "print(sorted({l.split()[-1] for l in maps if 'libamdhip64' in l}))\n")
+    root = Path(__file__).resolve().parents[1]
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr[-2000:]
+    libs = ast.literal_eval(out.stdout.strip().splitlines()[-1])
+    assert len(libs) == 1, libs
