@@ -50,6 +50,7 @@ def gs(nx=32, ny=32, **kw):
     lambda c: setattr(c, "F", float("inf")),
     lambda c: c.u.__setitem__(0, float("nan")),
     lambda c: (c.u.__setitem__(0, 0.5), c.u.__setitem__(1, 0.35)),   # u.u >= 1/3
+    lambda c: (setattr(c, "nx", 1 << 16), setattr(c, "ny", (1 << 15) + 1)),   # more than 2^31 sites
 ])
 def test_invalid_configs_rejected(mutate):
     c = gs()

@@ -482,6 +482,41 @@ def test_gray_scott_4096_sampled_windows(storage, quant):
         assert np.all(err <= fmt)
 
 
+@pytest.mark.parametrize("n,multi", [(7680, True), (8192, False)])
+def test_largest_lattices_sampled_windows(n, multi):
+    """The size limits of the two kernel families, FP32 Gray-Scott: at 7680^2
+    each buffer is just under 4 GiB, the largest the multi-step kernel's
+    32-bit byte offsets address, and the default launch uses it; at 8192^2 a
+    buffer exceeds 4 GiB and the default falls back to the one-step kernel
+    (64-bit offsets).  26 steps (ragged against four per launch); sampled
+    windows touching the first and last rows and columns against the FP64
+    oracle within 1e-5."""
+    steps = 26
+    rho0 = workloads.gray_scott_square(n, n, seed=3)
+    kw = dict(F=workloads.GS_F, k=workloads.GS_K)
+    cfg = lbrd.make_config(n, n, 2, storage="f32", tau=workloads.GS_TAU, reaction="gray_scott", **kw)
+    assert (lbrd.workspace_size(cfg) // 2 < (1 << 32)) == multi
+    s = lbrd.Solver(cfg)
+    try:
+        assert (s.tuning().fused_steps >= 2) == multi
+        s.init(rho0).step(steps)
+        rho, mass = s.moments()
+        rho = rho.cpu().numpy()
+    finally:
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    gots, refs = [], []
+    for centre in [(0, 0), (n - 1, n - 1), (n // 2, n // 2), (n - 5, 40), (7, n - 9)]:
+        ref, ys, xs = _window_reference(rho0, steps, centre, 32, **kw)
+        gots.append(rho[:, ys][:, :, xs])
+        refs.append(ref)
+    err = oracle.rel_l2(np.concatenate(gots, axis=2), np.concatenate(refs, axis=2))
+    log(f"{n}^2 f32 ({'multi-step' if multi else 'one-step'}) sampled vs FP64: {err}")
+    assert np.all(err <= 1e-5)
+    assert np.all(np.isfinite(mass))
+
+
 # ----- several steps per launch (temporal blocking) -------------------------
 
 FUSED_CASES = [("f64", "gray_scott", 2), ("f32", "gray_scott", 2), ("f16", "gray_scott", 2), ("bf16", "gray_scott", 2),
