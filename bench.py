@@ -374,7 +374,9 @@ def config1_leg(torch, lbrd, workloads, steps=1000):
 
 
 def copy_leg(torch, nbytes=1 << 30, reps=20):
-    """Device-to-device copy of a 1 GiB tensor: the achievable HBM rate."""
+    """Device-to-device copy of an nbytes tensor: at 1 GiB the achievable HBM
+    rate; at the size of one lattice buffer the rate of a plain read + write
+    of the same working set (inside the Infinity Cache when it fits)."""
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
     for _ in range(3):
@@ -522,6 +524,13 @@ def main():
             for key in ("hbm_4096_f32", "hbm_4096_f16", "hbm_4096_bf16", "batched"):
                 if key in extra:
                     extra[key]["frac_of_copy"] = round(extra[key]["achieved_GBs"] / copy, 4)
+            # and against a copy of one buffer of the headline lattice (the
+            # same 2 x buffer working set, cache-resident at 1024^2)
+            extra["copy_headline_buffer"] = copy_leg(torch, nbytes=line["roofline"]["bytes_per_launch"] // 2,
+                                                     reps=400)
+            same = extra["copy_headline_buffer"]["GBs"]
+            line["roofline"]["copy_same_size_GBs"] = same
+            line["roofline"]["frac_of_copy_same_size"] = round(line["roofline"]["achieved"] / same, 4)
         line["extra"] = extra
     print(json.dumps(line), flush=True)
 

@@ -453,19 +453,29 @@ int lbrd_create(const lbrd_config *cfg, void *workspace, size_t bytes, void *str
             h->tune.lanes_x = std::min(32, default_lanes(h->cfg.nx, 8));
         }
     }
-    // Four steps per launch on 64 x rows tiles staged in LDS (temporal
-    // blocking): measured 2.4x (1024^2) and 2.7x (4096^2, FP32) the one-step
-    // launches.  Rows: 4 while both buffers fit in the 256 MB Infinity Cache;
-    // beyond it 8 for 4- and 8-byte storage, 24 for the 16-bit forms (taller
-    // tiles re-read fewer halo rows); halved (then fewer steps per launch)
-    // until the shape fits in LDS and the register budget.  8 waves per
-    // workgroup, cached loads, streaming stores beyond the Infinity Cache
-    // (4 % faster at 4096^2; 40 % slower inside it), consecutive tiles on one
-    // XCD (each measured best).  Buffers of 4 GiB or more keep one-step
-    // launches.
+    // Four steps per launch on tiles staged in LDS (temporal blocking):
+    // measured 2.6x (1024^2) and 2.7x (4096^2, FP32) the one-step launches.
+    // While both buffers fit in the 256 MB Infinity Cache the halo's repeated
+    // collisions bound the launch, so the tiles are near-square within the
+    // LDS of about three workgroups per CU: 32 columns, rows by the bytes B
+    // of one site's populations (B <= 18: 64 x 24; <= 36: 32 x 20; <= 72:
+    // 32 x 12; beyond: 32 x 8).  Beyond the cache HBM traffic bounds it: 64
+    // columns, 8 rows for 4- and 8-byte storage, 24 for the 16-bit forms
+    // (taller tiles re-read fewer halo rows).  Rows are halved (then fewer
+    // steps per launch) until the shape fits in LDS and the register budget.
+    // 8 waves per workgroup, cached loads, streaming stores beyond the
+    // Infinity Cache (4 % faster at 4096^2; 40 % slower inside it),
+    // consecutive tiles on one XCD (each measured best).  Buffers of 4 GiB or
+    // more keep one-step launches.
     const bool in_cache = 2 * h->L.buf_bytes <= ((size_t)256 << 20);
-    h->tune.tile_cols = 64;
-    h->tune.tile_rows = in_cache ? 4 : (storage_bytes(h->cfg.storage) == 2 ? 24 : 8);
+    const int site_bytes = 9 * h->cfg.nspecies * storage_bytes(h->cfg.storage);
+    if (in_cache) {
+        h->tune.tile_cols = site_bytes <= 18 ? 64 : 32;
+        h->tune.tile_rows = site_bytes <= 18 ? 24 : site_bytes <= 36 ? 20 : site_bytes <= 72 ? 12 : 8;
+    } else {
+        h->tune.tile_cols = 64;
+        h->tune.tile_rows = storage_bytes(h->cfg.storage) == 2 ? 24 : 8;
+    }
     h->tune.fused_steps = 1;
     if (multi_step_possible(h)) {
         h->tune.waves = 8;
@@ -473,7 +483,7 @@ int lbrd_create(const lbrd_config *cfg, void *workspace, size_t bytes, void *str
         h->tune.plain_order = 0;
         for (int ts = kMaxFusedSteps; ts >= 2 && h->tune.fused_steps == 1; --ts) {
             for (int rows = h->tune.tile_rows; rows >= 1; rows /= 2)
-                if (stepT_shape_fits(h->cfg.storage, h->cfg.nspecies, 64, rows, ts, 8)) {
+                if (stepT_shape_fits(h->cfg.storage, h->cfg.nspecies, h->tune.tile_cols, rows, ts, 8)) {
                     h->tune.fused_steps = ts;
                     h->tune.tile_rows = rows;
                     break;
@@ -735,8 +745,8 @@ int lbrd_autotune(lbrd_solver *h, int steps, const char *cache_path, lbrd_tuning
                         }
     }
     for (int ts = 2; ts <= kMaxFusedSteps; ++ts)
-        for (int cols : {64, 128})
-            for (int rows : {4, 8, 16, 24, 32})
+        for (int cols : {32, 64, 128})
+            for (int rows : {4, 8, 12, 16, 20, 24, 32})
                 for (int w : {4, 8, 16})
                     for (int nt = 0; nt < 2; ++nt)
                         for (int order = 0; order < 2; ++order) {

@@ -54,7 +54,7 @@ int stepT_sites_per_thread(int tw, int th, int steps, int waves) {
 }
 
 bool stepT_shape_fits(int storage, int nspecies, int tw, int th, int steps, int waves) {
-    if (steps < 2 || steps > kMaxFusedSteps || (tw != 64 && tw != 128) || th < 1 || waves < 1 || waves > 16)
+    if (steps < 2 || steps > kMaxFusedSteps || (tw != 32 && tw != 64 && tw != 128) || th < 1 || waves < 1 || waves > 16)
         return false;
     if (stepT_lds_bytes(storage, nspecies, tw, th, steps) > (size_t)160 * 1024) return false;
     const int k = stepT_sites_per_thread(tw, th, steps, waves);

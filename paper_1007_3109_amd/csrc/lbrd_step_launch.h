@@ -95,6 +95,7 @@ template <int ST, int V>
 inline hipError_t launch_stepT_w(const StepLaunch &sl, const GridT &g, const void *params, hipStream_t st) {
     if (!stepT_shape_fits(ST, NSpecies<V>::value, g.tw, g.th, g.steps, sl.waves)) return hipErrorInvalidValue;
     switch (g.tw) {
+        case 32: return launch_stepT_n<ST, V, 32>(sl, g, params, st);
         case 64: return launch_stepT_n<ST, V, 64>(sl, g, params, st);
         case 128: return launch_stepT_n<ST, V, 128>(sl, g, params, st);
         default: return hipErrorInvalidValue;

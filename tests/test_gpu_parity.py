@@ -525,12 +525,12 @@ FUSED_CASES = [("f64", "gray_scott", 2), ("f32", "gray_scott", 2), ("f16", "gray
 
 
 def multi_step_shape_fits(b, ns, cols, rows, steps, waves):
-    """The documented limits of a multi-step launch shape: 64 or 128 columns;
+    """The documented limits of a multi-step launch shape: 32, 64 or 128 columns;
     the LDS region of rows + 2h rows (h = steps - 1), each row 9 ns (cols + 2h)
     values padded to a multiple of 256 bytes beyond cols + 2h, within 160 KB;
     and the second phase's rows (rows + 2h - 2 rows of cols + 2h sites) within
     1 site per thread, or 4 with at most 8 waves."""
-    if cols not in (64, 128):
+    if cols not in (32, 64, 128):
         return False
     h = steps - 1
     ew = cols + 2 * h
@@ -551,7 +551,7 @@ def test_multi_step_launch_is_bitwise_identical(storage, reaction, ns):
     shorter launch for a remainder of 2 .. T-1, a one-step launch for a single
     remaining step) is bitwise equal, on ragged and tiny lattices and on one
     with interior tiles (whose pulled region does not wrap), for 2, 3 and
-    4 steps per launch, both tile widths, several heights and workgroup
+    4 steps per launch, the three tile widths, several heights and workgroup
     sizes.  Shapes beyond the documented limits are rejected with EINVAL."""
     b = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[storage]
     ran = 0
@@ -570,7 +570,8 @@ def test_multi_step_launch_is_bitwise_identical(storage, reaction, ns):
         want = ref.get_populations()
         s = lbrd.Solver(cfg)
         for steps in (2, 3, 4):
-            for cols, rows in ((64, 1), (64, 8), (64, 16), (128, 2), (128, 8), (64, 24)):
+            for cols, rows in ((64, 1), (64, 8), (64, 16), (128, 2), (128, 8), (64, 24), (32, 3), (32, 12),
+                               (32, 20)):
                 for waves in (4, 8, 16):
                     if not multi_step_shape_fits(b, ns, cols, rows, steps, waves):
                         with pytest.raises(lbrd.LbrdError):
@@ -583,7 +584,7 @@ def test_multi_step_launch_is_bitwise_identical(storage, reaction, ns):
                     assert torch.equal(s.get_populations(), want), (ny, nx, steps, cols, rows, waves)
                     ran += 1
         assert s.time() == 7
-        for cols in (32, 96, 256):                    # widths the kernel does not take
+        for cols in (16, 48, 96, 256):                # widths the kernel does not take
             with pytest.raises(lbrd.LbrdError):
                 s.set_tuning(fused_steps=2, tile_cols=cols, tile_rows=2, waves=4, graph_steps=0)
     log(f"multi-step {storage} {reaction} N={ns}: {ran} shapes bitwise equal")
