@@ -104,7 +104,7 @@ typedef struct lbrd_config {
  *       16-bit forms).  Single solvers only.
  *  lanes_x: lanes per row segment, a power of two 1..64 (0 = choose from nx).
  *       Single solvers only.
- *  waves: waves (64 lanes) per workgroup: 1, 2, 4, 8 or 16.  One-step
+ *  waves: waves (64 lanes) per workgroup, 1..16 except 3.  One-step
  *       launches use min(waves, 4); multi-step launches use all of them.
  *  nontemporal: 1 = streaming (non-temporal) accesses: loads and stores of
  *       one-step launches, the result stores of multi-step launches.
@@ -124,10 +124,7 @@ typedef struct lbrd_config {
  *  tile_rows, tile_cols: multi-step tile, rows 1..64 and columns 32, 64 or 128.
  *       With h = T-1 and w = tile_cols + 2h, the LDS region of tile_rows + 2h
  *       rows of 9 N w populations (each row padded by fewer than 256 bytes)
- *       must fit in 160 KB, and for T >= 3 the second phase's
- *       w x (tile_rows + 2h - 2) sites must not exceed 64 * waves threads x 1
- *       site, or x 4 sites with at most 8 waves.  Ignored when
- *       fused_steps = 1. */
+ *       must fit in 160 KB.  Ignored when fused_steps = 1. */
 typedef struct lbrd_tuning {
     int32_t vec;
     int32_t lanes_x;

@@ -366,7 +366,7 @@ bool tuning_valid(const lbrd_solver *h, const lbrd_tuning &t) {
     if (t.plain_order != 0 && t.plain_order != 1) return false;
     if (t.graph_steps < 0 || (t.graph_steps & 1) || t.graph_steps > 4096) return false;
     if (t.nontemporal != 0 && t.nontemporal != 1) return false;
-    if (!(t.waves == 1 || t.waves == 2 || t.waves == 4 || t.waves == 8 || t.waves == 16)) return false;
+    if (t.waves < 1 || t.waves > 16) return false;
     if (t.fused_steps == 1) return true;
     if (!multi_step_possible(h)) return false;
     if (t.fused_steps < 2 || t.fused_steps > kMaxFusedSteps) return false;
@@ -459,9 +459,10 @@ int lbrd_create(const lbrd_config *cfg, void *workspace, size_t bytes, void *str
     // collisions bound the launch, so the tiles are near-square within the
     // LDS of about three workgroups per CU: 32 columns, rows by the bytes B
     // of one site's populations (B <= 18: 64 x 24; <= 36: 32 x 20; <= 72:
-    // 32 x 12; beyond: 32 x 8).  Beyond the cache HBM traffic bounds it: 64
-    // columns, 8 rows for 4- and 8-byte storage, 24 for the 16-bit forms
-    // (taller tiles re-read fewer halo rows).  Rows are halved (then fewer
+    // 32 x 12; beyond: 32 x 8).  Beyond the cache HBM traffic weighs in: 64
+    // columns, 8 rows for 4- and 8-byte storage, 12 for the 16-bit forms
+    // (three workgroups per CU; 24 rows re-read fewer halo lines but run 4 %
+    // slower at 4096^2 with two).  Rows are halved (then fewer
     // steps per launch) until the shape fits in LDS and the register budget.
     // 8 waves per workgroup, cached loads, streaming stores beyond the
     // Infinity Cache (4 % faster at 4096^2; 40 % slower inside it),
@@ -474,7 +475,7 @@ int lbrd_create(const lbrd_config *cfg, void *workspace, size_t bytes, void *str
         h->tune.tile_rows = site_bytes <= 18 ? 24 : site_bytes <= 36 ? 20 : site_bytes <= 72 ? 12 : 8;
     } else {
         h->tune.tile_cols = 64;
-        h->tune.tile_rows = storage_bytes(h->cfg.storage) == 2 ? 24 : 8;
+        h->tune.tile_rows = storage_bytes(h->cfg.storage) == 2 ? 12 : 8;
     }
     h->tune.fused_steps = 1;
     if (multi_step_possible(h)) {

@@ -47,18 +47,10 @@ size_t stepT_lds_bytes(int storage, int nspecies, int tw, int th, int steps) {
     return (size_t)(th + 2 * h) * stepT_row_stride(nspecies, tw + 2 * h, b) * b;
 }
 
-int stepT_sites_per_thread(int tw, int th, int steps, int waves) {
-    if (steps <= 2) return 0;
-    const int64_t middle = (int64_t)(tw + 2 * (steps - 1)) * (th + 2 * (steps - 1) - 2);
-    return (int)((middle + 64 * waves - 1) / (64 * waves));
-}
-
 bool stepT_shape_fits(int storage, int nspecies, int tw, int th, int steps, int waves) {
     if (steps < 2 || steps > kMaxFusedSteps || (tw != 32 && tw != 64 && tw != 128) || th < 1 || waves < 1 || waves > 16)
         return false;
-    if (stepT_lds_bytes(storage, nspecies, tw, th, steps) > (size_t)160 * 1024) return false;
-    const int k = stepT_sites_per_thread(tw, th, steps, waves);
-    return k <= 1 || (k <= 4 && waves <= 8);
+    return stepT_lds_bytes(storage, nspecies, tw, th, steps) <= (size_t)160 * 1024;
 }
 
 hipError_t launch_step(const StepLaunch &sl, const Grid &g, const void *params, hipStream_t st) {

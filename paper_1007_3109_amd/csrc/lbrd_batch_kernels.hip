@@ -87,7 +87,7 @@ __global__ __launch_bounds__(256) void k_batch_step(const BatchHeader *__restric
 
 // ------------------------------------------- several steps per launch --
 
-template <int ST, int V, int TS, int MAXK>
+template <int ST, int V, int TS>
 __device__ __forceinline__ void batch_tileT(const BatchInst &bi, int j, int64_t local, int m, int nt_store,
                                             unsigned char *smem) {
     using T = typename Traits<ST>::T;
@@ -103,24 +103,24 @@ __device__ __forceinline__ void batch_tileT(const BatchInst &bi, int j, int64_t 
     t.nt_store = nt_store;
     const int tx = (int)(local % bi.mt_ntx), ty = (int)(local / bi.mt_ntx);
     if constexpr (ST == kF64)
-        stepT_tile<ST, V, TS, MAXK, 64, true>(t, bi.pd, tx * 64, ty * bi.mt_th, m, reinterpret_cast<T *>(smem));
+        stepT_tile<ST, V, TS, 64, true>(t, bi.pd, tx * 64, ty * bi.mt_th, m, reinterpret_cast<T *>(smem));
     else
-        stepT_tile<ST, V, TS, MAXK, 64, true>(t, bi.pf, tx * 64, ty * bi.mt_th, m, reinterpret_cast<T *>(smem));
+        stepT_tile<ST, V, TS, 64, true>(t, bi.pf, tx * 64, ty * bi.mt_th, m, reinterpret_cast<T *>(smem));
 }
 
-template <int ST, int TS, int MAXK>
+template <int ST, int TS>
 __device__ __forceinline__ void batch_tileT_serve(const BatchInst &bi, int j, int64_t local, int m, int nt_store,
                                                   unsigned char *smem) {
-    if (bi.variant == kGS) batch_tileT<ST, kGS, TS, MAXK>(bi, j, local, m, nt_store, smem);
-    else batch_tileT<ST, kLin1, TS, MAXK>(bi, j, local, m, nt_store, smem);
+    if (bi.variant == kGS) batch_tileT<ST, kGS, TS>(bi, j, local, m, nt_store, smem);
+    else batch_tileT<ST, kLin1, TS>(bi, j, local, m, nt_store, smem);
 }
 
 // Launch j of a chunk, TS steps per launch: every workgroup walks the global
 // list of 64 x rows tiles; the owning instance is found by binary search over
 // tile_begin (workgroup-uniform).  Instance i takes m = min(TS, steps_i - j TS)
 // steps on its tiles when m > 0; its buffers alternate once per launch.
-template <int SET, int TS, int MAXK>
-__global__ __launch_bounds__(MAXK == 1 ? 1024 : 512) void k_batch_stepT(const BatchHeader *__restrict__ hdr,
+template <int SET, int TS>
+__global__ __launch_bounds__(1024) void k_batch_stepT(const BatchHeader *__restrict__ hdr,
                                                                         const BatchInst *__restrict__ inst, int j) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const int count = hdr->count, nt_store = hdr->nt_store;
@@ -140,52 +140,39 @@ __global__ __launch_bounds__(MAXK == 1 ? 1024 : 512) void k_batch_stepT(const Ba
         const int m = (int)(bi.steps - done < TS ? bi.steps - done : TS);
         const int64_t local = t - bi.tile_begin;
         if constexpr (SET == kBatchGSF32) {
-            batch_tileT<kF32, kGS, TS, MAXK>(bi, j, local, m, nt_store, smem);
+            batch_tileT<kF32, kGS, TS>(bi, j, local, m, nt_store, smem);
         } else {
             switch (bi.storage) {
-                case kF32: batch_tileT_serve<kF32, TS, MAXK>(bi, j, local, m, nt_store, smem); break;
-                case kF16: batch_tileT_serve<kF16, TS, MAXK>(bi, j, local, m, nt_store, smem); break;
-                default: batch_tileT_serve<kBF16, TS, MAXK>(bi, j, local, m, nt_store, smem); break;
+                case kF32: batch_tileT_serve<kF32, TS>(bi, j, local, m, nt_store, smem); break;
+                case kF16: batch_tileT_serve<kF16, TS>(bi, j, local, m, nt_store, smem); break;
+                default: batch_tileT_serve<kBF16, TS>(bi, j, local, m, nt_store, smem); break;
             }
         }
     }
 }
 
-template <int SET, int TS, int MAXK>
+template <int SET, int TS>
 static hipError_t launch_setT(const BatchHeader *hdr, const BatchInst *inst, int j, int64_t blocks, int waves,
                               size_t lds, hipStream_t st) {
     static bool attr_set = false;   // per instantiation: allow more than 64 KB of LDS
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch_stepT<SET, TS, MAXK>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch_stepT<SET, TS>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_batch_stepT<SET, TS, MAXK>), dim3((unsigned)blocks), dim3(64 * waves), lds, st, hdr, inst,
+    hipLaunchKernelGGL((k_batch_stepT<SET, TS>), dim3((unsigned)blocks), dim3(64 * waves), lds, st, hdr, inst,
                        j);
     return hipGetLastError();
-}
-
-template <int SET, int TS>
-static hipError_t launch_setT_k(const BatchHeader *hdr, const BatchInst *inst, int j, int64_t blocks, int waves,
-                                int rows, size_t lds, hipStream_t st) {
-    switch (stepT_sites_per_thread(64, rows, TS, waves)) {
-        case 0:
-        case 1: return launch_setT<SET, TS, 1>(hdr, inst, j, blocks, waves, lds, st);
-        case 2: return launch_setT<SET, TS, 2>(hdr, inst, j, blocks, waves, lds, st);
-        case 3: return launch_setT<SET, TS, 3>(hdr, inst, j, blocks, waves, lds, st);
-        case 4: return launch_setT<SET, TS, 4>(hdr, inst, j, blocks, waves, lds, st);
-        default: return hipErrorInvalidValue;
-    }
 }
 
 template <int SET>
 static hipError_t launch_setT_n(const BatchHeader *hdr, const BatchInst *inst, int j, int64_t blocks, int waves,
                                 int ts, int rows, size_t lds, hipStream_t st) {
     switch (ts) {
-        case 2: return launch_setT<SET, 2, 1>(hdr, inst, j, blocks, waves, lds, st);
-        case 3: return launch_setT_k<SET, 3>(hdr, inst, j, blocks, waves, rows, lds, st);
-        case 4: return launch_setT_k<SET, 4>(hdr, inst, j, blocks, waves, rows, lds, st);
+        case 2: return launch_setT<SET, 2>(hdr, inst, j, blocks, waves, lds, st);
+        case 3: return launch_setT<SET, 3>(hdr, inst, j, blocks, waves, lds, st);
+        case 4: return launch_setT<SET, 4>(hdr, inst, j, blocks, waves, lds, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -432,28 +432,57 @@ __device__ __forceinline__ uint32_t mul24(int a, uint32_t b) { return (uint32_t)
 
 // LDS layout of the multi-step region: row-interleaved planes, element
 // (plane P, column x, row y) at y * RS + P * EW + x, with EW the region width
-// and RS = stepT_row_stride (9 N EW plus bank padding).  A site's 9 N pulled
-// inputs then sit at compile-time offsets from one address (its lower-left
-// neighbour), and consecutive lanes touch consecutive banks.
-template <int ST, int NS, int EW>
+// and RS = stepT_row_stride (9 N EW plus bank padding).  Consecutive lanes
+// touch consecutive banks.
+//
+// The post-collision value leaving site z along e_i is kept in one of two
+// forms, alternating phase by phase (the "AA" arrangement):
+//   form A: in plane opp(i) at z itself;
+//   form B: in plane i at z + e_i, the site it streams to.
+// A site x then reads and writes the same cells within one step: from form
+// A it pulls plane opp(i) at x - e_i and writes form B into plane i at
+// x + e_i (the same cells); from form B it reads plane i at x and writes
+// form A into plane opp(i) at x.  No two sites share a cell, so a phase
+// updates its region in place with no barrier between its reads and writes.
+constexpr int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};   // e_opp(i) = -e_i
+
+template <int ST, int NS, int EW, bool FROM_B>
 __device__ __forceinline__ void gather_lds(const typename Traits<ST>::T *L, int lx, int ly,
                                            typename Traits<ST>::C (&f)[NS][9]) {
     constexpr int RS = stepT_row_stride(NS, EW, (int)sizeof(typename Traits<ST>::T));
-    const typename Traits<ST>::T *b = L + (ly - 1) * RS + (lx - 1);
+    if constexpr (FROM_B) {
+        const typename Traits<ST>::T *b = L + ly * RS + lx;
 #pragma unroll
-    for (int s = 0; s < NS; ++s)
+        for (int s = 0; s < NS; ++s)
 #pragma unroll
-        for (int i = 0; i < 9; ++i) f[s][i] = decode_dev<ST>(b[(1 - kEy[i]) * RS + (s * 9 + i) * EW + (1 - kEx[i])]);
+            for (int i = 0; i < 9; ++i) f[s][i] = decode_dev<ST>(b[(s * 9 + i) * EW]);
+    } else {
+        // from the lower-left neighbour, so every offset is non-negative
+        const typename Traits<ST>::T *b = L + (ly - 1) * RS + (lx - 1);
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                f[s][i] = decode_dev<ST>(b[(1 - kEy[i]) * RS + (s * 9 + kOpp[i]) * EW + (1 - kEx[i])]);
+    }
 }
-template <int ST, int NS, int EW>
+template <int ST, int NS, int EW, bool TO_B>
 __device__ __forceinline__ void put_lds(typename Traits<ST>::T *L, int lx, int ly,
                                         const typename Traits<ST>::T (&o)[NS][9]) {
     constexpr int RS = stepT_row_stride(NS, EW, (int)sizeof(typename Traits<ST>::T));
-    typename Traits<ST>::T *b = L + ly * RS + lx;
+    if constexpr (TO_B) {
+        typename Traits<ST>::T *b = L + (ly - 1) * RS + (lx - 1);
 #pragma unroll
-    for (int s = 0; s < NS; ++s)
+        for (int s = 0; s < NS; ++s)
 #pragma unroll
-        for (int i = 0; i < 9; ++i) b[(s * 9 + i) * EW] = o[s][i];
+            for (int i = 0; i < 9; ++i) b[(1 + kEy[i]) * RS + (s * 9 + i) * EW + (1 + kEx[i])] = o[s][i];
+    } else {
+        typename Traits<ST>::T *b = L + ly * RS + lx;
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int i = 0; i < 9; ++i) b[(s * 9 + kOpp[i]) * EW] = o[s][i];
+    }
 }
 
 // Geometry of one lattice as the multi-step tile reads it.
@@ -464,23 +493,81 @@ struct TileT {
     int nt_store;                  // 1: streaming stores of the result (working set beyond the caches)
 };
 
+// Middle phase J of a multi-step tile: the region shrunk by J-1 on every
+// side, read in the form phase J-1 wrote and written in the other one.
+template <int ST, int V, int EW, int J>
+__device__ __forceinline__ void stepT_middle(const Params<typename Traits<ST>::C> &p, typename Traits<ST>::T *L,
+                                             int eh, int nthr) {
+    using T = typename Traits<ST>::T;
+    using C = typename Traits<ST>::C;
+    constexpr int NS = NSpecies<V>::value;
+    constexpr bool kFromB = (J - 1) % 2 == 0;   // phase J-1 wrote form B when even
+    const int rsz = EW * (eh - 2 * (J - 1));
+    for (int q = threadIdx.x; q < rsz; q += nthr) {
+        const int lx = q % EW;
+        if (lx >= J - 1 && lx < EW - (J - 1)) {
+            const int ly = q / EW + J - 1;
+            C f[NS][9];
+            gather_lds<ST, NS, EW, kFromB>(L, lx, ly, f);
+            T o[NS][9];
+            collide_site<ST, V>(p, f, o);
+            put_lds<ST, NS, EW, !kFromB>(L, lx, ly, o);
+        }
+    }
+}
+
+// Last phase of a multi-step tile: pull from LDS (form B when the previous
+// phase was even), collide on the tile itself, store to the destination.
+template <int ST, int V, int TW, int H, bool FROM_B>
+__device__ __forceinline__ void stepT_last(const TileT &g, const Params<typename Traits<ST>::C> &p,
+                                           const typename Traits<ST>::T *L, int x0, int y0, int nthr) {
+    using T = typename Traits<ST>::T;
+    using C = typename Traits<ST>::C;
+    constexpr int NS = NSpecies<V>::value;
+    constexpr int EW = TW + 2 * H;
+    const int tsz = TW * g.th;
+    for (int q = threadIdx.x; q < tsz; q += nthr) {
+        const int lx = q % TW, ly = q / TW;
+        const int gx = x0 + lx, gy = y0 + ly;
+        C f[NS][9];
+        gather_lds<ST, NS, EW, FROM_B>(L, lx + H, ly + H, f);
+        T o[NS][9];
+        collide_site<ST, V>(p, f, o);
+        if (gx < g.nx && gy < g.ny) {
+            const uint32_t off = mul24(gy, g.pitch_b) + (uint32_t)gx * sizeof(T);
+            if (g.nt_store) {
+#pragma unroll
+                for (int s = 0; s < NS; ++s)
+#pragma unroll
+                    for (int i = 0; i < 9; ++i)
+                        buf_store<T, true>(g.dst, off, (uint32_t)(s * 9 + i) * g.pstride_b, o[s][i]);
+            } else {
+#pragma unroll
+                for (int s = 0; s < NS; ++s)
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) buf_store<T>(g.dst, off, (uint32_t)(s * 9 + i) * g.pstride_b, o[s][i]);
+            }
+        }
+    }
+}
+
 // TS time steps on one tile of TW x th sites whose lower-left site is
 // (x0, y0) (temporal blocking; called by every thread of the workgroup).
 // The workgroup keeps a (TW + 2h) x (th + 2h) region in LDS, h = TS - 1.
 // Phase 1 reads step t from the source buffer (pulling across the region's
 // edge), collides, and writes the post-collision values of step t+1 on the
-// whole region to LDS.  Each middle phase j = 2 .. m-1 advances the region
-// shrunk by j-1 sites on every side, in place: every thread first pulls the
-// inputs of its sites into registers (MAXK sites, 1 to 4), the workgroup
-// synchronises, then the threads collide and overwrite LDS.  The last phase
-// pulls from LDS, collides on the tile itself and stores step t+m.  Per m
+// whole region to LDS (form A).  Each middle phase j = 2 .. m-1 advances the
+// region shrunk by j-1 sites on every side, in place, alternating the two
+// forms so that a site's reads and writes hit cells no other site touches:
+// one barrier per phase.  The last phase pulls from LDS, collides on the
+// tile itself and stores step t+m.  Per m
 // steps the buffer is read once (tile plus a halo) and written once.  Every
 // site runs the arithmetic of the one-step kernel on the same encoded inputs,
 // so the result is bitwise identical to m one-step launches.  m = TS unless
 // VARM, where 1 <= m <= TS is a workgroup-uniform runtime count (m = 1 reads
 // and writes the buffers directly).  Byte offsets are 32-bit: the buffer
 // spans less than 4 GiB.
-template <int ST, int V, int TS, int MAXK, int TW, bool VARM>
+template <int ST, int V, int TS, int TW, bool VARM>
 __device__ __forceinline__ void stepT_tile(const TileT &g, const Params<typename Traits<ST>::C> &p, int x0, int y0,
                                            int m, typename Traits<ST>::T *L) {
     using T = typename Traits<ST>::T;
@@ -541,7 +628,7 @@ __device__ __forceinline__ void stepT_tile(const TileT &g, const Params<typename
                         g.src, rel, (uint32_t)(s * 9 + i) * g.pstride_b + base - kEy[i] * g.pitch_b - kEx[i] * B));
             T o[NS][9];
             collide_site<ST, V>(p, f, o);
-            put_lds<ST, NS, EW>(L, ex, ey, o);
+            put_lds<ST, NS, EW, false>(L, ex, ey, o);
             ex += dx;
             ey += dy;
             rel += step;
@@ -578,7 +665,7 @@ __device__ __forceinline__ void stepT_tile(const TileT &g, const Params<typename
                         buf_load<T>(g.src, ry[1 - kEy[i]] + cx[1 - kEx[i]], (uint32_t)(s * 9 + i) * g.pstride_b));
             T o[NS][9];
             collide_site<ST, V>(p, f, o);
-            put_lds<ST, NS, EW>(L, ex, ey, o);
+            put_lds<ST, NS, EW, false>(L, ex, ey, o);
             ex += dx;
             ey += dy;
             if (ex >= EW) {
@@ -588,63 +675,36 @@ __device__ __forceinline__ void stepT_tile(const TileT &g, const Params<typename
         }
     }
     __syncthreads();
-    // middle phases: step t+j-1 -> t+j on the region shrunk by j-1, in LDS.
-    // Threads walk whole region rows (all EW columns, the same order as phase
-    // 1, so the bank padding holds) and skip the columns outside the shrunk
-    // region.
-#pragma unroll
-    for (int j = 2; j < TS; ++j) {
-        if (VARM && j >= m) break;
-        const int rsz = EW * (eh - 2 * (j - 1));
-        C f[MAXK][NS][9];
-#pragma unroll
-        for (int k = 0; k < MAXK; ++k) {
-            const int q = threadIdx.x + k * nthr, lx = q % EW;
-            if (q < rsz && lx >= j - 1 && lx < EW - (j - 1)) gather_lds<ST, NS, EW>(L, lx, q / EW + j - 1, f[k]);
+    // middle phases j = 2 .. m-1: step t+j-1 -> t+j on the region shrunk by
+    // j-1, in LDS, in place (phase j reads the form phase j-1 wrote: A after
+    // odd phases, B after even ones).  Threads walk whole region rows (all EW
+    // columns, the same order as phase 1, so the bank padding holds) and skip
+    // the columns outside the shrunk region.
+    if constexpr (TS > 2) {
+        if (!VARM || m > 2) {
+            stepT_middle<ST, V, EW, 2>(p, L, eh, nthr);
+            __syncthreads();
         }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < MAXK; ++k) {
-            const int q = threadIdx.x + k * nthr, lx = q % EW;
-            if (q < rsz && lx >= j - 1 && lx < EW - (j - 1)) {
-                T o[NS][9];
-                collide_site<ST, V>(p, f[k], o);
-                put_lds<ST, NS, EW>(L, lx, q / EW + j - 1, o);
-            }
-        }
-        __syncthreads();
     }
+    if constexpr (TS > 3) {
+        if (!VARM || m > 3) {
+            stepT_middle<ST, V, EW, 3>(p, L, eh, nthr);
+            __syncthreads();
+        }
+    }
+    static_assert(TS <= 4, "middle phases are spelled out for up to four steps per launch");
     // last phase: step t+m-1 -> t+m on the tile, to the destination buffer
-    for (int q = threadIdx.x; q < tsz; q += nthr) {
-        const int lx = q % TW, ly = q / TW;
-        const int gx = x0 + lx, gy = y0 + ly;
-        C f[NS][9];
-        gather_lds<ST, NS, EW>(L, lx + H, ly + H, f);
-        T o[NS][9];
-        collide_site<ST, V>(p, f, o);
-        if (gx < nx && gy < ny) {
-            const uint32_t off = mul24(gy, g.pitch_b) + (uint32_t)gx * B;
-            if (g.nt_store) {
-#pragma unroll
-                for (int s = 0; s < NS; ++s)
-#pragma unroll
-                    for (int i = 0; i < 9; ++i)
-                        buf_store<T, true>(g.dst, off, (uint32_t)(s * 9 + i) * g.pstride_b, o[s][i]);
-            } else {
-#pragma unroll
-                for (int s = 0; s < NS; ++s)
-#pragma unroll
-                    for (int i = 0; i < 9; ++i) buf_store<T>(g.dst, off, (uint32_t)(s * 9 + i) * g.pstride_b, o[s][i]);
-            }
-        }
-    }
+    if (m & 1)
+        stepT_last<ST, V, TW, H, true>(g, p, L, x0, y0, nthr);
+    else
+        stepT_last<ST, V, TW, H, false>(g, p, L, x0, y0, nthr);
     __syncthreads();   // LDS is reused by the next tile
 }
 
 // TS steps per launch over one lattice: one workgroup per tile (or a
 // persistent grid walking the tiles).
-template <int ST, int V, int TS, int MAXK, int TW>
-__global__ __launch_bounds__(MAXK == 1 ? 1024 : 512) void k_stepT(GridT g, Params<typename Traits<ST>::C> p) {
+template <int ST, int V, int TS, int TW>
+__global__ __launch_bounds__(1024) void k_stepT(GridT g, Params<typename Traits<ST>::C> p) {
     using T = typename Traits<ST>::T;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     TileT t;
@@ -659,7 +719,7 @@ __global__ __launch_bounds__(MAXK == 1 ? 1024 : 512) void k_stepT(GridT g, Param
     const int b0 = g.xcd_order ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     for (int64_t tile = b0; tile < g.ntiles; tile += gridDim.x) {
         const int tx = (int)(tile % g.ntx), ty = (int)(tile / g.ntx);
-        stepT_tile<ST, V, TS, MAXK, TW, false>(t, p, tx * TW, ty * g.th, TS, reinterpret_cast<T *>(smem));
+        stepT_tile<ST, V, TS, TW, false>(t, p, tx * TW, ty * g.th, TS, reinterpret_cast<T *>(smem));
     }
 }
 

@@ -113,13 +113,6 @@ __host__ __device__ constexpr int stepT_row_stride(int nspecies, int ew, int byt
 }
 // LDS bytes of a launch of `steps` steps on tw x th tiles.
 size_t stepT_lds_bytes(int storage, int nspecies, int tw, int th, int steps);
-// Sites per thread that the middle phases of a multi-step launch hold in
-// registers: the largest middle region (all tw + 2h columns of the rows it
-// spans) over the workgroup's threads, rounded up (0 for two steps, which have
-// no middle phase).  Launch shapes that need
-// more than 4 are rejected; 2 to 4 need at most 8 waves (a 512-thread
-// register budget).
-int stepT_sites_per_thread(int tw, int th, int steps, int waves);
 bool stepT_shape_fits(int storage, int nspecies, int tw, int th, int steps, int waves);
 
 // ------------------------------------------------------------ launchers --

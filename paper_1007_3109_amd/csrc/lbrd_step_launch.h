@@ -49,14 +49,14 @@ inline hipError_t launch_step_s(const StepLaunch &sl, const Grid &g, const void 
     }
 }
 
-template <int ST, int V, int TS, int MAXK, int TW>
+template <int ST, int V, int TS, int TW>
 inline hipError_t launch_stepT_t(const StepLaunch &sl, const GridT &g, const void *params, hipStream_t st) {
     using C = typename Traits<ST>::C;
     const Params<C> &p = *static_cast<const Params<C> *>(params);
     const size_t lds = stepT_lds_bytes(ST, NSpecies<V>::value, TW, g.th, TS);
     static bool attr_set = false;   // per instantiation: allow more than 64 KB of LDS
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_stepT<ST, V, TS, MAXK, TW>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_stepT<ST, V, TS, TW>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
         attr_set = true;
@@ -64,29 +64,17 @@ inline hipError_t launch_stepT_t(const StepLaunch &sl, const GridT &g, const voi
     int64_t nb = g.ntiles;
     if (g.blocks > 0 && g.blocks < nb) nb = g.blocks;
     if (nb > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_stepT<ST, V, TS, MAXK, TW>), dim3((unsigned)nb), dim3(64 * sl.waves), lds, st, g, p);
+    hipLaunchKernelGGL((k_stepT<ST, V, TS, TW>), dim3((unsigned)nb), dim3(64 * sl.waves), lds, st, g, p);
     return hipGetLastError();
-}
-
-template <int ST, int V, int TS, int TW>
-inline hipError_t launch_stepT_k(const StepLaunch &sl, const GridT &g, const void *params, hipStream_t st) {
-    switch (stepT_sites_per_thread(TW, g.th, TS, sl.waves)) {
-        case 0:
-        case 1: return launch_stepT_t<ST, V, TS, 1, TW>(sl, g, params, st);
-        case 2: return launch_stepT_t<ST, V, TS, 2, TW>(sl, g, params, st);
-        case 3: return launch_stepT_t<ST, V, TS, 3, TW>(sl, g, params, st);
-        case 4: return launch_stepT_t<ST, V, TS, 4, TW>(sl, g, params, st);
-        default: return hipErrorInvalidValue;
-    }
 }
 
 template <int ST, int V, int TW>
 inline hipError_t launch_stepT_n(const StepLaunch &sl, const GridT &g, const void *params, hipStream_t st) {
     static_assert(kMaxFusedSteps == 4, "instantiate every step count");
     switch (g.steps) {
-        case 2: return launch_stepT_t<ST, V, 2, 1, TW>(sl, g, params, st);
-        case 3: return launch_stepT_k<ST, V, 3, TW>(sl, g, params, st);
-        case 4: return launch_stepT_k<ST, V, 4, TW>(sl, g, params, st);
+        case 2: return launch_stepT_t<ST, V, 2, TW>(sl, g, params, st);
+        case 3: return launch_stepT_t<ST, V, 3, TW>(sl, g, params, st);
+        case 4: return launch_stepT_t<ST, V, 4, TW>(sl, g, params, st);
         default: return hipErrorInvalidValue;
     }
 }

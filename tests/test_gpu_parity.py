@@ -527,21 +527,14 @@ FUSED_CASES = [("f64", "gray_scott", 2), ("f32", "gray_scott", 2), ("f16", "gray
 def multi_step_shape_fits(b, ns, cols, rows, steps, waves):
     """The documented limits of a multi-step launch shape: 32, 64 or 128 columns;
     the LDS region of rows + 2h rows (h = steps - 1), each row 9 ns (cols + 2h)
-    values padded to a multiple of 256 bytes beyond cols + 2h, within 160 KB;
-    and the second phase's rows (rows + 2h - 2 rows of cols + 2h sites) within
-    1 site per thread, or 4 with at most 8 waves."""
+    values padded to a multiple of 256 bytes beyond cols + 2h, within 160 KB."""
     if cols not in (32, 64, 128):
         return False
     h = steps - 1
     ew = cols + 2 * h
     unit = 256 // b
     stride = 9 * ns * ew + (ew - 9 * ns * ew) % unit
-    if (rows + 2 * h) * stride * b > 160 * 1024:
-        return False
-    if steps == 2:
-        return True
-    k = -(-(ew * (rows + 2 * h - 2)) // (64 * waves))
-    return k <= 1 or (k <= 4 and waves <= 8)
+    return (rows + 2 * h) * stride * b <= 160 * 1024
 
 
 @pytest.mark.parametrize("storage,reaction,ns", FUSED_CASES)
@@ -572,7 +565,7 @@ def test_multi_step_launch_is_bitwise_identical(storage, reaction, ns):
         for steps in (2, 3, 4):
             for cols, rows in ((64, 1), (64, 8), (64, 16), (128, 2), (128, 8), (64, 24), (32, 3), (32, 12),
                                (32, 20)):
-                for waves in (4, 8, 16):
+                for waves in (4, 8, 12, 16):
                     if not multi_step_shape_fits(b, ns, cols, rows, steps, waves):
                         with pytest.raises(lbrd.LbrdError):
                             s.set_tuning(fused_steps=steps, tile_cols=cols, tile_rows=rows, waves=waves,
@@ -587,6 +580,9 @@ def test_multi_step_launch_is_bitwise_identical(storage, reaction, ns):
         for cols in (16, 48, 96, 256):                # widths the kernel does not take
             with pytest.raises(lbrd.LbrdError):
                 s.set_tuning(fused_steps=2, tile_cols=cols, tile_rows=2, waves=4, graph_steps=0)
+        for waves in (0, 3, 17):                      # 3: the one-step launches take 1, 2 or 4
+            with pytest.raises(lbrd.LbrdError):
+                s.set_tuning(fused_steps=2, tile_cols=64, tile_rows=2, waves=waves, graph_steps=0)
     log(f"multi-step {storage} {reaction} N={ns}: {ran} shapes bitwise equal")
     assert ran >= 30
 
