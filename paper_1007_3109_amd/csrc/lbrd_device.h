@@ -502,17 +502,15 @@ __device__ __forceinline__ void stepT_middle(const Params<typename Traits<ST>::C
     using C = typename Traits<ST>::C;
     constexpr int NS = NSpecies<V>::value;
     constexpr bool kFromB = (J - 1) % 2 == 0;   // phase J-1 wrote form B when even
-    const int rsz = EW * (eh - 2 * (J - 1));
+    constexpr int W = EW - 2 * (J - 1);          // width of the shrunk region
+    const int rsz = W * (eh - 2 * (J - 1));
     for (int q = threadIdx.x; q < rsz; q += nthr) {
-        const int lx = q % EW;
-        if (lx >= J - 1 && lx < EW - (J - 1)) {
-            const int ly = q / EW + J - 1;
-            C f[NS][9];
-            gather_lds<ST, NS, EW, kFromB>(L, lx, ly, f);
-            T o[NS][9];
-            collide_site<ST, V>(p, f, o);
-            put_lds<ST, NS, EW, !kFromB>(L, lx, ly, o);
-        }
+        const int lx = q % W + (J - 1), ly = q / W + (J - 1);
+        C f[NS][9];
+        gather_lds<ST, NS, EW, kFromB>(L, lx, ly, f);
+        T o[NS][9];
+        collide_site<ST, V>(p, f, o);
+        put_lds<ST, NS, EW, !kFromB>(L, lx, ly, o);
     }
 }
 
@@ -677,9 +675,8 @@ __device__ __forceinline__ void stepT_tile(const TileT &g, const Params<typename
     __syncthreads();
     // middle phases j = 2 .. m-1: step t+j-1 -> t+j on the region shrunk by
     // j-1, in LDS, in place (phase j reads the form phase j-1 wrote: A after
-    // odd phases, B after even ones).  Threads walk whole region rows (all EW
-    // columns, the same order as phase 1, so the bank padding holds) and skip
-    // the columns outside the shrunk region.
+    // odd phases, B after even ones).  Consecutive threads take consecutive
+    // sites of the shrunk region, row by row.
     if constexpr (TS > 2) {
         if (!VARM || m > 2) {
             stepT_middle<ST, V, EW, 2>(p, L, eh, nthr);
