@@ -475,7 +475,12 @@ def main():
                      "steps_per_launch": steps_per_launch,
                      "launch_us": round(launch_seconds * 1e6, 3),
                      "bytes_per_launch": bytes_per_launch,
-                     "note": "1024^2 x 2 species x 9 x 2 buffers x 4 B = 151 MB ping-pong: resident in the 256 MB "
+                     # the same bytes counted once per time step (2 x 9 x 4 B per species-site-step): the
+                     # rate a one-step kernel would need; temporal blocking goes beyond the HBM peak there
+                     "one_step_equivalent_GBs": round(value * 1e6 * 2 * 9 * 4 / 1e9, 1),
+                     "one_step_equivalent_frac": round(value * 1e6 * 2 * 9 * 4 / 1e9 / HBM_PEAK_GBS, 3),
+                     "note": "frac counts the state read and written once per launch of steps_per_launch steps; "
+                             "1024^2 x 2 species x 9 x 2 buffers x 4 B = 151 MB ping-pong: resident in the 256 MB "
                              "Infinity Cache; see extra.hbm_4096_* for working sets beyond it"},
         "wall_s": round(wall, 3),
         "init_from_host_ms": round(init_ms, 3),

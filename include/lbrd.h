@@ -116,11 +116,12 @@ typedef struct lbrd_config {
  *       over tiles.
  *  plain_order: single solvers; 0 = consecutive tiles on the same XCD, 1 = the
  *       hardware's round-robin order.
- *  fused_steps: 1 = one step per launch; T = 2, 3 or 4 =
+ *  fused_steps: 1 = one step per launch; T = 2 .. 8 =
  *       T steps per launch on tile_cols x tile_rows tiles staged in LDS
  *       (temporal blocking; a remainder of 2 .. T-1 steps runs as one shorter
  *       launch on the same tiles, a single remaining step as a one-step
- *       launch).  Results are bitwise identical for every setting.
+ *       launch).  Results are bitwise identical for every setting.  Batches
+ *       take 1 .. 4.
  *  tile_rows, tile_cols: multi-step tile, rows 1..64 and columns 32, 64 or 128.
  *       With h = T-1 and w = tile_cols + 2h, the LDS region of tile_rows + 2h
  *       rows of 9 N w populations (each row padded by fewer than 256 bytes)
@@ -211,8 +212,9 @@ int lbrd_spectrum(lbrd_solver *h, int species, void *out, void *work, size_t wor
 int lbrd_get_tuning(const lbrd_solver *h, lbrd_tuning *out);
 int lbrd_set_tuning(lbrd_solver *h, const lbrd_tuning *t);
 
-/* Time every valid launch shape on this solver's buffers for `steps` steps
- * each and keep the fastest; writes it to *chosen if not NULL.  Overwrites
+/* Time every valid launch shape on this solver's buffers for about `steps`
+ * steps each (whole launches, compared per step) and keep the fastest;
+ * writes it to *chosen if not NULL.  Overwrites
  * the state: the solver must be (re)initialised afterwards (ESTATE until
  * then).  cache_path: text file of earlier results keyed by (device, storage,
  * reaction, N, nx, ny), read and appended; NULL disables the cache. */

@@ -453,43 +453,52 @@ int lbrd_create(const lbrd_config *cfg, void *workspace, size_t bytes, void *str
             h->tune.lanes_x = std::min(32, default_lanes(h->cfg.nx, 8));
         }
     }
-    // Four steps per launch on tiles staged in LDS (temporal blocking):
-    // measured 2.6x (1024^2) and 2.7x (4096^2, FP32) the one-step launches.
-    // While both buffers fit in the 256 MB Infinity Cache the halo's repeated
-    // collisions bound the launch, so the tiles are near-square within the
-    // LDS of about three workgroups per CU: 32 columns, rows by the bytes B
-    // of one site's populations (B <= 18: 64 x 24; <= 36: 32 x 20; <= 72:
-    // 32 x 12; beyond: 32 x 8).  Beyond the cache HBM traffic weighs in: 64
-    // columns, 8 rows for 4- and 8-byte storage, 12 for the 16-bit forms
-    // (three workgroups per CU; 24 rows re-read fewer halo lines but run 4 %
-    // slower at 4096^2 with two).  Rows are halved (then fewer
-    // steps per launch) until the shape fits in LDS and the register budget.
-    // 8 waves per workgroup, cached loads, streaming stores beyond the
-    // Infinity Cache (4 % faster at 4096^2; 40 % slower inside it),
-    // consecutive tiles on one XCD (each measured best).  Buffers of 4 GiB or
-    // more keep one-step launches.
+    // Several steps per launch on tiles staged in LDS (temporal blocking).
+    // The shape is taken from measurements (8 waves per workgroup, T steps
+    // per launch, cols x rows tiles), keyed by the bytes B of one site's
+    // populations and by whether both buffers fit in the 256 MB Infinity
+    // Cache; one species with a linear reaction is cheaper per site and
+    // takes more steps per launch:
+    //   inside the cache: B <= 18: T 5, 64 x 24; B <= 36: one species T 8,
+    //     32 x 32, else T 5, 32 x 24; B <= 72: T 5, 32 x 10; beyond: T 6,
+    //     32 x 16;
+    //   beyond it: B <= 36: one species T 8, 64 x 14, else T 6, 64 x 20;
+    //     B <= 72: T 7, 32 x 12; beyond: T 6, 32 x 16.
+    // (1024^2 FP32 Gray-Scott: 6.6 us per step against 7.3 at T = 4; 4096^2:
+    // 125 us against 149 in FP32, 76 against 85 in FP16.)  A shape that does
+    // not fit in LDS first loses rows (down to 4), then steps per launch.
+    // Cached loads, streaming stores beyond the Infinity Cache (4 % faster at
+    // 4096^2; 40 % slower inside it), consecutive tiles on one XCD (each
+    // measured best).  Buffers of 4 GiB or more keep one-step launches.
     const bool in_cache = 2 * h->L.buf_bytes <= ((size_t)256 << 20);
     const int site_bytes = 9 * h->cfg.nspecies * storage_bytes(h->cfg.storage);
-    if (in_cache) {
-        h->tune.tile_cols = site_bytes <= 18 ? 64 : 32;
-        h->tune.tile_rows = site_bytes <= 18 ? 24 : site_bytes <= 36 ? 20 : site_bytes <= 72 ? 12 : 8;
+    const bool cheap = h->cfg.nspecies == 1;
+    int ts0, cols, rows0;
+    if (site_bytes <= 18) {
+        ts0 = in_cache ? 5 : 6; cols = 64; rows0 = in_cache ? 24 : 20;
+    } else if (site_bytes <= 36) {
+        if (cheap) { ts0 = 8; cols = in_cache ? 32 : 64; rows0 = in_cache ? 32 : 14; }
+        else { ts0 = in_cache ? 5 : 6; cols = in_cache ? 32 : 64; rows0 = in_cache ? 24 : 20; }
+    } else if (site_bytes <= 72) {
+        ts0 = in_cache ? 5 : 7; cols = 32; rows0 = in_cache ? 10 : 12;
     } else {
-        h->tune.tile_cols = 64;
-        h->tune.tile_rows = storage_bytes(h->cfg.storage) == 2 ? 12 : 8;
+        ts0 = 6; cols = 32; rows0 = 16;
     }
+    h->tune.tile_cols = cols;
+    h->tune.tile_rows = rows0;
     h->tune.fused_steps = 1;
     if (multi_step_possible(h)) {
         h->tune.waves = 8;
         h->tune.nontemporal = in_cache ? 0 : 1;
         h->tune.plain_order = 0;
-        for (int ts = kMaxFusedSteps; ts >= 2 && h->tune.fused_steps == 1; --ts) {
-            for (int rows = h->tune.tile_rows; rows >= 1; rows /= 2)
-                if (stepT_shape_fits(h->cfg.storage, h->cfg.nspecies, h->tune.tile_cols, rows, ts, 8)) {
-                    h->tune.fused_steps = ts;
-                    h->tune.tile_rows = rows;
-                    break;
-                }
-        }
+        for (int min_rows : {4, 1})
+            for (int ts = ts0; ts >= 2 && h->tune.fused_steps == 1; --ts)
+                for (int rows = rows0; rows >= min_rows; rows /= 2)
+                    if (stepT_shape_fits(h->cfg.storage, h->cfg.nspecies, cols, rows, ts, 8)) {
+                        h->tune.fused_steps = ts;
+                        h->tune.tile_rows = rows;
+                        break;
+                    }
     }
     *out = h;
     return LBRD_OK;
@@ -690,7 +699,6 @@ int lbrd_time_steps(lbrd_solver *h, int64_t nsteps, double *ms) {
 
 int lbrd_autotune(lbrd_solver *h, int steps, const char *cache_path, lbrd_tuning *chosen) {
     if (!h || steps < 2) return LBRD_EINVAL;
-    steps = (steps + 11) / 12 * 12;   // whole launches for every step count 1 .. 4
     int dev = 0;
     hipGetDevice(&dev);
     hipDeviceProp_t prop;
@@ -748,9 +756,9 @@ int lbrd_autotune(lbrd_solver *h, int steps, const char *cache_path, lbrd_tuning
     for (int ts = 2; ts <= kMaxFusedSteps; ++ts)
         for (int cols : {32, 64, 128})
             for (int rows : {4, 8, 12, 16, 20, 24, 32})
-                for (int w : {4, 8, 16})
+                for (int w : {4, 8})
                     for (int nt = 0; nt < 2; ++nt)
-                        for (int order = 0; order < 2; ++order) {
+                        for (int order = 0; order < 1; ++order) {
                             lbrd_tuning t = h->tune;
                             t.vec = default_vec(h->cfg.storage);
                             t.lanes_x = default_lanes(h->cfg.nx, t.vec);
@@ -775,9 +783,13 @@ int lbrd_autotune(lbrd_solver *h, int steps, const char *cache_path, lbrd_tuning
         tt.graph_steps = 0;
         lbrd_set_tuning(h, &tt);
         double ms = 0;
-        int rc = lbrd_time_steps(h, 2, &ms);   // warm-up
-        if (rc == LBRD_OK) rc = lbrd_time_steps(h, steps, &ms);
+        // whole launches only, compared per step
+        const int per = std::max(1, (int)t.fused_steps);
+        const int n = (steps + per - 1) / per * per;
+        int rc = lbrd_time_steps(h, per, &ms);   // warm-up
+        if (rc == LBRD_OK) rc = lbrd_time_steps(h, n, &ms);
         if (rc != LBRD_OK) continue;
+        ms /= n;
         if (ms < best) {
             best = ms;
             best_t = t;

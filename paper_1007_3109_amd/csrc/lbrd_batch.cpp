@@ -175,7 +175,7 @@ bool batch_tuning_valid(const lbrd_batch *b, const lbrd_tuning &t) {
                !(t.graph_steps & 1);
     // multi-step launches: an even number of launches per captured chunk, so
     // every instance ends a chunk in the buffer it started from
-    if (!b->multi_ok || t.fused_steps < 2 || t.fused_steps > kMaxFusedSteps) return false;
+    if (!b->multi_ok || t.fused_steps < 2 || t.fused_steps > kMaxBatchFusedSteps) return false;
     if (t.graph_steps % (2 * t.fused_steps)) return false;
     if (t.blocks_per_cu < 0 || t.blocks_per_cu > 32) return false;
     return stepT_shape_fits(kF32, 2, 64, t.tile_rows, t.fused_steps, t.waves);
@@ -531,7 +531,7 @@ int lbrd_batch_autotune(lbrd_batch *b, int steps, lbrd_tuning *chosen) {
                 cands.push_back(t);
             }
     if (b->multi_ok)
-        for (int ts = 2; ts <= kMaxFusedSteps; ++ts)
+        for (int ts = 2; ts <= kMaxBatchFusedSteps; ++ts)
             for (int rows : {4, 8, 16})
                 for (int w : {4, 8, 16})
                     for (int nt = 0; nt < 2; ++nt) {

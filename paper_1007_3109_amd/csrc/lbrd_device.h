@@ -514,6 +514,19 @@ __device__ __forceinline__ void stepT_middle(const Params<typename Traits<ST>::C
     }
 }
 
+// Middle phases J, J+1, .. min(m, TS)-1, each followed by a barrier.
+template <int ST, int V, int TS, int EW, int J, bool VARM>
+__device__ __forceinline__ void stepT_middles(const Params<typename Traits<ST>::C> &p, typename Traits<ST>::T *L,
+                                              int eh, int nthr, int m) {
+    if constexpr (J < TS) {
+        if (!VARM || m > J) {
+            stepT_middle<ST, V, EW, J>(p, L, eh, nthr);
+            __syncthreads();
+            stepT_middles<ST, V, TS, EW, J + 1, VARM>(p, L, eh, nthr, m);
+        }
+    }
+}
+
 // Last phase of a multi-step tile: pull from LDS (form B when the previous
 // phase was even), collide on the tile itself, store to the destination.
 template <int ST, int V, int TW, int H, bool FROM_B>
@@ -677,19 +690,7 @@ __device__ __forceinline__ void stepT_tile(const TileT &g, const Params<typename
     // j-1, in LDS, in place (phase j reads the form phase j-1 wrote: A after
     // odd phases, B after even ones).  Consecutive threads take consecutive
     // sites of the shrunk region, row by row.
-    if constexpr (TS > 2) {
-        if (!VARM || m > 2) {
-            stepT_middle<ST, V, EW, 2>(p, L, eh, nthr);
-            __syncthreads();
-        }
-    }
-    if constexpr (TS > 3) {
-        if (!VARM || m > 3) {
-            stepT_middle<ST, V, EW, 3>(p, L, eh, nthr);
-            __syncthreads();
-        }
-    }
-    static_assert(TS <= 4, "middle phases are spelled out for up to four steps per launch");
+    stepT_middles<ST, V, TS, EW, 2, VARM>(p, L, eh, nthr, m);
     // last phase: step t+m-1 -> t+m on the tile, to the destination buffer
     if (m & 1)
         stepT_last<ST, V, TW, H, true>(g, p, L, x0, y0, nthr);

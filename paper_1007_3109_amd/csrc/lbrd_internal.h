@@ -98,7 +98,8 @@ struct GridT {
     int nt_store;     // 1: streaming (non-temporal) stores of the result
 };
 
-constexpr int kMaxFusedSteps = 4;
+constexpr int kMaxFusedSteps = 8;
+constexpr int kMaxBatchFusedSteps = 4;
 
 GridT make_gridT(const Layout &L, const void *src, void *dst, int tw, int th, int steps);
 // LDS row stride (elements) of the multi-step region of width ew with 9 N

@@ -70,11 +70,15 @@ inline hipError_t launch_stepT_t(const StepLaunch &sl, const GridT &g, const voi
 
 template <int ST, int V, int TW>
 inline hipError_t launch_stepT_n(const StepLaunch &sl, const GridT &g, const void *params, hipStream_t st) {
-    static_assert(kMaxFusedSteps == 4, "instantiate every step count");
+    static_assert(kMaxFusedSteps == 8, "instantiate every step count");
     switch (g.steps) {
         case 2: return launch_stepT_t<ST, V, 2, TW>(sl, g, params, st);
         case 3: return launch_stepT_t<ST, V, 3, TW>(sl, g, params, st);
         case 4: return launch_stepT_t<ST, V, 4, TW>(sl, g, params, st);
+        case 5: return launch_stepT_t<ST, V, 5, TW>(sl, g, params, st);
+        case 6: return launch_stepT_t<ST, V, 6, TW>(sl, g, params, st);
+        case 7: return launch_stepT_t<ST, V, 7, TW>(sl, g, params, st);
+        case 8: return launch_stepT_t<ST, V, 8, TW>(sl, g, params, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -146,6 +146,8 @@ def test_batch_multi_step_advance_equals_solo(ts, graph_steps, nt):
         n = counts[idx] + more[idx] + 9
         assert b.time(idx) == n
         assert torch.equal(b.moments(idx)[0], solo(cfg, rho0, n)), (idx, n)
+    with pytest.raises(lbrd.LbrdError):                 # batches take at most four steps per launch
+        b.set_tuning(fused_steps=5, tile_rows=4, waves=8, blocks_per_cu=0, graph_steps=0)
 
 
 @pytest.mark.parametrize("graph_steps", [0, 8])

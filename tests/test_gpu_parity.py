@@ -528,7 +528,7 @@ def multi_step_shape_fits(b, ns, cols, rows, steps, waves):
     """The documented limits of a multi-step launch shape: 32, 64 or 128 columns;
     the LDS region of rows + 2h rows (h = steps - 1), each row 9 ns (cols + 2h)
     values padded to a multiple of 256 bytes beyond cols + 2h, within 160 KB."""
-    if cols not in (32, 64, 128):
+    if cols not in (32, 64, 128) or not 2 <= steps <= 8:
         return False
     h = steps - 1
     ew = cols + 2 * h
@@ -540,11 +540,11 @@ def multi_step_shape_fits(b, ns, cols, rows, steps, waves):
 @pytest.mark.parametrize("storage,reaction,ns", FUSED_CASES)
 def test_multi_step_launch_is_bitwise_identical(storage, reaction, ns):
     """The LDS-tiled multi-step launch runs each site's arithmetic exactly as
-    the one-step launch, so every population after 7 steps (T-step launches, a
-    shorter launch for a remainder of 2 .. T-1, a one-step launch for a single
-    remaining step) is bitwise equal, on ragged and tiny lattices and on one
-    with interior tiles (whose pulled region does not wrap), for 2, 3 and
-    4 steps per launch, the three tile widths, several heights and workgroup
+    the one-step launch, so every population after 19 steps (T-step launches,
+    a shorter launch for a remainder of 2 .. T-1, a one-step launch for a
+    single remaining step) is bitwise equal, on ragged and tiny lattices and
+    on one with interior tiles (whose pulled region does not wrap), for 2 .. 8
+    steps per launch, the three tile widths, several heights and workgroup
     sizes.  Shapes beyond the documented limits are rejected with EINVAL."""
     b = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[storage]
     ran = 0
@@ -559,10 +559,10 @@ def test_multi_step_launch_is_bitwise_identical(storage, reaction, ns):
         f0 = rng.uniform(0.0, 0.1, size=(ns, 9, ny, nx))
         ref = lbrd.Solver(cfg)
         ref.set_tuning(fused_steps=1, graph_steps=0)
-        ref.set_populations(f0).step(7)
+        ref.set_populations(f0).step(19)
         want = ref.get_populations()
         s = lbrd.Solver(cfg)
-        for steps in (2, 3, 4):
+        for steps in range(2, 9):
             for cols, rows in ((64, 1), (64, 8), (64, 16), (128, 2), (128, 8), (64, 24), (32, 3), (32, 12),
                                (32, 20)):
                 for waves in (4, 8, 12, 16):
@@ -573,10 +573,12 @@ def test_multi_step_launch_is_bitwise_identical(storage, reaction, ns):
                         continue
                     s.set_tuning(fused_steps=steps, tile_cols=cols, tile_rows=rows, waves=waves, graph_steps=0,
                                  nontemporal=int(waves == 16))
-                    s.set_populations(f0).step(7)
+                    s.set_populations(f0).step(19)
                     assert torch.equal(s.get_populations(), want), (ny, nx, steps, cols, rows, waves)
                     ran += 1
-        assert s.time() == 7
+        assert s.time() == 19
+        with pytest.raises(lbrd.LbrdError):             # beyond eight steps per launch
+            s.set_tuning(fused_steps=9, tile_cols=32, tile_rows=2, waves=8, graph_steps=0)
         for cols in (16, 48, 96, 256):                # widths the kernel does not take
             with pytest.raises(lbrd.LbrdError):
                 s.set_tuning(fused_steps=2, tile_cols=cols, tile_rows=2, waves=4, graph_steps=0)
@@ -585,6 +587,36 @@ def test_multi_step_launch_is_bitwise_identical(storage, reaction, ns):
                 s.set_tuning(fused_steps=2, tile_cols=64, tile_rows=2, waves=waves, graph_steps=0)
     log(f"multi-step {storage} {reaction} N={ns}: {ran} shapes bitwise equal")
     assert ran >= 30
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
+def test_default_shape_for_every_species_count(storage):
+    """The default launch shape, chosen from the bytes of a site and whether
+    the state fits in the Infinity Cache, is a valid multi-step shape for 1 to
+    4 species on a small and on a cache-exceeding lattice, and a ragged number
+    of steps with it equals one-step launches bitwise."""
+    b = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[storage]
+    for ns in (1, 2, 3, 4):
+        beyond = int(math.ceil(math.sqrt(300e6 / (2 * 9 * ns * b))))
+        for ny, nx in ((80, 96), (beyond + 3, beyond)):
+            cfg = lbrd.make_config(nx, ny, ns, tau=[0.7, 1.2, 0.9, 0.8][:ns], storage=storage, reaction="linear",
+                                   K=-0.01 * np.eye(ns), rho_ref=(0.3,) * ns)
+            s = lbrd.Solver(cfg)
+            t = s.tuning()
+            assert 2 <= t.fused_steps <= 8 and t.waves == 8, (ns, nx, t.as_dict())
+            assert multi_step_shape_fits(b, ns, t.tile_cols, t.tile_rows, t.fused_steps, t.waves)
+            n = 2 * t.fused_steps + 3
+            f0 = np.random.default_rng(ns * 31 + nx).uniform(0.0, 0.1, size=(ns, 9, ny, nx))
+            s.set_populations(f0).step(n)
+            got = s.get_populations()
+            s.close()
+            ref = lbrd.Solver(cfg)
+            ref.set_tuning(fused_steps=1, graph_steps=0)
+            ref.set_populations(f0).step(n)
+            assert torch.equal(got, ref.get_populations()), (ns, nx, t.as_dict())
+            ref.close()
+            del got
+            torch.cuda.empty_cache()
 
 
 def test_multi_step_launch_with_graphs_and_oracle():
