@@ -4,8 +4,8 @@ Workload timed for the headline line: Gray-Scott (u, v), D2Q9 BGK, 1024 x 1024
 periodic, FP32 storage, tau = (1.0, 0.75), F = 0.04, k = 0.06, central 64 x 64
 square with u = 0.5, v = 0.25 plus U(-0.01, 0.01) noise (seed 0).  One "step"
 is one lattice time step of the whole field (every species, every site):
-collide, react and stream.  The library's default launch shape advances four
-steps per launch (64 x rows tiles staged in LDS); --tune runs its autotuner
+collide, react and stream.  The library's default launch shape advances five
+steps per launch (32 x 10 tiles staged in LDS); --tune runs its autotuner
 first.
 
 The JSON line carries the headline MLUPS per species, the roofline of the
@@ -153,7 +153,7 @@ def batch_leg(torch, lbrd, workloads, steps, warmup, seed=0):
     cfgs = [lbrd.make_config(i.side, i.side, 2, tau=workloads.GS_TAU, storage="f32", reaction="gray_scott",
                              F=i.F, k=i.k) for i in insts]
     b = lbrd.Batch(cfgs)
-    t = b.autotune(steps=3)
+    t = b.autotune(steps=14)
     for idx, inst in enumerate(insts):
         b.init(idx, workloads.batch_initial(inst))
     b.step(warmup)

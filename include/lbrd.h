@@ -120,8 +120,7 @@ typedef struct lbrd_config {
  *       T steps per launch on tile_cols x tile_rows tiles staged in LDS
  *       (temporal blocking; a remainder of 2 .. T-1 steps runs as one shorter
  *       launch on the same tiles, a single remaining step as a one-step
- *       launch).  Results are bitwise identical for every setting.  Batches
- *       take 1 .. 4.
+ *       launch).  Results are bitwise identical for every setting.
  *  tile_rows, tile_cols: multi-step tile, rows 1..64 and columns 32, 64 or 128.
  *       With h = T-1 and w = tile_cols + 2h, the LDS region of tile_rows + 2h
  *       rows of 9 N w populations (each row padded by fewer than 256 bytes)
@@ -255,8 +254,10 @@ int lbrd_batch_spectrum(lbrd_batch *b, int idx, int species, void *out, void *wo
 /* Launch shape of a batch.  Batches whose instances are all Gray-Scott FP32,
  * or all from the serving mix (one-species linear or Gray-Scott without a
  * velocity, in FP32 / F16 / BF16 storage, each buffer below 4 GiB), take
- * fused_steps = T in 2..4 on 64 x tile_rows tiles (default 4 steps on 64 x 8
- * tiles, 8 waves, blocks_per_cu 0 = one workgroup per tile, graph_steps 32):
+ * fused_steps = T in 2..8 on tile_cols x tile_rows tiles, tile_cols 32 or 64
+ * (default 5 steps on 32 x 10 tiles while the buffers fit in the 256 MB
+ * Infinity Cache, 7 steps on 32 x 12 beyond it, 8 waves, blocks_per_cu 0 =
+ * one workgroup per tile, graph_steps the multiple of 2T nearest 32):
  * launch j advances each instance by min(T, its steps left in the chunk), and
  * graph_steps must be a multiple of 2T.  Other batches use persistent
  * one-step launches: fused_steps = 1, waves 1/2/4, blocks_per_cu 1..32,

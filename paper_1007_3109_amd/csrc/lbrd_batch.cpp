@@ -107,7 +107,7 @@ hipError_t retile(lbrd_batch *b) {
     int64_t tiles = 0;
     for (int i = 0; i < b->count; ++i) {
         BatchInst &bi = b->inst[i];
-        set_batch_tiling(bi, b->L[i], steps_per_launch(b), b->tune.tile_rows);
+        set_batch_tiling(bi, b->L[i], steps_per_launch(b), b->tune.tile_rows, b->tune.tile_cols);
         bi.tile_begin = tiles;
         tiles += bi.ntiles;
     }
@@ -141,7 +141,7 @@ hipError_t enqueue(lbrd_batch *b, int64_t launches, hipStream_t st) {
     for (int64_t j = 0; j < launches; ++j) {
         hipError_t e =
             ts > 1 ? launch_batch_stepT(b->d_hdr, b->d_inst, (int)j, blocks_of(b), b->tune.waves, ts, b->tune.tile_rows,
-                                        b->set, st)
+                                        b->tune.tile_cols, b->set, st)
                    : launch_batch_step(b->d_hdr, b->d_inst, (int)j, (int)blocks_of(b), b->tune.waves,
                                        b->tune.nontemporal != 0, b->set, st);
         if (e != hipSuccess) return e;
@@ -178,7 +178,7 @@ bool batch_tuning_valid(const lbrd_batch *b, const lbrd_tuning &t) {
     if (!b->multi_ok || t.fused_steps < 2 || t.fused_steps > kMaxBatchFusedSteps) return false;
     if (t.graph_steps % (2 * t.fused_steps)) return false;
     if (t.blocks_per_cu < 0 || t.blocks_per_cu > 32) return false;
-    return stepT_shape_fits(kF32, 2, 64, t.tile_rows, t.fused_steps, t.waves);
+    return batch_shape_fits(t.fused_steps, t.tile_rows, t.tile_cols, t.waves);
 }
 
 const void *params_of(const lbrd_batch *b, int idx) {
@@ -235,17 +235,24 @@ int lbrd_batch_create(const lbrd_config *cfgs, int count, void *workspace, size_
         if (!batch_multi_ok(b->L[i], b->cfg[i].storage)) b->multi_ok = false;
     std::memset(&b->tune, 0, sizeof(b->tune));
     if (b->multi_ok) {
-        // four steps per launch on 64 x 8 tiles, one workgroup of 8 waves per
-        // tile, streaming stores when the buffers exceed the Infinity Cache
-        // (the single-lattice defaults beyond it)
+        // the single-lattice FP32 Gray-Scott shapes (the LDS of both sets is
+        // sized for it): five steps per launch on 32 x 10 tiles while the
+        // buffers fit in the Infinity Cache, seven on 32 x 12 beyond it
+        // (256-instance sweep: 221 us per step, against 261 with four steps
+        // on 64 x 8), one workgroup of 8 waves per tile, streaming stores
+        // beyond the cache, graphs of about 32 steps (an even number of
+        // launches)
         size_t bytes = 0;
         for (const Layout &L : b->L) bytes += 2 * L.buf_bytes;
-        b->tune.fused_steps = 4;
-        b->tune.tile_rows = 8;
+        const bool in_cache = bytes <= ((size_t)256 << 20);
+        b->tune.fused_steps = in_cache ? 5 : 7;
+        b->tune.tile_rows = in_cache ? 10 : 12;
+        b->tune.tile_cols = 32;
         b->tune.waves = 8;
         b->tune.blocks_per_cu = 0;
-        b->tune.graph_steps = 32;
-        b->tune.nontemporal = bytes > ((size_t)256 << 20) ? 1 : 0;
+        const int unit = 2 * b->tune.fused_steps;
+        b->tune.graph_steps = std::max(1, (32 + unit / 2) / unit) * unit;
+        b->tune.nontemporal = in_cache ? 0 : 1;
     } else {
         b->tune.fused_steps = 1;
         b->tune.waves = 4;
@@ -464,11 +471,11 @@ int lbrd_batch_set_tuning(lbrd_batch *b, const lbrd_tuning *t) {
     n.lanes_x = 0;
     n.plain_order = 0;
     if (n.fused_steps == 1) n.tile_rows = 0;
-    n.tile_cols = n.fused_steps > 1 ? 64 : 0;
+    if (n.fused_steps == 1) n.tile_cols = 0;
     if (!batch_tuning_valid(b, n)) return LBRD_EINVAL;
     if (std::memcmp(&n, &b->tune, sizeof(n)) == 0) return LBRD_OK;
     const bool tiling = n.fused_steps != b->tune.fused_steps || n.tile_rows != b->tune.tile_rows ||
-                        n.nontemporal != b->tune.nontemporal;
+                        n.tile_cols != b->tune.tile_cols || n.nontemporal != b->tune.nontemporal;
     drop_graph(b);
     b->tune = n;
     if (tiling) {
@@ -514,7 +521,6 @@ int lbrd_batch_autotune(lbrd_batch *b, int steps, lbrd_tuning *chosen) {
         b->initialised[i] = 1;
     }
     const lbrd_tuning keep = b->tune;
-    steps = (steps + 11) / 12 * 12;   // whole launches for every step count 1 .. 4
     // candidates: persistent one-step launches over blocks per CU, waves and
     // streaming accesses; multi-step launches over steps per launch, tile
     // heights and workgroup sizes (one workgroup per tile)
@@ -525,6 +531,7 @@ int lbrd_batch_autotune(lbrd_batch *b, int steps, lbrd_tuning *chosen) {
                 lbrd_tuning t = keep;
                 t.fused_steps = 1;
                 t.tile_rows = 0;
+                t.tile_cols = 0;
                 t.blocks_per_cu = bpc;
                 t.waves = w;
                 t.nontemporal = nt;
@@ -532,11 +539,13 @@ int lbrd_batch_autotune(lbrd_batch *b, int steps, lbrd_tuning *chosen) {
             }
     if (b->multi_ok)
         for (int ts = 2; ts <= kMaxBatchFusedSteps; ++ts)
-            for (int rows : {4, 8, 16})
-                for (int w : {4, 8, 16})
-                    for (int nt = 0; nt < 2; ++nt) {
+            for (int cols : {32, 64})
+                for (int rows : {4, 8, 12, 16, 20})
+                    for (int w : {4, 8})
+                        for (int nt = 0; nt < 2; ++nt) {
                         lbrd_tuning t = keep;
                         t.fused_steps = ts;
+                        t.tile_cols = cols;
                         t.tile_rows = rows;
                         t.blocks_per_cu = 0;
                         t.waves = w;
@@ -549,8 +558,12 @@ int lbrd_batch_autotune(lbrd_batch *b, int steps, lbrd_tuning *chosen) {
         t.graph_steps = 0;
         if (lbrd_batch_set_tuning(b, &t) != LBRD_OK) continue;
         double ms = 0;
-        if (lbrd_batch_time_steps(b, 2, &ms) != LBRD_OK) continue;
-        if (lbrd_batch_time_steps(b, steps, &ms) != LBRD_OK) continue;
+        // whole launches only, compared per step
+        const int per = std::max(1, (int)t.fused_steps);
+        const int n = (steps + per - 1) / per * per;
+        if (lbrd_batch_time_steps(b, per, &ms) != LBRD_OK) continue;
+        if (lbrd_batch_time_steps(b, n, &ms) != LBRD_OK) continue;
+        ms /= n;
         if (ms < best_ms) {
             best_ms = ms;
             best = t;

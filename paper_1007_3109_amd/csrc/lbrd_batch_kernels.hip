@@ -87,7 +87,7 @@ __global__ __launch_bounds__(256) void k_batch_step(const BatchHeader *__restric
 
 // ------------------------------------------- several steps per launch --
 
-template <int ST, int V, int TS>
+template <int ST, int V, int TS, int TW>
 __device__ __forceinline__ void batch_tileT(const BatchInst &bi, int j, int64_t local, int m, int nt_store,
                                             unsigned char *smem) {
     using T = typename Traits<ST>::T;
@@ -103,23 +103,23 @@ __device__ __forceinline__ void batch_tileT(const BatchInst &bi, int j, int64_t 
     t.nt_store = nt_store;
     const int tx = (int)(local % bi.mt_ntx), ty = (int)(local / bi.mt_ntx);
     if constexpr (ST == kF64)
-        stepT_tile<ST, V, TS, 64, true>(t, bi.pd, tx * 64, ty * bi.mt_th, m, reinterpret_cast<T *>(smem));
+        stepT_tile<ST, V, TS, TW, true>(t, bi.pd, tx * TW, ty * bi.mt_th, m, reinterpret_cast<T *>(smem));
     else
-        stepT_tile<ST, V, TS, 64, true>(t, bi.pf, tx * 64, ty * bi.mt_th, m, reinterpret_cast<T *>(smem));
+        stepT_tile<ST, V, TS, TW, true>(t, bi.pf, tx * TW, ty * bi.mt_th, m, reinterpret_cast<T *>(smem));
 }
 
-template <int ST, int TS>
+template <int ST, int TS, int TW>
 __device__ __forceinline__ void batch_tileT_serve(const BatchInst &bi, int j, int64_t local, int m, int nt_store,
                                                   unsigned char *smem) {
-    if (bi.variant == kGS) batch_tileT<ST, kGS, TS>(bi, j, local, m, nt_store, smem);
-    else batch_tileT<ST, kLin1, TS>(bi, j, local, m, nt_store, smem);
+    if (bi.variant == kGS) batch_tileT<ST, kGS, TS, TW>(bi, j, local, m, nt_store, smem);
+    else batch_tileT<ST, kLin1, TS, TW>(bi, j, local, m, nt_store, smem);
 }
 
 // Launch j of a chunk, TS steps per launch: every workgroup walks the global
-// list of 64 x rows tiles; the owning instance is found by binary search over
+// list of TW x rows tiles; the owning instance is found by binary search over
 // tile_begin (workgroup-uniform).  Instance i takes m = min(TS, steps_i - j TS)
 // steps on its tiles when m > 0; its buffers alternate once per launch.
-template <int SET, int TS>
+template <int SET, int TS, int TW>
 __global__ __launch_bounds__(1024) void k_batch_stepT(const BatchHeader *__restrict__ hdr,
                                                                         const BatchInst *__restrict__ inst, int j) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -140,64 +140,83 @@ __global__ __launch_bounds__(1024) void k_batch_stepT(const BatchHeader *__restr
         const int m = (int)(bi.steps - done < TS ? bi.steps - done : TS);
         const int64_t local = t - bi.tile_begin;
         if constexpr (SET == kBatchGSF32) {
-            batch_tileT<kF32, kGS, TS>(bi, j, local, m, nt_store, smem);
+            batch_tileT<kF32, kGS, TS, TW>(bi, j, local, m, nt_store, smem);
         } else {
             switch (bi.storage) {
-                case kF32: batch_tileT_serve<kF32, TS>(bi, j, local, m, nt_store, smem); break;
-                case kF16: batch_tileT_serve<kF16, TS>(bi, j, local, m, nt_store, smem); break;
-                default: batch_tileT_serve<kBF16, TS>(bi, j, local, m, nt_store, smem); break;
+                case kF32: batch_tileT_serve<kF32, TS, TW>(bi, j, local, m, nt_store, smem); break;
+                case kF16: batch_tileT_serve<kF16, TS, TW>(bi, j, local, m, nt_store, smem); break;
+                default: batch_tileT_serve<kBF16, TS, TW>(bi, j, local, m, nt_store, smem); break;
             }
         }
     }
 }
 
-template <int SET, int TS>
+template <int SET, int TS, int TW>
 static hipError_t launch_setT(const BatchHeader *hdr, const BatchInst *inst, int j, int64_t blocks, int waves,
                               size_t lds, hipStream_t st) {
     static bool attr_set = false;   // per instantiation: allow more than 64 KB of LDS
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch_stepT<SET, TS>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch_stepT<SET, TS, TW>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_batch_stepT<SET, TS>), dim3((unsigned)blocks), dim3(64 * waves), lds, st, hdr, inst,
+    hipLaunchKernelGGL((k_batch_stepT<SET, TS, TW>), dim3((unsigned)blocks), dim3(64 * waves), lds, st, hdr, inst,
                        j);
     return hipGetLastError();
 }
 
-template <int SET>
+template <int SET, int TW>
 static hipError_t launch_setT_n(const BatchHeader *hdr, const BatchInst *inst, int j, int64_t blocks, int waves,
-                                int ts, int rows, size_t lds, hipStream_t st) {
+                                int ts, size_t lds, hipStream_t st) {
+    static_assert(kMaxBatchFusedSteps == 8, "instantiate every step count");
     switch (ts) {
-        case 2: return launch_setT<SET, 2>(hdr, inst, j, blocks, waves, lds, st);
-        case 3: return launch_setT<SET, 3>(hdr, inst, j, blocks, waves, lds, st);
-        case 4: return launch_setT<SET, 4>(hdr, inst, j, blocks, waves, lds, st);
+        case 2: return launch_setT<SET, 2, TW>(hdr, inst, j, blocks, waves, lds, st);
+        case 3: return launch_setT<SET, 3, TW>(hdr, inst, j, blocks, waves, lds, st);
+        case 4: return launch_setT<SET, 4, TW>(hdr, inst, j, blocks, waves, lds, st);
+        case 5: return launch_setT<SET, 5, TW>(hdr, inst, j, blocks, waves, lds, st);
+        case 6: return launch_setT<SET, 6, TW>(hdr, inst, j, blocks, waves, lds, st);
+        case 7: return launch_setT<SET, 7, TW>(hdr, inst, j, blocks, waves, lds, st);
+        case 8: return launch_setT<SET, 8, TW>(hdr, inst, j, blocks, waves, lds, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int SET>
+static hipError_t launch_setT_w(const BatchHeader *hdr, const BatchInst *inst, int j, int64_t blocks, int waves,
+                                int ts, int cols, size_t lds, hipStream_t st) {
+    switch (cols) {
+        case 32: return launch_setT_n<SET, 32>(hdr, inst, j, blocks, waves, ts, lds, st);
+        case 64: return launch_setT_n<SET, 64>(hdr, inst, j, blocks, waves, ts, lds, st);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_batch_stepT(const BatchHeader *hdr, const BatchInst *inst, int j, int64_t blocks, int waves, int ts,
-                              int rows, int set, hipStream_t st) {
+                              int rows, int cols, int set, hipStream_t st) {
     // LDS of the largest member of either set: Gray-Scott in FP32
-    if (!stepT_shape_fits(kF32, 2, 64, rows, ts, waves) || blocks < 1 || blocks > 0x7fffffff)
-        return hipErrorInvalidValue;
-    const size_t lds = stepT_lds_bytes(kF32, 2, 64, rows, ts);
+    if (!batch_shape_fits(ts, rows, cols, waves) || blocks < 1 || blocks > 0x7fffffff) return hipErrorInvalidValue;
+    const size_t lds = stepT_lds_bytes(kF32, 2, cols, rows, ts);
     switch (set) {
-        case kBatchGSF32: return launch_setT_n<kBatchGSF32>(hdr, inst, j, blocks, waves, ts, rows, lds, st);
-        case kBatchServe: return launch_setT_n<kBatchServe>(hdr, inst, j, blocks, waves, ts, rows, lds, st);
+        case kBatchGSF32: return launch_setT_w<kBatchGSF32>(hdr, inst, j, blocks, waves, ts, cols, lds, st);
+        case kBatchServe: return launch_setT_w<kBatchServe>(hdr, inst, j, blocks, waves, ts, cols, lds, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+bool batch_shape_fits(int ts, int rows, int cols, int waves) {
+    return ts >= 2 && ts <= kMaxBatchFusedSteps && (cols == 32 || cols == 64) &&
+           stepT_shape_fits(kF32, 2, cols, rows, ts, waves);
 }
 
 bool batch_multi_ok(const Layout &L, int storage) {
     return L.buf_bytes < ((size_t)1 << 32) && (int64_t)L.pitch * storage_bytes(storage) < ((int64_t)1 << 24);
 }
 
-void set_batch_tiling(BatchInst &bi, const Layout &L, int ts, int rows) {
+void set_batch_tiling(BatchInst &bi, const Layout &L, int ts, int rows, int cols) {
     if (ts > 1) {
         bi.mt_th = rows;
-        bi.mt_ntx = (L.nx + 63) / 64;
+        bi.mt_ntx = (L.nx + cols - 1) / cols;
         bi.ntiles = (int64_t)bi.mt_ntx * ((L.ny + rows - 1) / rows);
         bi.bytes = (uint32_t)L.buf_bytes;
     } else {

@@ -99,7 +99,7 @@ struct GridT {
 };
 
 constexpr int kMaxFusedSteps = 8;
-constexpr int kMaxBatchFusedSteps = 4;
+constexpr int kMaxBatchFusedSteps = 8;
 
 GridT make_gridT(const Layout &L, const void *src, void *dst, int tw, int th, int steps);
 // LDS row stride (elements) of the multi-step region of width ew with 9 N
@@ -179,7 +179,7 @@ struct alignas(16) BatchInst {
     int32_t storage, variant, vec;
     int32_t cur;          // buffer holding the state at the start of the chunk
     int32_t steps;        // steps this instance takes in the chunk
-    int32_t mt_ntx, mt_th;   // multi-step tiling: 64 x mt_th tiles, mt_ntx per row
+    int32_t mt_ntx, mt_th;   // multi-step tiling: cols x mt_th tiles, mt_ntx per row
     uint32_t bytes;          // bytes of one buffer (multi-step launches: < 4 GiB)
     int32_t pad;
     union {
@@ -204,20 +204,23 @@ enum BatchSet : int { kBatchGSF32 = 0, kBatchServe = 1, kBatchAny = 2 };
 // device memory, so a captured graph stays valid when their contents change.
 hipError_t launch_batch_step(const BatchHeader *hdr, const BatchInst *inst, int j, int blocks, int waves,
                              bool nontemporal, int set, hipStream_t st);
-// Launch j of a chunk with `ts` steps per launch (2 .. kMaxFusedSteps) on 64 x
-// rows tiles: instance i advances min(ts, steps_i - j ts) steps if that is
-// positive.  Sets kBatchGSF32 and kBatchServe only; the descriptors must carry
-// the multi-step tiling (set_batch_tiling).  `blocks` workgroups of `waves`
-// waves walk the tiles.
+// Launch j of a chunk with `ts` steps per launch (2 .. kMaxBatchFusedSteps) on
+// cols x rows tiles (cols 32 or 64): instance i advances min(ts, steps_i - j ts)
+// steps if that is positive.  Sets kBatchGSF32 and kBatchServe only; the
+// descriptors must carry the same multi-step tiling (set_batch_tiling).
+// `blocks` workgroups of `waves` waves walk the tiles.
 hipError_t launch_batch_stepT(const BatchHeader *hdr, const BatchInst *inst, int j, int64_t blocks, int waves, int ts,
-                              int rows, int set, hipStream_t st);
+                              int rows, int cols, int set, hipStream_t st);
+// Whether a batched multi-step shape fits (LDS of the largest member of either
+// set, Gray-Scott in FP32).
+bool batch_shape_fits(int ts, int rows, int cols, int waves);
 // Whether an instance can take multi-step launches (32-bit byte offsets).
 bool batch_multi_ok(const Layout &L, int storage);
 // Number of launches that advance `steps` steps at `ts` steps per launch.
 inline int64_t launches_for(int64_t steps, int ts) { return ts > 1 ? (steps + ts - 1) / ts : steps; }
-// Fill the tiling fields of a descriptor: one-step tiles (ts = 1) or 64 x rows
-// multi-step tiles.
-void set_batch_tiling(BatchInst &bi, const Layout &L, int ts, int rows);
+// Fill the tiling fields of a descriptor: one-step tiles (ts = 1) or cols x
+// rows multi-step tiles.
+void set_batch_tiling(BatchInst &bi, const Layout &L, int ts, int rows, int cols);
 int batch_vec(int storage);
 void fill_batch_inst(BatchInst &bi, const lbrd_config &c, const Layout &L, const void *buf0, const void *buf1,
                      int vec, int lanes_x);

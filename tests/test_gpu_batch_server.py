@@ -55,20 +55,21 @@ def mixed_cases():
 
 @pytest.mark.parametrize("mode", ["default", "one-step", "three-step"])
 def test_batch_gs_f32_equals_solo_and_oracle(mode):
-    """The batched Gray-Scott FP32 job (default: four steps per launch on LDS
-    tiles, graphs of 32 steps; also persistent one-step launches and three
-    steps per launch) equals solo runs bitwise after 151 steps (graph replays
-    plus a ragged remainder) and the FP64 oracle within the FP32 floor."""
+    """The batched Gray-Scott FP32 job (default: five steps per launch on
+    32 x 10 LDS tiles inside the Infinity Cache, graphs of 30 steps; also
+    persistent one-step launches and three steps per launch) equals solo runs
+    bitwise after 151 steps (graph replays plus a ragged remainder) and the
+    FP64 oracle within the FP32 floor."""
     insts = [i for i in workloads.batch_sweep(3, grid=4, sides=(64, 96, 130))]
     cfgs = [lbrd.make_config(i.side, i.side, 2, tau=workloads.GS_TAU, storage="f32", reaction="gray_scott",
                              F=i.F, k=i.k) for i in insts]
     b = lbrd.Batch(cfgs)
     t = b.tuning()
-    assert t.fused_steps == 4 and t.tile_rows == 8 and t.graph_steps == 32
+    assert (t.fused_steps, t.tile_cols, t.tile_rows, t.graph_steps) == (5, 32, 10, 30)
     if mode == "one-step":
         b.set_tuning(fused_steps=1, waves=4, blocks_per_cu=8, graph_steps=16)
     elif mode == "three-step":
-        b.set_tuning(fused_steps=3, tile_rows=4, waves=8, graph_steps=18)
+        b.set_tuning(fused_steps=3, tile_rows=4, tile_cols=64, waves=8, graph_steps=18)
         with pytest.raises(lbrd.LbrdError):
             b.set_tuning(graph_steps=16)        # not an even number of three-step launches
     for idx, inst in enumerate(insts):
@@ -126,15 +127,17 @@ def serve_mix_cases():
     return [(c, r) for c, r in mixed_cases() if c.storage != lbrd.STORAGE["f64"]]
 
 
-@pytest.mark.parametrize("ts,graph_steps,nt", [(4, 0, 0), (4, 16, 1), (3, 12, 0), (2, 4, 1)])
-def test_batch_multi_step_advance_equals_solo(ts, graph_steps, nt):
+@pytest.mark.parametrize("ts,cols,graph_steps,nt", [(4, 64, 0, 0), (4, 64, 16, 1), (3, 64, 12, 0), (2, 32, 4, 1),
+                                                   (5, 32, 10, 0), (7, 32, 28, 1), (8, 64, 0, 0)])
+def test_batch_multi_step_advance_equals_solo(ts, cols, graph_steps, nt):
     """Per-instance step counts (lbrd_batch_advance) on the serving mix with
     T steps per launch: counts that are not multiples of T end with a shorter
     launch (down to a single step), instances with 0 steps stay put, and every
     instance equals its solo run bitwise."""
     cases = serve_mix_cases()
     b = lbrd.Batch([c for c, _ in cases])
-    b.set_tuning(fused_steps=ts, tile_rows=4, waves=8, blocks_per_cu=0, graph_steps=graph_steps, nontemporal=nt)
+    b.set_tuning(fused_steps=ts, tile_rows=4, tile_cols=cols, waves=8, blocks_per_cu=0, graph_steps=graph_steps,
+                 nontemporal=nt)
     for idx, (_, rho0) in enumerate(cases):
         b.init(idx, rho0)
     counts = [1, 2, 3, 0, 5, 23][:len(cases)]
@@ -146,8 +149,10 @@ def test_batch_multi_step_advance_equals_solo(ts, graph_steps, nt):
         n = counts[idx] + more[idx] + 9
         assert b.time(idx) == n
         assert torch.equal(b.moments(idx)[0], solo(cfg, rho0, n)), (idx, n)
-    with pytest.raises(lbrd.LbrdError):                 # batches take at most four steps per launch
-        b.set_tuning(fused_steps=5, tile_rows=4, waves=8, blocks_per_cu=0, graph_steps=0)
+    with pytest.raises(lbrd.LbrdError):                 # at most eight steps per launch, 32 or 64 columns
+        b.set_tuning(fused_steps=9, tile_rows=4, waves=8, blocks_per_cu=0, graph_steps=0)
+    with pytest.raises(lbrd.LbrdError):
+        b.set_tuning(fused_steps=4, tile_rows=4, tile_cols=128, waves=8, blocks_per_cu=0, graph_steps=0)
 
 
 @pytest.mark.parametrize("graph_steps", [0, 8])
@@ -198,7 +203,8 @@ def test_batch_autotune_then_run():
     if t.fused_steps == 1:
         assert 1 <= t.blocks_per_cu <= 32 and t.waves in (1, 2, 4)
     else:
-        assert 2 <= t.fused_steps <= 4 and t.tile_rows in (4, 8, 16) and t.graph_steps % (2 * t.fused_steps) == 0
+        assert 2 <= t.fused_steps <= 8 and t.tile_cols in (32, 64) and t.tile_rows in (4, 8, 12, 16, 20)
+        assert t.graph_steps % (2 * t.fused_steps) == 0
     log(f"batch autotune chose {t.as_dict()}")
     assert lbrd.lib.lbrd_batch_step(b._h, 1) == lbrd.ESTATE
     for idx, inst in enumerate(insts):
