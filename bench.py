@@ -194,7 +194,7 @@ def serve_leg(torch, lbrd, workloads, n_requests, pool_gb, steps_range, seed=0, 
 
     if rate is None:
         # offered load near the server's measured throughput (about 2e11
-        # species-site-steps per second with four steps per launch): mean work
+        # species-site-steps per second; measured 2.2e11 while busy): mean work
         # per request / 2e11, at 85% utilisation
         e_side2 = (2048 ** 2 - 64 ** 2) / (2 * math.log(32))
         e_work = 1.5 * e_side2 * (steps_range[0] + steps_range[1]) / 2

@@ -7,7 +7,7 @@
 //   2. advances every resident request by min(chunk, steps left) with a
 //      replayed graph of persistent batched launches (per-slot step limits
 //      live in device descriptors, so the graph is reused across rounds);
-//      rounds of the serving mix advance four steps per launch on LDS tiles;
+//      rounds of the serving mix advance five steps per launch on LDS tiles;
 //   3. enqueues the density read-out of requests that finish in this round
 //      and records an event;
 //   4. while the GPU works on that round, retires the previous round's

@@ -93,14 +93,16 @@ def test_batch_gs_f32_equals_solo_and_oracle(mode):
 
 def test_full_size_sweep_batch_sampled():
     """The benchmark's batched workload at full size (256 Gray-Scott instances,
-    sides 128..512, seed 0, default launch shape: four steps per launch,
-    graphs of 32 steps): after 70 steps (two graph replays and a ragged
+    sides 128..512, seed 0, default launch shape: seven steps per launch on
+    32 x 12 tiles, graphs of 28 steps): after 70 steps (two graph replays and a ragged
     remainder) a sample of instances equals their solo runs bitwise, and the
     smallest sampled lattice equals the FP64 oracle within the FP32 floor."""
     insts = workloads.batch_sweep(0)
     cfgs = [lbrd.make_config(i.side, i.side, 2, tau=workloads.GS_TAU, storage="f32", reaction="gray_scott",
                              F=i.F, k=i.k) for i in insts]
     b = lbrd.Batch(cfgs)
+    t = b.tuning()
+    assert (t.fused_steps, t.tile_cols, t.tile_rows, t.graph_steps) == (7, 32, 12, 28)
     for idx, inst in enumerate(insts):
         b.init(idx, workloads.batch_initial(inst))
     steps = 70
@@ -215,8 +217,8 @@ def test_batch_autotune_then_run():
 
 
 def test_server_results_equal_solo_runs():
-    """The serving mix (four steps per launch inside the server's rounds):
-    request lengths that are not multiples of the chunk or of four, including
+    """The serving mix (five steps per launch inside the server's rounds):
+    request lengths that are not multiples of the chunk or of five, including
     a single step, equal their solo runs bitwise."""
     cases = serve_mix_cases()
     steps = [130, 64, 300, 1, 77, 250]
