@@ -121,7 +121,8 @@ typedef struct lbrd_config {
  *       (temporal blocking; a remainder of 2 .. T-1 steps runs as one shorter
  *       launch on the same tiles, a single remaining step as a one-step
  *       launch).  Results are bitwise identical for every setting.
- *  tile_rows, tile_cols: multi-step tile, rows 1..64 and columns 32, 64 or 128.
+ *  tile_rows, tile_cols: multi-step tile, rows 1..64 and columns 32, 64 or 128
+ *       (0 = 64).
  *       With h = T-1 and w = tile_cols + 2h, the LDS region of tile_rows + 2h
  *       rows of 9 N w populations (each row padded by fewer than 256 bytes)
  *       must fit in 160 KB.  Ignored when fused_steps = 1. */

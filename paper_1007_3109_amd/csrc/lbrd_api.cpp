@@ -661,6 +661,7 @@ int lbrd_set_tuning(lbrd_solver *h, const lbrd_tuning *t) {
     if (!h || !t) return LBRD_EINVAL;
     lbrd_tuning n = *t;
     if (n.lanes_x == 0) n.lanes_x = default_lanes(h->cfg.nx, n.vec);
+    if (n.fused_steps > 1 && n.tile_cols == 0) n.tile_cols = 64;
     if (!tuning_valid(h, n)) return LBRD_EINVAL;
     const bool rebuild = std::memcmp(&n, &h->tune, sizeof(n)) != 0;
     h->tune = n;

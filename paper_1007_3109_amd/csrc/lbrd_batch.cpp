@@ -472,6 +472,7 @@ int lbrd_batch_set_tuning(lbrd_batch *b, const lbrd_tuning *t) {
     n.plain_order = 0;
     if (n.fused_steps == 1) n.tile_rows = 0;
     if (n.fused_steps == 1) n.tile_cols = 0;
+    else if (n.tile_cols == 0) n.tile_cols = 64;
     if (!batch_tuning_valid(b, n)) return LBRD_EINVAL;
     if (std::memcmp(&n, &b->tune, sizeof(n)) == 0) return LBRD_OK;
     const bool tiling = n.fused_steps != b->tune.fused_steps || n.tile_rows != b->tune.tile_rows ||

@@ -571,8 +571,8 @@ __device__ __forceinline__ void stepT_last(const TileT &g, const Params<typename
 // region shrunk by j-1 sites on every side, in place, alternating the two
 // forms so that a site's reads and writes hit cells no other site touches:
 // one barrier per phase.  The last phase pulls from LDS, collides on the
-// tile itself and stores step t+m.  Per m
-// steps the buffer is read once (tile plus a halo) and written once.  Every
+// tile itself and stores step t+m.  Per m steps the buffer is read once
+// (tile plus a halo) and written once.  Every
 // site runs the arithmetic of the one-step kernel on the same encoded inputs,
 // so the result is bitwise identical to m one-step launches.  m = TS unless
 // VARM, where 1 <= m <= TS is a workgroup-uniform runtime count (m = 1 reads
