@@ -97,6 +97,15 @@ typedef struct lbrd_config {
                                        /* needs u.u < 1/3 and GRAY_SCOTT, or N = 1 with */
                                        /* LINEAR or NONE; otherwise LBRD_EINVAL.  The  */
                                        /* source term keeps w_i R_s.                   */
+    double shear[2];                   /* prescribed shear flow added to u: the site   */
+                                       /* (x, y) sees u_x = u[0] + A sin(2 pi m y / ny) */
+                                       /* and u_y = u[1], with A = shear[0] and m =     */
+                                       /* shear[1] a whole number >= 1 of periods over */
+                                       /* the lattice; (0, 0) = no shear.  A shear     */
+                                       /* needs (|u[0]| + |A|)^2 + u[1]^2 < 1/3, the   */
+                                       /* reactions allowed with u, FP64 or FP32       */
+                                       /* storage and a single solver (batches and the */
+                                       /* server refuse it); otherwise LBRD_EINVAL.    */
 } lbrd_config;
 
 /* Kernel launch shape.

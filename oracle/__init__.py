@@ -82,9 +82,10 @@ def _load():
             pd = ctypes.POINTER(ctypes.c_double)
             pi = ctypes.POINTER(ctypes.c_int)
             getattr(lib, f"orc_tables_{sfx}").argtypes = [P, pi, pi]
-            getattr(lib, f"orc_init_{sfx}").argtypes = [ctypes.c_int] * 3 + [pd, pd, P]
+            getattr(lib, f"orc_init_{sfx}").argtypes = [ctypes.c_int] * 3 + [pd, pd, ctypes.c_int, P]
             fn = getattr(lib, f"orc_run_{sfx}")
-            fn.argtypes = [ctypes.c_int] * 3 + [pd, ctypes.c_int, pd, ctypes.c_int, pd, pd, P, P, ctypes.c_int64]
+            fn.argtypes = ([ctypes.c_int] * 3 + [pd, ctypes.c_int, pd, ctypes.c_int, pd, pd, ctypes.c_int, P, P,
+                                                  ctypes.c_int64])
             getattr(lib, f"orc_eq_coefs_{sfx}").argtypes = [pd, P]
             fn.restype = ctypes.c_int
             getattr(lib, f"orc_moments_{sfx}").argtypes = [ctypes.c_int] * 3 + [P, pd]
@@ -124,11 +125,16 @@ def tables(precision: str = "f64"):
 
 
 def _velocity(u):
-    """None, or the 2 components of the equilibrium velocity as a C array."""
+    """None, the 2 components of a uniform equilibrium velocity, or a
+    prescribed field [ny][nx][2], as a C array."""
     if u is None:
         return None
-    a = np.ascontiguousarray(np.asarray(u, np.float64).reshape(2))
-    return a
+    a = np.asarray(u, np.float64)
+    return np.ascontiguousarray(a if a.ndim == 3 else a.reshape(2))
+
+
+def _is_field(ua) -> int:
+    return int(ua is not None and ua.ndim == 3)
 
 
 def _uptr(a):
@@ -147,13 +153,16 @@ def eq_coefs(u=None, precision: str = "f64") -> np.ndarray:
 
 def init(rho0: np.ndarray, precision: str = "f64", u=None) -> np.ndarray:
     """Equilibrium populations f_{i,s} = c_i(u) rho0_s (c_i = w_i without a
-    velocity), shape [N][9][ny][nx]."""
+    velocity; u uniform or a field [ny][nx][2]), shape [N][9][ny][nx]."""
     rho0 = np.ascontiguousarray(rho0, dtype=np.float64)
     n, ny, nx = rho0.shape
     npdt, ct = _dt(precision)
     f = np.zeros((n, 9, ny, nx), npdt)
     ua = _velocity(u)
-    getattr(_load(), f"orc_init_{precision}")(n, nx, ny, _ptr(rho0, ctypes.c_double), _uptr(ua), _ptr(f, ct))
+    if _is_field(ua):
+        assert ua.shape == (ny, nx, 2)
+    getattr(_load(), f"orc_init_{precision}")(n, nx, ny, _ptr(rho0, ctypes.c_double), _uptr(ua), _is_field(ua),
+                                              _ptr(f, ct))
     return f
 
 
@@ -175,7 +184,8 @@ def run(f: np.ndarray, nsteps: int, tau, reaction: int = REACT_NONE, *, K=None, 
     rounding-floor / storage-emulation build).  ``quant`` (float32 only) rounds
     every stored population to binary16 or bfloat16 after subtracting
     c_i * rho_ref[s], the 16-bit shifted storage form.  ``u`` is the
-    equilibrium velocity of Eq. "Maxwellian" (None: the paper's u = 0).
+    equilibrium velocity of Eq. "Maxwellian" (None: the paper's u = 0; two
+    values: uniform; an array [ny][nx][2]: a prescribed field).
     """
     f = np.array(f, copy=True, order="C")
     precision = {np.dtype(np.float64): "f64", np.dtype(np.float32): "f32"}[f.dtype]
@@ -189,9 +199,13 @@ def run(f: np.ndarray, nsteps: int, tau, reaction: int = REACT_NONE, *, K=None, 
         raise ValueError("storage emulation runs in the float build")
     work = np.empty_like(f)
     ua = _velocity(u)
+    if _is_field(ua):
+        assert ua.shape == (ny, nx, 2)
+        if quant != Q_NONE:
+            raise ValueError("the storage emulation takes a uniform velocity")
     rc = getattr(_load(), f"orc_run_{precision}")(
         n, nx, ny, _ptr(tau, ctypes.c_double), reaction, _ptr(params, ctypes.c_double), quant,
-        _ptr(rref, ctypes.c_double), _uptr(ua), _ptr(f, ct), _ptr(work, ct), int(nsteps))
+        _ptr(rref, ctypes.c_double), _uptr(ua), _is_field(ua), _ptr(f, ct), _ptr(work, ct), int(nsteps))
     if rc != 0:
         raise ValueError("oracle rejected its arguments")
     return f

@@ -24,9 +24,10 @@
  * with rho_s = sum_i f_{i,s} (Section II.A, the sentence after Eq. "relax"),
  * f^eq_{i,s} = w_i rho_s (Eq. "equili"), periodic wrap in x and y
  * (Section II.B and Section IV), lattice units dx = dt = 1.  With a
- * prescribed uniform velocity u the equilibrium is the low-Mach Maxwellian
- * of Eq. "Maxwellian", f^eq_{i,s} = c_i(u) rho_s (the paper's runs have
- * u = 0, which gives c_i = w_i exactly).
+ * prescribed velocity u (uniform, or a field given site by site) the
+ * equilibrium is the low-Mach Maxwellian of Eq. "Maxwellian",
+ * f^eq_{i,s}(x) = c_i(u(x)) rho_s(x) (the paper's runs have u = 0, which gives
+ * c_i = w_i exactly).
  */
 #include <stdint.h>
 #include <stddef.h>
@@ -83,6 +84,15 @@ static REAL eq_coef(int i, const double *u)
     const REAL eu = (REAL)EX[i] * ux + (REAL)EY[i] * uy;
     const REAL uu = ux * ux + uy * uy;
     return w * ((REAL)1 + eu / cs2 + eu * eu / ((REAL)2 * cs2 * cs2) - uu / ((REAL)2 * cs2));
+}
+
+/* The velocity at site (x, y): u is NULL (no advection), 2 values (one
+ * uniform velocity), or, with u_field != 0, a prescribed field of 2 nx ny
+ * values laid out [y][x][component]. */
+static const double *site_u(const double *u, int u_field, int nx, int x, int y)
+{
+    if (!u || !u_field) return u;
+    return u + 2 * ((size_t)y * nx + x);
 }
 
 /* Expose the equilibrium coefficients c_i(u) (for the tests). */
@@ -211,21 +221,21 @@ void SFX(orc_encode)(int n, int nx, int ny, int quant, const double *rho_ref, co
 /* Initial populations: local equilibrium f_{i,s}(x,0) = c_i rho_s(x,0)
  * (Eq. "equili", or Eq. "Maxwellian" with velocity u; the paper does not
  * state the initial populations, this is the reading used throughout).
- * rho0 is [N][ny][nx]; u is NULL or 2 values. */
-void SFX(orc_init)(int n, int nx, int ny, const double *rho0, const double *u, REAL *f)
+ * rho0 is [N][ny][nx]; u and u_field as for site_u. */
+void SFX(orc_init)(int n, int nx, int ny, const double *rho0, const double *u, int u_field, REAL *f)
 {
     for (int s = 0; s < n; ++s)
         for (int i = 0; i < 9; ++i)
             for (int y = 0; y < ny; ++y)
                 for (int x = 0; x < nx; ++x)
                     f[idx(nx, ny, s, i, y, x)] =
-                        eq_coef(i, u) * (REAL)rho0[((size_t)s * ny + y) * nx + x];
+                        eq_coef(i, site_u(u, u_field, nx, x, y)) * (REAL)rho0[((size_t)s * ny + y) * nx + x];
 }
 
 /* One time step t -> t+1 of the update equation, push form, f -> fn. */
 static void step_once(int n, int nx, int ny, const double *tau, int kind,
                       const double *params, int quant, const double *rho_ref,
-                      const double *u, const REAL *f, REAL *fn)
+                      const double *u, int u_field, const REAL *f, REAL *fn)
 {
 #pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; ++y) {
@@ -238,11 +248,12 @@ static void step_once(int n, int nx, int ny, const double *tau, int kind,
                 rho[s] = acc;
             }
             reaction(kind, n, params, rho, R);
+            const double *us = site_u(u, u_field, nx, x, y);
             for (int s = 0; s < n; ++s) {
                 for (int i = 0; i < 9; ++i) {
                     const REAL fi = f[idx(nx, ny, s, i, y, x)];
                     const REAL wi = weight(i);
-                    const REAL ci = eq_coef(i, u);
+                    const REAL ci = eq_coef(i, us);
                     REAL g = fi + (ci * rho[s] - fi) / (REAL)tau[s] + wi * R[s];
                     if (quant != ORC_Q_NONE) {
                         /* storage form: g - c_i rho_ref,s rounded to 16 bits */
@@ -262,17 +273,17 @@ static void step_once(int n, int nx, int ny, const double *tau, int kind,
 }
 
 /* Advance f (in place, [N][9][ny][nx]) by nsteps.  work is a caller buffer
- * of the same size; u is NULL (no advection) or the 2 components of the
- * equilibrium velocity.  Returns 0, or -1 on bad arguments. */
+ * of the same size; u and u_field as for site_u (the equilibrium velocity).
+ * Returns 0, or -1 on bad arguments. */
 int SFX(orc_run)(int n, int nx, int ny, const double *tau, int kind,
                  const double *params, int quant, const double *rho_ref,
-                 const double *u, REAL *f, REAL *work, int64_t nsteps)
+                 const double *u, int u_field, REAL *f, REAL *work, int64_t nsteps)
 {
     if (n < 1 || n > ORC_MAX_SPECIES || nx < 1 || ny < 1 || nsteps < 0) return -1;
     if (kind == ORC_REACT_GRAY_SCOTT && n != 2) return -1;
     REAL *a = f, *b = work;
     for (int64_t t = 0; t < nsteps; ++t) {
-        step_once(n, nx, ny, tau, kind, params, quant, rho_ref, u, a, b);
+        step_once(n, nx, ny, tau, kind, params, quant, rho_ref, u, u_field, a, b);
         REAL *tmp = a;
         a = b;
         b = tmp;

@@ -65,7 +65,7 @@ Params<C> make_params(const lbrd_config &c) {
     const C w[3] = {C(4) / C(9), C(1) / C(9), C(1) / C(36)};
     // equilibrium coefficients: the weights, or the low-Mach Maxwellian
     // c_i = w_i [1 + 3 e.u + 9/2 (e.u)^2 - 3/2 u.u] evaluated in double
-    p.adv = (c.u[0] != 0.0 || c.u[1] != 0.0) ? 1 : 0;
+    p.adv = (c.u[0] != 0.0 || c.u[1] != 0.0 || has_shear(c)) ? 1 : 0;
     for (int i = 0; i < 9; ++i) {
         const C wi = i == 0 ? w[0] : (i < 5 ? w[1] : w[2]);
         if (!p.adv) {
@@ -96,6 +96,13 @@ Params<C> make_params(const lbrd_config &c) {
         p.F = C(c.F);
         p.k = C(c.k);
         p.Fk = p.F + p.k;
+    }
+    if (has_shear(c)) {
+        p.u0x = C(c.u[0]);
+        p.u0y = C(c.u[1]);
+        p.amp = C(c.shear[0]);
+        p.shear_m = (int32_t)c.shear[1];
+        p.shear_ny = c.ny;
     }
     return p;
 }
@@ -215,6 +222,19 @@ int validate_config(const lbrd_config *c) {
         // advective variants: Gray-Scott, or one species with a linear (or no) reaction
         if (!(c->reaction == LBRD_REACT_GRAY_SCOTT || c->nspecies == 1)) return LBRD_EINVAL;
         if (!(c->u[0] * c->u[0] + c->u[1] * c->u[1] < 1.0 / 3.0)) return LBRD_EINVAL;
+    }
+    if (!std::isfinite(c->shear[0]) || !std::isfinite(c->shear[1])) return LBRD_EINVAL;
+    if (c->shear[0] != 0.0) {
+        // shear variants: the same reactions, FP64 / FP32 storage, a whole
+        // number of periods, |u| below the bound on every row
+        if (!(c->reaction == LBRD_REACT_GRAY_SCOTT || c->nspecies == 1)) return LBRD_EINVAL;
+        if (c->storage != LBRD_F64 && c->storage != LBRD_F32) return LBRD_EINVAL;
+        const double m = c->shear[1];
+        if (!(m >= 1.0 && m <= 1e6 && m == std::floor(m))) return LBRD_EINVAL;
+        const double umax = std::fabs(c->u[0]) + std::fabs(c->shear[0]);
+        if (!(umax * umax + c->u[1] * c->u[1] < 1.0 / 3.0)) return LBRD_EINVAL;
+    } else if (c->shear[1] != 0.0) {
+        return LBRD_EINVAL;
     }
     return LBRD_OK;
 }

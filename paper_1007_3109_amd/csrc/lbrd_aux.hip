@@ -93,9 +93,17 @@ __global__ void k_init(Layout L, Params<typename Traits<ST>::C> p, const void *r
                 // collide_site)
                 C v;
                 if (p.adv) {
+                    // the coefficients of the site the population belongs to
+                    // (row ys: it streams into (xs, ys) next)
+                    C ceq[9];
+                    if (p.shear_ny > 0) {
+                        shear_ceq<C>(p, ys, ceq);
+                    } else {
+                        for (int j = 0; j < 9; ++j) ceq[j] = p.ceq[j];
+                    }
                     C moving = C(0);
-                    for (int j = 1; j < 9; ++j) moving += p.ceq[j] * r;
-                    v = i == 0 ? r - moving : p.ceq[i] * r;
+                    for (int j = 1; j < 9; ++j) moving += ceq[j] * r;
+                    v = i == 0 ? r - moving : ceq[i] * r;
                 } else {
                     v = i == 0 ? r - C(4) * (wgt<C>(1) * r) - C(4) * (wgt<C>(5) * r) : wgt<C>(i) * r;
                 }

@@ -192,8 +192,10 @@ extern "C" {
 
 int lbrd_batch_workspace_size(const lbrd_config *cfgs, int count, size_t *bytes) {
     if (!cfgs || count < 1 || !bytes) return LBRD_EINVAL;
-    for (int i = 0; i < count; ++i)
+    for (int i = 0; i < count; ++i) {
         if (int rc = validate_config(&cfgs[i])) return rc;
+        if (has_shear(cfgs[i])) return LBRD_EINVAL;   // single solvers only
+    }
     *bytes = plan_batch(cfgs, count).total;
     return LBRD_OK;
 }

@@ -139,9 +139,11 @@ __device__ __forceinline__ void store_vec(T *p, const T (&e)[VEC]) {
 
 // The reaction of a variant without its advection, and whether it advects.
 template <int V>
-constexpr int kReactionOf = V == kAdvLin1 ? kLin1 : (V == kAdvGS ? kGS : V);
+constexpr int kReactionOf = (V == kAdvLin1 || V == kShearLin1) ? kLin1 : ((V == kAdvGS || V == kShearGS) ? kGS : V);
 template <int V>
-constexpr bool kAdvective = V == kAdvLin1 || V == kAdvGS;
+constexpr bool kShear = V == kShearLin1 || V == kShearGS;
+template <int V>
+constexpr bool kAdvective = V == kAdvLin1 || V == kAdvGS || kShear<V>;
 
 template <int V>
 struct NSpecies {
@@ -179,10 +181,30 @@ __device__ __forceinline__ void reaction(const Params<C> &p, const C (&rho)[NSpe
 // one) and the update f' = f (1 - 1/tau) + c_i rho / tau + w_i R reads
 // d' = d (1 - 1/tau) + c_i m / tau + w_i R; without advection c_i = w_i and
 // d' = d (1 - 1/tau) + w_i (m / tau + R).
+__device__ __forceinline__ float sinpi_c(float a) { return sinpif(a); }
+__device__ __forceinline__ double sinpi_c(double a) { return sinpi(a); }
+
+// Equilibrium coefficients c_i(u) of Eq. "Maxwellian" for the shear flow's
+// velocity on row gy: u_x = u0x + amp sin(2 pi m gy / ny), u_y = u0y (the
+// phase m gy mod ny is taken in integers).
+template <class C>
+__device__ __forceinline__ void shear_ceq(const Params<C> &p, int gy, C (&c)[9]) {
+    const int r = (int)(((int64_t)p.shear_m * gy) % p.shear_ny);
+    const C ux = p.u0x + p.amp * sinpi_c(C(2 * r) / C(p.shear_ny));
+    const C uy = p.u0y;
+    const C uu = ux * ux + uy * uy;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const C eu = C(kEx[i]) * ux + C(kEy[i]) * uy;
+        c[i] = wgt<C>(i) * (C(1) + C(3) * eu + C(4.5) * eu * eu - C(1.5) * uu);
+    }
+}
+
+// gy: the site's row (used by the shear variants only).
 template <int ST, int V>
 __device__ __forceinline__ void collide_site(const Params<typename Traits<ST>::C> &p,
                                              const typename Traits<ST>::C (&f)[NSpecies<V>::value][9],
-                                             typename Traits<ST>::T (&o)[NSpecies<V>::value][9]) {
+                                             typename Traits<ST>::T (&o)[NSpecies<V>::value][9], int gy) {
     using C = typename Traits<ST>::C;
     constexpr int NS = NSpecies<V>::value;
     C m[NS], rho[NS], R[NS];
@@ -196,6 +218,13 @@ __device__ __forceinline__ void collide_site(const Params<typename Traits<ST>::C
     }
     reaction<V, C>(p, rho, R);
     if constexpr (kAdvective<V>) {
+        C ceq[9];
+        if constexpr (kShear<V>) {
+            shear_ceq<C>(p, gy, ceq);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) ceq[i] = p.ceq[i];
+        }
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             // c_i m / tau + w_i R for the moving populations; the rest
@@ -205,7 +234,7 @@ __device__ __forceinline__ void collide_site(const Params<typename Traits<ST>::C
             C e[9], moving = C(0);
 #pragma unroll
             for (int i = 1; i < 9; ++i) {
-                e[i] = p.ceq[i] * om + wgt<C>(i) * R[s];
+                e[i] = ceq[i] * om + wgt<C>(i) * R[s];
                 moving += e[i];
             }
             e[0] = a - moving;
@@ -353,7 +382,7 @@ __device__ __forceinline__ void step_tile(const typename Traits<ST>::T *__restri
         for (int s = 0; s < NS; ++s)
 #pragma unroll
             for (int i = 0; i < 9; ++i) fs[s][i] = f[s][i][j];
-        collide_site<ST, V>(p, fs, os);
+        collide_site<ST, V>(p, fs, os, yc);
 #pragma unroll
         for (int s = 0; s < NS; ++s)
 #pragma unroll
@@ -497,7 +526,7 @@ struct TileT {
 // side, read in the form phase J-1 wrote and written in the other one.
 template <int ST, int V, int EW, int J>
 __device__ __forceinline__ void stepT_middle(const Params<typename Traits<ST>::C> &p, typename Traits<ST>::T *L,
-                                             int eh, int nthr) {
+                                             int eh, int nthr, int gy0, int ny) {
     using T = typename Traits<ST>::T;
     using C = typename Traits<ST>::C;
     constexpr int NS = NSpecies<V>::value;
@@ -509,7 +538,7 @@ __device__ __forceinline__ void stepT_middle(const Params<typename Traits<ST>::C
         C f[NS][9];
         gather_lds<ST, NS, EW, kFromB>(L, lx, ly, f);
         T o[NS][9];
-        collide_site<ST, V>(p, f, o);
+        collide_site<ST, V>(p, f, o, kShear<V> ? wrap_mod(gy0 + ly, ny) : 0);
         put_lds<ST, NS, EW, !kFromB>(L, lx, ly, o);
     }
 }
@@ -517,12 +546,12 @@ __device__ __forceinline__ void stepT_middle(const Params<typename Traits<ST>::C
 // Middle phases J, J+1, .. min(m, TS)-1, each followed by a barrier.
 template <int ST, int V, int TS, int EW, int J, bool VARM>
 __device__ __forceinline__ void stepT_middles(const Params<typename Traits<ST>::C> &p, typename Traits<ST>::T *L,
-                                              int eh, int nthr, int m) {
+                                              int eh, int nthr, int m, int gy0, int ny) {
     if constexpr (J < TS) {
         if (!VARM || m > J) {
-            stepT_middle<ST, V, EW, J>(p, L, eh, nthr);
+            stepT_middle<ST, V, EW, J>(p, L, eh, nthr, gy0, ny);
             __syncthreads();
-            stepT_middles<ST, V, TS, EW, J + 1, VARM>(p, L, eh, nthr, m);
+            stepT_middles<ST, V, TS, EW, J + 1, VARM>(p, L, eh, nthr, m, gy0, ny);
         }
     }
 }
@@ -543,7 +572,7 @@ __device__ __forceinline__ void stepT_last(const TileT &g, const Params<typename
         C f[NS][9];
         gather_lds<ST, NS, EW, FROM_B>(L, lx + H, ly + H, f);
         T o[NS][9];
-        collide_site<ST, V>(p, f, o);
+        collide_site<ST, V>(p, f, o, kShear<V> ? wrap_mod(gy, g.ny) : 0);
         if (gx < g.nx && gy < g.ny) {
             const uint32_t off = mul24(gy, g.pitch_b) + (uint32_t)gx * sizeof(T);
             if (g.nt_store) {
@@ -608,7 +637,7 @@ __device__ __forceinline__ void stepT_tile(const TileT &g, const Params<typename
                         f[s][i] = decode_dev<ST>(
                             buf_load<T>(g.src, ry[1 - kEy[i]] + cx[1 - kEx[i]], (uint32_t)(s * 9 + i) * g.pstride_b));
                 T o[NS][9];
-                collide_site<ST, V>(p, f, o);
+                collide_site<ST, V>(p, f, o, gy);
 #pragma unroll
                 for (int s = 0; s < NS; ++s)
 #pragma unroll
@@ -638,7 +667,7 @@ __device__ __forceinline__ void stepT_tile(const TileT &g, const Params<typename
                     f[s][i] = decode_dev<ST>(buf_load<T>(
                         g.src, rel, (uint32_t)(s * 9 + i) * g.pstride_b + base - kEy[i] * g.pitch_b - kEx[i] * B));
             T o[NS][9];
-            collide_site<ST, V>(p, f, o);
+            collide_site<ST, V>(p, f, o, y0 - H + ey);
             put_lds<ST, NS, EW, false>(L, ex, ey, o);
             ex += dx;
             ey += dy;
@@ -675,7 +704,7 @@ __device__ __forceinline__ void stepT_tile(const TileT &g, const Params<typename
                     f[s][i] = decode_dev<ST>(
                         buf_load<T>(g.src, ry[1 - kEy[i]] + cx[1 - kEx[i]], (uint32_t)(s * 9 + i) * g.pstride_b));
             T o[NS][9];
-            collide_site<ST, V>(p, f, o);
+            collide_site<ST, V>(p, f, o, gy);
             put_lds<ST, NS, EW, false>(L, ex, ey, o);
             ex += dx;
             ey += dy;
@@ -690,7 +719,7 @@ __device__ __forceinline__ void stepT_tile(const TileT &g, const Params<typename
     // j-1, in LDS, in place (phase j reads the form phase j-1 wrote: A after
     // odd phases, B after even ones).  Consecutive threads take consecutive
     // sites of the shrunk region, row by row.
-    stepT_middles<ST, V, TS, EW, 2, VARM>(p, L, eh, nthr, m);
+    stepT_middles<ST, V, TS, EW, 2, VARM>(p, L, eh, nthr, m, y0 - H, ny);
     // last phase: step t+m-1 -> t+m on the tile, to the destination buffer
     if (m & 1)
         stepT_last<ST, V, TW, H, true>(g, p, L, x0, y0, nthr);

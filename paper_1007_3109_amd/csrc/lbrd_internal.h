@@ -21,12 +21,18 @@ inline int storage_bytes(int st) { return st == kF64 ? 8 : st == kF32 ? 4 : 2; }
 
 // Reaction variants compiled into the step kernel.  NONE runs as LINEAR
 // with K = 0, c = 0, which adds exactly +0 to every population.  The
-// advective variants carry an equilibrium velocity (one species linear, or
-// Gray-Scott).
-enum Variant : int { kLin1 = 0, kLin2 = 1, kLin3 = 2, kLin4 = 3, kGS = 4, kAdvLin1 = 5, kAdvGS = 6, kNumVariants = 7 };
+// advective variants carry a uniform equilibrium velocity, the shear
+// variants a velocity that varies with the row (one species linear, or
+// Gray-Scott; FP64 and FP32 storage).
+enum Variant : int {
+    kLin1 = 0, kLin2 = 1, kLin3 = 2, kLin4 = 3, kGS = 4, kAdvLin1 = 5, kAdvGS = 6, kShearLin1 = 7, kShearGS = 8,
+    kNumVariants = 9
+};
 
+inline bool has_shear(const lbrd_config &c) { return c.shear[0] != 0.0; }
 inline int variant_of(const lbrd_config &c) {
     const bool adv = c.u[0] != 0.0 || c.u[1] != 0.0;
+    if (has_shear(c)) return c.reaction == LBRD_REACT_GRAY_SCOTT ? kShearGS : kShearLin1;
     if (c.reaction == LBRD_REACT_GRAY_SCOTT) return adv ? kAdvGS : kGS;
     return adv ? kAdvLin1 : c.nspecies - 1;
 }
@@ -57,6 +63,9 @@ struct Params {
     C shift[LBRD_MAX_SPECIES][9];   // c_i rho_ref,s
     C ceq[9];                    // equilibrium coefficients c_i (w_i without a velocity)
     int32_t adv;                 // 1: c_i carry an advection velocity
+    // shear flow u_x(y) = u0x + amp sin(2 pi m y / ny), u_y = u0y (shear variants)
+    C u0x, u0y, amp;
+    int32_t shear_m, shear_ny;
 };
 
 template <class C>

@@ -406,6 +406,7 @@ extern "C" {
 
 int lbrd_server_footprint(const lbrd_config *cfg, size_t *bytes) {
     if (int rc = validate_config(cfg)) return rc;
+    if (has_shear(*cfg)) return LBRD_EINVAL;   // single solvers only
     if (!bytes) return LBRD_EINVAL;
     *bytes = request_footprint(normalise(*cfg), nullptr);
     return LBRD_OK;
@@ -483,6 +484,7 @@ int lbrd_server_submit(lbrd_server *s, const lbrd_config *cfg, const double *rho
                        int64_t *ticket) {
     if (!s || !rho0_host || !ticket || nsteps < 1) return LBRD_EINVAL;
     if (int rc = validate_config(cfg)) return rc;
+    if (has_shear(*cfg)) return LBRD_EINVAL;   // single solvers only
     Request r;
     r.cfg = normalise(*cfg);
     r.footprint = request_footprint(r.cfg, &r.L);

@@ -45,6 +45,12 @@ inline hipError_t launch_step_s(const StepLaunch &sl, const Grid &g, const void 
         case kGS: return launch_step_v<ST, kGS>(sl, g, params, st);
         case kAdvLin1: return launch_step_v<ST, kAdvLin1>(sl, g, params, st);
         case kAdvGS: return launch_step_v<ST, kAdvGS>(sl, g, params, st);
+        case kShearLin1:
+            if constexpr (ST == kF64 || ST == kF32) return launch_step_v<ST, kShearLin1>(sl, g, params, st);
+            return hipErrorInvalidValue;
+        case kShearGS:
+            if constexpr (ST == kF64 || ST == kF32) return launch_step_v<ST, kShearGS>(sl, g, params, st);
+            return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }
@@ -105,6 +111,12 @@ inline hipError_t launch_stepT_s(const StepLaunch &sl, const GridT &g, const voi
         case kGS: return launch_stepT_w<ST, kGS>(sl, g, params, st);
         case kAdvLin1: return launch_stepT_w<ST, kAdvLin1>(sl, g, params, st);
         case kAdvGS: return launch_stepT_w<ST, kAdvGS>(sl, g, params, st);
+        case kShearLin1:
+            if constexpr (ST == kF64 || ST == kF32) return launch_stepT_w<ST, kShearLin1>(sl, g, params, st);
+            return hipErrorInvalidValue;
+        case kShearGS:
+            if constexpr (ST == kF64 || ST == kF32) return launch_stepT_w<ST, kShearGS>(sl, g, params, st);
+            return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }

@@ -31,6 +31,7 @@ class Config(ctypes.Structure):
         ("tau", ctypes.c_double * MAX_SPECIES), ("rho_ref", ctypes.c_double * MAX_SPECIES),
         ("K", ctypes.c_double * (MAX_SPECIES * MAX_SPECIES)), ("c", ctypes.c_double * MAX_SPECIES),
         ("F", ctypes.c_double), ("k", ctypes.c_double), ("u", ctypes.c_double * 2),
+        ("shear", ctypes.c_double * 2),
     ]
 
 
@@ -152,7 +153,8 @@ def check(status: int, where: str) -> int:
 
 
 def make_config(nx: int, ny: int, nspecies: int = 1, tau=1.0, storage: str = "f32", reaction: str = "none",
-                K=None, c=None, F: float = 0.0, k: float = 0.0, rho_ref=None, u=None) -> Config:
+                K=None, c=None, F: float = 0.0, k: float = 0.0, rho_ref=None, u=None, shear=None) -> Config:
+    """shear = (A, m): u_x(y) = u[0] + A sin(2 pi m y / ny) on row y."""
     cfg = Config()
     cfg.nspecies, cfg.nx, cfg.ny = nspecies, nx, ny
     cfg.storage = STORAGE[storage]
@@ -174,6 +176,8 @@ def make_config(nx: int, ny: int, nspecies: int = 1, tau=1.0, storage: str = "f3
     cfg.F, cfg.k = float(F), float(k)
     if u is not None:
         cfg.u[0], cfg.u[1] = (float(x) for x in u)
+    if shear is not None:
+        cfg.shear[0], cfg.shear[1] = float(shear[0]), float(shear[1])
     return cfg
 
 

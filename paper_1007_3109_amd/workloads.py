@@ -38,6 +38,17 @@ def sinusoid(nx: int, ny: int, amplitude: float = 0.1, mode: int = 1, background
     return np.ascontiguousarray(np.broadcast_to(row, (1, ny, nx)))
 
 
+def shear_field(nx: int, ny: int, u=(0.0, 0.0), amp: float = 0.0, m: int = 1) -> np.ndarray:
+    """Prescribed velocity field [ny][nx][2] of a sinusoidal shear flow:
+    u_x = u[0] + amp sin(2 pi m y / ny), u_y = u[1] (the field the solver's
+    ``shear`` option describes, for the oracle side)."""
+    phase = (m * np.arange(ny)) % ny   # whole periods: the phase in integers
+    field = np.empty((ny, nx, 2), np.float64)
+    field[..., 0] = (u[0] + amp * np.sin(2.0 * np.pi * phase / ny))[:, None]
+    field[..., 1] = u[1]
+    return field
+
+
 def point_source(nx: int, ny: int, nspecies: int = 2) -> np.ndarray:
     """Species 0 is 1 at (nx//2, ny//2) and 0 elsewhere; other species are 0."""
     rho = np.zeros((nspecies, ny, nx))

@@ -63,6 +63,26 @@ def propagator(q, taus, J, w, ex, ey, ceq=None) -> np.ndarray:
     return P
 
 
+def row_field_propagator(qx, ny, tau, kappa, w, ex, ey, ceq_rows) -> np.ndarray:
+    """One-step propagator of one species with the decay R = -kappa rho for a
+    Fourier mode exp(i qx x) when the equilibrium coefficients depend on the
+    row only (ceq_rows[y][i]): the state is the complex amplitude A[i][y]
+    (index i * ny + y).  Collision on row y: (1 - 1/tau) A_i + (c_i(y) / tau -
+    kappa w_i) sum_j A_j; then the post-collision amplitude moves to row
+    y + e_iy and picks up exp(-i qx e_ix)."""
+    om = 1.0 / tau
+    M = np.zeros((9 * ny, 9 * ny), complex)
+    for i in range(9):
+        ph = np.exp(-1j * qx * ex[i])
+        for y in range(ny):
+            yd = (y + ey[i]) % ny
+            row = i * ny + yd
+            M[row, i * ny + y] += ph * (1.0 - om)
+            for j in range(9):
+                M[row, j * ny + y] += ph * (ceq_rows[y][i] * om - kappa * w[i])
+    return M
+
+
 def source_vector(c, w, ex, ey, npts) -> np.ndarray:
     """Affine part at q = 0: the constant source c_s enters every site, so its
     q = 0 transform is npts * c_s, weighted by w_i (the phase is 1 at q = 0)."""

@@ -75,6 +75,31 @@ def test_advection_velocity_validation():
     assert lbrd.validate(gs(u=(0.4, 0.42))) == lbrd.EINVAL
 
 
+def test_shear_flow_validation():
+    """A shear flow is accepted for Gray-Scott and one-species linear solvers
+    in FP64 / FP32 storage with a whole number of periods and |u| below the
+    bound on every row; refused in 16-bit storage, with a fractional or
+    missing period count, past the bound, for a multi-species linear system,
+    and by batches and the server (single solvers only)."""
+    ok = gs(40, 30, u=(0.05, 0.02), shear=(0.2, 3))
+    assert lbrd.validate(ok) == lbrd.OK
+    assert lbrd.validate(lbrd.make_config(8, 8, 1, tau=0.8, storage="f64", reaction="linear", K=[[-0.01]],
+                                          shear=(0.1, 1))) == lbrd.OK
+    bad = [gs(40, 30, storage="f16", rho_ref=(1.0, 0.0), shear=(0.1, 1)),
+           gs(40, 30, shear=(0.1, 1.5)),
+           gs(40, 30, shear=(0.1, 0)),
+           gs(40, 30, shear=(0.0, 2)),
+           gs(40, 30, u=(0.3, 0.0), shear=(0.3, 1)),
+           gs(40, 30, shear=(float("nan"), 1)),
+           lbrd.make_config(8, 8, 2, tau=0.8, reaction="linear", K=-0.01 * np.eye(2), shear=(0.1, 1))]
+    for c in bad:
+        assert lbrd.validate(c) == lbrd.EINVAL
+    arr = (lbrd.Config * 1)(ok)
+    n = ctypes.c_size_t()
+    assert lbrd.lib.lbrd_batch_workspace_size(arr, 1, ctypes.byref(n)) == lbrd.EINVAL
+    assert lbrd.lib.lbrd_server_footprint(ctypes.byref(ok), ctypes.byref(n)) == lbrd.EINVAL
+
+
 def test_workspace_size_covers_two_padded_buffers():
     for storage, b in (("f64", 8), ("f32", 4), ("f16", 2), ("bf16", 2)):
         for nx, ny in ((1, 1), (67, 45), (1024, 1024)):

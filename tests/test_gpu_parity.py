@@ -254,6 +254,56 @@ def test_advective_populations_f64(shape):
             assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max(), (shape, ns, fused)
 
 
+@pytest.mark.parametrize("shape", [(1, 1), (3, 5), (33, 70), (96, 40)])
+def test_shear_flow_populations_f64(shape):
+    """A prescribed shear flow u_x = u0 + A sin(2 pi m y / ny), u_y = u1 in
+    the equilibrium: random non-equilibrium populations, Gray-Scott and the
+    one-species linear variant, one step per launch and T = 2..8 per launch
+    on 32 x 4 tiles: the populations after 11 steps match the oracle (given
+    the same field site by site) to 1e-13 of the largest."""
+    ny, nx = shape
+    rng = np.random.default_rng(9 + nx)
+    u, shear = (0.03, -0.05), (0.1, 2)
+    field = workloads.shear_field(nx, ny, u, *shear)
+    for ns, reaction, kw in [(2, "gray_scott", dict(F=0.04, k=0.06)), (1, "linear", dict(K=[[-0.02]]))]:
+        f0 = rng.uniform(0.0, 0.1, size=(ns, 9, ny, nx))
+        taus = [0.7, 1.2][:ns]
+        okw = dict(kw) if ns == 2 else dict(K=np.array(kw["K"]))
+        ref = oracle.run(f0, 11, taus, oracle.REACT_GRAY_SCOTT if ns == 2 else oracle.REACT_LINEAR, u=field, **okw)
+        cfg = lbrd.make_config(nx, ny, ns, tau=taus, storage="f64", reaction=reaction, u=u, shear=shear, **kw)
+        s = lbrd.Solver(cfg)
+        for fused in range(1, 9):
+            s.set_tuning(fused_steps=fused, tile_cols=32, tile_rows=4, waves=8, graph_steps=0)
+            s.set_populations(f0).step(11)
+            got = s.get_populations().cpu().numpy()
+            assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max(), (shape, ns, fused)
+        s.close()
+
+
+def test_shear_flow_gray_scott_f32_and_uniform_density():
+    """Gray-Scott FP32 in a shear flow from the square start (default launch
+    shape): the FP64 oracle with the same field within the FP32 floor after
+    300 steps; and the equilibrium init plus the default launches keep a
+    uniform density uniform in FP64 storage (the scheme's exact property)."""
+    n = 96
+    u, shear = (0.02, 0.0), (0.12, 3)
+    field = workloads.shear_field(n, n, u, *shear)
+    rho0 = workloads.gray_scott_square(n, n, seed=6)
+    kw = dict(F=workloads.GS_F, k=workloads.GS_K)
+    rho, _, s = gpu_solve(rho0, 300, "f32", tau=workloads.GS_TAU, reaction="gray_scott", u=u, shear=shear, **kw)
+    assert s.tuning().fused_steps >= 2
+    ref = oracle.solve(rho0, 300, list(workloads.GS_TAU), oracle.REACT_GRAY_SCOTT, u=field, **kw)
+    floor = oracle.rel_l2(oracle.solve(rho0, 300, list(workloads.GS_TAU), oracle.REACT_GRAY_SCOTT, precision="f32",
+                                       u=field, **kw), ref)
+    tol = np.where(floor <= 1e-6, 1e-5, 3 * floor)
+    err = oracle.rel_l2(rho, ref)
+    log(f"shear GS f32: rel L2 {err}, FP32 floor {floor}")
+    assert np.all(err <= tol)
+    flat = np.full((1, 40, 50), 0.7)
+    rho_flat, _, _ = gpu_solve(flat, 200, "f64", tau=0.8, reaction="none", u=(0.05, 0.0), shear=(0.15, 2))
+    assert np.abs(rho_flat - 0.7).max() <= 1e-13
+
+
 def test_advected_gray_scott_f32_and_drift():
     """Gray-Scott FP32 with u = (0.1, 0.05) from the square start: the FP64
     oracle within the FP32 floor after 300 steps, and a blob without reaction
@@ -521,7 +571,8 @@ def test_largest_lattices_sampled_windows(n, multi):
 
 FUSED_CASES = [("f64", "gray_scott", 2), ("f32", "gray_scott", 2), ("f16", "gray_scott", 2), ("bf16", "gray_scott", 2),
                ("f32", "linear", 1), ("f32", "linear", 3), ("f16", "linear", 1), ("f64", "linear", 4),
-               ("f32", "gray_scott_advected", 2), ("bf16", "linear_advected", 1)]
+               ("f32", "gray_scott_advected", 2), ("bf16", "linear_advected", 1),
+               ("f32", "gray_scott_shear", 2), ("f64", "linear_shear", 1)]
 
 
 def multi_step_shape_fits(b, ns, cols, rows, steps, waves):
@@ -553,9 +604,12 @@ def test_multi_step_launch_is_bitwise_identical(storage, reaction, ns):
         kw = dict(F=0.04, k=0.06) if reaction.startswith("gray_scott") else dict(K=-0.01 * np.eye(ns))
         if reaction.endswith("_advected"):
             kw["u"] = (0.09, -0.13)
+        if reaction.endswith("_shear"):
+            kw["u"] = (0.02, -0.04)
+            kw["shear"] = (0.11, 2)
         rref = (0.3,) * ns
         cfg = lbrd.make_config(nx, ny, ns, tau=[0.7, 1.2, 0.9, 0.8][:ns], storage=storage,
-                               reaction=reaction.replace("_advected", ""), rho_ref=rref, **kw)
+                               reaction=reaction.replace("_advected", "").replace("_shear", ""), rho_ref=rref, **kw)
         f0 = rng.uniform(0.0, 0.1, size=(ns, 9, ny, nx))
         ref = lbrd.Solver(cfg)
         ref.set_tuning(fused_steps=1, graph_steps=0)

@@ -14,7 +14,8 @@ import pytest
 
 import oracle
 from paper_1007_3109_amd import analysis, workloads
-from pins import gaussian_point_source, golden, gs_jacobian, gs_reaction, maxwellian_coefs, propagator, source_vector
+from pins import (gaussian_point_source, golden, gs_jacobian, gs_reaction, maxwellian_coefs, propagator,
+                  row_field_propagator, source_vector)
 
 G = golden()
 
@@ -205,6 +206,79 @@ def test_advective_linear_fourier_propagator(u):
             P = propagator((2 * math.pi * mx / nx, 2 * math.pi * my / ny), taus, K, w, ex, ey, ceq)
             v = np.linalg.matrix_power(P, nsteps) @ F0[:, my, mx]
             assert np.abs(v - Fn[:, my, mx]).max() <= 1e-12 * scale
+
+
+def test_velocity_field_of_one_value_equals_uniform_velocity():
+    """A prescribed field that holds the same velocity at every site gives
+    exactly the populations of that uniform velocity (same arithmetic, site
+    by site): init and 9 steps of Gray-Scott, bitwise."""
+    ny, nx = 6, 9
+    u = (0.11, -0.06)
+    rho0 = workloads.gray_scott_square(nx, ny, seed=4)
+    field = np.broadcast_to(np.asarray(u), (ny, nx, 2)).copy()
+    fu = oracle.init(rho0, u=u)
+    ff = oracle.init(rho0, u=field)
+    assert np.array_equal(fu, ff)
+    kw = dict(F=0.04, k=0.06)
+    assert np.array_equal(oracle.run(fu, 9, [1.0, 0.75], oracle.REACT_GRAY_SCOTT, u=u, **kw),
+                          oracle.run(ff, 9, [1.0, 0.75], oracle.REACT_GRAY_SCOTT, u=field, **kw))
+
+
+def test_shear_flow_keeps_a_uniform_density():
+    """A shear flow u_x(y), u_y = 0 is divergence free, and the scheme keeps a
+    uniform density exactly: the populations that reach a site from one row
+    (e_iy fixed) carry weights whose Maxwellian terms in u_x cancel within
+    that row's group (2/3, 1/6, 1/6 whatever u_x), so rho stays uniform to
+    rounding for any tau, at every step.  A field that varies along x (not
+    divergence free) moves density at once, which shows the check sees the
+    field's orientation."""
+    ny, nx = 12, 10
+    rho0 = np.full((1, ny, nx), 0.7)
+    shear = workloads.shear_field(nx, ny, (0.05, 0.0), 0.15, 2)
+    f = oracle.run(oracle.init(rho0, u=shear), 300, [0.8], oracle.REACT_NONE, u=shear)
+    assert np.abs(oracle.moments(f) - 0.7).max() <= 1e-14
+    along_x = np.ascontiguousarray(np.transpose(workloads.shear_field(ny, nx, (0.05, 0.0), 0.15, 2), (1, 0, 2)))
+    g = oracle.run(oracle.init(rho0, u=along_x), 20, [0.8], oracle.REACT_NONE, u=along_x)
+    assert np.abs(oracle.moments(g) - 0.7).max() >= 1e-4
+
+
+def test_shear_flow_mode_propagator():
+    """With a velocity that depends on the row only, an x-Fourier mode
+    exp(i q x) A_i(y) evolves by the (9 ny) x (9 ny) one-step matrix of
+    collision (c_i(u(y)) on row y) and streaming: random non-equilibrium
+    amplitudes, shear u_x = 0.03 + 0.12 sin(2 pi y / 8) with u_y = 0.04, one
+    species with decay, 25 steps, to 1e-12."""
+    ny, nx, k, nsteps, tau, kappa = 8, 10, 2, 25, 0.9, 0.02
+    q = 2 * math.pi * k / nx
+    rng = np.random.default_rng(21)
+    A = rng.uniform(-1, 1, size=(9, ny)) + 1j * rng.uniform(-1, 1, size=(9, ny))
+    x = np.arange(nx)
+    f0 = np.real(A[:, :, None] * np.exp(1j * q * x)[None, None, :])[None]
+    field = workloads.shear_field(nx, ny, (0.03, 0.04), 0.12, 1)
+    f = oracle.run(f0, nsteps, [tau], oracle.REACT_LINEAR, K=[[-kappa]], u=field)
+    B = (2.0 / nx) * np.sum(f[0] * np.exp(-1j * q * x)[None, None, :], axis=2)
+    w, ex, ey = oracle.tables()
+    ceq_rows = [maxwellian_coefs(field[y, 0], w, ex, ey) for y in range(ny)]
+    M = row_field_propagator(q, ny, tau, kappa, w, ex, ey, ceq_rows)
+    want = (np.linalg.matrix_power(M, nsteps) @ A.reshape(-1)).reshape(9, ny)
+    assert np.abs(B - want).max() <= 1e-12 * np.abs(A).max()
+
+
+def test_shear_flow_moves_centre_of_mass_by_uy():
+    """The first moment of the Maxwellian along y is rho u_y whatever u_x, so
+    with a shear u_x(y) and a uniform u_y the total y-momentum stays M u_y and
+    the centre of mass moves by exactly u_y per step along y (no reaction).
+    Gaussian blob on a 160 x 160 box, 60 steps."""
+    L, n, uy = 160, 60, 0.07
+    y, x = np.mgrid[0:L, 0:L]
+    rho0 = (1e-3 + np.exp(-((x - 80.0) ** 2 + (y - 60.0) ** 2) / (2 * 36.0)))[None]
+    field = workloads.shear_field(L, L, (0.0, uy), 0.1, 1)
+    f = oracle.run(oracle.init(rho0, u=field), n, [0.7], oracle.REACT_NONE, u=field)
+    rho = oracle.moments(f)[0]
+    base = 1e-3
+    cy0 = np.sum((rho0[0] - base) * y) / np.sum(rho0[0] - base)
+    cy = np.sum((rho - base) * y) / np.sum(rho - base)
+    assert abs((cy - cy0) - n * uy) <= 1e-9
 
 
 @pytest.mark.parametrize("u", VELOCITIES)
