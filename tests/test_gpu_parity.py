@@ -673,14 +673,19 @@ def test_default_shape_for_every_species_count(storage):
             torch.cuda.empty_cache()
 
 
-def test_multi_step_launch_with_graphs_and_oracle():
+@pytest.mark.parametrize("ts,cols,rows,graph", [(3, 64, 8, 8), (5, 32, 10, 12), (7, 32, 12, 30), (8, 64, 14, 16)])
+def test_multi_step_launch_with_graphs_and_oracle(ts, cols, rows, graph):
+    """Captured graphs of T-step launches (a graph's last launch may be
+    shorter, and a graph may end on a one-step launch) replayed between eager
+    remainders equal plain one-step launches bitwise, and the FP64 oracle
+    within 1e-5 after 52 steps."""
     rho0 = workloads.gray_scott_square(200, 160, seed=7)
     kw = dict(F=workloads.GS_F, k=workloads.GS_K)
     cfg = lbrd.make_config(200, 160, 2, tau=workloads.GS_TAU, storage="f32", reaction="gray_scott", **kw)
     a = lbrd.Solver(cfg)
     a.set_tuning(fused_steps=1, graph_steps=0)
     b = lbrd.Solver(cfg)
-    b.set_tuning(fused_steps=3, tile_rows=8, tile_cols=64, waves=8, graph_steps=8)   # 3 + 3 + 2 per graph
+    b.set_tuning(fused_steps=ts, tile_rows=rows, tile_cols=cols, waves=8, graph_steps=graph)
     a.init(rho0)
     b.init(rho0)
     for n in (13, 6, 31, 2):
