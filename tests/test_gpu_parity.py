@@ -402,6 +402,21 @@ def test_step_before_init_is_a_state_error():
     assert lbrd.lib.lbrd_moments(s._h, None, 0, (lbrd.ctypes.c_double * 1)()) == lbrd.ESTATE
 
 
+def test_zero_and_negative_step_counts():
+    """Zero steps leave the state and the clock alone (also with graphs);
+    a negative count is refused with EINVAL and changes nothing."""
+    rho0 = workloads.gray_scott_square(40, 30, seed=2)
+    cfg = lbrd.make_config(40, 30, 2, tau=workloads.GS_TAU, storage="f32", reaction="gray_scott", F=0.04, k=0.06)
+    s = lbrd.Solver(cfg)
+    s.set_tuning(graph_steps=10)
+    s.init(rho0).step(7)
+    before = s.get_populations()
+    assert lbrd.lib.lbrd_step(s._h, 0) == lbrd.OK
+    assert lbrd.lib.lbrd_step(s._h, -3) == lbrd.EINVAL
+    assert s.time() == 7
+    assert torch.equal(s.get_populations(), before)
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
 def test_checkpoint_and_resume(storage):
     """Checkpoint / resume through the populations: 50 steps, read the
