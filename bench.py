@@ -415,6 +415,10 @@ def main():
     ap.add_argument("--legs", default="hbm4096_f32,hbm4096_f16,hbm4096_bf16,batch,serve,precision,rescaling,config1,copy",
                     help="extra legs to run (comma list)")
     ap.add_argument("--serve-requests", type=int, default=120)
+    ap.add_argument("--serve-pool-gb", type=float, default=16.0, help="device arena of the serving leg")
+    ap.add_argument("--serve-rate", type=float, default=None,
+                    help="Poisson arrival rate of the serving leg (default: 85%% of the measured capacity)")
+    ap.add_argument("--serve-seed", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
@@ -514,7 +518,8 @@ def main():
             extra["batched"] = batch_leg(torch, lbrd, workloads, 2000, 32)
         if "serve" in legs:
             log("bench: serving")
-            extra["serving"] = serve_leg(torch, lbrd, workloads, args.serve_requests, 16, (1000, 10000))
+            extra["serving"] = serve_leg(torch, lbrd, workloads, args.serve_requests, args.serve_pool_gb, (1000, 10000),
+                                         seed=args.serve_seed, rate=args.serve_rate)
         if "precision" in legs:
             log("bench: precision forms")
             extra["precision"] = precision_leg(torch, lbrd, workloads)
