@@ -515,7 +515,7 @@ def main():
                                                        tune=args.tune)
         if "batch" in legs:
             log("bench: batched sweep")
-            extra["batched"] = batch_leg(torch, lbrd, workloads, 2000, 32)
+            extra["batched"] = batch_leg(torch, lbrd, workloads, 5000, 32)
         if "serve" in legs:
             log("bench: serving")
             extra["serving"] = serve_leg(torch, lbrd, workloads, args.serve_requests, args.serve_pool_gb, (1000, 10000),
