@@ -137,6 +137,34 @@ def test_gray_scott_f32(n, steps):
     assert np.all(err <= tol)
 
 
+def test_gray_scott_f32_checkpoints_to_5000():
+    """The FP32 kernel (default launch shape) against the FP64 oracle at the
+    checkpoints n = 100, 1000 and 5000 of one run on 256^2 (the square start
+    of the 4096^2 workload, scaled), with the oracle's own float build as the
+    rounding floor F(n): relative L2 <= 1e-5 where F(n) <= 1e-6, else <= 3 F(n)
+    (the pattern dynamics amplify rounding differences with time)."""
+    n = 256
+    rho0 = workloads.gray_scott_square(n, n, seed=5)
+    kw = dict(F=workloads.GS_F, k=workloads.GS_K)
+    taus = list(workloads.GS_TAU)
+    s = lbrd.Solver(lbrd.make_config(n, n, 2, tau=taus, storage="f32", reaction="gray_scott", **kw))
+    s.init(rho0)
+    f64 = oracle.init(rho0)
+    f32 = oracle.init(rho0, "f32")
+    done = 0
+    for cp in (100, 1000, 5000):
+        s.step(cp - done)
+        f64 = oracle.run(f64, cp - done, taus, oracle.REACT_GRAY_SCOTT, **kw)
+        f32 = oracle.run(f32, cp - done, taus, oracle.REACT_GRAY_SCOTT, **kw)
+        done = cp
+        ref = oracle.moments(f64)
+        floor = oracle.rel_l2(oracle.moments(f32), ref)
+        err = oracle.rel_l2(s.moments()[0].cpu().numpy(), ref)
+        tol = np.where(floor <= 1e-6, 1e-5, 3 * floor)
+        log(f"GS f32 256^2 step {cp}: err {err} floor {floor}")
+        assert np.all(err <= tol), (cp, err, floor)
+
+
 # ----- 16-bit shifted storage ------------------------------------------------
 
 QUANT = {"f16": 1, "bf16": 2}
