@@ -222,11 +222,14 @@ int lbrd_get_tuning(const lbrd_solver *h, lbrd_tuning *out);
 int lbrd_set_tuning(lbrd_solver *h, const lbrd_tuning *t);
 
 /* Time every valid launch shape on this solver's buffers for about `steps`
- * steps each (whole launches, compared per step) and keep the fastest;
- * writes it to *chosen if not NULL.  Overwrites
- * the state: the solver must be (re)initialised afterwards (ESTATE until
- * then).  cache_path: text file of earlier results keyed by (device, storage,
- * reaction, N, nx, ny), read and appended; NULL disables the cache. */
+ * steps each (whole launches, at least about 1 ms, compared per step), then
+ * the three fastest multi-step shapes again with the other tile order, and
+ * keep the fastest; writes it to *chosen if not NULL.  The shapes are timed
+ * on the solver's own state when it is initialised, else on a scrambled field
+ * of densities in [0.5, 1); either way the state is overwritten: the solver
+ * must be (re)initialised afterwards (ESTATE until then).  cache_path: text
+ * file of earlier results keyed by (device, storage, reaction, N, nx, ny),
+ * read and appended; NULL disables the cache. */
 int lbrd_autotune(lbrd_solver *h, int steps, const char *cache_path, lbrd_tuning *chosen);
 
 /* Device time in milliseconds of `nsteps` steps measured with HIP events on

@@ -561,11 +561,17 @@ int lbrd_batch_autotune(lbrd_batch *b, int steps, lbrd_tuning *chosen) {
         t.graph_steps = 0;
         if (lbrd_batch_set_tuning(b, &t) != LBRD_OK) continue;
         double ms = 0;
-        // whole launches only, compared per step
+        // whole launches only, compared per step; short runs are dominated by
+        // launch jitter, so each candidate runs for about 1 ms at least
         const int per = std::max(1, (int)t.fused_steps);
-        const int n = (steps + per - 1) / per * per;
+        int n = (steps + per - 1) / per * per;
         if (lbrd_batch_time_steps(b, per, &ms) != LBRD_OK) continue;
         if (lbrd_batch_time_steps(b, n, &ms) != LBRD_OK) continue;
+        if (ms < 1.0) {
+            const double grow = std::min(64.0, 1.0 / std::max(ms, 1e-3));
+            n = ((int)(n * grow) + per - 1) / per * per;
+            if (lbrd_batch_time_steps(b, n, &ms) != LBRD_OK) continue;
+        }
         ms /= n;
         if (ms < best_ms) {
             best_ms = ms;
