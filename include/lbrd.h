@@ -223,8 +223,9 @@ int lbrd_set_tuning(lbrd_solver *h, const lbrd_tuning *t);
 
 /* Time every valid launch shape on this solver's buffers for about `steps`
  * steps each (whole launches, at least about 1 ms, compared per step), then
- * the three fastest multi-step shapes again with the other tile order, and
- * keep the fastest; writes it to *chosen if not NULL.  The shapes are timed
+ * re-time with runs of about 10 ms the six fastest, the shape in use and the
+ * three fastest multi-step shapes with the other tile order, and keep the
+ * fastest of those; writes it to *chosen if not NULL.  The shapes are timed
  * on the solver's own state when it is initialised, else on a scrambled field
  * of densities in [0.5, 1); either way the state is overwritten: the solver
  * must be (re)initialised afterwards (ESTATE until then).  cache_path: text

@@ -811,8 +811,10 @@ int lbrd_autotune(lbrd_solver *h, int steps, const char *cache_path, lbrd_tuning
         }
         if (int rc = lbrd_init(h, rho.data(), LBRD_DTYPE_F64, 0)) return rc;
     }
-    // milliseconds per step of one candidate (whole launches only), or +inf
-    auto time_one = [&](const lbrd_tuning &t) {
+    const lbrd_tuning entry = h->tune;   // the shape in use: always a finalist
+    // milliseconds per step of one candidate (whole launches only, running
+    // for at least min_ms), or +inf
+    auto time_one = [&](const lbrd_tuning &t, double min_ms) {
         lbrd_tuning tt = t;
         tt.graph_steps = 0;
         if (lbrd_set_tuning(h, &tt) != LBRD_OK) return 1e300;
@@ -821,30 +823,40 @@ int lbrd_autotune(lbrd_solver *h, int steps, const char *cache_path, lbrd_tuning
         int n = (steps + per - 1) / per * per;
         int rc = lbrd_time_steps(h, per, &ms);   // warm-up
         if (rc == LBRD_OK) rc = lbrd_time_steps(h, n, &ms);
-        if (rc == LBRD_OK && ms < 1.0) {
-            // short runs are dominated by launch jitter: time about 1 ms
-            const double grow = std::min(64.0, 1.0 / std::max(ms, 1e-3));
+        if (rc == LBRD_OK && ms < min_ms) {
+            // short runs are dominated by launch jitter and by clocks that
+            // have not settled: grow the run to about min_ms
+            const double grow = std::min(256.0, min_ms / std::max(ms, 1e-3));
             n = ((int)(n * grow) + per - 1) / per * per;
             rc = lbrd_time_steps(h, n, &ms);
         }
         return rc == LBRD_OK ? ms / n : 1e300;
     };
+    // first pass: every candidate for about 1 ms
     std::vector<std::pair<double, lbrd_tuning>> timed;
-    for (const lbrd_tuning &t : cands) timed.emplace_back(time_one(t), t);
+    for (const lbrd_tuning &t : cands) timed.emplace_back(time_one(t, 1.0), t);
     std::stable_sort(timed.begin(), timed.end(),
                      [](const auto &a, const auto &b) { return a.first < b.first; });
-    double best = timed.empty() ? 1e300 : timed[0].first;
-    lbrd_tuning best_t = timed.empty() ? h->tune : timed[0].second;
-    // second pass: the fastest multi-step shapes with the other tile order
-    // (XCD-grouped or the hardware's round-robin; which one wins depends on
+    // second pass, runs of about 10 ms: the six fastest, the default shape,
+    // and the three fastest multi-step shapes with the other tile order
+    // (XCD-grouped or the hardware's round-robin: which one wins depends on
     // the lattice and the shape)
-    int tried = 0;
-    for (size_t q = 0; q < timed.size() && tried < 3; ++q) {
+    std::vector<lbrd_tuning> finals;
+    for (size_t q = 0; q < timed.size() && finals.size() < 6; ++q)
+        if (timed[q].first < 1e300) finals.push_back(timed[q].second);
+    finals.push_back(entry);
+    int flipped = 0;
+    for (size_t q = 0; q < timed.size() && flipped < 3; ++q) {
         if (timed[q].second.fused_steps < 2 || timed[q].first >= 1e300) continue;
         lbrd_tuning t = timed[q].second;
         t.plain_order ^= 1;
-        ++tried;
-        const double ms = time_one(t);
+        finals.push_back(t);
+        ++flipped;
+    }
+    double best = 1e300;
+    lbrd_tuning best_t = entry;
+    for (const lbrd_tuning &t : finals) {
+        const double ms = time_one(t, 10.0);
         if (ms < best) {
             best = ms;
             best_t = t;
