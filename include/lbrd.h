@@ -134,7 +134,15 @@ typedef struct lbrd_config {
  *       (0 = 64).
  *       With h = T-1 and w = tile_cols + 2h, the LDS region of tile_rows + 2h
  *       rows of 9 N w populations (each row padded by fewer than 256 bytes)
- *       must fit in 160 KB.  Ignored when fused_steps = 1. */
+ *       must fit in 160 KB.  Ignored when fused_steps = 1.
+ *  tile_strip: order of the tiles of a multi-step launch (single solvers;
+ *       batches set it to 0): 0 = row-major over the lattice, S = 1..65536 =
+ *       strips of S tile columns, row-major inside each strip, so that the
+ *       tiles above and below one in flight are in flight too and their
+ *       shared halo rows are read once from L2.  lbrd_create sets half the
+ *       workgroups that one XCD holds at once (from the LDS of the default
+ *       shape) when the lattice is wider than twice that many tiles, else 0.
+ *       Results are bitwise identical for every order. */
 typedef struct lbrd_tuning {
     int32_t vec;
     int32_t lanes_x;
@@ -146,6 +154,7 @@ typedef struct lbrd_tuning {
     int32_t fused_steps;
     int32_t tile_rows;
     int32_t tile_cols;
+    int32_t tile_strip;
 } lbrd_tuning;
 
 const char *lbrd_strerror(int status);
@@ -222,10 +231,11 @@ int lbrd_get_tuning(const lbrd_solver *h, lbrd_tuning *out);
 int lbrd_set_tuning(lbrd_solver *h, const lbrd_tuning *t);
 
 /* Time every valid launch shape on this solver's buffers for about `steps`
- * steps each (whole launches, at least about 1 ms, compared per step), then
+ * steps each (whole launches, at least about 1 ms, compared per step; each
+ * multi-step shape with the tile_strip lbrd_create would give it), then
  * re-time with runs of about 10 ms the six fastest, the shape in use and the
- * three fastest multi-step shapes with the other tile order, and keep the
- * fastest of those; writes it to *chosen if not NULL.  The shapes are timed
+ * three fastest multi-step shapes with the other XCD order and with the other
+ * strip choice (strips or row-major), and keep the fastest of those; writes it to *chosen if not NULL.  The shapes are timed
  * on the solver's own state when it is initialised, else on a scrambled field
  * of densities in [0.5, 1); either way the state is overwritten: the solver
  * must be (re)initialised afterwards (ESTATE until then).  cache_path: text

@@ -150,6 +150,7 @@ GridT make_gridT(const Layout &L, const void *src, void *dst, int tw, int th, in
     g.ntiles = (int64_t)g.ntx * g.nty;
     g.blocks = 0;
     g.xcd_order = 1;
+    g.strip = g.ntx;
     g.steps = steps;
     g.bytes = L.buf_bytes < ((size_t)1 << 32) ? (uint32_t)L.buf_bytes : 0;   // 0: too large, launch refused
     g.nt_store = 0;
@@ -319,6 +320,7 @@ hipError_t enqueue_steps(lbrd_solver *h, int from, int64_t n, hipStream_t st, in
             GridT g = make_gridT(h->L, h->buf[a], h->buf[a ^ 1], h->tune.tile_cols, h->tune.tile_rows, m);
             g.blocks = h->tune.blocks_per_cu > 0 ? h->tune.blocks_per_cu * h->cus : 0;
             g.xcd_order = h->tune.plain_order == 0 ? 1 : 0;
+            if (h->tune.tile_strip > 0) g.strip = std::min(h->tune.tile_strip, g.ntx);
             g.nt_store = h->tune.nontemporal;
             e = launch_stepT(sl, g, h->params, st);
             k += m;
@@ -379,12 +381,36 @@ bool multi_step_possible(const lbrd_solver *h) {
            (int64_t)h->L.pitch * storage_bytes(h->cfg.storage) < ((int64_t)1 << 24);
 }
 
+// Tile order of multi-step launches.  Row-major over a wide lattice puts
+// the tiles above and below a running one a whole tile row away in launch
+// order: with fewer workgroups resident on an XCD than tiles in a row, the
+// halo rows they share have left the XCD's L2 by then and are fetched again
+// (4096^2 FP32 at T = 7 on 32 x 12 tiles reads 2.0x the algorithmic bytes).
+// Strips of S tile columns, S = half the workgroups one XCD holds at once
+// (LDS-limited, 32 CUs per XCD, at most 32 waves per CU), keep about two
+// tile rows of a strip in flight.  Measured per step against row-major:
+// 4096^2 FP32 115 against 128 us, 4096^2 FP64 309 against 347 us, 2048^2
+// FP64 73 against 84 us; 2048^2 FP32 (64 tiles across, within twice S)
+// 2-5 % slower, hence row-major up to 2S tiles across.
+int strip_width(const lbrd_solver *h, const lbrd_tuning &t) {
+    const size_t lds = stepT_lds_bytes(h->cfg.storage, h->cfg.nspecies, t.tile_cols, t.tile_rows, t.fused_steps);
+    if (lds == 0 || t.waves < 1) return 1;
+    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(kLdsBytes / lds, (size_t)(32 / t.waves)));
+    return std::max(1, per_cu * std::max(1, h->cus / 8) / 2);
+}
+int tiles_across(const lbrd_solver *h, const lbrd_tuning &t) { return (h->cfg.nx + t.tile_cols - 1) / t.tile_cols; }
+int default_strip(const lbrd_solver *h, const lbrd_tuning &t) {
+    const int strip = strip_width(h, t);
+    return tiles_across(h, t) > 2 * strip ? strip : 0;
+}
+
 bool tuning_valid(const lbrd_solver *h, const lbrd_tuning &t) {
     // the one-step shape is used for every one-step launch (also the odd
     // remainder of a fused run)
     if (!step_shape_valid(h->cfg.storage, t.vec, t.lanes_x, std::min(t.waves, 4))) return false;
     if (t.blocks_per_cu < 0 || t.blocks_per_cu > 64) return false;
     if (t.plain_order != 0 && t.plain_order != 1) return false;
+    if (t.tile_strip < 0 || t.tile_strip > 65536) return false;
     if (t.graph_steps < 0 || (t.graph_steps & 1) || t.graph_steps > 4096) return false;
     if (t.nontemporal != 0 && t.nontemporal != 1) return false;
     if (t.waves < 1 || t.waves > 16) return false;
@@ -520,6 +546,7 @@ int lbrd_create(const lbrd_config *cfg, void *workspace, size_t bytes, void *str
                         h->tune.tile_rows = rows;
                         break;
                     }
+        if (h->tune.fused_steps > 1) h->tune.tile_strip = default_strip(h, h->tune);
     }
     *out = h;
     return LBRD_OK;
@@ -738,9 +765,9 @@ int lbrd_autotune(lbrd_solver *h, int steps, const char *cache_path, lbrd_tuning
             if (bar == std::string::npos || line.substr(0, bar) != k) continue;
             lbrd_tuning t;
             std::memset(&t, 0, sizeof(t));
-            if (std::sscanf(line.c_str() + bar + 1, "%d %d %d %d %d %d %d %d %d %d", &t.vec, &t.lanes_x, &t.waves,
-                            &t.nontemporal, &t.graph_steps, &t.plain_order, &t.blocks_per_cu, &t.fused_steps,
-                            &t.tile_rows, &t.tile_cols) == 10 &&
+            if (std::sscanf(line.c_str() + bar + 1, "%d %d %d %d %d %d %d %d %d %d %d", &t.vec, &t.lanes_x,
+                            &t.waves, &t.nontemporal, &t.graph_steps, &t.plain_order, &t.blocks_per_cu,
+                            &t.fused_steps, &t.tile_rows, &t.tile_cols, &t.tile_strip) == 11 &&
                 tuning_valid(h, t)) {
                 lbrd_set_tuning(h, &t);
                 h->initialised = false;
@@ -791,7 +818,10 @@ int lbrd_autotune(lbrd_solver *h, int steps, const char *cache_path, lbrd_tuning
                             t.fused_steps = ts;
                             t.tile_rows = rows;
                             t.tile_cols = cols;
-                            if (tuning_valid(h, t)) cands.push_back(t);
+                            t.tile_strip = 0;
+                            if (!tuning_valid(h, t)) continue;
+                            t.tile_strip = default_strip(h, t);
+                            cands.push_back(t);
                         }
     // the state is scratch from here on.  Timings depend a little on the
     // data (an all-zero field runs faster than real states and favours other
@@ -839,8 +869,8 @@ int lbrd_autotune(lbrd_solver *h, int steps, const char *cache_path, lbrd_tuning
                      [](const auto &a, const auto &b) { return a.first < b.first; });
     // second pass, runs of about 10 ms: the six fastest, the default shape,
     // and the three fastest multi-step shapes with the other tile order
-    // (XCD-grouped or the hardware's round-robin: which one wins depends on
-    // the lattice and the shape)
+    // (XCD-grouped or the hardware's round-robin; row-major or strips:
+    // which one wins depends on the lattice and the shape)
     std::vector<lbrd_tuning> finals;
     for (size_t q = 0; q < timed.size() && finals.size() < 6; ++q)
         if (timed[q].first < 1e300) finals.push_back(timed[q].second);
@@ -851,6 +881,9 @@ int lbrd_autotune(lbrd_solver *h, int steps, const char *cache_path, lbrd_tuning
         lbrd_tuning t = timed[q].second;
         t.plain_order ^= 1;
         finals.push_back(t);
+        t.plain_order ^= 1;
+        t.tile_strip = t.tile_strip ? 0 : strip_width(h, t);
+        if (t.tile_strip < tiles_across(h, t)) finals.push_back(t);
         ++flipped;
     }
     double best = 1e300;
@@ -869,7 +902,8 @@ int lbrd_autotune(lbrd_solver *h, int steps, const char *cache_path, lbrd_tuning
         std::ofstream outf(cache_path, std::ios::app);
         outf << k << "|" << best_t.vec << " " << best_t.lanes_x << " " << best_t.waves << " " << best_t.nontemporal
              << " " << best_t.graph_steps << " " << best_t.plain_order << " " << best_t.blocks_per_cu << " "
-             << best_t.fused_steps << " " << best_t.tile_rows << " " << best_t.tile_cols << "\n";
+             << best_t.fused_steps << " " << best_t.tile_rows << " " << best_t.tile_cols << " " << best_t.tile_strip
+             << "\n";
     }
     if (chosen) *chosen = h->tune;
     return LBRD_OK;

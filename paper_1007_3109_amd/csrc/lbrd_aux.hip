@@ -50,7 +50,7 @@ size_t stepT_lds_bytes(int storage, int nspecies, int tw, int th, int steps) {
 bool stepT_shape_fits(int storage, int nspecies, int tw, int th, int steps, int waves) {
     if (steps < 2 || steps > kMaxFusedSteps || (tw != 32 && tw != 64 && tw != 128) || th < 1 || waves < 1 || waves > 16)
         return false;
-    return stepT_lds_bytes(storage, nspecies, tw, th, steps) <= (size_t)160 * 1024;
+    return stepT_lds_bytes(storage, nspecies, tw, th, steps) <= kLdsBytes;
 }
 
 hipError_t launch_step(const StepLaunch &sl, const Grid &g, const void *params, hipStream_t st) {

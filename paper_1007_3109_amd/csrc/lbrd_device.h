@@ -744,8 +744,14 @@ __global__ __launch_bounds__(1024) void k_stepT(GridT g, Params<typename Traits<
     t.pstride_b = (uint32_t)g.pstride * (uint32_t)sizeof(T);
     t.nt_store = g.nt_store;
     const int b0 = g.xcd_order ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    for (int64_t tile = b0; tile < g.ntiles; tile += gridDim.x) {
-        const int tx = (int)(tile % g.ntx), ty = (int)(tile / g.ntx);
+    // tiles in strips of g.strip tile columns (g.ntx: plain row-major),
+    // row-major inside a strip, the last strip possibly narrower; a launch
+    // has fewer than 2^31 tiles (its buffers are below 4 GiB)
+    const int per = g.strip * g.nty;
+    for (int tile = b0; tile < (int)g.ntiles; tile += gridDim.x) {
+        const int si = tile / per, r = tile - si * per;
+        const int sw = min(g.strip, g.ntx - si * g.strip);
+        const int ty = r / sw, tx = si * g.strip + (r - ty * sw);
         stepT_tile<ST, V, TS, TW, false>(t, p, tx * TW, ty * g.th, TS, reinterpret_cast<T *>(smem));
     }
 }

@@ -102,6 +102,7 @@ struct GridT {
     int64_t ntiles;
     int blocks;
     int xcd_order;
+    int strip;        // tiles in strips of this many tile columns (ntx: row-major order)
     int steps;        // 2 .. kMaxFusedSteps
     uint32_t bytes;   // bytes of one buffer (less than 4 GiB)
     int nt_store;     // 1: streaming (non-temporal) stores of the result
@@ -121,6 +122,7 @@ __host__ __device__ constexpr int stepT_row_stride(int nspecies, int ew, int byt
     const int base = 9 * nspecies * ew;
     return base + ((ew - base) % unit + unit) % unit;
 }
+constexpr size_t kLdsBytes = (size_t)160 * 1024;   // LDS of one CU
 // LDS bytes of a launch of `steps` steps on tw x th tiles.
 size_t stepT_lds_bytes(int storage, int nspecies, int tw, int th, int steps);
 bool stepT_shape_fits(int storage, int nspecies, int tw, int th, int steps, int waves);

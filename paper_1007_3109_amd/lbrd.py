@@ -40,12 +40,12 @@ class Tuning(ctypes.Structure):
         ("vec", ctypes.c_int32), ("lanes_x", ctypes.c_int32), ("waves", ctypes.c_int32),
         ("nontemporal", ctypes.c_int32), ("graph_steps", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
         ("plain_order", ctypes.c_int32), ("fused_steps", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
-        ("tile_cols", ctypes.c_int32),
+        ("tile_cols", ctypes.c_int32), ("tile_strip", ctypes.c_int32),
     ]
 
     def as_dict(self):
         return {k: getattr(self, k) for k in ("vec", "lanes_x", "waves", "nontemporal", "graph_steps", "blocks_per_cu",
-                                              "plain_order", "fused_steps", "tile_rows", "tile_cols")}
+                                              "plain_order", "fused_steps", "tile_rows", "tile_cols", "tile_strip")}
 
 
 class ServerConfig(ctypes.Structure):

@@ -668,10 +668,14 @@ def test_multi_step_launch_is_bitwise_identical(storage, reaction, ns):
                             s.set_tuning(fused_steps=steps, tile_cols=cols, tile_rows=rows, waves=waves,
                                          graph_steps=0)
                         continue
+                    # tile orders: row-major or strips of 1, 2 or 3 tile columns
+                    # (a ragged last strip on the wider lattices), XCD-grouped
+                    # or round-robin
+                    strip, order = ran % 4, (ran // 4) % 2
                     s.set_tuning(fused_steps=steps, tile_cols=cols, tile_rows=rows, waves=waves, graph_steps=0,
-                                 nontemporal=int(waves == 16))
+                                 nontemporal=int(waves == 16), tile_strip=strip, plain_order=order)
                     s.set_populations(f0).step(19)
-                    assert torch.equal(s.get_populations(), want), (ny, nx, steps, cols, rows, waves)
+                    assert torch.equal(s.get_populations(), want), (ny, nx, steps, cols, rows, waves, strip, order)
                     ran += 1
         assert s.time() == 19
         with pytest.raises(lbrd.LbrdError):             # beyond eight steps per launch
@@ -682,6 +686,10 @@ def test_multi_step_launch_is_bitwise_identical(storage, reaction, ns):
         for waves in (0, 3, 17):                      # 3: the one-step launches take 1, 2 or 4
             with pytest.raises(lbrd.LbrdError):
                 s.set_tuning(fused_steps=2, tile_cols=64, tile_rows=2, waves=waves, graph_steps=0)
+        for strip, order in ((-1, 0), (65537, 0), (0, 2), (0, -1)):
+            with pytest.raises(lbrd.LbrdError):
+                s.set_tuning(fused_steps=2, tile_cols=64, tile_rows=2, waves=4, graph_steps=0, tile_strip=strip,
+                             plain_order=order)
     log(f"multi-step {storage} {reaction} N={ns}: {ran} shapes bitwise equal")
     assert ran >= 30
 
@@ -714,6 +722,36 @@ def test_default_shape_for_every_species_count(storage):
             ref.close()
             del got
             torch.cuda.empty_cache()
+
+
+def test_default_tile_order():
+    """The default order of multi-step tiles: strips of S tile columns, S half
+    the workgroups one XCD holds at once (LDS-limited, at most 32 waves per
+    CU, CUs / 8 per XCD), when the lattice is more than 2S tiles wide, else
+    row-major (0)."""
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    seen = set()
+    for n, storage in ((1024, "f32"), (2048, "f32"), (4096, "f32"), (2048, "f64"), (4096, "f16"), (6144, "f32")):
+        b = {"f64": 8, "f32": 4, "f16": 2}[storage]
+        extra = dict(rho_ref=(1.0, 0.0)) if storage == "f16" else {}
+        cfg = lbrd.make_config(n, n, 2, tau=workloads.GS_TAU, storage=storage, reaction="gray_scott",
+                               F=workloads.GS_F, k=workloads.GS_K, **extra)
+        s = lbrd.Solver(cfg)
+        t = s.tuning()
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+        h = t.fused_steps - 1
+        ew = t.tile_cols + 2 * h
+        stride = 9 * 2 * ew + (ew - 9 * 2 * ew) % (256 // b)
+        lds = (t.tile_rows + 2 * h) * stride * b
+        per_cu = max(1, min(160 * 1024 // lds, 32 // t.waves))
+        strip = max(1, per_cu * max(1, cus // 8) // 2)
+        want = strip if -(-n // t.tile_cols) > 2 * strip else 0
+        log(f"{n}^2 {storage}: T {t.fused_steps}, {t.tile_cols} x {t.tile_rows}, tile_strip {t.tile_strip}")
+        assert t.tile_strip == want, (n, storage, t.as_dict())
+        seen.add(t.tile_strip > 0)
+    assert seen == {True, False}
 
 
 @pytest.mark.parametrize("ts,cols,rows,graph", [(3, 64, 8, 8), (5, 32, 10, 12), (7, 32, 12, 30), (8, 64, 14, 16)])
