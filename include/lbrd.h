@@ -129,9 +129,13 @@ typedef struct lbrd_config {
  *       T steps per launch on tile_cols x tile_rows tiles staged in LDS
  *       (temporal blocking; a remainder of 2 .. T-1 steps runs as one shorter
  *       launch on the same tiles, a single remaining step as a one-step
- *       launch).  Results are bitwise identical for every setting.
+ *       launch).  Results are bitwise identical for every setting.  Multi-step
+ *       launches need each plane (one population of one species, pitch x ny
+ *       values plus padding) below 4 GiB and a row below 16 MiB; a buffer of
+ *       4 GiB or more is then addressed plane by plane.  Otherwise only
+ *       fused_steps = 1 is valid (64-bit offsets).
  *  tile_rows, tile_cols: multi-step tile, rows 1..64 and columns 32, 64 or 128
- *       (0 = 64).
+ *       (0 = 64; 128 only for buffers below 4 GiB).
  *       With h = T-1 and w = tile_cols + 2h, the LDS region of tile_rows + 2h
  *       rows of 9 N w populations (each row padded by fewer than 256 bytes)
  *       must fit in 160 KB.  Ignored when fused_steps = 1.

@@ -152,7 +152,10 @@ GridT make_gridT(const Layout &L, const void *src, void *dst, int tw, int th, in
     g.xcd_order = 1;
     g.strip = g.ntx;
     g.steps = steps;
-    g.bytes = L.buf_bytes < ((size_t)1 << 32) ? (uint32_t)L.buf_bytes : 0;   // 0: too large, launch refused
+    // a buffer of 4 GiB or more is addressed plane by plane (0: no launch)
+    g.bytes = L.buf_bytes < ((size_t)1 << 32) ? (uint32_t)L.buf_bytes : 0;
+    const uint64_t plane = (uint64_t)L.pstride * (uint64_t)L.esize;
+    g.plane_bytes = plane < ((uint64_t)1 << 32) ? (uint32_t)plane : 0;
     g.nt_store = 0;
     return g;
 }
@@ -375,9 +378,11 @@ int stage_host(lbrd_solver *h, const void *host, size_t bytes, const void **dev)
     return LBRD_OK;
 }
 
-// The multi-step kernel addresses a buffer with 32-bit byte offsets.
+// The multi-step kernel addresses a buffer, or each plane of a buffer of
+// 4 GiB or more, with 32-bit byte offsets.
+bool big_buffers(const lbrd_solver *h) { return h->L.buf_bytes >= ((size_t)1 << 32); }
 bool multi_step_possible(const lbrd_solver *h) {
-    return h->L.buf_bytes < ((size_t)1 << 32) &&
+    return (uint64_t)h->L.pstride * (uint64_t)h->L.esize < ((uint64_t)1 << 32) &&
            (int64_t)h->L.pitch * storage_bytes(h->cfg.storage) < ((int64_t)1 << 24);
 }
 
@@ -418,6 +423,7 @@ bool tuning_valid(const lbrd_solver *h, const lbrd_tuning &t) {
     if (!multi_step_possible(h)) return false;
     if (t.fused_steps < 2 || t.fused_steps > kMaxFusedSteps) return false;
     if (t.tile_rows < 1 || t.tile_rows > 64) return false;
+    if (big_buffers(h) && t.tile_cols == 128) return false;   // plane-by-plane launches: 32 or 64 wide
     return stepT_shape_fits(h->cfg.storage, h->cfg.nspecies, t.tile_cols, t.tile_rows, t.fused_steps, t.waves);
 }
 
@@ -516,7 +522,8 @@ int lbrd_create(const lbrd_config *cfg, void *workspace, size_t bytes, void *str
     // not fit in LDS first loses rows (down to 4), then steps per launch.
     // Cached loads, streaming stores beyond the Infinity Cache (4 % faster at
     // 4096^2; 40 % slower inside it), consecutive tiles on one XCD (each
-    // measured best).  Buffers of 4 GiB or more keep one-step launches.
+    // measured best).  Buffers of 4 GiB or more are addressed plane by plane
+    // (planes below 4 GiB; else one-step launches, 64-bit offsets).
     const bool in_cache = 2 * h->L.buf_bytes <= ((size_t)256 << 20);
     const int site_bytes = 9 * h->cfg.nspecies * storage_bytes(h->cfg.storage);
     const bool cheap = h->cfg.nspecies == 1;

@@ -29,9 +29,10 @@ bool step_shape_valid(int storage, int vec, int lanes_x, int waves) {
 hipError_t launch_stepT(const StepLaunch &sl, const GridT &g, const void *params, hipStream_t st) {
     if (g.ntiles <= 0) return hipSuccess;
     if (g.src == g.dst) return hipErrorInvalidValue;   // the step is never in place (ping-pong buffers)
-    // 32-bit byte offsets: the whole buffer below 4 GiB, a row pitch below
-    // 16 MiB (24-bit multiplies)
-    if ((int64_t)g.pitch * storage_bytes(sl.storage) >= (1 << 24) || g.bytes == 0) return hipErrorInvalidValue;
+    // 32-bit byte offsets: the whole buffer or each plane below 4 GiB, a row
+    // pitch below 16 MiB (24-bit multiplies)
+    if ((int64_t)g.pitch * storage_bytes(sl.storage) >= (1 << 24) || (g.bytes == 0 && g.plane_bytes == 0))
+        return hipErrorInvalidValue;
     switch (sl.storage) {
         case kF64: return launch_stepT_f64(sl, g, params, st);
         case kF32: return launch_stepT_f32(sl, g, params, st);

@@ -514,13 +514,32 @@ __device__ __forceinline__ void put_lds(typename Traits<ST>::T *L, int lx, int l
     }
 }
 
-// Geometry of one lattice as the multi-step tile reads it.
+// Geometry of one lattice as the multi-step tile reads it.  A buffer below
+// 4 GiB is one buffer resource, the plane selected by the wave-uniform
+// offset; a larger one (BIG) is addressed plane by plane, each plane below
+// 4 GiB its own resource from the 64-bit base pointer.
 struct TileT {
     __amdgpu_buffer_rsrc_t src, dst;
     int nx, ny, th;
     uint32_t pitch_b, pstride_b;   // row and plane strides in bytes
     int nt_store;                  // 1: streaming stores of the result (working set beyond the caches)
+    const char *src_p;             // BIG: base pointers, plane stride and plane bytes
+    char *dst_p;
+    uint64_t pstride_64;
+    uint32_t plane_b;
 };
+
+// Value of plane P at byte offset voff + soff from the plane's origin.
+template <class T, bool BIG>
+__device__ __forceinline__ T tile_load(const TileT &g, int P, uint32_t voff, uint32_t soff) {
+    if constexpr (BIG) return buf_load<T>(buffer_rsrc(g.src_p + (uint64_t)P * g.pstride_64, g.plane_b), voff, soff);
+    else return buf_load<T>(g.src, voff, (uint32_t)P * g.pstride_b + soff);
+}
+template <class T, bool BIG, bool NT = false>
+__device__ __forceinline__ void tile_store(const TileT &g, int P, uint32_t voff, T v) {
+    if constexpr (BIG) buf_store<T, NT>(buffer_rsrc(g.dst_p + (uint64_t)P * g.pstride_64, g.plane_b), voff, 0u, v);
+    else buf_store<T, NT>(g.dst, voff, (uint32_t)P * g.pstride_b, v);
+}
 
 // Middle phase J of a multi-step tile: the region shrunk by J-1 on every
 // side, read in the form phase J-1 wrote and written in the other one.
@@ -558,7 +577,7 @@ __device__ __forceinline__ void stepT_middles(const Params<typename Traits<ST>::
 
 // Last phase of a multi-step tile: pull from LDS (form B when the previous
 // phase was even), collide on the tile itself, store to the destination.
-template <int ST, int V, int TW, int H, bool FROM_B>
+template <int ST, int V, int TW, int H, bool FROM_B, bool BIG>
 __device__ __forceinline__ void stepT_last(const TileT &g, const Params<typename Traits<ST>::C> &p,
                                            const typename Traits<ST>::T *L, int x0, int y0, int nthr) {
     using T = typename Traits<ST>::T;
@@ -579,13 +598,12 @@ __device__ __forceinline__ void stepT_last(const TileT &g, const Params<typename
 #pragma unroll
                 for (int s = 0; s < NS; ++s)
 #pragma unroll
-                    for (int i = 0; i < 9; ++i)
-                        buf_store<T, true>(g.dst, off, (uint32_t)(s * 9 + i) * g.pstride_b, o[s][i]);
+                    for (int i = 0; i < 9; ++i) tile_store<T, BIG, true>(g, s * 9 + i, off, o[s][i]);
             } else {
 #pragma unroll
                 for (int s = 0; s < NS; ++s)
 #pragma unroll
-                    for (int i = 0; i < 9; ++i) buf_store<T>(g.dst, off, (uint32_t)(s * 9 + i) * g.pstride_b, o[s][i]);
+                    for (int i = 0; i < 9; ++i) tile_store<T, BIG>(g, s * 9 + i, off, o[s][i]);
             }
         }
     }
@@ -605,9 +623,9 @@ __device__ __forceinline__ void stepT_last(const TileT &g, const Params<typename
 // site runs the arithmetic of the one-step kernel on the same encoded inputs,
 // so the result is bitwise identical to m one-step launches.  m = TS unless
 // VARM, where 1 <= m <= TS is a workgroup-uniform runtime count (m = 1 reads
-// and writes the buffers directly).  Byte offsets are 32-bit: the buffer
-// spans less than 4 GiB.
-template <int ST, int V, int TS, int TW, bool VARM>
+// and writes the buffers directly).  Byte offsets are 32-bit: within the
+// buffer, or within a plane when BIG.
+template <int ST, int V, int TS, int TW, bool VARM, bool BIG = false>
 __device__ __forceinline__ void stepT_tile(const TileT &g, const Params<typename Traits<ST>::C> &p, int x0, int y0,
                                            int m, typename Traits<ST>::T *L) {
     using T = typename Traits<ST>::T;
@@ -634,15 +652,13 @@ __device__ __forceinline__ void stepT_tile(const TileT &g, const Params<typename
                 for (int s = 0; s < NS; ++s)
 #pragma unroll
                     for (int i = 0; i < 9; ++i)
-                        f[s][i] = decode_dev<ST>(
-                            buf_load<T>(g.src, ry[1 - kEy[i]] + cx[1 - kEx[i]], (uint32_t)(s * 9 + i) * g.pstride_b));
+                        f[s][i] = decode_dev<ST>(tile_load<T, BIG>(g, s * 9 + i, ry[1 - kEy[i]] + cx[1 - kEx[i]], 0u));
                 T o[NS][9];
                 collide_site<ST, V>(p, f, o, gy);
 #pragma unroll
                 for (int s = 0; s < NS; ++s)
 #pragma unroll
-                    for (int i = 0; i < 9; ++i)
-                        buf_store<T>(g.dst, ry[1] + cx[1], (uint32_t)(s * 9 + i) * g.pstride_b, o[s][i]);
+                    for (int i = 0; i < 9; ++i) tile_store<T, BIG>(g, s * 9 + i, ry[1] + cx[1], o[s][i]);
             }
         }
         return;
@@ -664,8 +680,8 @@ __device__ __forceinline__ void stepT_tile(const TileT &g, const Params<typename
             for (int s = 0; s < NS; ++s)
 #pragma unroll
                 for (int i = 0; i < 9; ++i)
-                    f[s][i] = decode_dev<ST>(buf_load<T>(
-                        g.src, rel, (uint32_t)(s * 9 + i) * g.pstride_b + base - kEy[i] * g.pitch_b - kEx[i] * B));
+                    f[s][i] = decode_dev<ST>(
+                        tile_load<T, BIG>(g, s * 9 + i, rel, base - kEy[i] * g.pitch_b - kEx[i] * B));
             T o[NS][9];
             collide_site<ST, V>(p, f, o, y0 - H + ey);
             put_lds<ST, NS, EW, false>(L, ex, ey, o);
@@ -701,8 +717,7 @@ __device__ __forceinline__ void stepT_tile(const TileT &g, const Params<typename
             for (int s = 0; s < NS; ++s)
 #pragma unroll
                 for (int i = 0; i < 9; ++i)
-                    f[s][i] = decode_dev<ST>(
-                        buf_load<T>(g.src, ry[1 - kEy[i]] + cx[1 - kEx[i]], (uint32_t)(s * 9 + i) * g.pstride_b));
+                    f[s][i] = decode_dev<ST>(tile_load<T, BIG>(g, s * 9 + i, ry[1 - kEy[i]] + cx[1 - kEx[i]], 0u));
             T o[NS][9];
             collide_site<ST, V>(p, f, o, gy);
             put_lds<ST, NS, EW, false>(L, ex, ey, o);
@@ -722,15 +737,16 @@ __device__ __forceinline__ void stepT_tile(const TileT &g, const Params<typename
     stepT_middles<ST, V, TS, EW, 2, VARM>(p, L, eh, nthr, m, y0 - H, ny);
     // last phase: step t+m-1 -> t+m on the tile, to the destination buffer
     if (m & 1)
-        stepT_last<ST, V, TW, H, true>(g, p, L, x0, y0, nthr);
+        stepT_last<ST, V, TW, H, true, BIG>(g, p, L, x0, y0, nthr);
     else
-        stepT_last<ST, V, TW, H, false>(g, p, L, x0, y0, nthr);
+        stepT_last<ST, V, TW, H, false, BIG>(g, p, L, x0, y0, nthr);
     __syncthreads();   // LDS is reused by the next tile
 }
 
 // TS steps per launch over one lattice: one workgroup per tile (or a
-// persistent grid walking the tiles).
-template <int ST, int V, int TS, int TW>
+// persistent grid walking the tiles).  BIG: buffers of 4 GiB or more,
+// addressed plane by plane.
+template <int ST, int V, int TS, int TW, bool BIG>
 __global__ __launch_bounds__(1024) void k_stepT(GridT g, Params<typename Traits<ST>::C> p) {
     using T = typename Traits<ST>::T;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -743,16 +759,20 @@ __global__ __launch_bounds__(1024) void k_stepT(GridT g, Params<typename Traits<
     t.pitch_b = (uint32_t)g.pitch * (uint32_t)sizeof(T);
     t.pstride_b = (uint32_t)g.pstride * (uint32_t)sizeof(T);
     t.nt_store = g.nt_store;
+    t.src_p = static_cast<const char *>(g.src);
+    t.dst_p = static_cast<char *>(g.dst);
+    t.pstride_64 = (uint64_t)g.pstride * sizeof(T);
+    t.plane_b = g.plane_bytes;
     const int b0 = g.xcd_order ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     // tiles in strips of g.strip tile columns (g.ntx: plain row-major),
     // row-major inside a strip, the last strip possibly narrower; a launch
-    // has fewer than 2^31 tiles (its buffers are below 4 GiB)
+    // has fewer than 2^31 tiles (each plane is below 4 GiB)
     const int per = g.strip * g.nty;
     for (int tile = b0; tile < (int)g.ntiles; tile += gridDim.x) {
         const int si = tile / per, r = tile - si * per;
         const int sw = min(g.strip, g.ntx - si * g.strip);
         const int ty = r / sw, tx = si * g.strip + (r - ty * sw);
-        stepT_tile<ST, V, TS, TW, false>(t, p, tx * TW, ty * g.th, TS, reinterpret_cast<T *>(smem));
+        stepT_tile<ST, V, TS, TW, false, BIG>(t, p, tx * TW, ty * g.th, TS, reinterpret_cast<T *>(smem));
     }
 }
 

@@ -104,7 +104,8 @@ struct GridT {
     int xcd_order;
     int strip;        // tiles in strips of this many tile columns (ntx: row-major order)
     int steps;        // 2 .. kMaxFusedSteps
-    uint32_t bytes;   // bytes of one buffer (less than 4 GiB)
+    uint32_t bytes;   // bytes of one buffer below 4 GiB, else 0 (addressed plane by plane)
+    uint32_t plane_bytes;   // bytes of one plane (pstride elements, below 4 GiB)
     int nt_store;     // 1: streaming (non-temporal) stores of the result
 };
 

@@ -55,14 +55,14 @@ inline hipError_t launch_step_s(const StepLaunch &sl, const Grid &g, const void 
     }
 }
 
-template <int ST, int V, int TS, int TW>
+template <int ST, int V, int TS, int TW, bool BIG>
 inline hipError_t launch_stepT_t(const StepLaunch &sl, const GridT &g, const void *params, hipStream_t st) {
     using C = typename Traits<ST>::C;
     const Params<C> &p = *static_cast<const Params<C> *>(params);
     const size_t lds = stepT_lds_bytes(ST, NSpecies<V>::value, TW, g.th, TS);
     static bool attr_set = false;   // per instantiation: allow more than 64 KB of LDS
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_stepT<ST, V, TS, TW>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_stepT<ST, V, TS, TW, BIG>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
         attr_set = true;
@@ -70,21 +70,21 @@ inline hipError_t launch_stepT_t(const StepLaunch &sl, const GridT &g, const voi
     int64_t nb = g.ntiles;
     if (g.blocks > 0 && g.blocks < nb) nb = g.blocks;
     if (nb > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_stepT<ST, V, TS, TW>), dim3((unsigned)nb), dim3(64 * sl.waves), lds, st, g, p);
+    hipLaunchKernelGGL((k_stepT<ST, V, TS, TW, BIG>), dim3((unsigned)nb), dim3(64 * sl.waves), lds, st, g, p);
     return hipGetLastError();
 }
 
-template <int ST, int V, int TW>
+template <int ST, int V, int TW, bool BIG>
 inline hipError_t launch_stepT_n(const StepLaunch &sl, const GridT &g, const void *params, hipStream_t st) {
     static_assert(kMaxFusedSteps == 8, "instantiate every step count");
     switch (g.steps) {
-        case 2: return launch_stepT_t<ST, V, 2, TW>(sl, g, params, st);
-        case 3: return launch_stepT_t<ST, V, 3, TW>(sl, g, params, st);
-        case 4: return launch_stepT_t<ST, V, 4, TW>(sl, g, params, st);
-        case 5: return launch_stepT_t<ST, V, 5, TW>(sl, g, params, st);
-        case 6: return launch_stepT_t<ST, V, 6, TW>(sl, g, params, st);
-        case 7: return launch_stepT_t<ST, V, 7, TW>(sl, g, params, st);
-        case 8: return launch_stepT_t<ST, V, 8, TW>(sl, g, params, st);
+        case 2: return launch_stepT_t<ST, V, 2, TW, BIG>(sl, g, params, st);
+        case 3: return launch_stepT_t<ST, V, 3, TW, BIG>(sl, g, params, st);
+        case 4: return launch_stepT_t<ST, V, 4, TW, BIG>(sl, g, params, st);
+        case 5: return launch_stepT_t<ST, V, 5, TW, BIG>(sl, g, params, st);
+        case 6: return launch_stepT_t<ST, V, 6, TW, BIG>(sl, g, params, st);
+        case 7: return launch_stepT_t<ST, V, 7, TW, BIG>(sl, g, params, st);
+        case 8: return launch_stepT_t<ST, V, 8, TW, BIG>(sl, g, params, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -92,10 +92,19 @@ inline hipError_t launch_stepT_n(const StepLaunch &sl, const GridT &g, const voi
 template <int ST, int V>
 inline hipError_t launch_stepT_w(const StepLaunch &sl, const GridT &g, const void *params, hipStream_t st) {
     if (!stepT_shape_fits(ST, NSpecies<V>::value, g.tw, g.th, g.steps, sl.waves)) return hipErrorInvalidValue;
+    if (g.bytes == 0) {
+        // buffers of 4 GiB or more, planes below it: tiles 32 or 64 wide
+        if (g.plane_bytes == 0) return hipErrorInvalidValue;
+        switch (g.tw) {
+            case 32: return launch_stepT_n<ST, V, 32, true>(sl, g, params, st);
+            case 64: return launch_stepT_n<ST, V, 64, true>(sl, g, params, st);
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (g.tw) {
-        case 32: return launch_stepT_n<ST, V, 32>(sl, g, params, st);
-        case 64: return launch_stepT_n<ST, V, 64>(sl, g, params, st);
-        case 128: return launch_stepT_n<ST, V, 128>(sl, g, params, st);
+        case 32: return launch_stepT_n<ST, V, 32, false>(sl, g, params, st);
+        case 64: return launch_stepT_n<ST, V, 64, false>(sl, g, params, st);
+        case 128: return launch_stepT_n<ST, V, 128, false>(sl, g, params, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -575,23 +575,29 @@ def test_gray_scott_4096_sampled_windows(storage, quant):
         assert np.all(err <= fmt)
 
 
-@pytest.mark.parametrize("n,multi", [(7680, True), (8192, False)])
-def test_largest_lattices_sampled_windows(n, multi):
-    """The size limits of the two kernel families, FP32 Gray-Scott: at 7680^2
-    each buffer is just under 4 GiB, the largest the multi-step kernel's
-    32-bit byte offsets address, and the default launch uses it; at 8192^2 a
-    buffer exceeds 4 GiB and the default falls back to the one-step kernel
-    (64-bit offsets).  26 steps (ragged against four per launch); sampled
-    windows touching the first and last rows and columns against the FP64
-    oracle within 1e-5."""
+@pytest.mark.parametrize("n,small,fused", [(7680, True, None), (8192, False, None), (8192, False, 1)])
+def test_largest_lattices_sampled_windows(n, small, fused):
+    """The addressing limits of the kernels, FP32 Gray-Scott: at 7680^2 each
+    buffer is just under 4 GiB, the largest one buffer resource with 32-bit
+    byte offsets covers; at 8192^2 a buffer exceeds 4 GiB and the default
+    multi-step launch addresses it plane by plane (each plane 256 MiB); the
+    one-step kernel (64-bit offsets) is forced there too.  26 steps (ragged
+    against the steps per launch); sampled windows touching the first and
+    last rows and columns against the FP64 oracle within 1e-5."""
     steps = 26
     rho0 = workloads.gray_scott_square(n, n, seed=3)
     kw = dict(F=workloads.GS_F, k=workloads.GS_K)
     cfg = lbrd.make_config(n, n, 2, storage="f32", tau=workloads.GS_TAU, reaction="gray_scott", **kw)
-    assert (lbrd.workspace_size(cfg) // 2 < (1 << 32)) == multi
+    assert (lbrd.workspace_size(cfg) // 2 < (1 << 32)) == small
     s = lbrd.Solver(cfg)
     try:
-        assert (s.tuning().fused_steps >= 2) == multi
+        t = s.tuning()
+        assert t.fused_steps >= 2 and t.tile_cols in (32, 64), t.as_dict()
+        if not small:
+            with pytest.raises(lbrd.LbrdError):   # 128-wide tiles need buffers below 4 GiB
+                s.set_tuning(tile_cols=128, tile_rows=4, fused_steps=4)
+        if fused is not None:
+            s.set_tuning(fused_steps=fused)
         s.init(rho0).step(steps)
         rho, mass = s.moments()
         rho = rho.cpu().numpy()
@@ -605,9 +611,42 @@ def test_largest_lattices_sampled_windows(n, multi):
         gots.append(rho[:, ys][:, :, xs])
         refs.append(ref)
     err = oracle.rel_l2(np.concatenate(gots, axis=2), np.concatenate(refs, axis=2))
-    log(f"{n}^2 f32 ({'multi-step' if multi else 'one-step'}) sampled vs FP64: {err}")
+    log(f"{n}^2 f32 ({'one-step' if fused == 1 else 'multi-step'}) sampled vs FP64: {err}")
     assert np.all(err <= 1e-5)
     assert np.all(np.isfinite(mass))
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_plane_addressed_multi_step_is_bitwise_identical(storage):
+    """Buffers of 4 GiB or more (8192^2 FP32; 12288^2 F16 with two species):
+    the multi-step launch that addresses each plane with its own 32-bit
+    resource equals one-step launches (64-bit offsets) bitwise on every
+    population, default shape and a 64-wide one, 2..T-1 remainders included."""
+    n = 8192 if storage == "f32" else 12288
+    extra = dict(rho_ref=(1.0, 0.0)) if storage == "f16" else {}
+    cfg = lbrd.make_config(n, n, 2, storage=storage, tau=workloads.GS_TAU, reaction="gray_scott",
+                           F=workloads.GS_F, k=workloads.GS_K, **extra)
+    assert lbrd.workspace_size(cfg) // 2 >= (1 << 32)
+    rho0 = workloads.gray_scott_square(n, n, seed=5)
+    s = lbrd.Solver(cfg)
+    try:
+        d = s.tuning()
+        assert d.fused_steps >= 2
+        s.set_tuning(fused_steps=1, graph_steps=0)
+        s.init(rho0).step(11)
+        want = s.get_populations(dtype=torch.float32)
+        for T, cols, rows in ((d.fused_steps, d.tile_cols, d.tile_rows), (4, 64, 8)):
+            s.set_tuning(fused_steps=T, tile_cols=cols, tile_rows=rows, tile_strip=d.tile_strip)
+            s.init(rho0).step(11)
+            got = s.get_populations(dtype=torch.float32)
+            assert torch.equal(got, want), (storage, T, cols, rows)
+            del got
+        log(f"{n}^2 {storage}: plane-addressed multi-step ({d.fused_steps}, {d.tile_cols} x {d.tile_rows}) "
+            f"bitwise equal to one-step launches")
+    finally:
+        s.close()
+        del s
+        torch.cuda.empty_cache()
 
 
 # ----- several steps per launch (temporal blocking) -------------------------
