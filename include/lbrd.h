@@ -118,7 +118,9 @@ typedef struct lbrd_config {
  *  nontemporal: 1 = streaming (non-temporal) accesses: loads and stores of
  *       one-step launches, the result stores of multi-step launches.
  *  graph_steps: steps per captured HIP graph (0 = plain launches; else even;
- *       batches with T steps per launch: a multiple of 2T).
+ *       batches with T steps per launch: a multiple of 2T).  Single solvers
+ *       default to 32 for one-step launches on lattices of at most 2^18
+ *       sites, else 0.
  *  blocks_per_cu: persistent workgroups per compute unit.  Batches: 1..32
  *       (one-step) or 0..32 (multi-step, 0 = one workgroup per tile).
  *       Single solvers: 0 = one tile per wave / workgroup, else 1..64 looping
@@ -236,10 +238,12 @@ int lbrd_set_tuning(lbrd_solver *h, const lbrd_tuning *t);
 
 /* Time every valid launch shape on this solver's buffers for about `steps`
  * steps each (whole launches, at least about 1 ms, compared per step; each
- * multi-step shape with the tile_strip lbrd_create would give it), then
- * re-time with runs of about 10 ms the six fastest, the shape in use and the
- * three fastest multi-step shapes with the other XCD order and with the other
- * strip choice (strips or row-major), and keep the fastest of those; writes it to *chosen if not NULL.  The shapes are timed
+ * multi-step shape with the tile_strip lbrd_create would give it, plain
+ * launches), then re-time with runs of about 10 ms the six fastest, the shape
+ * in use and the three fastest multi-step shapes with the other XCD order and
+ * with the other strip choice (strips or row-major), keep the fastest of
+ * those, and finally keep or drop captured graphs of 32 steps on it, whichever
+ * is faster; writes the choice to *chosen if not NULL.  The shapes are timed
  * on the solver's own state when it is initialised, else on a scrambled field
  * of densities in [0.5, 1); either way the state is overwritten: the solver
  * must be (re)initialised afterwards (ESTATE until then).  cache_path: text

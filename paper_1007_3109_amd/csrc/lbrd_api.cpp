@@ -492,7 +492,7 @@ int lbrd_create(const lbrd_config *cfg, void *workspace, size_t bytes, void *str
     h->tune.vec = default_vec(h->cfg.storage);
     h->tune.lanes_x = default_lanes(h->cfg.nx, h->tune.vec);
     h->tune.waves = 4;
-    h->tune.graph_steps = ((int64_t)h->cfg.nx * h->cfg.ny <= (1 << 18)) ? 32 : 0;
+    const int64_t sites = (int64_t)h->cfg.nx * h->cfg.ny;
     if (2 * h->L.buf_bytes > ((size_t)256 << 20)) {
         // one-step launches (odd remainders) beyond the 256 MB Infinity
         // Cache: streaming accesses and the shapes measured fastest on
@@ -538,6 +538,18 @@ int lbrd_create(const lbrd_config *cfg, void *workspace, size_t bytes, void *str
     } else {
         ts0 = 6; cols = 32; rows0 = 16;
     }
+    // Small lattices are bound by the latency of a launch, not by a
+    // throughput: more steps per launch on tiles small enough to give most
+    // CUs one (per step against the table above: 64^2 FP64 decay 0.87
+    // against 1.17 us, 128^2 FP32 Gray-Scott 1.03 against 1.38, 128^2 FP64
+    // Gray-Scott 1.31 against 2.12, 256^2 1.22 against 1.48, 384^2 1.76
+    // against 2.20, 512^2 2.32 against 2.65).
+    if (in_cache && sites <= 512 * 512) {
+        if (sites <= 128 * 128) { ts0 = 8; cols = 32; rows0 = 4; }
+        else if (sites <= 256 * 256) { ts0 = 8; cols = 32; rows0 = 8; }
+        else if (sites <= 384 * 384) { ts0 = 7; cols = 32; rows0 = 20; }
+        else { ts0 = 7; cols = 64; rows0 = 16; }
+    }
     h->tune.tile_cols = cols;
     h->tune.tile_rows = rows0;
     h->tune.fused_steps = 1;
@@ -555,6 +567,11 @@ int lbrd_create(const lbrd_config *cfg, void *workspace, size_t bytes, void *str
                     }
         if (h->tune.fused_steps > 1) h->tune.tile_strip = default_strip(h, h->tune);
     }
+    // Captured graphs pay where one-step launches on a small lattice are
+    // bound by the host's launch rate; multi-step launches keep the GPU busy
+    // longer than a launch takes (plain launches measured 4-10 % faster on
+    // 64^2 to 512^2 lattices).
+    h->tune.graph_steps = h->tune.fused_steps == 1 && sites <= (1 << 18) ? 32 : 0;
     *out = h;
     return LBRD_OK;
 }
@@ -805,7 +822,7 @@ int lbrd_autotune(lbrd_solver *h, int steps, const char *cache_path, lbrd_tuning
                             t.plain_order = order;
                             t.blocks_per_cu = bpc;
                             t.fused_steps = 1;
-                            t.graph_steps = h->tune.graph_steps;
+                            t.graph_steps = 0;
                             if (tuning_valid(h, t)) cands.push_back(t);
                         }
     }
@@ -826,6 +843,7 @@ int lbrd_autotune(lbrd_solver *h, int steps, const char *cache_path, lbrd_tuning
                             t.tile_rows = rows;
                             t.tile_cols = cols;
                             t.tile_strip = 0;
+                            t.graph_steps = 0;
                             if (!tuning_valid(h, t)) continue;
                             t.tile_strip = default_strip(h, t);
                             cands.push_back(t);
@@ -852,9 +870,7 @@ int lbrd_autotune(lbrd_solver *h, int steps, const char *cache_path, lbrd_tuning
     // milliseconds per step of one candidate (whole launches only, running
     // for at least min_ms), or +inf
     auto time_one = [&](const lbrd_tuning &t, double min_ms) {
-        lbrd_tuning tt = t;
-        tt.graph_steps = 0;
-        if (lbrd_set_tuning(h, &tt) != LBRD_OK) return 1e300;
+        if (lbrd_set_tuning(h, &t) != LBRD_OK) return 1e300;
         double ms = 0;
         const int per = std::max(1, (int)t.fused_steps);
         int n = (steps + per - 1) / per * per;
@@ -902,6 +918,10 @@ int lbrd_autotune(lbrd_solver *h, int steps, const char *cache_path, lbrd_tuning
             best_t = t;
         }
     }
+    // the winner with captured graphs of 32 steps, or without them
+    lbrd_tuning flip = best_t;
+    flip.graph_steps = best_t.graph_steps ? 0 : 32;
+    if (time_one(flip, 10.0) < best) best_t = flip;
     lbrd_set_tuning(h, &best_t);
     h->initialised = false;
     h->t = 0;
