@@ -88,6 +88,15 @@ __device__ __forceinline__ typename Traits<ST>::T encode(typename Traits<ST>::C 
 template <int ST>
 constexpr bool kShifted = ST == kF16 || ST == kBF16;
 
+// acc + h in FP32 (one rounding; h converts exactly), reading the binary16
+// operand directly: one mixed-precision multiply-add by 1.0 instead of a
+// conversion and an add.  The population sums of the 16-bit form take it.
+__device__ __forceinline__ float add_half(float acc, _Float16 h) {
+    float r;
+    asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(h), "v"(acc));
+    return r;
+}
+
 // Stored value <-> deviation d (= f for F64 / F32, f - w_i rho_ref,s for the
 // 16-bit forms).
 template <int ST>
@@ -212,7 +221,10 @@ __device__ __forceinline__ void collide_site(const Params<typename Traits<ST>::C
     for (int s = 0; s < NS; ++s) {
         C acc = f[s][0];
 #pragma unroll
-        for (int i = 1; i < 9; ++i) acc += f[s][i];
+        for (int i = 1; i < 9; ++i) {
+            if constexpr (ST == kF16) acc = add_half(acc, (_Float16)f[s][i]);   // f holds binary16 values
+            else acc += f[s][i];
+        }
         m[s] = acc;
         rho[s] = kShifted<ST> ? acc + p.rho_ref[s] : acc;
     }
