@@ -112,6 +112,30 @@ __device__ __forceinline__ typename Traits<ST>::T encode_dev(typename Traits<ST>
     else return d;
 }
 
+// Two FP32 values rounded to the 16-bit form by one packed conversion
+// (round to nearest even, as two single conversions).
+typedef float float2_v __attribute__((ext_vector_type(2)));
+typedef _Float16 half2_v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf162_v __attribute__((ext_vector_type(2)));
+// The halves are taken from the packed word: bit casts of the vector's
+// elements compiled to one conversion stored twice with this compiler.
+template <int ST>
+__device__ __forceinline__ void encode_pair(float a, float b, uint16_t &oa, uint16_t &ob) {
+    uint32_t u;
+    if constexpr (ST == kF16) u = __builtin_bit_cast(uint32_t, __builtin_convertvector((float2_v){a, b}, half2_v));
+    else u = __builtin_bit_cast(uint32_t, __builtin_convertvector((float2_v){a, b}, bf162_v));
+    oa = (uint16_t)u;
+    ob = (uint16_t)(u >> 16);
+}
+// The 9 NS results of one site, paired in species-major order.
+template <int ST, int NS>
+__device__ __forceinline__ void encode_sites(const float (&r)[NS][9], uint16_t (&o)[NS][9]) {
+#pragma unroll
+    for (int k = 0; k + 1 < 9 * NS; k += 2)
+        encode_pair<ST>(r[k / 9][k % 9], r[(k + 1) / 9][(k + 1) % 9], o[k / 9][k % 9], o[(k + 1) / 9][(k + 1) % 9]);
+    if constexpr ((9 * NS) % 2) o[NS - 1][8] = encode_dev<ST>(r[NS - 1][8]);
+}
+
 // D2Q9 weights w_i (Eq. "Weights") in the compute type.
 template <class C>
 __device__ __forceinline__ constexpr C wgt(int i) {
@@ -217,6 +241,7 @@ __device__ __forceinline__ void collide_site(const Params<typename Traits<ST>::C
     using C = typename Traits<ST>::C;
     constexpr int NS = NSpecies<V>::value;
     C m[NS], rho[NS], R[NS];
+    C res[NS][9];   // 16-bit forms: the FP32 results before rounding
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         C acc = f[s][0];
@@ -253,10 +278,15 @@ __device__ __forceinline__ void collide_site(const Params<typename Traits<ST>::C
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
                 C r = f[s][i] * p.keep[s] + e[i];
-                if constexpr (kShifted<ST>) asm volatile("" : "+v"(r));
-                o[s][i] = encode_dev<ST>(r);
+                if constexpr (kShifted<ST>) {
+                    asm volatile("" : "+v"(r));
+                    res[s][i] = r;
+                } else {
+                    o[s][i] = r;
+                }
             }
         }
+        if constexpr (kShifted<ST>) encode_sites<ST, NS>(res, o);
         return;
     }
 #pragma unroll
@@ -277,10 +307,15 @@ __device__ __forceinline__ void collide_site(const Params<typename Traits<ST>::C
             // the conversion always rounds the float (the compiler may
             // otherwise fold the multiply-add into a mixed-precision
             // instruction that rounds once, differently in different kernels)
-            if constexpr (kShifted<ST>) asm volatile("" : "+v"(r));
-            o[s][i] = encode_dev<ST>(r);
+            if constexpr (kShifted<ST>) {
+                asm volatile("" : "+v"(r));
+                res[s][i] = r;
+            } else {
+                o[s][i] = r;
+            }
         }
     }
+    if constexpr (kShifted<ST>) encode_sites<ST, NS>(res, o);
 }
 
 // ---------------------------------------------------------- step tile --
