@@ -113,22 +113,21 @@ constexpr int kMaxFusedSteps = 8;
 constexpr int kMaxBatchFusedSteps = 8;
 
 GridT make_gridT(const Layout &L, const void *src, void *dst, int tw, int th, int steps);
-// LDS row stride (elements) of the multi-step region of width ew = tw + 2h
-// (tile width tw = 32, 64 or 128, h = T - 1 < 16) with 9 N planes of
-// `bytes`-byte elements: 9 N ew rounded up so that stride - w is a multiple
-// of 256 bytes (64 banks of 4 bytes) for w = ew - 2 floor(h / 2), the width
-// of the middle one of the shrunk middle regions.  Consecutive sites of a
-// region of width w in row-major order then fall in consecutive banks even
-// where a wave wraps to the next row; the other middle phases and phase 1
-// (width ew) skip a few banks at a wrap, the last phase (width tw, 32 or
-// more lanes to a row) never wraps inside a half wave.  Against padding for
-// ew: the same LDS bytes within 256 per row, 1.2 % faster at 1024^2 FP32
-// Gray-Scott (T = 5 on 32 x 10), unchanged at 4096^2.
+// LDS row stride (elements) of the multi-step region of width ew with 9 N
+// planes of `bytes`-byte elements: 9 N ew rounded up so that stride - w is a
+// multiple of 256 bytes (64 banks of 4 bytes) for w = ew - 2, the width of
+// the first (largest) shrunk middle region.  Consecutive sites of that
+// region in row-major order then fall in consecutive banks even where a wave
+// wraps to the next row; the later middle phases and phase 1 (width ew) skip
+// a few banks at a wrap, the last phase (32 or more lanes to a tile row)
+// never wraps inside a half wave.  Measured against padding for ew, ew - 4
+// and ew - 6 in alternating runs: 1024^2 FP32 Gray-Scott (T = 5 on 32 x 10)
+// 32.9 against 33.6, 33.1 and 33.1 us per launch; 4096^2 FP32 and F16 equal
+// or slower with the others.
 __host__ __device__ constexpr int stepT_row_stride(int nspecies, int ew, int bytes) {
     const int unit = 256 / bytes;
     const int base = 9 * nspecies * ew;
-    const int tw = ew >= 128 ? 128 : (ew >= 64 ? 64 : 32);
-    const int w = ew - 2 * ((ew - tw) / 2 / 2);
+    const int w = ew - 2;
     return base + ((w - base) % unit + unit) % unit;
 }
 constexpr size_t kLdsBytes = (size_t)160 * 1024;   // LDS of one CU

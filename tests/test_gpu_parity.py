@@ -661,13 +661,13 @@ def multi_step_shape_fits(b, ns, cols, rows, steps, waves):
     """The documented limits of a multi-step launch shape: 32, 64 or 128 columns;
     the LDS region of rows + 2h rows (h = steps - 1), each row 9 ns (cols + 2h)
     values padded by less than 256 bytes (to a multiple of 256 bytes beyond
-    cols + 2h - 2 floor(h / 2)), within 160 KB."""
+    cols + 2h - 2), within 160 KB."""
     if cols not in (32, 64, 128) or not 2 <= steps <= 8:
         return False
     h = steps - 1
     ew = cols + 2 * h
     unit = 256 // b
-    w = ew - 2 * (h // 2)                       # the row stride is padded for this width
+    w = ew - 2                                  # the row stride is padded for this width
     stride = 9 * ns * ew + (w - 9 * ns * ew) % unit
     return (rows + 2 * h) * stride * b <= 160 * 1024
 
@@ -784,7 +784,7 @@ def test_default_tile_order():
         torch.cuda.empty_cache()
         h = t.fused_steps - 1
         ew = t.tile_cols + 2 * h
-        stride = 9 * 2 * ew + (ew - 2 * (h // 2) - 9 * 2 * ew) % (256 // b)
+        stride = 9 * 2 * ew + (ew - 2 - 9 * 2 * ew) % (256 // b)
         lds = (t.tile_rows + 2 * h) * stride * b
         per_cu = max(1, min(160 * 1024 // lds, 32 // t.waves))
         strip = max(1, per_cu * max(1, cus // 8) // 2)
