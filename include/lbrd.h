@@ -147,7 +147,8 @@ typedef struct lbrd_config {
  *       tiles above and below one in flight are in flight too and their
  *       shared halo rows are read once from L2.  lbrd_create sets half the
  *       workgroups that one XCD holds at once (from the LDS of the default
- *       shape) when the lattice is wider than twice that many tiles, else 0.
+ *       shape) when the lattice is wider than twice that many tiles (16-bit
+ *       forms: at least twice), else 0.
  *       Results are bitwise identical for every order. */
 typedef struct lbrd_tuning {
     int32_t vec;

@@ -396,7 +396,8 @@ bool multi_step_possible(const lbrd_solver *h) {
 // tile rows of a strip in flight.  Measured per step against row-major:
 // 4096^2 FP32 115 against 128 us, 4096^2 FP64 309 against 347 us, 2048^2
 // FP64 73 against 84 us; 2048^2 FP32 (64 tiles across, within twice S)
-// 2-5 % slower, hence row-major up to 2S tiles across.
+// 2-5 % slower, hence row-major up to 2S tiles across (up to 2S - 1 in
+// the 16-bit forms).
 int strip_width(const lbrd_solver *h, const lbrd_tuning &t) {
     const size_t lds = stepT_lds_bytes(h->cfg.storage, h->cfg.nspecies, t.tile_cols, t.tile_rows, t.fused_steps);
     if (lds == 0 || t.waves < 1) return 1;
@@ -405,8 +406,11 @@ int strip_width(const lbrd_solver *h, const lbrd_tuning &t) {
 }
 int tiles_across(const lbrd_solver *h, const lbrd_tuning &t) { return (h->cfg.nx + t.tile_cols - 1) / t.tile_cols; }
 int default_strip(const lbrd_solver *h, const lbrd_tuning &t) {
-    const int strip = strip_width(h, t);
-    return tiles_across(h, t) > 2 * strip ? strip : 0;
+    // exactly 2S tiles across: strips measured 1-1.3 % faster for the 16-bit
+    // forms (4096^2 on 64 x 20 tiles), 2-5 % slower in FP32 (2048^2, 32 x 12)
+    const int strip = strip_width(h, t), across = tiles_across(h, t);
+    const bool narrow16 = storage_bytes(h->cfg.storage) == 2 && across == 2 * strip;
+    return across > 2 * strip || narrow16 ? strip : 0;
 }
 
 bool tuning_valid(const lbrd_solver *h, const lbrd_tuning &t) {
