@@ -7,7 +7,7 @@
 //   2. advances every resident request by min(chunk, steps left) with a
 //      replayed graph of persistent batched launches (per-slot step limits
 //      live in device descriptors, so the graph is reused across rounds);
-//      rounds of the serving mix advance five steps per launch on LDS tiles;
+//      rounds of the serving mix advance seven steps per launch on LDS tiles;
 //   3. enqueues the density read-out of requests that finish in this round
 //      and records an event;
 //   4. while the GPU works on that round, retires the previous round's
@@ -158,10 +158,13 @@ void mark_busy(lbrd_server *s) {
 int blocks_for(const lbrd_server *s) { return 8 * s->cus; }
 
 // Multi-step rounds (the serving mix, every request below 4 GiB per buffer):
-// five steps per launch on 32 x 10 tiles (on a batch of 40 requests of the
-// serving mix: 160 us per step, against 203 us with four steps on 64 x 4), a
-// persistent grid of 8-wave workgroups, four per CU.
-constexpr int kServeSteps = 5, kServeRows = 10, kServeCols = 32, kServeWaves = 8, kServeBlocksPerCu = 4;
+// seven steps per launch on 32 x 12 tiles, a persistent grid of 8-wave
+// workgroups, four per CU.  On the benchmark's request stream (120 requests,
+// 16 GB pool), in alternating runs: p50 0.42 s, p99 1.61 s and 238 k
+// MLUPS per species while busy, against 0.47 s, 2.0 s and 217 k with five
+// steps on 32 x 10, 0.45 s / 1.77 s / 229 k with six on 32 x 12, and worse
+// with eight on 32 x 8 or seven on 32 x 16.
+constexpr int kServeSteps = 7, kServeRows = 12, kServeCols = 32, kServeWaves = 8, kServeBlocksPerCu = 4;
 
 hipError_t enqueue_chunk(lbrd_server *s, int set, bool multi, hipStream_t st) {
     const int64_t launches = launches_for(s->sc.chunk_steps, multi ? kServeSteps : 1);

@@ -217,8 +217,8 @@ def test_batch_autotune_then_run():
 
 
 def test_server_results_equal_solo_runs():
-    """The serving mix (five steps per launch inside the server's rounds):
-    request lengths that are not multiples of the chunk or of five, including
+    """The serving mix (seven steps per launch inside the server's rounds):
+    request lengths that are not multiples of the chunk or of seven, including
     a single step, equal their solo runs bitwise."""
     cases = serve_mix_cases()
     steps = [130, 64, 300, 1, 77, 250]
