@@ -34,6 +34,20 @@ void set_error(const char *where, hipError_t e) {
 
 static int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
+std::vector<double> scrambled_densities(size_t n) {
+    std::vector<double> rho(n);
+    uint64_t z = 0x9e3779b97f4a7c15ull;
+    for (double &r : rho) {
+        z += 0x9e3779b97f4a7c15ull;   // splitmix64
+        uint64_t x = z;
+        x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+        x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+        x ^= x >> 31;
+        r = 0.5 + 0.5 * (double)(x >> 11) * (1.0 / 9007199254740992.0);
+    }
+    return rho;
+}
+
 // Extra bytes between consecutive planes so that the 9N concurrent streams of
 // a step do not start on the same HBM channel.  LBRD_PLANE_SKEW overrides it.
 static int64_t plane_skew_bytes() {
@@ -380,10 +394,13 @@ int stage_host(lbrd_solver *h, const void *host, size_t bytes, const void **dev)
 
 // The multi-step kernel addresses a buffer, or each plane of a buffer of
 // 4 GiB or more, with 32-bit byte offsets.
+// Row offsets are formed with 24-bit multiplies (row index times row pitch),
+// so rows and pitches must also stay below 2^24.
 bool big_buffers(const lbrd_solver *h) { return h->L.buf_bytes >= ((size_t)1 << 32); }
 bool multi_step_possible(const lbrd_solver *h) {
     return (uint64_t)h->L.pstride * (uint64_t)h->L.esize < ((uint64_t)1 << 32) &&
-           (int64_t)h->L.pitch * storage_bytes(h->cfg.storage) < ((int64_t)1 << 24);
+           (int64_t)h->L.pitch * storage_bytes(h->cfg.storage) < ((int64_t)1 << 24) &&
+           h->L.ny <= (1 << 24);
 }
 
 // Tile order of multi-step launches.  Row-major over a wide lattice puts
@@ -857,17 +874,7 @@ int lbrd_autotune(lbrd_solver *h, int steps, const char *cache_path, lbrd_tuning
     // shapes), so an initialised solver is timed on its own state and an
     // uninitialised one on a scrambled field of densities in [0.5, 1).
     if (!h->initialised) {
-        const size_t sites = (size_t)h->cfg.nx * h->cfg.ny;
-        std::vector<double> rho((size_t)h->cfg.nspecies * sites);
-        uint64_t z = 0x9e3779b97f4a7c15ull;
-        for (double &r : rho) {
-            z += 0x9e3779b97f4a7c15ull;   // splitmix64
-            uint64_t x = z;
-            x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
-            x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
-            x ^= x >> 31;
-            r = 0.5 + 0.5 * (double)(x >> 11) * (1.0 / 9007199254740992.0);
-        }
+        const std::vector<double> rho = scrambled_densities((size_t)h->cfg.nspecies * h->cfg.nx * h->cfg.ny);
         if (int rc = lbrd_init(h, rho.data(), LBRD_DTYPE_F64, 0)) return rc;
     }
     const lbrd_tuning entry = h->tune;   // the shape in use: always a finalist

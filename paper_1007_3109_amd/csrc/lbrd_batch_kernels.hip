@@ -154,13 +154,12 @@ __global__ __launch_bounds__(1024) void k_batch_stepT(const BatchHeader *__restr
 template <int SET, int TS, int TW>
 static hipError_t launch_setT(const BatchHeader *hdr, const BatchInst *inst, int j, int64_t blocks, int waves,
                               size_t lds, hipStream_t st) {
-    static bool attr_set = false;   // per instantiation: allow more than 64 KB of LDS
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch_stepT<SET, TS, TW>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    // per instantiation, once (thread-safe static initialisation): allow more
+    // than 64 KB of LDS
+    static const hipError_t attr = hipFuncSetAttribute(
+        reinterpret_cast<const void *>(&k_batch_stepT<SET, TS, TW>), hipFuncAttributeMaxDynamicSharedMemorySize,
+        160 * 1024);
+    if (attr != hipSuccess) return attr;
     hipLaunchKernelGGL((k_batch_stepT<SET, TS, TW>), dim3((unsigned)blocks), dim3(64 * waves), lds, st, hdr, inst,
                        j);
     return hipGetLastError();
@@ -210,7 +209,9 @@ bool batch_shape_fits(int ts, int rows, int cols, int waves) {
 }
 
 bool batch_multi_ok(const Layout &L, int storage) {
-    return L.buf_bytes < ((size_t)1 << 32) && (int64_t)L.pitch * storage_bytes(storage) < ((int64_t)1 << 24);
+    // 32-bit byte offsets; row offsets from 24-bit multiplies (row x pitch)
+    return L.buf_bytes < ((size_t)1 << 32) && (int64_t)L.pitch * storage_bytes(storage) < ((int64_t)1 << 24) &&
+           L.ny <= (1 << 24);
 }
 
 void set_batch_tiling(BatchInst &bi, const Layout &L, int ts, int rows, int cols) {

@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "lbrd.h"
 
 namespace lbrd {
@@ -245,5 +247,9 @@ void fill_batch_inst(BatchInst &bi, const lbrd_config &c, const Layout &L, const
                      int vec, int lanes_x);
 
 int device_cu_count();
+
+// n densities in [0.5, 1) from a fixed splitmix64 sequence: a stand-in state
+// for timing runs (an all-zero field runs faster than real states).
+std::vector<double> scrambled_densities(size_t n);
 
 }  // namespace lbrd

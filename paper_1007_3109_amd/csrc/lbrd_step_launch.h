@@ -60,13 +60,12 @@ inline hipError_t launch_stepT_t(const StepLaunch &sl, const GridT &g, const voi
     using C = typename Traits<ST>::C;
     const Params<C> &p = *static_cast<const Params<C> *>(params);
     const size_t lds = stepT_lds_bytes(ST, NSpecies<V>::value, TW, g.th, TS);
-    static bool attr_set = false;   // per instantiation: allow more than 64 KB of LDS
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_stepT<ST, V, TS, TW, BIG>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    // per instantiation, once (thread-safe static initialisation): allow more
+    // than 64 KB of LDS
+    static const hipError_t attr = hipFuncSetAttribute(
+        reinterpret_cast<const void *>(&k_stepT<ST, V, TS, TW, BIG>), hipFuncAttributeMaxDynamicSharedMemorySize,
+        160 * 1024);
+    if (attr != hipSuccess) return attr;
     int64_t nb = g.ntiles;
     if (g.blocks > 0 && g.blocks < nb) nb = g.blocks;
     if (nb > 0x7fffffff) return hipErrorInvalidValue;
