@@ -233,6 +233,23 @@ int lbrd_time(const lbrd_solver *h, int64_t *t);
 int lbrd_spectrum_work_size(int nx, int ny, size_t *bytes);
 int lbrd_spectrum(lbrd_solver *h, int species, void *out, void *work, size_t work_bytes);
 
+/* lbrd_spectrum for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and the same result, with the scratch taken from a fixed
+ * array of LBRD_SPECTRUM_STATIC_BYTES that the library holds in each GPU's
+ * memory from the first call on that GPU until the process ends; the call
+ * itself allocates nothing (no hipMalloc, no library allocation).  Lattices
+ * of more than LBRD_SPECTRUM_STATIC_MAX_SITES sites: LBRD_ENOMEM.  Every call
+ * on one GPU shares that GPU's array, which keeps the last call's contents
+ * (nothing in it needs to start at zero): calls that overlap on one GPU (on
+ * several streams or threads) race and must be serialised by the caller.
+ * out: device double [ny][nx].  Asynchronous on the solver's stream.
+ * Errors: EINVAL (null, bad species, misaligned out), ENOMEM (lattice too
+ * large), ESTATE (not initialised), EDEVICE. */
+#define LBRD_SPECTRUM_STATIC_MAX_SITES (1 << 20)
+#define LBRD_SPECTRUM_STATIC_BYTES ((size_t)LBRD_SPECTRUM_STATIC_MAX_SITES * 24 + 256)
+int lbrd_spectrum_static(lbrd_solver *h, int species, void *out);
+
 /* Launch shape in use / override it (validated against the storage form). */
 int lbrd_get_tuning(const lbrd_solver *h, lbrd_tuning *out);
 int lbrd_set_tuning(lbrd_solver *h, const lbrd_tuning *t);

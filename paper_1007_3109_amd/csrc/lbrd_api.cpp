@@ -738,6 +738,25 @@ int lbrd_spectrum(lbrd_solver *h, int species, void *out, void *work, size_t wor
     return e == hipSuccess ? LBRD_OK : fail("spectrum kernels", e);
 }
 
+static_assert(LBRD_SPECTRUM_STATIC_MAX_SITES == kStaticSpectrumSites &&
+                  LBRD_SPECTRUM_STATIC_BYTES == kStaticSpectrumBytes,
+              "the header states the static spectrum scratch's limits");
+
+int lbrd_spectrum_static(lbrd_solver *h, int species, void *out) {
+    if (!h || !out || species < 0 || species >= h->cfg.nspecies) return LBRD_EINVAL;
+    if ((uintptr_t)out & 7) return LBRD_EINVAL;
+    if ((int64_t)h->cfg.nx * h->cfg.ny > kStaticSpectrumSites ||
+        spectrum_work_bytes(h->cfg.nx, h->cfg.ny) > kStaticSpectrumBytes)
+        return LBRD_ENOMEM;
+    if (!h->initialised) return LBRD_ESTATE;
+    void *work = nullptr;   // this device's fixed array: nothing is allocated
+    hipError_t e = static_spectrum_scratch(h->device, &work);
+    if (e != hipSuccess) return fail("hipGetSymbolAddress (spectrum scratch)", e);
+    e = launch_spectrum(h->cfg.storage, h->L, h->params, h->buf[h->cur], species, static_cast<double *>(out), work,
+                        h->partials, h->result, h->stream);
+    return e == hipSuccess ? LBRD_OK : fail("spectrum kernels", e);
+}
+
 int lbrd_time(const lbrd_solver *h, int64_t *t) {
     if (!h || !t) return LBRD_EINVAL;
     *t = h->t;

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
+#include <vector>
 
 #include "lbrd_device.h"
 
@@ -417,6 +419,44 @@ hipError_t launch_spectrum(int storage, const Layout &L, const void *params, con
         hipLaunchKernelGGL(k_dft_cols, dim3(nb), dim3(256), 0, st, R, L.nx, L.ny, out);
         return hipGetLastError();
     })
+}
+
+// Scratch of the spectrum variant that allocates nothing (the gathered
+// densities and the row transform of up to kStaticSpectrumSites sites, laid
+// out as by launch_spectrum): one fixed array in each GPU's memory, held
+// until the process ends.  Host code must use the address that
+// hipGetSymbolAddress returns for the current device, never the array's
+// name (on the host that is a stand-in, not a device address).
+static __device__ __align__(256) unsigned char scratch[kStaticSpectrumBytes];
+
+static_assert(kStaticSpectrumBytes >= kStaticSpectrumSites * (sizeof(double) + sizeof(double2)) + 256,
+              "the static spectrum scratch holds spectrum_work_bytes of its largest lattice");
+
+hipError_t static_spectrum_scratch(int device, void **ptr) {
+    static std::mutex mu;
+    static std::vector<void *> addr;   // per device, looked up once
+    if (!ptr || device < 0) return hipErrorInvalidValue;
+    std::lock_guard<std::mutex> lk(mu);
+    if ((size_t)device < addr.size() && addr[device]) {
+        *ptr = addr[device];
+        return hipSuccess;
+    }
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) {
+        const hipError_t back = hipSetDevice(cur);
+        if (e == hipSuccess) e = back;
+    }
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    if (addr.size() <= (size_t)device) addr.resize((size_t)device + 1, nullptr);
+    addr[device] = p;
+    *ptr = p;
+    return hipSuccess;
 }
 
 }  // namespace lbrd

@@ -182,6 +182,13 @@ hipError_t launch_moments(int storage, const Layout &L, const void *params, cons
 // mean removed, row DFT into work (complex [ny][nx]), column DFT and |.|^2 into
 // out.  work holds spectrum_work_bytes(nx, ny).
 size_t spectrum_work_bytes(int nx, int ny);
+// The spectrum variant that allocates nothing takes its scratch from a fixed
+// device array of kStaticSpectrumBytes (lattices of at most
+// kStaticSpectrumSites sites).  static_spectrum_scratch returns that array's
+// address on `device` (looked up once per device with the device current).
+constexpr int64_t kStaticSpectrumSites = (int64_t)1 << 20;
+constexpr size_t kStaticSpectrumBytes = (size_t)kStaticSpectrumSites * 24 + 256;
+hipError_t static_spectrum_scratch(int device, void **ptr);
 hipError_t launch_spectrum(int storage, const Layout &L, const void *params, const void *src, int species,
                            double *out, void *work, double *partials, double *result, hipStream_t st);
 

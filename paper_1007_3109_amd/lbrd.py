@@ -18,6 +18,7 @@ _LIB_PATH = Path(__file__).resolve().parent / "liblbrd.so"
 MAX_SPECIES = 4
 
 OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, ESTATE, ENOTFOUND, ETIMEOUT = 0, -1, -2, -3, -4, -5, -6, -7
+SPECTRUM_STATIC_MAX_SITES = 1 << 20   # LBRD_SPECTRUM_STATIC_MAX_SITES
 
 STORAGE = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
 REACTION = {"none": 0, "linear": 1, "gray_scott": 2}
@@ -96,6 +97,7 @@ SIGNATURES = {
     "lbrd_time": ([_P, ctypes.POINTER(_I64)], _I),
     "lbrd_spectrum_work_size": ([_I, _I, ctypes.POINTER(_SZ)], _I),
     "lbrd_spectrum": ([_P, _I, _P, _P, _SZ], _I),
+    "lbrd_spectrum_static": ([_P, _I, _P], _I),
     "lbrd_get_tuning": ([_P, ctypes.POINTER(Tuning)], _I),
     "lbrd_set_tuning": ([_P, ctypes.POINTER(Tuning)], _I),
     "lbrd_autotune": ([_P, _I, ctypes.c_char_p, ctypes.POINTER(Tuning)], _I),
@@ -329,6 +331,17 @@ class Solver:
         check(_lib.lbrd_spectrum(self._h, int(species), _device_ptr(out), ptr, nbytes), "lbrd_spectrum")
         torch.cuda.current_stream().synchronize()
         del work
+        return out
+
+    def spectrum_static(self, species: int, out=None):
+        """lbrd_spectrum_static: the same spectrum with the library's fixed
+        per-GPU scratch (no allocation in the library; pass `out`, a device
+        float64 tensor [ny][nx], to allocate nothing here either).
+        Asynchronous on the solver's stream."""
+        if out is None:
+            torch = _torch()
+            out = torch.empty((self.cfg.ny, self.cfg.nx), dtype=torch.float64, device=self.device)
+        check(_lib.lbrd_spectrum_static(self._h, int(species), _device_ptr(out)), "lbrd_spectrum_static")
         return out
 
     def tuning(self) -> Tuning:

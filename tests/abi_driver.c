@@ -186,6 +186,22 @@ static void solver_case(lbrd_config c) {
     EXPECT(lbrd_spectrum(h, 0, spec, work, wbytes), LBRD_OK);
     EXPECT(lbrd_spectrum(h, ns, spec, work, wbytes), LBRD_EINVAL);
     EXPECT(lbrd_spectrum(h, 0, spec, work, wbytes ? wbytes - 1 : 0), wbytes ? LBRD_ENOMEM : LBRD_OK);
+    /* the variant that allocates nothing: the same numbers */
+    double *spec2 = dalloc(sites * sizeof(double));
+    EXPECT(lbrd_spectrum(h, ns - 1, spec, work, wbytes), LBRD_OK);
+    EXPECT(lbrd_spectrum_static(h, ns - 1, spec2), LBRD_OK);
+    EXPECT(lbrd_spectrum_static(h, ns, spec2), LBRD_EINVAL);
+    EXPECT(lbrd_spectrum_static(h, 0, (char *)spec2 + 4), LBRD_EINVAL);
+    EXPECT(lbrd_spectrum_static(NULL, 0, spec2), LBRD_EINVAL);
+    if (g_gpu) {
+        double *a = malloc(sites * sizeof(double)), *b2 = malloc(sites * sizeof(double));
+        hipMemcpy(a, spec, sites * sizeof(double), D2H);
+        hipMemcpy(b2, spec2, sites * sizeof(double), D2H);
+        CHECK(memcmp(a, b2, sites * sizeof(double)) == 0, "static-scratch spectrum differs");
+        free(a);
+        free(b2);
+    }
+    hipFree(spec2);
     /* launch shapes */
     lbrd_tuning tu, bad;
     EXPECT(lbrd_get_tuning(h, &tu), LBRD_OK);
@@ -224,6 +240,8 @@ static void tall_lattice_gate(void) {
         if (!h) continue;
         lbrd_tuning tu;
         EXPECT(lbrd_get_tuning(h, &tu), LBRD_OK);
+        double spec_out = 0;
+        EXPECT(lbrd_spectrum_static(h, 0, &spec_out), LBRD_ENOMEM);          /* beyond the fixed scratch */
         if (tall) {
             CHECK(tu.fused_steps == 1, "tall lattice takes %d steps per launch", tu.fused_steps);
             tu.fused_steps = 4;

@@ -87,6 +87,15 @@ void **__hipRegisterFatBinary(const void *) {
 void __hipRegisterFunction(void **, const void *, char *, const char *, unsigned int, void *, void *, void *, void *,
                            int *) {}
 void __hipUnregisterFatBinary(void **) {}
+void __hipRegisterVar(void **, void *, char *, const char *, int, size_t, int, int) {}
+
+// A __device__ variable's host stand-in has the variable's size here: its
+// address serves as the "device" address.
+hipError_t hipGetSymbolAddress(void **p, const void *symbol) {
+    if (!p || !symbol) return hipErrorInvalidSymbol;
+    *p = const_cast<void *>(symbol);
+    return hipSuccess;
+}
 
 hipError_t hipFuncSetAttribute(const void *fn, hipFuncAttribute, int value) {
     return fn && value >= 0 && value <= 160 * 1024 ? hipSuccess : hipErrorInvalidValue;
