@@ -1,31 +1,43 @@
 """Benchmark of the reacting-species D2Q9 lattice Boltzmann step on one MI355X.
 
-Workload timed for the headline line: Gray-Scott (u, v), D2Q9 BGK, 1024 x 1024
-periodic, FP32 storage, tau = (1.0, 0.75), F = 0.04, k = 0.06, central 64 x 64
-square with u = 0.5, v = 0.25 plus U(-0.01, 0.01) noise (seed 0).  One "step"
-is one lattice time step of the whole field (every species, every site):
-collide, react and stream.  The library's default launch shape advances five
-steps per launch (32 x 10 tiles staged in LDS); --tune runs its autotuner
-first.
+Headline workload: Gray-Scott (u, v), D2Q9 BGK, 4096 x 4096 periodic, FP32
+storage (the FP32 run of the 4096^2 workload: 2.4 GB of ping-pong state,
+beyond the 256 MB Infinity Cache, so the step streams from HBM), tau = (1.0,
+0.75), F = 0.04, k = 0.06, central 64 x 64 square with u = 0.5, v = 0.25 plus
+U(-0.01, 0.01) noise (seed 0).  One "step" is one lattice time step of the
+whole field (every species, every site): collide, react and stream.
 
-The JSON line carries the headline MLUPS per species, the roofline of the
-step kernel (algorithmic bytes of one launch: every population read once and
-written once, 2 * 9 * sizeof(storage) bytes per species-site, over the launch
-time measured with HIP events on the launch stream), the HBM traffic per
-launch from the committed hardware-counter summary when it was taken on the
-current kernel sources and launch shape, the FP64 oracle timed on the host
-cores, and extra legs: the 4096^2 lattices (working set larger than the
-256 MB Infinity Cache) in FP32 / FP16 / BF16 storage, the batched sweep, the
-continuous-batching server, the 16-bit storage errors and a device copy.
+Timing: W untimed warm-up steps, then windows of exactly K = --steps steps,
+each bracketed by HIP events on the solver's stream and a device
+synchronisation on both sides, repeated until at least five windows and one
+second of timed device time; the line reports the median window (and the
+spread).  --tune runs the library's autotuner first.
+
+The roofline of the step kernel follows the algorithmic byte count per
+species-site-step, 2 x 9 x sizeof(storage) (every population read once and
+written once per time step), times the species-site-steps one launch
+advances, over the launch duration from the same events, against the 8 TB/s
+HBM peak.  A kernel that keeps several time steps on chip moves the state
+through HBM once per launch, so this per-step fraction can exceed 1; the
+HBM bytes it really moves per launch (hardware counters, from the committed
+summary when it was taken on the current kernel sources and launch shape)
+and the fraction of VALU issue slots it uses are reported beside it.
+
+Also reported: the FP64 oracle on the host cores (a bounded sample of the
+same workload), and extra legs: the 1024^2 workload (cache-resident), the
+one-step kernel at 4096^2, 16-bit storage at 4096^2, the batched sweep, the
+continuous-batching server at its defined load, the 16-bit storage errors,
+the 64^2 FP64 decay, the rescaling study and device copies.
 """
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
-import re
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -35,13 +47,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, 8 TB/s
+VALU_ISSUE_PEAK = 256 * 2.4e9   # wave-instructions per second: 256 CUs x 1 VALU issue per cycle per CU (4 SIMDs x 1/4)
+METRIC = "MLUPS per species and % HBM roofline; batched p50/p99 solve latency"
 
-
-# sources that define the multi-step FP32 kernel; the committed counter summary
-# records their digest, and its traffic figure is reported only while it matches
+# sources that define the multi-step kernels; a committed counter summary
+# records their digest, and its figures are reported only while it matches
 STEP_SOURCES = ("paper_1007_3109_amd/csrc/lbrd_device.h", "paper_1007_3109_amd/csrc/lbrd_internal.h",
                 "paper_1007_3109_amd/csrc/lbrd_step_launch.h", "paper_1007_3109_amd/csrc/step_f32.hip")
-TRAFFIC_SUMMARY = "profiles/pmc_k_stepT_gray_scott_1024_f32.txt"
+TRAFFIC_SUMMARY = "profiles/pmc_gray_scott_4096_f32.txt"
+ISSUE_SUMMARY = "profiles/sq_gray_scott_4096_f32.txt"
 
 
 def source_digest():
@@ -57,24 +71,52 @@ def source_digest():
     return h.hexdigest()
 
 
-def measured_traffic(tuning):
-    """HBM bytes per launch (FETCH_SIZE and WRITE_SIZE, scaled by the plain
-    copy calibration) from the committed counter summary, or None when the
-    summary is missing or was taken on other kernel sources or launch shape."""
-    path = os.path.join(ROOT, TRAFFIC_SUMMARY)
+def read_summary(rel):
+    """key: value lines of a committed profile summary (not indented, not
+    comments)."""
+    path = os.path.join(ROOT, rel)
     if not os.path.exists(path):
-        return None, "no counter summary"
+        return None
     kv = {}
     with open(path) as fh:
         for line in fh:
             if ":" in line and not line.startswith((" ", "#")):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
+    return kv
+
+
+def summary_for(rel, tuning):
+    """The summary's key/values when it was taken on the current kernel
+    sources and this launch shape, else (None, reason)."""
+    kv = read_summary(rel)
+    if kv is None:
+        return None, "no counter summary"
     if kv.get("source_sha256") != source_digest():
         return None, "kernel sources changed since the counters were taken"
     if kv.get("tuning") != json.dumps(tuning, sort_keys=True):
         return None, "launch shape differs from the one the counters were taken on"
-    return int(kv["traffic_bytes_per_launch"]), TRAFFIC_SUMMARY
+    return kv, rel
+
+
+def measured_traffic(tuning):
+    """HBM bytes per launch (FETCH_SIZE and WRITE_SIZE, scaled by the plain
+    copy calibration) from the committed counter summary, or None with the
+    reason when it was taken on other kernel sources or launch shape."""
+    kv, src = summary_for(TRAFFIC_SUMMARY, tuning)
+    if kv is None:
+        return None, src
+    return int(kv["traffic_bytes_per_launch"]), src
+
+
+def measured_issue(tuning):
+    """Fraction of the chip's VALU issue slots the kernel used per launch
+    (SQ_ACTIVE_INST_VALU x 4 cycles / 1024 SIMDs over the launch's cycles),
+    from the committed instruction-counter summary, or None with the reason."""
+    kv, src = summary_for(ISSUE_SUMMARY, tuning)
+    if kv is None:
+        return None, src
+    return float(kv["valu_issue_frac"]), src
 
 
 def log(msg):
@@ -82,24 +124,72 @@ def log(msg):
 
 
 def algorithmic_bytes(nspecies, sites, storage_bytes):
+    """Bytes of one time step over the lattice: every population read once and
+    written once, 2 x 9 x sizeof(storage) per species-site-step."""
     return 2 * 9 * storage_bytes * nspecies * sites
 
 
-def time_solver(torch, s, steps, warmup):
-    """Warm up, then time exactly `steps` steps between two events on the
-    solver's stream, bracketed by device synchronisation."""
+STORAGE_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
+
+
+def time_windows(torch, s, steps, warmup, min_total_s=1.0, min_reps=5, max_reps=4000):
+    """W warm-up steps, then windows of exactly `steps` steps, each between two
+    HIP events on the solver's stream (torch's current stream) with the device
+    synchronised on both sides, until at least `min_reps` windows and
+    `min_total_s` of timed device time.  Returns the window times (s)."""
     s.step(warmup)
     torch.cuda.synchronize()
     st = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record(st)
-    s.step(steps)
-    e1.record(st)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    return e0.elapsed_time(e1) / 1e3, wall
+    wins = []
+    while len(wins) < max_reps and (len(wins) < min_reps or sum(wins) < min_total_s):
+        torch.cuda.synchronize()
+        e0.record(st)
+        s.step(steps)
+        e1.record(st)
+        torch.cuda.synchronize()
+        wins.append(e0.elapsed_time(e1) / 1e3)
+    return wins
+
+
+def window_stats(wins, steps):
+    w = np.array(wins)
+    med = float(np.median(w))
+    return med, {"windows": len(wins), "steps_per_window": steps, "median_ms": round(med * 1e3, 4),
+                 "min_ms": round(float(w.min()) * 1e3, 4), "max_ms": round(float(w.max()) * 1e3, 4),
+                 "spread_pct": round(float((w.max() - w.min()) / med * 100), 2),
+                 "timed_s": round(float(w.sum()), 3)}
+
+
+def roofline(nspecies, sites, storage, steps_per_launch, launch_s, kernel, traffic=None, traffic_src=None,
+             issue=None, issue_src=None, note=None):
+    """Roofline of one launch: algorithmic bytes = 2 x 9 x sizeof(storage) per
+    species-site-step x the species-site-steps of one launch (N sites T)."""
+    b = STORAGE_BYTES[storage]
+    per_launch = algorithmic_bytes(nspecies, sites, b) * steps_per_launch
+    achieved = per_launch / launch_s / 1e9
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+           "kernel": kernel, "steps_per_launch": steps_per_launch, "launch_us": round(launch_s * 1e6, 3),
+           "algorithmic_bytes_per_launch": per_launch,
+           "bytes_per_species_site_step": 2 * 9 * b,
+           "species_site_steps_per_launch": nspecies * sites * steps_per_launch}
+    if traffic is not None:
+        out["traffic_unit"] = "HBM bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE, copy-calibrated)"
+        out["traffic_source"] = traffic_src
+        out["hbm_measured_GBs"] = round(traffic / launch_s / 1e9, 1)
+        out["hbm_measured_frac"] = round(traffic / launch_s / 1e9 / HBM_PEAK_GBS, 4)
+    elif traffic_src:
+        out["traffic_null_reason"] = traffic_src
+    if issue is not None:
+        out["valu_issue_frac"] = issue
+        out["valu_issue_source"] = issue_src
+    elif issue_src:
+        out["valu_issue_null_reason"] = issue_src
+    if note:
+        out["note"] = note
+    return out
 
 
 def gs_config(lbrd, workloads, n, storage):
@@ -108,46 +198,72 @@ def gs_config(lbrd, workloads, n, storage):
                             F=workloads.GS_F, k=workloads.GS_K, **extra)
 
 
-def cpu_baseline(workloads, n, budget_s):
-    """The FP64 oracle on the host cores, on a bounded sample: the same
-    1024^2 Gray-Scott field, stepped in chunks until `budget_s` of CPU time."""
+def kernel_name(t):
+    if t.fused_steps > 1:
+        return f"k_stepT ({t.fused_steps} steps per launch, {t.tile_cols} x {t.tile_rows} tiles in LDS)"
+    return "k_step (one step per launch)"
+
+
+def cpu_info():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model
+
+
+def cpu_baseline(workloads, n, budget_s, max_steps=200):
+    """The FP64 oracle on the host cores, on a bounded sample of the headline
+    workload: the same n^2 Gray-Scott field, stepped in chunks of 10 until
+    max_steps steps or budget_s of wall time."""
     import oracle
 
     rho0 = workloads.gray_scott_square(n, n, seed=0)
     f = oracle.init(rho0)
     steps = 0
-    chunk = 5
+    chunk = 10
     t0 = time.perf_counter()
-    while True:
+    while steps < max_steps:
         f = oracle.run(f, chunk, list(workloads.GS_TAU), oracle.REACT_GRAY_SCOTT, F=workloads.GS_F,
                        k=workloads.GS_K)
         steps += chunk
         el = time.perf_counter() - t0
-        if el >= budget_s or steps >= 4000:
+        if el >= budget_s:
             break
+    del f
     mlups = 2 * n * n * steps / el / 1e6
     return {"value": round(mlups, 2), "unit": "MLUPS per species", "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"Gray-Scott {n}x{n}, FP64 oracle (C, OpenMP), {steps} steps from the benchmark's initial "
-                      f"state, {el:.1f} s"}
+            "sample": f"Gray-Scott {n}x{n} (the headline field), FP64 oracle (C, OpenMP over rows), first {steps} "
+                      f"steps from the benchmark's initial state, {el:.1f} s",
+            "cpu_model": cpu_info(), "nproc": os.cpu_count(),
+            "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS")}
 
 
-def hbm_leg(torch, lbrd, workloads, n, storage, steps, warmup, tune=False):
+def solver_leg(torch, lbrd, workloads, n, storage, steps, warmup, tune=False, fused=None, note=None):
+    """One Gray-Scott lattice, the headline timing protocol; the roofline of
+    its step kernel."""
     cfg = gs_config(lbrd, workloads, n, storage)
     s = lbrd.Solver(cfg)
     if tune:
         s.autotune(steps=10)
+    if fused is not None:
+        s.set_tuning(fused_steps=fused)
     s.init(workloads.gray_scott_square(n, n, seed=0))
-    secs, _ = time_solver(torch, s, steps, warmup)
-    b = {"f32": 4, "f16": 2, "bf16": 2, "f64": 8}[storage]
+    wins = time_windows(torch, s, steps, warmup)
+    med, stats = window_stats(wins, steps)
+    t = s.tuning()
     sites = n * n
-    per_step = secs / steps
-    spl = s.tuning().fused_steps
-    gbs = algorithmic_bytes(2, sites, b) / (per_step * spl) / 1e9
-    out = {"workload": f"gray_scott {n}x{n} {storage}", "steps": steps, "ms_per_step": round(per_step * 1e3, 4),
-           "mlups_per_species": round(2 * sites / per_step / 1e6, 1), "steps_per_launch": spl,
-           "achieved_GBs": round(gbs, 1), "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
-           "one_step_equivalent_GBs": round(algorithmic_bytes(2, sites, b) / per_step / 1e9, 1),
-           "tuning": s.tuning().as_dict()}
+    per_step = med / steps
+    spl = t.fused_steps
+    out = {"workload": f"gray_scott {n}x{n} {storage}", "ms_per_step": round(per_step * 1e3, 5),
+           "mlups_per_species": round(2 * sites / per_step / 1e6, 1), "timing": stats,
+           "roofline": roofline(2, sites, storage, spl, per_step * spl, kernel_name(t), note=note),
+           "tuning": t.as_dict()}
     s.close()
     del s
     torch.cuda.empty_cache()
@@ -168,8 +284,7 @@ def batch_leg(torch, lbrd, workloads, steps, warmup, seed=0):
     species_sites = sum(2 * i.side * i.side for i in insts)
     mlups = species_sites * steps / (ms / 1e3) / 1e6
     spl = t.fused_steps
-    # per launch: the state of every instance read once and written once
-    gbs = species_sites * 72 * steps / spl / (ms / 1e3) / 1e9
+    launch_s = ms / 1e3 / steps * spl
     # the plain single-lattice kernel on the same instances, one after another
     solo_ms = 0.0
     solo_steps = 20
@@ -182,30 +297,34 @@ def batch_leg(torch, lbrd, workloads, steps, warmup, seed=0):
         solo_ms += s.time_steps(solo_steps)
         s.close()
     solo_mlups = species_sites * solo_steps / (solo_ms / 1e3) / 1e6
+    rl = roofline(1, species_sites, "f32", spl, launch_s, f"k_batch_stepT ({spl} steps per launch)")
     out = {"workload": f"{len(insts)} Gray-Scott instances, sides {sorted(set(i.side for i in insts))}, FP32",
            "species_sites": species_sites, "steps": steps, "ms_per_step": round(ms / steps, 4),
-           "mlups_per_species": round(mlups, 1), "steps_per_launch": spl, "achieved_GBs": round(gbs, 1),
-           "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4), "one_step_equivalent_GBs": round(gbs * spl, 1),
-           "tuning": t.as_dict(),
-           "plain_kernel_one_by_one_mlups_per_species": round(solo_mlups, 1)}
+           "mlups_per_species": round(mlups, 1), "roofline": rl, "tuning": t.as_dict(),
+           "plain_kernel_one_by_one_mlups_per_species": round(solo_mlups, 1),
+           "vs_plain_kernel": round(mlups / solo_mlups, 3)}
     b.close()
     del b
     torch.cuda.empty_cache()
     return out
 
 
-def serve_leg(torch, lbrd, workloads, n_requests, pool_gb, steps_range, seed=0, rate=None):
-    """Poisson stream of mixed requests into the continuous-batching server."""
+def serve_leg(torch, lbrd, workloads, n_requests, pool_gb, steps_range, seed=0, rate=None, occupancy=0.8):
+    """Poisson stream of mixed requests into the continuous-batching server at
+    the load its configuration defines: the arrival rate keeps the mean
+    resident footprint near `occupancy` of the pool.  The starting rate comes
+    from a processor-sharing model (the server shares its throughput Theta
+    among the resident requests; at load rho = lambda E[work] / Theta the mean
+    resident footprint is rho / (1 - rho) x E[footprint x work] / E[work]),
+    with the expectations over this stream's own requests and Theta from the
+    plain kernel on a sample of them; while requests arrive, the rate is then
+    corrected every half second from the arena occupancy the server measured
+    over the last two seconds (arrival gaps exponential at the current rate:
+    a Poisson stream with a slowly varying rate).  A fixed `rate` disables
+    the correction."""
     import threading
 
-    if rate is None:
-        # offered load near the server's measured throughput (about 2e11
-        # species-site-steps per second; measured 2.2e11 while busy): mean work
-        # per request / 2e11, at 85% utilisation
-        e_side2 = (2048 ** 2 - 64 ** 2) / (2 * math.log(32))
-        e_work = 1.5 * e_side2 * (steps_range[0] + steps_range[1]) / 2
-        rate = 0.85 * 2e11 / e_work
-    reqs = workloads.request_stream(n_requests, rate, seed=seed, steps_range=steps_range)
+    reqs = workloads.request_stream(n_requests, 1.0, seed=seed, steps_range=steps_range)
     cfgs, inits = [], []
     for r in reqs:
         if r.reaction == "linear":
@@ -216,32 +335,8 @@ def serve_leg(torch, lbrd, workloads, n_requests, pool_gb, steps_range, seed=0, 
                                    k=r.k, rho_ref=(1.0, 0.0))
         cfgs.append(cfg)
         inits.append(workloads.request_initial(r))
-    srv = lbrd.Server(arena_bytes=int(pool_gb * (1 << 30)), chunk_steps=500)
-    tickets = [None] * len(reqs)
-
-    def feeder():
-        t0 = time.perf_counter()
-        for i, r in enumerate(reqs):
-            dt = r.arrival - (time.perf_counter() - t0)
-            if dt > 0:
-                time.sleep(dt)
-            tickets[i] = srv.submit(cfgs[i], inits[i], r.nsteps)
-
-    th = threading.Thread(target=feeder)
-    t0 = time.perf_counter()
-    th.start()
-    th.join()
-    lat, work = [], 0
-    for i, t in enumerate(tickets):
-        srv.wait(t, 600)
-        _, _, info = srv.take(t)
-        lat.append(info.done_s - info.submit_s)
-        work += cfgs[i].nspecies * cfgs[i].nx * cfgs[i].ny * reqs[i].nsteps
-    makespan = time.perf_counter() - t0
-    st = srv.stats()
-    srv.close()
-    del srv
-    torch.cuda.empty_cache()
+    work = np.array([c.nspecies * c.nx * c.ny * r.nsteps for c, r in zip(cfgs, reqs)], np.float64)
+    fp = np.array([lbrd.server_footprint(c) for c in cfgs], np.float64)
     # the plain single-lattice kernel on a sample of the same requests
     solo_work, solo_s = 0, 0.0
     for i in range(0, len(reqs), max(1, len(reqs) // 12)):
@@ -252,16 +347,88 @@ def serve_leg(torch, lbrd, workloads, n_requests, pool_gb, steps_range, seed=0, 
         solo_s += s.time_steps(n) / 1e3
         solo_work += cfgs[i].nspecies * cfgs[i].nx * cfgs[i].ny * n
         s.close()
+    plain = solo_work / solo_s
+    pool = pool_gb * (1 << 30)
+    m = float((fp * work).sum() / work.sum())            # work-weighted mean footprint
+    target = occupancy * pool
+    rho = target / (target + m)
+    controlled = rate is None
+    rate0 = rho * 0.9 * plain / float(work.mean()) if controlled else rate
+    lam = [rate0]
+    srv = lbrd.Server(arena_bytes=int(pool), chunk_steps=500)
+    tickets = [None] * len(reqs)
+    gaps = np.random.default_rng([seed, 1]).exponential(1.0, size=len(reqs))
+
+    def feeder():
+        t0 = time.perf_counter()
+        t_next = 0.0
+        for i in range(len(reqs)):
+            t_next += gaps[i] / lam[0]
+            dt = t_next - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            tickets[i] = srv.submit(cfgs[i], inits[i], reqs[i].nsteps)
+
+    th = threading.Thread(target=feeder)
+    t0 = time.perf_counter()
+    st0 = srv.stats()
+    th.start()
+    hist = [(st0.clock_s, st0.arena_used_byte_s)]
+    samples, rates = [], []
+    while th.is_alive():
+        th.join(0.5)
+        st = srv.stats()
+        samples.append((st.resident, st.queued))
+        hist.append((st.clock_s, st.arena_used_byte_s))
+        if controlled:
+            old = [h for h in hist if h[0] <= st.clock_s - 2.0]
+            if old:
+                c0, b0 = old[-1]
+                occ = (st.arena_used_byte_s - b0) / max(st.clock_s - c0, 1e-9) / st.arena_bytes
+                lam[0] *= float(np.clip((occupancy / max(occ, 0.05)) ** 0.25, 0.9, 1.1))
+                rates.append(lam[0])
+    st_arr = srv.stats()          # the end of the arrivals: occupancy is averaged over the arrival period
+    lat = []
+    for i, t in enumerate(tickets):
+        srv.wait(t, 900)
+        _, _, info = srv.take(t)
+        lat.append(info.done_s - info.submit_s)
+        if (i + 1) % 50 == 0:
+            log(f"bench: serving, {i + 1} of {len(reqs)} requests done")
+    makespan = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    del srv
+    torch.cuda.empty_cache()
+    arrival_period = st_arr.clock_s - st0.clock_s
+    mean_occ = (st_arr.arena_used_byte_s - st0.arena_used_byte_s) / max(arrival_period, 1e-9) / st.arena_bytes
+    # the second half of the arrival period (the controller settled)
+    mid = [h for h in hist if h[0] <= st0.clock_s + arrival_period / 2]
+    c_mid, b_mid = mid[-1]
+    occ_late = (st_arr.arena_used_byte_s - b_mid) / max(st_arr.clock_s - c_mid, 1e-9) / st.arena_bytes
+    mean_occ_all = st.arena_used_byte_s / max(st.clock_s, 1e-9) / st.arena_bytes
     lat = np.array(lat)
-    return {"workload": f"{len(reqs)} requests, Poisson rate {rate:.2f}/s, sides log-uniform [64, 2048], steps "
-                        f"U[{steps_range[0]}, {steps_range[1]}], half linear N=1 / half Gray-Scott, FP32 or F16 "
-                        f"storage, pool {pool_gb} GB",
-            "p50_latency_s": round(float(np.percentile(lat, 50)), 4), "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
-            "mean_latency_s": round(float(lat.mean()), 4), "makespan_s": round(makespan, 3),
-            "aggregate_mlups_per_species": round(work / makespan / 1e6, 1),
-            "busy_mlups_per_species": round(work / max(st.busy_s, 1e-9) / 1e6, 1),
-            "plain_kernel_sample_mlups_per_species": round(solo_work / solo_s / 1e6, 1),
-            "arena_peak_used_gb": round(st.arena_peak_used / 2 ** 30, 3)}
+    total = float(work.sum())
+    return {"workload": f"{len(reqs)} requests, Poisson arrivals at a rate held near {occupancy:.0%} arena occupancy, "
+                        f"sides log-uniform [64, 2048], steps U[{steps_range[0]}, {steps_range[1]}], half linear N=1 / "
+                        f"half Gray-Scott, FP32 or F16 storage, pool {pool_gb} GiB",
+            "rate_start_per_s": round(rate0, 4), "rate_end_per_s": round(lam[0], 4),
+            "rate_mean_per_s": round(len(reqs) / arrival_period, 4),
+            "target_occupancy": occupancy, "model_load_rho": round(rho, 4),
+            "work_weighted_mean_footprint_mb": round(m / 1e6, 1),
+            "mean_arena_occupancy_during_arrivals": round(float(mean_occ), 4),
+            "mean_arena_occupancy_second_half_of_arrivals": round(float(occ_late), 4),
+            "mean_arena_occupancy_whole_run": round(float(mean_occ_all), 4),
+            "arena_peak_occupancy": round(st.arena_peak_used / st.arena_bytes, 4),
+            "mean_resident_requests": round(float(np.mean([a for a, _ in samples])) if samples else 0.0, 2),
+            "mean_queued_requests": round(float(np.mean([q for _, q in samples])) if samples else 0.0, 2),
+            "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
+            "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
+            "mean_latency_s": round(float(lat.mean()), 4), "arrival_period_s": round(arrival_period, 3),
+            "makespan_s": round(makespan, 3),
+            "aggregate_mlups_per_species": round(total / makespan / 1e6, 1),
+            "busy_mlups_per_species": round(total / max(st.busy_s, 1e-9) / 1e6, 1),
+            "plain_kernel_sample_mlups_per_species": round(plain / 1e6, 1)}
 
 
 def rescaling_leg(torch, steps=400000):
@@ -362,19 +529,26 @@ def precision_leg(torch, lbrd, workloads, n=4096, steps=(1000, 10000), check_n=2
 
 
 def config1_leg(torch, lbrd, workloads, steps=1000):
-    """64^2 single species, FP64, linear decay k = 1e-3, tau = 1: launch-bound;
-    plain launches against replayed graphs."""
+    """64^2 single species, FP64, linear decay k = 1e-3, tau = 1 (the decay
+    workload): launch-bound, state in the Infinity Cache; the default launches
+    and replayed graphs of one-step launches, each with its roofline."""
     rho0 = workloads.sinusoid(64, 64, 0.1, 1)
-    out = {"workload": "linear decay 64x64 f64, tau 1, k 1e-3"}
-    for gs in (0, 32):
+    out = {"workload": "linear decay 64x64 f64, tau 1, k 1e-3, 1000-step windows"}
+    for name, kw in (("default", {}), ("graphs32_one_step", dict(fused_steps=1, graph_steps=32))):
         s = lbrd.Solver(lbrd.make_config(64, 64, 1, tau=1.0, storage="f64", reaction="linear", K=[[-1e-3]]))
-        s.set_tuning(graph_steps=gs)
+        if kw:
+            s.set_tuning(**kw)
         s.init(rho0)
-        s.step(64)
-        torch.cuda.synchronize()
-        ms = s.time_steps(steps)
-        out[f"graph{gs}_us_per_step"] = round(ms * 1e3 / steps, 3)
-        out[f"graph{gs}_mlups"] = round(64 * 64 * steps / (ms / 1e3) / 1e6, 1)
+        wins = time_windows(torch, s, steps, 64, min_total_s=0.2)
+        med, stats = window_stats(wins, steps)
+        t = s.tuning()
+        per_step = med / steps
+        out[name] = {"us_per_step": round(per_step * 1e6, 3), "mlups": round(64 * 64 / per_step / 1e6, 1),
+                     "timing": stats,
+                     "roofline": roofline(1, 64 * 64, "f64", t.fused_steps, per_step * t.fused_steps, kernel_name(t),
+                                          note="0.6 MB of state: launch-bound and cache-resident, not an HBM "
+                                               "measurement"),
+                     "tuning": t.as_dict()}
         s.close()
     return out
 
@@ -402,26 +576,32 @@ def copy_leg(torch, nbytes=1 << 30, reps=20):
     return out
 
 
+ALL_LEGS = "gs1024_f32,one_step_4096_f32,hbm4096_f16,hbm4096_bf16,batch,serve,precision,rescaling,config1,copy"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--steps", type=int, default=10000, help="steps per timed window (K)")
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--size", type=int, default=4096, help="side of the headline lattice")
+    ap.add_argument("--cpu-budget", type=float, default=30.0)
+    ap.add_argument("--cpu-steps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--tune", action="store_true", help="run the library's autotuner before timing")
-    ap.add_argument("--extra-steps", type=int, default=300)
-    ap.add_argument("--legs", default="hbm4096_f32,hbm4096_f16,hbm4096_bf16,batch,serve,precision,rescaling,config1,copy",
-                    help="extra legs to run (comma list)")
-    ap.add_argument("--serve-requests", type=int, default=120)
-    ap.add_argument("--serve-pool-gb", type=float, default=16.0, help="device arena of the serving leg")
+    ap.add_argument("--extra-steps", type=int, default=300, help="steps per window of the 4096^2 extra legs")
+    ap.add_argument("--legs", default=ALL_LEGS, help="extra legs to run (comma list)")
+    ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--serve-pool-gb", type=float, default=4.0, help="device arena of the serving leg (GiB)")
     ap.add_argument("--serve-rate", type=float, default=None,
-                    help="Poisson arrival rate of the serving leg (default: 85%% of the measured capacity)")
+                    help="Poisson arrival rate of the serving leg (default: from the footprint, ~80%% occupancy)")
+    ap.add_argument("--serve-steps", default="1000,50000", help="range of steps per request")
     ap.add_argument("--serve-seed", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only (the build has no multi-GPU path); "
+                                   "--gpus must be 1"}))
         sys.exit(2)
 
     import torch
@@ -429,7 +609,7 @@ def main():
     from paper_1007_3109_amd import lbrd, workloads
 
     torch.cuda.set_device(0)
-    n = 1024
+    n = args.size
     cfg = gs_config(lbrd, workloads, n, "f32")
     s = lbrd.Solver(cfg)
     if args.tune:
@@ -446,79 +626,83 @@ def main():
         torch.cuda.synchronize()
         init_ms.append((time.perf_counter() - t_init) * 1e3)
     first_init_ms, init_ms = init_ms
-    log(f"bench: Gray-Scott {n}x{n} f32, warmup {args.warmup}, steps {args.steps}, tuning {s.tuning().as_dict()}")
-    secs, wall = time_solver(torch, s, args.steps, args.warmup)
+    log(f"bench: Gray-Scott {n}x{n} f32, warmup {args.warmup}, windows of {args.steps} steps, "
+        f"tuning {s.tuning().as_dict()}")
+    wall0 = time.perf_counter()
+    wins = time_windows(torch, s, args.steps, args.warmup)
+    wall = time.perf_counter() - wall0
+    med, stats = window_stats(wins, args.steps)
     sites = n * n
-    ms_per_step = secs / args.steps * 1e3
-    value = 2 * sites * args.steps / secs / 1e6
+    per_step = med / args.steps
+    value = 2 * sites / per_step / 1e6
     tun = s.tuning()
-    steps_per_launch = tun.fused_steps
-    # algorithmic bytes of one launch: the state read once and written once
-    # (2 * 9 * 4 B per species-site), whatever the number of steps the launch
-    # advances (the tile halo's re-reads are not counted)
-    bytes_per_launch = algorithmic_bytes(2, sites, 4)
-    launch_seconds = secs / args.steps * steps_per_launch
-    achieved = bytes_per_launch / launch_seconds / 1e9
+    spl = tun.fused_steps
     traffic, traffic_src = measured_traffic(tun.as_dict())
+    issue, issue_src = measured_issue(tun.as_dict())
     _, mass = s.moments()
     line = {
-        "metric": "MLUPS per species and % HBM roofline; batched p50/p99 solve latency",
+        "metric": METRIC,
         "value": round(value, 1),
         "unit": "MLUPS per species",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 5),
+        "ms_per_step": round(per_step * 1e3, 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "gray_scott_1024x1024_f32", "lattice": [n, n], "species": 2, "storage": "f32",
+        "config": {"workload": f"gray_scott_{n}x{n}_f32", "lattice": [n, n], "species": 2, "storage": "f32",
                    "tau": list(workloads.GS_TAU), "F": workloads.GS_F, "k": workloads.GS_K, "seed": 0,
+                   "initial": "u=1, v=0, central 64x64 square u=0.5 v=0.25, U(-0.01,0.01) noise",
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "traffic_unit": "bytes per launch", "traffic_source": traffic_src,
-                     "kernel": (f"k_stepT ({steps_per_launch} steps per launch, {tun.tile_cols} x {tun.tile_rows} "
-                                f"tiles in LDS)") if steps_per_launch > 1 else "k_step (one step per launch)",
-                     "steps_per_launch": steps_per_launch,
-                     "launch_us": round(launch_seconds * 1e6, 3),
-                     "bytes_per_launch": bytes_per_launch,
-                     # the same bytes counted once per time step (2 x 9 x 4 B per species-site-step): the
-                     # rate a one-step kernel would need; temporal blocking goes beyond the HBM peak there
-                     "one_step_equivalent_GBs": round(value * 1e6 * 2 * 9 * 4 / 1e9, 1),
-                     "one_step_equivalent_frac": round(value * 1e6 * 2 * 9 * 4 / 1e9 / HBM_PEAK_GBS, 3),
-                     "note": "frac counts the state read and written once per launch of steps_per_launch steps; "
-                             "1024^2 x 2 species x 9 x 2 buffers x 4 B = 151 MB ping-pong: resident in the 256 MB "
-                             "Infinity Cache; see extra.hbm_4096_* for working sets beyond it"},
+        "timing": stats,
+        "roofline": roofline(2, sites, "f32", spl, per_step * spl, kernel_name(tun), traffic, traffic_src, issue,
+                             issue_src,
+                             note="achieved counts 72 B per species-site-step (every population read and written "
+                                  "once per step) x the steps one launch advances; the launch keeps its "
+                                  f"{spl} steps on chip and moves the state through HBM once (hbm_measured_*), so "
+                                  "frac above 1 is the gain of temporal blocking over a one-pass kernel"),
         "wall_s": round(wall, 3),
         "init_from_host_ms": round(init_ms, 3),
         "first_init_from_host_ms": round(first_init_ms, 3),
-        "host_inclusive_mlups_per_species": round(2 * sites * args.steps / (secs + init_ms / 1e3) / 1e6, 1),
+        "host_inclusive_mlups_per_species": round(2 * sites * args.steps / (med + init_ms / 1e3) / 1e6, 1),
         "mass_after": [float(m) for m in mass],
-        "tuning": s.tuning().as_dict(),
+        "tuning": tun.as_dict(),
     }
     s.close()
     del s
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
-        line["cpu_baseline"] = cpu_baseline(workloads, n, args.cpu_budget)
+        line["cpu_baseline"] = cpu_baseline(workloads, n, args.cpu_budget, args.cpu_steps)
     if not args.no_extra:
         extra = {}
         legs = [x for x in args.legs.split(",") if x]
-        for storage in ("f32", "f16", "bf16"):
+        if "gs1024_f32" in legs:
+            log("bench: 1024^2 f32")
+            extra["gs_1024_f32"] = solver_leg(torch, lbrd, workloads, 1024, "f32", 5000, 100, tune=args.tune,
+                                              note="1024^2 x 2 species x 9 x 2 buffers x 4 B = 151 MB: resident in "
+                                                   "the 256 MB Infinity Cache, not an HBM measurement")
+        if "one_step_4096_f32" in legs:
+            log("bench: 4096^2 f32, one step per launch")
+            extra["one_step_4096_f32"] = solver_leg(torch, lbrd, workloads, 4096, "f32", args.extra_steps, 20,
+                                                    fused=1,
+                                                    note="one step per launch: the fraction of the HBM roofline "
+                                                         "of a one-pass kernel")
+        for storage in ("f16", "bf16"):
             if f"hbm4096_{storage}" in legs:
                 log(f"bench: 4096^2 {storage}")
-                extra[f"hbm_4096_{storage}"] = hbm_leg(torch, lbrd, workloads, 4096, storage, args.extra_steps, 20,
-                                                       tune=args.tune)
+                extra[f"hbm_4096_{storage}"] = solver_leg(torch, lbrd, workloads, 4096, storage, args.extra_steps, 20,
+                                                          tune=args.tune)
         if "batch" in legs:
             log("bench: batched sweep")
             extra["batched"] = batch_leg(torch, lbrd, workloads, 5000, 32)
         if "serve" in legs:
             log("bench: serving")
-            extra["serving"] = serve_leg(torch, lbrd, workloads, args.serve_requests, args.serve_pool_gb, (1000, 10000),
+            lo, hi = (int(x) for x in args.serve_steps.split(","))
+            extra["serving"] = serve_leg(torch, lbrd, workloads, args.serve_requests, args.serve_pool_gb, (lo, hi),
                                          seed=args.serve_seed, rate=args.serve_rate)
         if "precision" in legs:
             log("bench: precision forms")
@@ -532,21 +716,10 @@ def main():
         if "copy" in legs:
             log("bench: copy")
             extra["copy_1GiB"] = copy_leg(torch)
-            # the same launch's algorithmic rate against a plain device copy
-            # measured in this process (read + write of 1 GiB)
             copy = extra["copy_1GiB"]["GBs"]
             line["roofline"]["copy_GBs"] = copy
-            line["roofline"]["frac_of_copy"] = round(line["roofline"]["achieved"] / copy, 4)
-            for key in ("hbm_4096_f32", "hbm_4096_f16", "hbm_4096_bf16", "batched"):
-                if key in extra:
-                    extra[key]["frac_of_copy"] = round(extra[key]["achieved_GBs"] / copy, 4)
-            # and against a copy of one buffer of the headline lattice (the
-            # same 2 x buffer working set, cache-resident at 1024^2)
-            extra["copy_headline_buffer"] = copy_leg(torch, nbytes=line["roofline"]["bytes_per_launch"] // 2,
-                                                     reps=400)
-            same = extra["copy_headline_buffer"]["GBs"]
-            line["roofline"]["copy_same_size_GBs"] = same
-            line["roofline"]["frac_of_copy_same_size"] = round(line["roofline"]["achieved"] / same, 4)
+            if "hbm_measured_GBs" in line["roofline"]:
+                line["roofline"]["hbm_measured_frac_of_copy"] = round(line["roofline"]["hbm_measured_GBs"] / copy, 4)
         line["extra"] = extra
     print(json.dumps(line), flush=True)
 

@@ -149,7 +149,15 @@ typedef struct lbrd_config {
  *       workgroups that one XCD holds at once (from the LDS of the default
  *       shape) when the lattice is wider than twice that many tiles (16-bit
  *       forms: at least twice), else 0.
- *       Results are bitwise identical for every order. */
+ *       Results are bitwise identical for every order.
+ *  march_rows: single solvers with fused_steps = T >= 2 and buffers below
+ *       4 GiB: 0 = the LDS tiles above; R = 1..65536 = marching wave strips
+ *       instead: each wave (min(waves, 4) waves per workgroup) owns 64
+ *       columns, 2(T-1) of them recomputed halo, and marches down segments of
+ *       R rows carrying the launch's intermediate rows in registers (no LDS,
+ *       no barriers; only the x-halo is recomputed).  tile_cols, tile_rows and
+ *       tile_strip are then ignored.  Batches take 0.  Results are bitwise
+ *       identical either way. */
 typedef struct lbrd_tuning {
     int32_t vec;
     int32_t lanes_x;
@@ -162,6 +170,7 @@ typedef struct lbrd_tuning {
     int32_t tile_rows;
     int32_t tile_cols;
     int32_t tile_strip;
+    int32_t march_rows;
 } lbrd_tuning;
 
 const char *lbrd_strerror(int status);
@@ -355,6 +364,10 @@ typedef struct lbrd_server_stats {
     int64_t arena_bytes, arena_peak_used;
     double busy_s;                /* wall time with at least one resident request   */
     double clock_s;               /* server clock now                               */
+    int64_t arena_used;           /* arena bytes held by resident requests now      */
+    double arena_used_byte_s;     /* integral of arena_used over the server clock   */
+                                  /* (byte-seconds): the mean occupancy over a      */
+                                  /* period is its change / (period x arena_bytes)  */
 } lbrd_server_stats;
 
 /* arena: device pointer, 256-byte aligned, owned by the caller until destroy. */

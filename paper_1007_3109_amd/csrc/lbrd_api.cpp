@@ -171,6 +171,7 @@ GridT make_gridT(const Layout &L, const void *src, void *dst, int tw, int th, in
     const uint64_t plane = (uint64_t)L.pstride * (uint64_t)L.esize;
     g.plane_bytes = plane < ((uint64_t)1 << 32) ? (uint32_t)plane : 0;
     g.nt_store = 0;
+    g.march = 0;
     return g;
 }
 
@@ -334,12 +335,21 @@ hipError_t enqueue_steps(lbrd_solver *h, int from, int64_t n, hipStream_t st, in
         const int64_t left = n - k;
         if (T >= 2 && left >= 2) {
             const int m = left < T ? (int)left : T;
-            GridT g = make_gridT(h->L, h->buf[a], h->buf[a ^ 1], h->tune.tile_cols, h->tune.tile_rows, m);
-            g.blocks = h->tune.blocks_per_cu > 0 ? h->tune.blocks_per_cu * h->cus : 0;
-            g.xcd_order = h->tune.plain_order == 0 ? 1 : 0;
-            if (h->tune.tile_strip > 0) g.strip = std::min(h->tune.tile_strip, g.ntx);
-            g.nt_store = h->tune.nontemporal;
-            e = launch_stepT(sl, g, h->params, st);
+            if (h->tune.march_rows > 0) {
+                // marching wave strips: 64 - 2(m-1) result columns a wave
+                GridT g = make_gridT(h->L, h->buf[a], h->buf[a ^ 1], 64 - 2 * (m - 1), h->tune.march_rows, m);
+                g.march = 1;
+                g.xcd_order = h->tune.plain_order == 0 ? 1 : 0;
+                g.nt_store = h->tune.nontemporal;
+                e = launch_stepT(step_launch1(h), g, h->params, st);
+            } else {
+                GridT g = make_gridT(h->L, h->buf[a], h->buf[a ^ 1], h->tune.tile_cols, h->tune.tile_rows, m);
+                g.blocks = h->tune.blocks_per_cu > 0 ? h->tune.blocks_per_cu * h->cus : 0;
+                g.xcd_order = h->tune.plain_order == 0 ? 1 : 0;
+                if (h->tune.tile_strip > 0) g.strip = std::min(h->tune.tile_strip, g.ntx);
+                g.nt_store = h->tune.nontemporal;
+                e = launch_stepT(sl, g, h->params, st);
+            }
             k += m;
         } else {
             Grid g = make_grid(h->L, h->buf[a], h->buf[a ^ 1], h->tune.vec, h->tune.lanes_x);
@@ -437,12 +447,15 @@ bool tuning_valid(const lbrd_solver *h, const lbrd_tuning &t) {
     if (t.blocks_per_cu < 0 || t.blocks_per_cu > 64) return false;
     if (t.plain_order != 0 && t.plain_order != 1) return false;
     if (t.tile_strip < 0 || t.tile_strip > 65536) return false;
+    if (t.march_rows < 0 || t.march_rows > 65536) return false;
+    if (t.march_rows > 0 && (t.fused_steps < 2 || big_buffers(h))) return false;
     if (t.graph_steps < 0 || (t.graph_steps & 1) || t.graph_steps > 4096) return false;
     if (t.nontemporal != 0 && t.nontemporal != 1) return false;
     if (t.waves < 1 || t.waves > 16) return false;
     if (t.fused_steps == 1) return true;
     if (!multi_step_possible(h)) return false;
     if (t.fused_steps < 2 || t.fused_steps > kMaxFusedSteps) return false;
+    if (t.march_rows > 0) return true;   // marching wave strips: no LDS tile
     if (t.tile_rows < 1 || t.tile_rows > 64) return false;
     if (big_buffers(h) && t.tile_cols == 128) return false;   // plane-by-plane launches: 32 or 64 wide
     return stepT_shape_fits(h->cfg.storage, h->cfg.nspecies, t.tile_cols, t.tile_rows, t.fused_steps, t.waves);
@@ -829,9 +842,9 @@ int lbrd_autotune(lbrd_solver *h, int steps, const char *cache_path, lbrd_tuning
             if (bar == std::string::npos || line.substr(0, bar) != k) continue;
             lbrd_tuning t;
             std::memset(&t, 0, sizeof(t));
-            if (std::sscanf(line.c_str() + bar + 1, "%d %d %d %d %d %d %d %d %d %d %d", &t.vec, &t.lanes_x,
+            if (std::sscanf(line.c_str() + bar + 1, "%d %d %d %d %d %d %d %d %d %d %d %d", &t.vec, &t.lanes_x,
                             &t.waves, &t.nontemporal, &t.graph_steps, &t.plain_order, &t.blocks_per_cu,
-                            &t.fused_steps, &t.tile_rows, &t.tile_cols, &t.tile_strip) == 11 &&
+                            &t.fused_steps, &t.tile_rows, &t.tile_cols, &t.tile_strip, &t.march_rows) == 12 &&
                 tuning_valid(h, t)) {
                 lbrd_set_tuning(h, &t);
                 h->initialised = false;
@@ -960,6 +973,7 @@ int lbrd_autotune(lbrd_solver *h, int steps, const char *cache_path, lbrd_tuning
         outf << k << "|" << best_t.vec << " " << best_t.lanes_x << " " << best_t.waves << " " << best_t.nontemporal
              << " " << best_t.graph_steps << " " << best_t.plain_order << " " << best_t.blocks_per_cu << " "
              << best_t.fused_steps << " " << best_t.tile_rows << " " << best_t.tile_cols << " " << best_t.tile_strip
+             << " " << best_t.march_rows
              << "\n";
     }
     if (chosen) *chosen = h->tune;

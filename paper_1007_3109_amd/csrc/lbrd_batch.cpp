@@ -473,6 +473,7 @@ int lbrd_batch_set_tuning(lbrd_batch *b, const lbrd_tuning *t) {
     n.lanes_x = 0;
     n.plain_order = 0;
     n.tile_strip = 0;
+    n.march_rows = 0;
     if (n.fused_steps == 1) n.tile_rows = 0;
     if (n.fused_steps == 1) n.tile_cols = 0;
     else if (n.tile_cols == 0) n.tile_cols = 64;

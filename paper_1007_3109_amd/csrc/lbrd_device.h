@@ -24,6 +24,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "lbrd_internal.h"
 
 namespace lbrd {
@@ -183,23 +185,32 @@ struct NSpecies {
     static constexpr int value = kReactionOf<V> == kGS ? 2 : kReactionOf<V> + 1;
 };
 
+// a * b + c rounded once.  The site update turns automatic contraction off
+// and writes every fused multiply-add out with this, so that each kernel
+// that inlines it (one-step, LDS tiles, marching strips, batches) rounds
+// exactly alike: a contraction left to the compiler may fuse a different
+// product of the same expression in a different kernel.
+__device__ __forceinline__ float fma_c(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_c(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // Reaction term for one site (Section II.B linear decay; Section III
 // Gray-Scott with A_0 = k_1 = 1).
 template <int V, class C>
 __device__ __forceinline__ void reaction(const Params<C> &p, const C (&rho)[NSpecies<V>::value],
                                          C (&R)[NSpecies<V>::value]) {
+#pragma clang fp contract(off)
     constexpr int NS = NSpecies<V>::value;
     if constexpr (kReactionOf<V> == kGS) {
         const C u = rho[0], v = rho[1];
         const C uvv = u * v * v;
-        R[0] = -uvv + p.F * (C(1) - u);
-        R[1] = uvv - p.Fk * v;
+        R[0] = fma_c(p.F, C(1) - u, -uvv);
+        R[1] = fma_c(-p.Fk, v, uvv);
     } else {
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             C acc = C(0);
 #pragma unroll
-            for (int j = 0; j < NS; ++j) acc += p.K[s * NS + j] * rho[j];
+            for (int j = 0; j < NS; ++j) acc = fma_c(p.K[s * NS + j], rho[j], acc);
             R[s] = acc + p.c[s];
         }
     }
@@ -222,14 +233,15 @@ __device__ __forceinline__ double sinpi_c(double a) { return sinpi(a); }
 // phase m gy mod ny is taken in integers).
 template <class C>
 __device__ __forceinline__ void shear_ceq(const Params<C> &p, int gy, C (&c)[9]) {
+#pragma clang fp contract(off)
     const int r = (int)(((int64_t)p.shear_m * gy) % p.shear_ny);
-    const C ux = p.u0x + p.amp * sinpi_c(C(2 * r) / C(p.shear_ny));
+    const C ux = fma_c(p.amp, sinpi_c(C(2 * r) / C(p.shear_ny)), p.u0x);
     const C uy = p.u0y;
-    const C uu = ux * ux + uy * uy;
+    const C uu = fma_c(ux, ux, uy * uy);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        const C eu = C(kEx[i]) * ux + C(kEy[i]) * uy;
-        c[i] = wgt<C>(i) * (C(1) + C(3) * eu + C(4.5) * eu * eu - C(1.5) * uu);
+        const C eu = fma_c(C(kEx[i]), ux, C(kEy[i]) * uy);
+        c[i] = wgt<C>(i) * fma_c(C(-1.5), uu, fma_c(C(4.5) * eu, eu, fma_c(C(3), eu, C(1))));
     }
 }
 
@@ -238,6 +250,7 @@ template <int ST, int V>
 __device__ __forceinline__ void collide_site(const Params<typename Traits<ST>::C> &p,
                                              const typename Traits<ST>::C (&f)[NSpecies<V>::value][9],
                                              typename Traits<ST>::T (&o)[NSpecies<V>::value][9], int gy) {
+#pragma clang fp contract(off)
     using C = typename Traits<ST>::C;
     constexpr int NS = NSpecies<V>::value;
     C m[NS], rho[NS], R[NS];
@@ -271,13 +284,13 @@ __device__ __forceinline__ void collide_site(const Params<typename Traits<ST>::C
             C e[9], moving = C(0);
 #pragma unroll
             for (int i = 1; i < 9; ++i) {
-                e[i] = ceq[i] * om + wgt<C>(i) * R[s];
+                e[i] = fma_c(ceq[i], om, wgt<C>(i) * R[s]);
                 moving += e[i];
             }
             e[0] = a - moving;
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
-                C r = f[s][i] * p.keep[s] + e[i];
+                C r = fma_c(f[s][i], p.keep[s], e[i]);
                 if constexpr (kShifted<ST>) {
                     asm volatile("" : "+v"(r));
                     res[s][i] = r;
@@ -296,13 +309,13 @@ __device__ __forceinline__ void collide_site(const Params<typename Traits<ST>::C
         // m / tau + R up to unbiased rounding (the rounded weights of a
         // binary format sum to 1 + O(eps), which would add a systematic mass
         // drift every step).
-        const C a = p.omega[s] * m[s] + R[s];
+        const C a = fma_c(p.omega[s], m[s], R[s]);
         const C e1 = wgt<C>(1) * a, e5 = wgt<C>(5) * a;
-        const C e0 = a - C(4) * e1 - C(4) * e5;
+        const C e0 = a - C(4) * e1 - C(4) * e5;   // 4 e1 and 4 e5 are exact
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             const C e = i == 0 ? e0 : (i < 5 ? e1 : e5);
-            C r = f[s][i] * p.keep[s] + e;
+            C r = fma_c(f[s][i], p.keep[s], e);
             // 16-bit forms: keep the float result as a value of its own so
             // the conversion always rounds the float (the compiler may
             // otherwise fold the multiply-add into a mixed-precision
@@ -821,6 +834,199 @@ __global__ __launch_bounds__(1024) void k_stepT(GridT g, Params<typename Traits<
         const int ty = r / sw, tx = si * g.strip + (r - ty * sw);
         stepT_tile<ST, V, TS, TW, false, BIG>(t, p, tx * TW, ty * g.th, TS, reinterpret_cast<T *>(smem));
     }
+}
+
+// ------------------------------------------------- marching wave strips --
+//
+// TS time steps per launch without LDS and without barriers.  Each wave owns
+// a strip of 64 columns (one per lane; the 2(TS-1) outer columns are halo,
+// recomputed by the neighbouring strips) and marches down a segment of rows.
+// Level k (the state after k of the launch's steps) is computed one row
+// behind level k-1: in iteration j, level 1 computes row r = y0 - h + j from
+// the source buffer and level k row r - (k-1) from level k-1, in ascending k,
+// so every input of a level is ready when it runs.  Level k at row q pulls,
+// from level k-1, the planes with e_y = -1 of row q+1 (computed in the same
+// iteration), those with e_y = 0 of row q (the previous iteration) and those
+// with e_y = +1 of row q-1 (two iterations back): each level keeps 9 values
+// per species of its last two rows in registers.  A pull along x (e_x = +-1)
+// takes the neighbouring lane's value by a wavefront shift (DPP).  Level TS
+// stores its row; the rows above a segment (its first 2h iterations) only
+// fill the pipeline, so a segment of L rows computes L + 2h level-1 rows.
+// Only the x-halo is recomputed: 64 / (64 - 2h) per level.  Every site runs
+// collide_site on the decoded values the one-step kernel would read, so the
+// result is bitwise identical to TS one-step launches.
+
+// v of lane l+1 (wave_shl:1) and of lane l-1 (wave_shr:1); the lanes at the
+// wave's edges get their own value back (they hold halo columns).
+template <class T>
+__device__ __forceinline__ T from_right(T v) {
+    if constexpr (sizeof(T) == 8) {
+        const uint64_t u = __builtin_bit_cast(uint64_t, v);
+        const int lo = __builtin_amdgcn_update_dpp((int)u, (int)u, 0x130, 0xf, 0xf, false);
+        const int hi = __builtin_amdgcn_update_dpp((int)(u >> 32), (int)(u >> 32), 0x130, 0xf, 0xf, false);
+        return __builtin_bit_cast(T, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+    } else if constexpr (sizeof(T) == 4) {
+        const int u = __builtin_bit_cast(int, v);
+        return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(u, u, 0x130, 0xf, 0xf, false));
+    } else {
+        const int u = (int)__builtin_bit_cast(uint16_t, v);
+        return __builtin_bit_cast(T, (uint16_t)__builtin_amdgcn_update_dpp(u, u, 0x130, 0xf, 0xf, false));
+    }
+}
+template <class T>
+__device__ __forceinline__ T from_left(T v) {
+    if constexpr (sizeof(T) == 8) {
+        const uint64_t u = __builtin_bit_cast(uint64_t, v);
+        const int lo = __builtin_amdgcn_update_dpp((int)u, (int)u, 0x138, 0xf, 0xf, false);
+        const int hi = __builtin_amdgcn_update_dpp((int)(u >> 32), (int)(u >> 32), 0x138, 0xf, 0xf, false);
+        return __builtin_bit_cast(T, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+    } else if constexpr (sizeof(T) == 4) {
+        const int u = __builtin_bit_cast(int, v);
+        return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(u, u, 0x138, 0xf, 0xf, false));
+    } else {
+        const int u = (int)__builtin_bit_cast(uint16_t, v);
+        return __builtin_bit_cast(T, (uint16_t)__builtin_amdgcn_update_dpp(u, u, 0x138, 0xf, 0xf, false));
+    }
+}
+
+// The values a level keeps for the next one, already moved to the column
+// that pulls them (planes with e_x = +1 from the left lane, e_x = -1 from the
+// right lane): row q-1's planes with e_y = 0 (a: planes 0, 1, 3) and the
+// planes with e_y = +1 of the two latest rows (b: planes 2, 5, 6), b[P] for
+// the rows of iterations of parity P.  The iteration loop is unrolled by two,
+// so a level's new values go to registers of their own and no value is
+// copied from one register to another between iterations.
+template <class T, int NS>
+struct MarchCarry {
+    T a[NS][3];
+    T b[2][NS][3];
+};
+
+// Level K+1 .. TS of an iteration of parity P, from level K's outputs o (row
+// q) and the carry of level K; level K+1 computes row q-1 when it is active
+// (iteration j >= 2K).  Level TS stores its row.
+template <int ST, int V, int TS, int K, int P>
+__device__ __forceinline__ void march_levels(const Params<typename Traits<ST>::C> &p,
+                                             typename Traits<ST>::T (&o)[NSpecies<V>::value][9],
+                                             MarchCarry<typename Traits<ST>::T, NSpecies<V>::value> (&c)[TS - 1],
+                                             int j, int q, int ny, __amdgpu_buffer_rsrc_t dst, uint32_t pstride_b,
+                                             uint32_t pitch_b, uint32_t col_b, bool store_lane, bool nt) {
+    using T = typename Traits<ST>::T;
+    using C = typename Traits<ST>::C;
+    constexpr int NS = NSpecies<V>::value;
+    if constexpr (K == TS) {
+        // the last level: row q is the launch's result (active from j >= 2(TS-1))
+        if (j >= 2 * (TS - 1) && store_lane && q < ny) {
+            const uint32_t row = (uint32_t)q * pitch_b;
+            if (nt) {
+#pragma unroll
+                for (int s = 0; s < NS; ++s)
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) buf_store<T, true>(dst, col_b, (uint32_t)(s * 9 + i) * pstride_b + row, o[s][i]);
+            } else {
+#pragma unroll
+                for (int s = 0; s < NS; ++s)
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) buf_store<T>(dst, col_b, (uint32_t)(s * 9 + i) * pstride_b + row, o[s][i]);
+            }
+        }
+    } else {
+        MarchCarry<T, NS> &m = c[K - 1];
+        C f[NS][9];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            f[s][4] = decode_dev<ST>(o[s][4]);               // e = ( 0,-1): row q, own column
+            f[s][7] = decode_dev<ST>(from_right(o[s][7]));   // e = (-1,-1): row q, column x+1
+            f[s][8] = decode_dev<ST>(from_left(o[s][8]));    // e = ( 1,-1): row q, column x-1
+            f[s][0] = decode_dev<ST>(m.a[s][0]);             // row q-1
+            f[s][1] = decode_dev<ST>(m.a[s][1]);
+            f[s][3] = decode_dev<ST>(m.a[s][2]);
+            f[s][2] = decode_dev<ST>(m.b[P][s][0]);          // row q-2
+            f[s][5] = decode_dev<ST>(m.b[P][s][1]);
+            f[s][6] = decode_dev<ST>(m.b[P][s][2]);
+            m.a[s][0] = o[s][0];
+            m.a[s][1] = from_left(o[s][1]);      // e = ( 1, 0)
+            m.a[s][2] = from_right(o[s][3]);     // e = (-1, 0)
+            m.b[P][s][0] = o[s][2];              // e = ( 0, 1)
+            m.b[P][s][1] = from_left(o[s][5]);   // e = ( 1, 1)
+            m.b[P][s][2] = from_right(o[s][6]);  // e = (-1, 1)
+        }
+        if (j >= 2 * K) {
+            T o2[NS][9];
+            collide_site<ST, V>(p, f, o2, kShear<V> ? wrap_mod(q - 1, ny) : 0);
+            march_levels<ST, V, TS, K + 1, P>(p, o2, c, j, q - 1, ny, dst, pstride_b, pitch_b, col_b, store_lane,
+                                              nt);
+        }
+    }
+}
+
+// TS steps per launch (2 .. 8) on marching wave strips: g.tw = 64 - 2(TS-1)
+// result columns per strip, g.th rows per segment, g.ntx strips across and
+// g.nty segments down, one wave each (g.ntiles of them); buffers below 4 GiB.
+template <int ST, int V, int TS>
+__global__ __launch_bounds__(256) void k_stepW(GridT g, Params<typename Traits<ST>::C> p) {
+    using T = typename Traits<ST>::T;
+    using C = typename Traits<ST>::C;
+    constexpr int NS = NSpecies<V>::value;
+    constexpr int H = TS - 1;
+    constexpr int U = 64 - 2 * H;
+    constexpr uint32_t B = sizeof(T);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int b = g.xcd_order ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int w = b * (int)(blockDim.x >> 6) + wave;
+    if (w >= (int)g.ntiles) return;
+    const int nx = g.nx, ny = g.ny;
+    const int sy = w / g.ntx, sx = w - sy * g.ntx;
+    const int x0 = sx * U, y0 = sy * g.th;
+    const int rows = min(g.th, ny - y0);
+    const int xc = x0 - H + lane;   // this lane's column, before the periodic wrap
+    const uint32_t cx[3] = {(uint32_t)wrap_mod(xc - 1, nx) * B, (uint32_t)wrap_mod(xc, nx) * B,
+                            (uint32_t)wrap_mod(xc + 1, nx) * B};
+    const bool store_lane = lane >= H && lane < H + U && xc < nx;
+    const __amdgpu_buffer_rsrc_t src = buffer_rsrc(g.src, g.bytes), dst = buffer_rsrc(g.dst, g.bytes);
+    const uint32_t pitch_b = (uint32_t)g.pitch * B, pstride_b = (uint32_t)g.pstride * B;
+    const bool nt = g.nt_store != 0;
+    const int iters = rows + 2 * H;
+    MarchCarry<T, NS> c[TS - 1];
+    // the source values of level 1 for iteration j: plane i at row r - e_iy,
+    // column x - e_ix (r = y0 - h + j), loaded two iterations ahead into
+    // raw[j & 1] (about two iterations of arithmetic hide the memory latency)
+    T raw[2][NS][9];
+    auto load_row = [&](auto parity, int r) {
+        constexpr int P = decltype(parity)::value;
+        const uint32_t ry[3] = {(uint32_t)wrap_mod(r - 1, ny) * pitch_b, (uint32_t)wrap_mod(r, ny) * pitch_b,
+                                (uint32_t)wrap_mod(r + 1, ny) * pitch_b};
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                raw[P][s][i] = buf_load<T>(src, cx[1 - kEx[i]], (uint32_t)(s * 9 + i) * pstride_b + ry[1 - kEy[i]]);
+    };
+    // one iteration of parity P: level 1 at row r = y0 - h + j from the
+    // prefetched values, the values of iteration j + 2 requested, then the
+    // levels above
+    auto iteration = [&](auto parity, int j) {
+        constexpr int P = decltype(parity)::value;
+        const int r = y0 - H + j;
+        C f[NS][9];
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int i = 0; i < 9; ++i) f[s][i] = decode_dev<ST>(raw[P][s][i]);
+        if (j + 2 < iters) load_row(parity, r + 2);
+        T o[NS][9];
+        collide_site<ST, V>(p, f, o, kShear<V> ? wrap_mod(r, ny) : 0);
+        march_levels<ST, V, TS, 1, P>(p, o, c, j, r, ny, dst, pstride_b, pitch_b, cx[1], store_lane, nt);
+    };
+    load_row(std::integral_constant<int, 0>{}, y0 - H);
+    if (iters > 1) load_row(std::integral_constant<int, 1>{}, y0 - H + 1);
+    int j = 0;
+    for (; j + 1 < iters; j += 2) {
+        iteration(std::integral_constant<int, 0>{}, j);
+        iteration(std::integral_constant<int, 1>{}, j + 1);
+    }
+    if (j < iters) iteration(std::integral_constant<int, 0>{}, j);
 }
 
 }  // namespace lbrd

@@ -109,6 +109,7 @@ struct GridT {
     uint32_t bytes;   // bytes of one buffer below 4 GiB, else 0 (addressed plane by plane)
     uint32_t plane_bytes;   // bytes of one plane (pstride elements, below 4 GiB)
     int nt_store;     // 1: streaming (non-temporal) stores of the result
+    int march;        // 1: marching wave strips (tw = 64 - 2(steps-1) columns, th rows a segment)
 };
 
 constexpr int kMaxFusedSteps = 8;

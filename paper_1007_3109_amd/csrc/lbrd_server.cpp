@@ -137,6 +137,7 @@ struct lbrd_server {
     std::chrono::steady_clock::time_point t0;
     lbrd_server_stats stats;
     double busy_since = -1;
+    double arena_since = 0;   // server clock of the last arena accounting
 
     double now() const {
         return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -153,6 +154,14 @@ void mark_busy(lbrd_server *s) {
         s->stats.busy_s += t - s->busy_since;
         s->busy_since = -1;
     }
+}
+
+// Integral of the arena bytes in use over the server clock, brought up to
+// now; called (with the lock held) before every change of the bytes in use.
+void account_arena(lbrd_server *s) {
+    const double t = s->now();
+    s->stats.arena_used_byte_s += (double)s->arena.used() * (t - s->arena_since);
+    s->arena_since = t;
 }
 
 int blocks_for(const lbrd_server *s) { return 8 * s->cus; }
@@ -256,6 +265,7 @@ void worker_loop(lbrd_server *s) {
             Request *r = &s->reqs.at(id);
             r->mass.resize(r->cfg.nspecies);
             std::vector<double>().swap(r->rho0);
+            account_arena(s);
             s->arena.release(r->off, r->footprint);
             r->done_s = s->now();
             r->state = err == hipSuccess ? 2 : 3;
@@ -284,6 +294,7 @@ void worker_loop(lbrd_server *s) {
                     if ((int)s->resident.size() >= s->sc.max_slots) break;
                     Request &r = s->reqs.at(*it);
                     size_t off = 0;
+                    account_arena(s);
                     if (s->arena.alloc(r.footprint, &off)) {
                         r.off = off;
                         r.state = 1;
@@ -576,6 +587,9 @@ int lbrd_server_stats_get(lbrd_server *s, lbrd_server_stats *out) {
     out->resident = (int64_t)s->resident.size();
     out->queued = (int64_t)s->queue.size();
     out->arena_peak_used = (int64_t)s->arena.peak();
+    account_arena(s);
+    out->arena_used = (int64_t)s->arena.used();
+    out->arena_used_byte_s = s->stats.arena_used_byte_s;
     out->clock_s = s->now();
     if (s->busy_since >= 0) out->busy_s += out->clock_s - s->busy_since;
     return LBRD_OK;

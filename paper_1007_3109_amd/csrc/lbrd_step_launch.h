@@ -88,8 +88,36 @@ inline hipError_t launch_stepT_n(const StepLaunch &sl, const GridT &g, const voi
     }
 }
 
+template <int ST, int V, int TS>
+inline hipError_t launch_stepW_t(const StepLaunch &sl, const GridT &g, const void *params, hipStream_t st) {
+    using C = typename Traits<ST>::C;
+    const Params<C> &p = *static_cast<const Params<C> *>(params);
+    if (g.tw != 64 - 2 * (TS - 1) || g.th < 1 || g.bytes == 0 || sl.waves < 1 || sl.waves > 4)
+        return hipErrorInvalidValue;
+    const int64_t nb = (g.ntiles + sl.waves - 1) / sl.waves;
+    if (nb > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_stepW<ST, V, TS>), dim3((unsigned)nb), dim3(64 * sl.waves), 0, st, g, p);
+    return hipGetLastError();
+}
+
+template <int ST, int V>
+inline hipError_t launch_stepW_n(const StepLaunch &sl, const GridT &g, const void *params, hipStream_t st) {
+    static_assert(kMaxFusedSteps == 8, "instantiate every step count");
+    switch (g.steps) {
+        case 2: return launch_stepW_t<ST, V, 2>(sl, g, params, st);
+        case 3: return launch_stepW_t<ST, V, 3>(sl, g, params, st);
+        case 4: return launch_stepW_t<ST, V, 4>(sl, g, params, st);
+        case 5: return launch_stepW_t<ST, V, 5>(sl, g, params, st);
+        case 6: return launch_stepW_t<ST, V, 6>(sl, g, params, st);
+        case 7: return launch_stepW_t<ST, V, 7>(sl, g, params, st);
+        case 8: return launch_stepW_t<ST, V, 8>(sl, g, params, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <int ST, int V>
 inline hipError_t launch_stepT_w(const StepLaunch &sl, const GridT &g, const void *params, hipStream_t st) {
+    if (g.march) return launch_stepW_n<ST, V>(sl, g, params, st);
     if (!stepT_shape_fits(ST, NSpecies<V>::value, g.tw, g.th, g.steps, sl.waves)) return hipErrorInvalidValue;
     if (g.bytes == 0) {
         // buffers of 4 GiB or more, planes below it: tiles 32 or 64 wide

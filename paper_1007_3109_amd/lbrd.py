@@ -41,12 +41,13 @@ class Tuning(ctypes.Structure):
         ("vec", ctypes.c_int32), ("lanes_x", ctypes.c_int32), ("waves", ctypes.c_int32),
         ("nontemporal", ctypes.c_int32), ("graph_steps", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
         ("plain_order", ctypes.c_int32), ("fused_steps", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
-        ("tile_cols", ctypes.c_int32), ("tile_strip", ctypes.c_int32),
+        ("tile_cols", ctypes.c_int32), ("tile_strip", ctypes.c_int32), ("march_rows", ctypes.c_int32),
     ]
 
     def as_dict(self):
         return {k: getattr(self, k) for k in ("vec", "lanes_x", "waves", "nontemporal", "graph_steps", "blocks_per_cu",
-                                              "plain_order", "fused_steps", "tile_rows", "tile_cols", "tile_strip")}
+                                              "plain_order", "fused_steps", "tile_rows", "tile_cols", "tile_strip",
+                                              "march_rows")}
 
 
 class ServerConfig(ctypes.Structure):
@@ -64,7 +65,8 @@ class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64), ("completed", ctypes.c_int64),
                 ("rejected", ctypes.c_int64), ("resident", ctypes.c_int64), ("queued", ctypes.c_int64),
                 ("species_site_steps", ctypes.c_int64), ("arena_bytes", ctypes.c_int64),
-                ("arena_peak_used", ctypes.c_int64), ("busy_s", ctypes.c_double), ("clock_s", ctypes.c_double)]
+                ("arena_peak_used", ctypes.c_int64), ("busy_s", ctypes.c_double), ("clock_s", ctypes.c_double),
+                ("arena_used", ctypes.c_int64), ("arena_used_byte_s", ctypes.c_double)]
 
 
 class LbrdError(RuntimeError):

@@ -396,6 +396,8 @@ static void server_case(void) {
     EXPECT(lbrd_server_wait(srv, 987654321, 0.01), LBRD_ENOTFOUND);
     lbrd_server_stats st;
     EXPECT(lbrd_server_stats_get(srv, &st), LBRD_OK);
+    CHECK(st.arena_used == 0 && st.arena_used_byte_s >= 0.0 && st.resident == 0, "arena after all retired: %lld",
+          (long long)st.arena_used);
     /* the 1024^2 request exceeds the whole arena: refused at submit, counted */
     CHECK(st.completed == 5 && st.rejected == 1 && st.submitted == 5 && st.arena_peak_used <= (int64_t)arena_bytes,
           "server stats: completed %lld rejected %lld submitted %lld peak %lld", (long long)st.completed,

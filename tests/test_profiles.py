@@ -6,6 +6,7 @@ otherwise the benchmark reports null with the reason.  Every profile summary
 names the command that produced it."""
 from __future__ import annotations
 
+import json
 from pathlib import Path
 
 import bench
@@ -13,23 +14,20 @@ import bench
 ROOT = Path(__file__).resolve().parents[1]
 
 
-def _summary():
-    kv = {}
-    for line in (ROOT / bench.TRAFFIC_SUMMARY).read_text().splitlines():
-        if ":" in line and not line.startswith((" ", "#")):
-            k, v = line.split(":", 1)
-            kv[k.strip()] = v.strip()
-    return kv
-
-
 def test_traffic_is_reported_only_for_the_profiled_kernel():
-    kv = _summary()
-    traffic, why = bench.measured_traffic(__import__("json").loads(kv["tuning"]))
-    if kv["source_sha256"] == bench.source_digest():
-        assert traffic == int(kv["traffic_bytes_per_launch"])
-        assert traffic >= int(kv["algorithmic_bytes_per_launch"])
-    else:
-        assert traffic is None and "changed" in why
+    for rel, key, reader in ((bench.TRAFFIC_SUMMARY, "traffic_bytes_per_launch", bench.measured_traffic),
+                             (bench.ISSUE_SUMMARY, "valu_issue_frac", bench.measured_issue)):
+        kv = bench.read_summary(rel)
+        if kv is None:
+            assert reader({})[0] is None
+            continue
+        value, why = reader(json.loads(kv["tuning"]))
+        if kv["source_sha256"] == bench.source_digest():
+            assert value == type(value)(kv[key])
+            if key == "traffic_bytes_per_launch":
+                assert value >= int(kv["algorithmic_bytes_per_launch"])
+        else:
+            assert value is None and "changed" in why
 
 
 def test_every_profile_summary_names_its_command():
