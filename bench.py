@@ -199,6 +199,9 @@ def gs_config(lbrd, workloads, n, storage):
 
 
 def kernel_name(t):
+    if t.fused_steps > 1 and t.march_rows > 0:
+        return (f"k_stepW ({t.fused_steps} steps per launch, marching wave strips of "
+                f"{64 - 2 * (t.fused_steps - 1)} columns x {t.march_rows} rows, {t.waves} waves per workgroup)")
     if t.fused_steps > 1:
         return f"k_stepT ({t.fused_steps} steps per launch, {t.tile_cols} x {t.tile_rows} tiles in LDS)"
     return "k_step (one step per launch)"

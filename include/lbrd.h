@@ -156,8 +156,11 @@ typedef struct lbrd_config {
  *       columns, 2(T-1) of them recomputed halo, and marches down segments of
  *       R rows carrying the launch's intermediate rows in registers (no LDS,
  *       no barriers; only the x-halo is recomputed).  tile_cols, tile_rows and
- *       tile_strip are then ignored.  Batches take 0.  Results are bitwise
- *       identical either way. */
+ *       tile_strip are then ignored.  Ignored when fused_steps = 1 (one-step
+ *       launches); refused (LBRD_EINVAL) with T >= 2 on buffers of 4 GiB or
+ *       more.  lbrd_create chooses it from measurements (marching strips
+ *       where they measured faster: most forms beyond the Infinity Cache).
+ *       Batches take 0.  Results are bitwise identical either way. */
 typedef struct lbrd_tuning {
     int32_t vec;
     int32_t lanes_x;

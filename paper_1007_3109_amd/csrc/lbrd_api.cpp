@@ -440,6 +440,82 @@ int default_strip(const lbrd_solver *h, const lbrd_tuning &t) {
     return across > 2 * strip || narrow16 ? strip : 0;
 }
 
+struct MarchShape {
+    int steps = 0, rows = 0, waves = 0;
+};
+
+// The default marching shape (steps per launch, rows per segment, waves per
+// workgroup), or steps 0 where the LDS tiles measured faster.  Marching
+// strips recompute only the x-halo and keep no tile in LDS, so they win where
+// the state streams from HBM (beyond the 256 MB Infinity Cache, "beyond"),
+// and in FP64 also inside it from 1024^2 sites (FP64 LDS tiles are small);
+// small lattices and FP32/16-bit lattices inside the cache keep the LDS tiles
+// (more workgroups, shorter launches).  Measured per step, marching against
+// the LDS defaults ("big": more than 2048^2 sites):
+//   Gray-Scott and two linear species: FP32 beyond T 7, 64 rows when big
+//     (4096^2: 86.4 against 110.8 us), else 32 (2048^2: 28.3 against 30.8);
+//     16-bit beyond T 6, 64 rows when big (F16 66.1 against 73.3, BF16 69.4
+//     against 75.2), else T 5, 16 rows (19.9 against 20.6); FP64 beyond T 7,
+//     64 rows when big (174 against 307), else T 8, 32 rows (47.0 against
+//     72.3); FP64 inside from 1024^2, one-wave workgroups: T 7, 32 rows (13.8
+//     against 18.2), at 512^2 T 5, 8 rows (4.9 against 6.6).  Inside the
+//     cache FP32 loses (1024^2: 7.5 against 7.1; 256^2: 3.4 against 1.25).
+//   One linear species: FP32 beyond T 8, 32 rows (43.0 against 49.8;
+//     2048^2 10.4 against 14.0); 16-bit beyond T 7, 64 rows when big (31.0
+//     against 39.5), else T 4, 16 rows (9.5 against 9.8); FP64 beyond T 8,
+//     16 rows when big (78.8 against 87.5), else 64 rows, one wave (20.7
+//     against 25.4), inside from 1024^2 T 8, 32 rows, one wave (4.9 against
+//     7.6).
+//   Three species: FP32 beyond T 7, 64 rows when big, else 32, one wave
+//     (157 against 266; 50.6 against 68.3); 16-bit beyond T 5, 16 rows (F16
+//     125 against 155).  Four species: FP32 beyond T 5, 64 rows when big
+//     (276 against 361), else 16 rows, one wave (75.7 against 85.5); 16-bit
+//     even (210 against 205): LDS tiles.
+//   Shear flow, FP32 beyond, big: T 4, 32 rows (one species 78.3 against
+//     109; Gray-Scott 174 against 182).  Uniform velocity, one species,
+//     16-bit beyond: T 6, 64 rows (BF16 36.9 against 42.2).  Gray-Scott with
+//     a uniform velocity measured even or slower (FP32 4096^2 118.6 against
+//     118.2, 2048^2 37.0 against 33.6; F16 79.7 against 80.1): LDS tiles.
+// Forms not measured keep the LDS tiles (FP64 with three or more species,
+// with a velocity, or one species inside the cache below 1024^2).
+MarchShape march_default(const lbrd_solver *h, bool in_cache, int64_t sites) {
+    const int st = h->cfg.storage;
+    const bool f64 = st == LBRD_F64, f32 = st == LBRD_F32, b16 = !f64 && !f32;
+    const bool big = sites > (int64_t)2048 * 2048;
+    switch (variant_of(h->cfg)) {
+        case kGS:
+        case kLin2:
+            if (in_cache) {
+                if (!f64 || sites < (int64_t)512 * 512) return {};
+                return sites < (int64_t)1024 * 1024 ? MarchShape{5, 8, 1} : MarchShape{7, 32, 1};
+            }
+            if (f32) return {7, big ? 64 : 32, 4};
+            if (b16) return big ? MarchShape{6, 64, 4} : MarchShape{5, 16, 4};
+            return big ? MarchShape{7, 64, 4} : MarchShape{8, 32, 4};
+        case kLin1:
+            if (in_cache) return f64 && sites >= (int64_t)1024 * 1024 ? MarchShape{8, 32, 1} : MarchShape{};
+            if (f32) return {8, 32, 4};
+            if (b16) return big ? MarchShape{7, 64, 4} : MarchShape{4, 16, 4};
+            return big ? MarchShape{8, 16, 4} : MarchShape{8, 64, 1};
+        case kLin3:
+            if (in_cache || f64) return {};
+            if (f32) return big ? MarchShape{7, 64, 1} : MarchShape{7, 32, 1};
+            return {5, 16, 4};
+        case kLin4:
+            if (in_cache || !f32) return {};
+            return big ? MarchShape{5, 64, 4} : MarchShape{5, 16, 1};
+        case kShearLin1:
+        case kShearGS:
+            if (in_cache || !f32 || !big) return {};
+            return {4, 32, 4};
+        case kAdvLin1:
+            if (in_cache || !b16) return {};
+            return {6, 64, 4};
+        default:
+            return {};
+    }
+}
+
 bool tuning_valid(const lbrd_solver *h, const lbrd_tuning &t) {
     // the one-step shape is used for every one-step launch (also the odd
     // remainder of a fused run)
@@ -448,7 +524,7 @@ bool tuning_valid(const lbrd_solver *h, const lbrd_tuning &t) {
     if (t.plain_order != 0 && t.plain_order != 1) return false;
     if (t.tile_strip < 0 || t.tile_strip > 65536) return false;
     if (t.march_rows < 0 || t.march_rows > 65536) return false;
-    if (t.march_rows > 0 && (t.fused_steps < 2 || big_buffers(h))) return false;
+    if (t.march_rows > 0 && t.fused_steps >= 2 && big_buffers(h)) return false;
     if (t.graph_steps < 0 || (t.graph_steps & 1) || t.graph_steps > 4096) return false;
     if (t.nontemporal != 0 && t.nontemporal != 1) return false;
     if (t.waves < 1 || t.waves > 16) return false;
@@ -600,6 +676,15 @@ int lbrd_create(const lbrd_config *cfg, void *workspace, size_t bytes, void *str
                         break;
                     }
         if (h->tune.fused_steps > 1) h->tune.tile_strip = default_strip(h, h->tune);
+    }
+    // Marching wave strips replace the LDS tiles where they measured faster.
+    const MarchShape ms = march_default(h, in_cache, sites);
+    if (h->tune.fused_steps > 1 && !big_buffers(h) && ms.steps > 0) {
+        h->tune.fused_steps = ms.steps;
+        h->tune.march_rows = ms.rows;
+        h->tune.waves = ms.waves;
+        h->tune.nontemporal = 0;
+        h->tune.tile_strip = 0;
     }
     // Captured graphs pay where one-step launches on a small lattice are
     // bound by the host's launch rate; multi-step launches keep the GPU busy
@@ -896,11 +981,31 @@ int lbrd_autotune(lbrd_solver *h, int steps, const char *cache_path, lbrd_tuning
                             t.tile_rows = rows;
                             t.tile_cols = cols;
                             t.tile_strip = 0;
+                            t.march_rows = 0;
                             t.graph_steps = 0;
                             if (!tuning_valid(h, t)) continue;
                             t.tile_strip = default_strip(h, t);
                             cands.push_back(t);
                         }
+    // marching wave strips: steps per launch, segment lengths, waves per
+    // workgroup, streaming stores
+    for (int ts = 2; ts <= kMaxFusedSteps; ++ts)
+        for (int rows : {16, 24, 32, 64, 128})
+            for (int w : {1, 4})
+                for (int nt = 0; nt < 2; ++nt) {
+                    lbrd_tuning t = h->tune;
+                    t.vec = default_vec(h->cfg.storage);
+                    t.lanes_x = default_lanes(h->cfg.nx, t.vec);
+                    t.waves = w;
+                    t.nontemporal = nt;
+                    t.plain_order = 0;
+                    t.blocks_per_cu = 0;
+                    t.fused_steps = ts;
+                    t.march_rows = rows;
+                    t.tile_strip = 0;
+                    t.graph_steps = 0;
+                    if (tuning_valid(h, t)) cands.push_back(t);
+                }
     // the state is scratch from here on.  Timings depend a little on the
     // data (an all-zero field runs faster than real states and favours other
     // shapes), so an initialised solver is timed on its own state and an

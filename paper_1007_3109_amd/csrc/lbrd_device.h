@@ -916,7 +916,7 @@ __device__ __forceinline__ void march_levels(const Params<typename Traits<ST>::C
     constexpr int NS = NSpecies<V>::value;
     if constexpr (K == TS) {
         // the last level: row q is the launch's result (active from j >= 2(TS-1))
-        if (j >= 2 * (TS - 1) && store_lane && q < ny) {
+        if (j >= 2 * (TS - 1) && store_lane) {
             const uint32_t row = (uint32_t)q * pitch_b;
             if (nt) {
 #pragma unroll
@@ -1004,8 +1004,8 @@ __global__ __launch_bounds__(256) void k_stepW(GridT g, Params<typename Traits<S
                 raw[P][s][i] = buf_load<T>(src, cx[1 - kEx[i]], (uint32_t)(s * 9 + i) * pstride_b + ry[1 - kEy[i]]);
     };
     // one iteration of parity P: level 1 at row r = y0 - h + j from the
-    // prefetched values, the values of iteration j + 2 requested, then the
-    // levels above
+    // prefetched values, then the values of iteration j + 2 requested, then
+    // the levels above (level k from iteration 2(k-1) on).
     auto iteration = [&](auto parity, int j) {
         constexpr int P = decltype(parity)::value;
         const int r = y0 - H + j;
@@ -1014,19 +1014,27 @@ __global__ __launch_bounds__(256) void k_stepW(GridT g, Params<typename Traits<S
         for (int s = 0; s < NS; ++s)
 #pragma unroll
             for (int i = 0; i < 9; ++i) f[s][i] = decode_dev<ST>(raw[P][s][i]);
-        if (j + 2 < iters) load_row(parity, r + 2);
         T o[NS][9];
         collide_site<ST, V>(p, f, o, kShear<V> ? wrap_mod(r, ny) : 0);
+        // requested once level 1 has consumed raw[P], unconditionally (rows
+        // wrap, so the two past the segment's end are valid rows): a load
+        // under a branch leaves the wait counter unsure at the join, which
+        // then waits for every access in flight, the prefetch included
+        __builtin_amdgcn_sched_barrier(0);
+        load_row(parity, r + 2);
+        __builtin_amdgcn_sched_barrier(0);
         march_levels<ST, V, TS, 1, P>(p, o, c, j, r, ny, dst, pstride_b, pitch_b, cx[1], store_lane, nt);
     };
-    load_row(std::integral_constant<int, 0>{}, y0 - H);
-    if (iters > 1) load_row(std::integral_constant<int, 1>{}, y0 - H + 1);
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    load_row(I0{}, y0 - H);
+    load_row(I1{}, y0 - H + 1);
     int j = 0;
     for (; j + 1 < iters; j += 2) {
-        iteration(std::integral_constant<int, 0>{}, j);
-        iteration(std::integral_constant<int, 1>{}, j + 1);
+        iteration(I0{}, j);
+        iteration(I1{}, j + 1);
     }
-    if (j < iters) iteration(std::integral_constant<int, 0>{}, j);
+    if (j < iters) iteration(I0{}, j);
 }
 
 }  // namespace lbrd

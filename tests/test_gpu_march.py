@@ -67,11 +67,13 @@ def test_march_launch_is_bitwise_identical(storage, reaction, ns):
 def test_march_tuning_limits():
     cfg = _config("f32", "gray_scott", 2, 40, 30)
     s = lbrd.Solver(cfg)
-    for bad in (dict(fused_steps=1, march_rows=8), dict(fused_steps=4, march_rows=-1),
-                dict(fused_steps=4, march_rows=65537)):
+    for bad in (dict(fused_steps=4, march_rows=-1), dict(fused_steps=4, march_rows=65537),
+                dict(fused_steps=1, march_rows=-1)):
         with pytest.raises(lbrd.LbrdError):
             s.set_tuning(graph_steps=0, **bad)
     s.set_tuning(fused_steps=4, march_rows=65536, graph_steps=0)
+    s.set_tuning(fused_steps=1, graph_steps=0)       # one-step launches ignore march_rows
+    assert s.tuning().march_rows == 65536 and s.tuning().fused_steps == 1
     s.close()
 
 

@@ -853,8 +853,10 @@ def test_multi_step_launch_is_bitwise_identical(storage, reaction, ns):
 def test_default_shape_for_every_species_count(storage):
     """The default launch shape, chosen from the bytes of a site and whether
     the state fits in the Infinity Cache, is a valid multi-step shape for 1 to
-    4 species on a small and on a cache-exceeding lattice, and a ragged number
-    of steps with it equals one-step launches bitwise."""
+    4 species on a small and on a cache-exceeding lattice (LDS tiles of 8
+    waves on the small one; marching strips beyond the cache for one and two
+    species, and for the forms of more species where they measured faster),
+    and a ragged number of steps with it equals one-step launches bitwise."""
     b = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[storage]
     for ns in (1, 2, 3, 4):
         beyond = int(math.ceil(math.sqrt(300e6 / (2 * 9 * ns * b))))
@@ -863,8 +865,14 @@ def test_default_shape_for_every_species_count(storage):
                                    K=-0.01 * np.eye(ns), rho_ref=(0.3,) * ns)
             s = lbrd.Solver(cfg)
             t = s.tuning()
-            assert 2 <= t.fused_steps <= 8 and t.waves == 8, (ns, nx, t.as_dict())
-            assert multi_step_shape_fits(b, ns, t.tile_cols, t.tile_rows, t.fused_steps, t.waves)
+            assert 2 <= t.fused_steps <= 8, (ns, nx, t.as_dict())
+            if nx > 96 and ns <= 2:
+                assert t.march_rows > 0, (ns, nx, t.as_dict())
+            if t.march_rows > 0:
+                assert nx > 96 and t.waves in (1, 4), (ns, nx, t.as_dict())
+            else:
+                assert t.march_rows == 0 and t.waves == 8, (ns, nx, t.as_dict())
+                assert multi_step_shape_fits(b, ns, t.tile_cols, t.tile_rows, t.fused_steps, t.waves)
             n = 2 * t.fused_steps + 3
             f0 = np.random.default_rng(ns * 31 + nx).uniform(0.0, 0.1, size=(ns, 9, ny, nx))
             s.set_populations(f0).step(n)
@@ -880,32 +888,45 @@ def test_default_shape_for_every_species_count(storage):
 
 
 def test_default_tile_order():
-    """The default order of multi-step tiles: strips of S tile columns, S half
-    the workgroups one XCD holds at once (LDS-limited, at most 32 waves per
-    CU, CUs / 8 per XCD), when the lattice is more than 2S tiles wide, else
-    row-major (0); the 16-bit forms take strips at exactly 2S tiles too."""
+    """The default order of LDS tiles: strips of S tile columns, S half the
+    workgroups one XCD holds at once (LDS-limited, at most 32 waves per CU,
+    CUs / 8 per XCD), when the lattice is more than 2S tiles wide, else
+    row-major (0); the 16-bit forms take strips at exactly 2S tiles too.
+    Marching strips (the default for one or two species beyond the Infinity
+    Cache, below 4 GiB buffers) take no tile order."""
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     seen = set()
-    for n, storage in ((1024, "f32"), (2048, "f32"), (4096, "f32"), (2048, "f64"), (4096, "f16"), (6144, "f32")):
+    for n, storage, ns in ((1024, "f32", 2), (4096, "f32", 2), (8192, "f32", 2), (4096, "f16", 3),
+                           (2048, "f32", 3), (6144, "f32", 4), (2048, "f64", 3)):
         b = {"f64": 8, "f32": 4, "f16": 2}[storage]
-        extra = dict(rho_ref=(1.0, 0.0)) if storage == "f16" else {}
-        cfg = lbrd.make_config(n, n, 2, tau=workloads.GS_TAU, storage=storage, reaction="gray_scott",
-                               F=workloads.GS_F, k=workloads.GS_K, **extra)
+        if ns == 2:
+            cfg = lbrd.make_config(n, n, 2, tau=workloads.GS_TAU, storage=storage, reaction="gray_scott",
+                                   F=workloads.GS_F, k=workloads.GS_K)
+        else:
+            cfg = lbrd.make_config(n, n, ns, tau=[0.7, 1.2, 0.9, 0.8][:ns], storage=storage, reaction="linear",
+                                   K=-0.01 * np.eye(ns), rho_ref=(0.3,) * ns)
         s = lbrd.Solver(cfg)
         t = s.tuning()
         s.close()
         del s
         torch.cuda.empty_cache()
+        log(f"{n}^2 {storage} N={ns}: T {t.fused_steps}, {t.tile_cols} x {t.tile_rows}, march rows {t.march_rows}, "
+            f"tile_strip {t.tile_strip}")
+        beyond = 2 * 9 * ns * b * n * n > (256 << 20)
+        if ns <= 2 and beyond and 9 * ns * b * n * n < (1 << 32):
+            assert t.march_rows > 0, (n, storage, t.as_dict())
+        if t.march_rows > 0:
+            assert beyond and t.tile_strip == 0, (n, storage, ns, t.as_dict())
+            continue
         h = t.fused_steps - 1
         ew = t.tile_cols + 2 * h
-        stride = 9 * 2 * ew + (ew - 2 - 9 * 2 * ew) % (256 // b)
+        stride = 9 * ns * ew + (ew - 2 - 9 * ns * ew) % (256 // b)
         lds = (t.tile_rows + 2 * h) * stride * b
         per_cu = max(1, min(160 * 1024 // lds, 32 // t.waves))
         strip = max(1, per_cu * max(1, cus // 8) // 2)
         across = -(-n // t.tile_cols)
         want = strip if across > 2 * strip or (b == 2 and across == 2 * strip) else 0
-        log(f"{n}^2 {storage}: T {t.fused_steps}, {t.tile_cols} x {t.tile_rows}, tile_strip {t.tile_strip}")
-        assert t.tile_strip == want, (n, storage, t.as_dict())
+        assert t.tile_strip == want, (n, storage, ns, t.as_dict())
         seen.add(t.tile_strip > 0)
     assert seen == {True, False}
 
