@@ -46,6 +46,14 @@ def feed_kill(eta: float, tau: float) -> tuple[float, float]:
     return F, (tau - 1.0) * F
 
 
+def eta_for_eta_B_minus(x: float) -> float:
+    """eta with eta B~- = x (x >= 2): from B~- = (eta + sqrt(eta^2 - 4)) / 2 of
+    Eq. "reac_diff19", eta^2 = x^2 / (x - 1)."""
+    if x < 2.0:
+        raise ValueError("eta B~- >= 2 on the B~- branch")
+    return x / math.sqrt(x - 1.0)
+
+
 def steady_states(eta: float):
     """Homogeneous steady states (A~, B~) of Eq. "reac_diff18".
 

@@ -75,14 +75,21 @@ def dominant_mode(P: np.ndarray):
 
 
 def phase_diagram(points, Du_over_Dv: float = 8.0, L: int = 64, steps: int = 4000, phi: float = 1e-3,
-                  noise: float = 1e-4, seed: int = 0, storage: str = "f32", device="cuda"):
+                  noise: float = 1e-4, seed: int = 0, storage: str = "f32", device="cuda", zero_offset: float = 0.0,
+                  probe: int = 0):
     """Gray-Scott runs over (eta, tau_GS) points as one batch (Section III.D,
     Figs. 6-8): each lattice starts from the homogeneous state (A~-, B~-) plus
-    phi cos(2 pi x / L) cos(2 pi y / L) and seeded U(-noise, noise) on both
-    species, runs `steps` steps, and reports the power spectrum of v, its
-    dominant mode, the growth of the largest non-zero mode, and the linear
-    stability prediction (Hopf line, exact Turing onset, band of unstable
-    wavenumbers in lattice units)."""
+    phi cos(2 pi x / L) cos(2 pi y / L), seeded U(-noise, noise) on both
+    species and `zero_offset` added to v everywhere (a seed of the zero mode,
+    whose growth is the Hopf instability), runs `steps` steps, and reports
+    the power spectrum of v, its dominant mode, the growth of the largest
+    non-zero mode, the amplitude of the zero mode (|mean v - v-|) at the start,
+    after `probe` steps (0: not measured) and at the end, the dominant mode
+    and its growth after `probe` steps too (the linear stage, where the
+    unstable band of Eq. "reac_diff32" applies; a saturated pattern can put
+    its power anywhere), the number of sign changes of mean v - v- at 50
+    samples over the run, and the linear stability prediction (Hopf line,
+    exact Turing onset, band of unstable wavenumbers in lattice units)."""
     import torch
 
     from . import lbrd
@@ -97,25 +104,52 @@ def phase_diagram(points, Du_over_Dv: float = 8.0, L: int = 64, steps: int = 400
         c = analysis.classify(F, k, Du, Dv)
         u, v = analysis.lattice_state(F, k, "-")
         rho0 = workloads.perturbed_state(L, L, u, v, phi, (1, 1)) + rng.uniform(-noise, noise, size=(2, L, L))
+        rho0[1] += zero_offset
         band = analysis.band(c.eta, c.eps2, c.eta_B_minus / c.eta)
         qband = None if band is None else tuple(float(np.sqrt(max(b, 0.0) * F / Du)) for b in band)
         cfgs.append(lbrd.make_config(L, L, 2, tau=taus, storage=storage, reaction="gray_scott", F=F, k=k))
         inits.append(rho0)
-        meta.append(dict(eta=eta, tau=tau, F=F, k=k, hopf_unstable=c.hopf_unstable, turing_unstable=c.turing_unstable,
-                         q_band=qband))
+        meta.append(dict(eta=eta, tau=tau, F=F, k=k, eta_B_minus=c.eta_B_minus, hopf_unstable=c.hopf_unstable,
+                         turing_unstable=c.turing_unstable, q_band=qband, v_minus=v))
     b = lbrd.Batch(cfgs, device=device)
     for i, r in enumerate(inits):
         b.init(i, r)
+    sites = float(L * L)
+
+    def zero_mode(i):
+        return b.moments(i)[1][1] / sites - meta[i]["v_minus"]
+
     p0 = [float(b.spectrum(i, 1).max()) for i in range(len(cfgs))]
-    t0 = time.perf_counter()
-    b.step(steps)
-    torch.cuda.synchronize()
-    secs = time.perf_counter() - t0
+    z0 = [zero_mode(i) for i in range(len(cfgs))]
+    samples = 50
+    marks = sorted({int(round(steps * (q + 1) / samples)) for q in range(samples)} | ({probe} if probe else set()))
+    series = [[] for _ in cfgs]
+    zprobe = [None] * len(cfgs)
+    mprobe = [(None, None, None)] * len(cfgs)
+    done, secs = 0, 0.0
+    for mark in marks:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(mark - done)
+        torch.cuda.synchronize()
+        secs += time.perf_counter() - t0
+        done = mark
+        for i in range(len(cfgs)):
+            z = zero_mode(i)
+            series[i].append(z)
+            if mark == probe:
+                zprobe[i] = abs(z)
+                mprobe[i] = dominant_mode(b.spectrum(i, 1).cpu().numpy())
     out = []
     for i, m in enumerate(meta):
         P = b.spectrum(i, 1).cpu().numpy()
         mode, q, pmax = dominant_mode(P)
-        m.update(mode=mode, q=q, growth=pmax / max(p0[i], 1e-300), spectrum=P)
+        zs = np.array(series[i])
+        m.update(mode=mode, q=q, growth=pmax / max(p0[i], 1e-300), spectrum=P, zero_start=abs(z0[i]),
+                 zero_probe=zprobe[i], zero_end=float(abs(zs[-1])), zero_series=zs, mode_probe=mprobe[i][0],
+                 q_probe=mprobe[i][1],
+                 growth_probe=None if mprobe[i][2] is None else mprobe[i][2] / max(p0[i], 1e-300),
+                 zero_sign_changes=int(np.sum(np.sign(zs[1:]) != np.sign(zs[:-1]))))
         out.append(m)
     b.close()
     return out, {"seconds": secs, "mlups_per_species": 2 * L * L * steps * len(cfgs) / secs / 1e6}

@@ -89,6 +89,58 @@ def test_phase_diagram_signs_and_band():
     assert np.all(oracle.rel_l2(got, ref) <= np.maximum(1e-5, 3 * floor))
 
 
+# (eta B~-, tau_GS) at D_u / D_v = 2: the Hopf line is tau_GS = eta B~-
+# (tr M(0) = 0), the exact Turing onset eps^2 = 2 tau_GS = y+(eta B~-); each
+# point is at least 15 % in tau_GS from both (Turing-only points exist only
+# for eta B~- < 16/7)
+RATIO2_POINTS = [(2.05, 1.2), (2.05, 1.69), (2.05, 2.6), (2.1, 1.86), (3.0, 2.4), (3.0, 3.75), (3.0, 5.6),
+                 (2.2657, 2.733)]
+
+
+def test_phase_diagram_at_the_papers_ratio():
+    """Section III.C-D at the diffusivity ratio of the paper's phase diagram
+    (Fig. 6, D_A / D_B = 2), 256^2 lattices from the B~- state with a small
+    seed of the zero mode (1e-5 on v) and of the other modes (U(-1e-6, 1e-6),
+    no cosine seed): points on both sides of the Hopf line and of the exact
+    Turing onset, including the Fig. 7 point.  Hopf-unstable points
+    (tr M(0) > 0) grow the zero mode by more than 30x within 1000 steps (its
+    linear rate is 0.006 to 0.01 per step), Hopf-stable ones damp it; among the
+    Hopf-stable points the Turing-unstable ones grow a pattern (the largest
+    non-zero mode by more than 100x in power after 1000 steps, still linear:
+    the fastest rates are 0.007 and 0.009 per step, amplitudes stay near
+    1e-3, and at the end of the run) whose dominant wavenumber after 1000
+    steps lies in the linear band (within one lattice mode), and the others
+    decay.  (Saturated, the pattern of the point at tau_GS = 1.69 puts most
+    of its power in a mode far below the band by step 6000.)"""
+    from paper_1007_3109_amd import analysis, studies
+
+    points = [(analysis.eta_for_eta_B_minus(x), tau) for x, tau in RATIO2_POINTS]
+    res, perf = studies.phase_diagram(points, Du_over_Dv=2.0, L=256, steps=6000, phi=0.0, noise=1e-6,
+                                      zero_offset=1e-5, probe=1000)
+    print(f"phase diagram at D_u/D_v = 2: {perf}", flush=True)
+    kinds = set()
+    for (x, tau), r in zip(RATIO2_POINTS, res):
+        zratio = r["zero_probe"] / r["zero_start"]
+        print(f"eta B- {x} tau {tau}: hopf {r['hopf_unstable']} turing {r['turing_unstable']} | zero mode x{zratio:.3g} "
+              f"after 1000 steps, {r['zero_sign_changes']} sign changes, pattern growth {r['growth_probe']:.3g} "
+              f"(mode {r['mode_probe']} q {r['q_probe']:.4f}) after 1000 steps, {r['growth']:.3g} (mode {r['mode']} "
+              f"q {r['q']:.4f}) at the end, band {r['q_band']}", flush=True)
+        assert abs(r["eta_B_minus"] - x) <= 1e-12 * x
+        if r["hopf_unstable"]:
+            assert zratio > 30
+        else:
+            assert zratio < 1
+            if r["turing_unstable"]:
+                lo, hi = r["q_band"]
+                dq = 2 * np.pi / 256
+                assert r["growth_probe"] > 100 and r["growth"] > 100
+                assert lo - dq <= r["q_probe"] <= hi + dq
+            else:
+                assert r["growth"] < 1
+        kinds.add((r["hopf_unstable"], r["turing_unstable"]))
+    assert kinds == {(False, False), (False, True), (True, False), (True, True)}
+
+
 def test_rescaling_study_keeps_stripe_count():
     """Section IV (Figs. 11, 12): at the Turing-regime point eta = 2.016933,
     tau_GS = 2.7303 (D_u / D_v = 2), boxes of side 64 .. 256 with both

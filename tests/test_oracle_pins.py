@@ -697,3 +697,16 @@ def test_mirror_and_rotation_equivariance():
     out = run(fr)
     ok = any(np.abs(np.roll(out, (dy, dx), axis=(2, 3)) - br).max() <= 1e-14 for dy in range(7) for dx in range(7))
     assert ok
+
+
+def test_eta_for_eta_b_minus_inverts_the_steady_state():
+    """eta = x / sqrt(x - 1) gives eta B~- = x on the B~- branch of Eq.
+    "reac_diff19", for the paper's Fig. 7 point (eta B~- = 2.2657 at
+    eta = 2.0139) and across the branch."""
+    for x in (2.0, 2.05, 2.2657, 3.0, 7.5):
+        eta = analysis.eta_for_eta_B_minus(x)
+        A, B = analysis.steady_states(eta)["-"]
+        assert abs(eta * B - x) <= 1e-12 * x
+    assert abs(analysis.eta_for_eta_B_minus(2.2657) - G["fig7_eta"]) <= 2e-4
+    with pytest.raises(ValueError):
+        analysis.eta_for_eta_B_minus(1.9)
