@@ -436,20 +436,57 @@ def serve_leg(torch, lbrd, workloads, n_requests, pool_gb, steps_range, seed=0, 
 
 def rescaling_leg(torch, steps=400000):
     """Section IV length-rescaling study at paper scale (Figs. 11, 12): the
-    Turing-regime point eta = 2.016933, tau_GS = 2.7303 on boxes of side 128 ..
-    512 with diffusivities (L / 128)^2 (0.03, 0.015), 400000 steps (the
-    paper's t), plus control boxes of twice the side with unscaled
-    diffusivities; one batch."""
+    Turing-regime point of the text, eta = 2.014, tau_GS = 2.733 (D_u / D_v =
+    2), on boxes of side 50 .. 500 with diffusivities (L / 100)^2 (0.0625,
+    0.03125) from the cos start, 400000 steps (the paper's t), plus control
+    boxes of twice the side with unscaled diffusivities; one batch.  Reports
+    the stripe count |n| of the dominant mode, the stripes crossed along y / L
+    = 0.85, the range of v on that line and the relative gaps between the
+    profiles of boxes L and 2L."""
     from paper_1007_3109_amd import studies
 
-    sizes = [128, 192, 256, 384, 512]
-    r = studies.rescaling_study(sizes, 128, (0.03, 0.015), 2.016933, 2.7303, steps, start="cos")
-    out = {"workload": f"Gray-Scott eta 2.016933 tau 2.7303, sides {sizes} with D scaled as L^2, {steps} steps, "
-                       f"controls at twice the side with unscaled D",
+    sizes = [50, 100, 200, 400, 500]
+    r = studies.rescaling_study(sizes, 100, (0.0625, 0.03125), 2.014, 2.733, steps, start="cos")
+
+    def crossings(row):
+        d = np.sign(row - row.mean())
+        d[d == 0] = 1
+        return int(np.sum(d != np.roll(d, 1))) // 2
+
+    rows = {L: r["sizes"][L]["v"][int(round(0.85 * L)) % L] for L in sizes}
+    prof = {L: r["sizes"][L]["profile"] for L in sizes}
+    out = {"workload": f"Gray-Scott eta 2.014 tau 2.733, sides {sizes} with D scaled as L^2 (D_u 0.0625 at 100), "
+                       f"{steps} steps, controls at twice the side with unscaled D",
            "stripe_count": {str(L): round(r["sizes"][L]["n"], 2) for L in sizes},
            "q_max_L": {str(L): round(r["sizes"][L]["qL"], 2) for L in sizes},
+           "stripes_along_y_0.85": {str(L): crossings(rows[L]) for L in sizes},
+           "v_range_along_y_0.85": {str(L): [round(float(rows[L].min()), 4), round(float(rows[L].max()), 4)]
+                                    for L in sizes},
+           "profile_gap_L_vs_2L": {f"{L}->{2 * L}": round(float(np.sqrt(((prof[L] - prof[2 * L]) ** 2).mean() /
+                                                                        (prof[2 * L] ** 2).mean())), 4)
+                                   for L in sizes if 2 * L in sizes},
            "control_stripe_count": {f"{a}->{b}": round(c["n"], 2) for (a, b), c in r["control_modes"].items()},
            "seconds": round(r["seconds"], 3), "mlups_per_species": round(r["mlups_per_species"], 1)}
+    torch.cuda.empty_cache()
+    return out
+
+
+def truncation_leg(torch):
+    """Section II.B point-source study (Figs. 1c,d): E_rho against the exact
+    Gaussian for kappa = 0.01 and 0.033 over D, at the same diffusive time
+    D t = C for every D, for C = 2, 4, 8; one FP64 batch of 100^2 lattices per
+    C (per-lattice step counts)."""
+    from paper_1007_3109_amd import studies
+
+    Ds = [0.004, 0.006, 0.008, 0.01, 0.012, 0.015, 0.02, 0.025, 0.03, 0.04, 0.05, 0.06]
+    kappas = [0.01, 0.033]
+    out = {"workload": "point source on 100^2, FP64, t = C / D", "D": Ds, "E_rho": {}, "D_min": {}, "seconds": 0.0}
+    for C in (2.0, 4.0, 8.0):
+        r = studies.truncation_error_sweep(Ds, kappas, C=C)
+        key = f"C={C:g}"
+        out["E_rho"][key] = {f"kappa={k}": [round(float(e), 6) for e in r["E"][a]] for a, k in enumerate(kappas)}
+        out["D_min"][key] = {f"kappa={k}": float(r["D_min"][a]) for a, k in enumerate(kappas)}
+        out["seconds"] = round(out["seconds"] + r["seconds"], 4)
     torch.cuda.empty_cache()
     return out
 
@@ -579,7 +616,8 @@ def copy_leg(torch, nbytes=1 << 30, reps=20):
     return out
 
 
-ALL_LEGS = "gs1024_f32,one_step_4096_f32,hbm4096_f16,hbm4096_bf16,batch,serve,precision,rescaling,config1,copy"
+ALL_LEGS = ("gs1024_f32,one_step_4096_f32,hbm4096_f16,hbm4096_bf16,batch,serve,precision,rescaling,truncation,config1,"
+            "copy")
 
 
 def main():
@@ -713,6 +751,9 @@ def main():
         if "rescaling" in legs:
             log("bench: rescaling study")
             extra["rescaling"] = rescaling_leg(torch)
+        if "truncation" in legs:
+            log("bench: truncation-error curves")
+            extra["truncation"] = truncation_leg(torch)
         if "config1" in legs:
             log("bench: 64^2 f64")
             extra["config1"] = config1_leg(torch, lbrd, workloads)
