@@ -300,7 +300,9 @@ def batch_leg(torch, lbrd, workloads, steps, warmup, seed=0):
         solo_ms += s.time_steps(solo_steps)
         s.close()
     solo_mlups = species_sites * solo_steps / (solo_ms / 1e3) / 1e6
-    rl = roofline(1, species_sites, "f32", spl, launch_s, f"k_batch_stepT ({spl} steps per launch)")
+    kname = (f"k_batch_stepW ({spl} steps per launch, marching strips of {t.march_rows} rows)" if t.march_rows > 0
+             else f"k_batch_stepT ({spl} steps per launch, {t.tile_cols} x {t.tile_rows} tiles in LDS)")
+    rl = roofline(1, species_sites, "f32", spl, launch_s, kname)
     out = {"workload": f"{len(insts)} Gray-Scott instances, sides {sorted(set(i.side for i in insts))}, FP32",
            "species_sites": species_sites, "steps": steps, "ms_per_step": round(ms / steps, 4),
            "mlups_per_species": round(mlups, 1), "roofline": rl, "tuning": t.as_dict(),

@@ -160,7 +160,12 @@ typedef struct lbrd_config {
  *       launches); refused (LBRD_EINVAL) with T >= 2 on buffers of 4 GiB or
  *       more.  lbrd_create chooses it from measurements (marching strips
  *       where they measured faster: most forms beyond the Infinity Cache).
- *       Batches take 0.  Results are bitwise identical either way. */
+ *       Batches (FP32 Gray-Scott sets and serving mixes): R > 0 with T >= 2
+ *       runs their multi-step launches on marching strips too (waves 1, 2
+ *       or 4; blocks_per_cu 0 = one wave per strip segment, else a
+ *       persistent grid of that many workgroups per CU); lbrd_batch_create
+ *       chooses them when the batch's buffers exceed the Infinity Cache.
+ *       Results are bitwise identical either way. */
 typedef struct lbrd_tuning {
     int32_t vec;
     int32_t lanes_x;
@@ -316,10 +321,12 @@ int lbrd_batch_spectrum(lbrd_batch *b, int idx, int species, void *out, void *wo
 /* Launch shape of a batch.  Batches whose instances are all Gray-Scott FP32,
  * or all from the serving mix (one-species linear or Gray-Scott without a
  * velocity, in FP32 / F16 / BF16 storage, each buffer below 4 GiB), take
- * fused_steps = T in 2..8 on tile_cols x tile_rows tiles, tile_cols 32 or 64
- * (default 5 steps on 32 x 10 tiles while the buffers fit in the 256 MB
- * Infinity Cache, 7 steps on 32 x 12 beyond it, 8 waves, blocks_per_cu 0 =
- * one workgroup per tile, graph_steps the multiple of 2T nearest 32):
+ * fused_steps = T in 2..8 on tile_cols x tile_rows tiles, tile_cols 32 or 64,
+ * or with march_rows > 0 on marching strips (default 5 steps on 32 x 10
+ * tiles, 8 waves, while the buffers fit in the 256 MB Infinity Cache;
+ * beyond it 7 steps on marching strips of 64 rows, 4 waves; blocks_per_cu 0
+ * = one workgroup per tile or strip segments, graph_steps the multiple of 2T
+ * nearest 32):
  * launch j advances each instance by min(T, its steps left in the chunk), and
  * graph_steps must be a multiple of 2T.  Other batches use persistent
  * one-step launches: fused_steps = 1, waves 1/2/4, blocks_per_cu 1..32,

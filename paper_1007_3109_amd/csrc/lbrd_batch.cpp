@@ -88,8 +88,16 @@ void drop_graph(lbrd_batch *b) {
 }
 
 int steps_per_launch(const lbrd_batch *b) { return b->tune.fused_steps; }
+bool marching(const lbrd_batch *b) { return b->tune.fused_steps > 1 && b->tune.march_rows > 0; }
 
 int64_t blocks_of(const lbrd_batch *b) {
+    if (marching(b)) {
+        // one wave per strip segment, or a persistent grid of blocks_per_cu
+        // workgroups per CU
+        const int64_t need = (b->total_tiles + b->tune.waves - 1) / b->tune.waves;
+        if (b->tune.blocks_per_cu == 0) return std::max<int64_t>(1, need);
+        return std::max<int64_t>(1, std::min<int64_t>((int64_t)b->tune.blocks_per_cu * b->cus, need));
+    }
     if (steps_per_launch(b) > 1) {
         // one workgroup per tile, or a persistent grid of blocks_per_cu per CU
         const int64_t need = b->total_tiles;
@@ -107,7 +115,8 @@ hipError_t retile(lbrd_batch *b) {
     int64_t tiles = 0;
     for (int i = 0; i < b->count; ++i) {
         BatchInst &bi = b->inst[i];
-        set_batch_tiling(bi, b->L[i], steps_per_launch(b), b->tune.tile_rows, b->tune.tile_cols);
+        if (marching(b)) set_batch_tiling_march(bi, b->L[i], steps_per_launch(b), b->tune.march_rows);
+        else set_batch_tiling(bi, b->L[i], steps_per_launch(b), b->tune.tile_rows, b->tune.tile_cols);
         bi.tile_begin = tiles;
         tiles += bi.ntiles;
     }
@@ -140,10 +149,11 @@ hipError_t enqueue(lbrd_batch *b, int64_t launches, hipStream_t st) {
     const int ts = steps_per_launch(b);
     for (int64_t j = 0; j < launches; ++j) {
         hipError_t e =
-            ts > 1 ? launch_batch_stepT(b->d_hdr, b->d_inst, (int)j, blocks_of(b), b->tune.waves, ts, b->tune.tile_rows,
-                                        b->tune.tile_cols, b->set, st)
-                   : launch_batch_step(b->d_hdr, b->d_inst, (int)j, (int)blocks_of(b), b->tune.waves,
-                                       b->tune.nontemporal != 0, b->set, st);
+            marching(b) ? launch_batch_stepW(b->d_hdr, b->d_inst, (int)j, blocks_of(b), b->tune.waves, ts, b->set, st)
+            : ts > 1    ? launch_batch_stepT(b->d_hdr, b->d_inst, (int)j, blocks_of(b), b->tune.waves, ts,
+                                             b->tune.tile_rows, b->tune.tile_cols, b->set, st)
+                        : launch_batch_step(b->d_hdr, b->d_inst, (int)j, (int)blocks_of(b), b->tune.waves,
+                                            b->tune.nontemporal != 0, b->set, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -178,6 +188,8 @@ bool batch_tuning_valid(const lbrd_batch *b, const lbrd_tuning &t) {
     if (!b->multi_ok || t.fused_steps < 2 || t.fused_steps > kMaxBatchFusedSteps) return false;
     if (t.graph_steps % (2 * t.fused_steps)) return false;
     if (t.blocks_per_cu < 0 || t.blocks_per_cu > 32) return false;
+    if (t.march_rows < 0 || t.march_rows > 65536) return false;
+    if (t.march_rows > 0) return t.waves == 1 || t.waves == 2 || t.waves == 4;   // marching strips: no LDS
     return batch_shape_fits(t.fused_steps, t.tile_rows, t.tile_cols, t.waves);
 }
 
@@ -237,24 +249,24 @@ int lbrd_batch_create(const lbrd_config *cfgs, int count, void *workspace, size_
         if (!batch_multi_ok(b->L[i], b->cfg[i].storage)) b->multi_ok = false;
     std::memset(&b->tune, 0, sizeof(b->tune));
     if (b->multi_ok) {
-        // the single-lattice FP32 Gray-Scott shapes (the LDS of both sets is
-        // sized for it): five steps per launch on 32 x 10 tiles while the
-        // buffers fit in the Infinity Cache, seven on 32 x 12 beyond it
-        // (256-instance sweep: 221 us per step, against 261 with four steps
-        // on 64 x 8), one workgroup of 8 waves per tile, streaming stores
-        // beyond the cache, graphs of about 32 steps (an even number of
-        // launches)
+        // the single-lattice FP32 Gray-Scott shapes: while the buffers fit in
+        // the Infinity Cache, five steps per launch on 32 x 10 LDS tiles (the
+        // LDS of both sets is sized for it), one workgroup of 8 waves per
+        // tile; beyond it, marching wave strips (seven steps per launch,
+        // segments of 64 rows, one wave per segment, four to a workgroup);
+        // graphs of about 32 steps (an even number of launches)
         size_t bytes = 0;
         for (const Layout &L : b->L) bytes += 2 * L.buf_bytes;
         const bool in_cache = bytes <= ((size_t)256 << 20);
         b->tune.fused_steps = in_cache ? 5 : 7;
-        b->tune.tile_rows = in_cache ? 10 : 12;
-        b->tune.tile_cols = 32;
-        b->tune.waves = 8;
+        b->tune.tile_rows = in_cache ? 10 : 0;
+        b->tune.tile_cols = in_cache ? 32 : 0;
+        b->tune.march_rows = in_cache ? 0 : 64;
+        b->tune.waves = in_cache ? 8 : 4;
         b->tune.blocks_per_cu = 0;
         const int unit = 2 * b->tune.fused_steps;
         b->tune.graph_steps = std::max(1, (32 + unit / 2) / unit) * unit;
-        b->tune.nontemporal = in_cache ? 0 : 1;
+        b->tune.nontemporal = 0;
     } else {
         b->tune.fused_steps = 1;
         b->tune.waves = 4;
@@ -473,14 +485,15 @@ int lbrd_batch_set_tuning(lbrd_batch *b, const lbrd_tuning *t) {
     n.lanes_x = 0;
     n.plain_order = 0;
     n.tile_strip = 0;
-    n.march_rows = 0;
-    if (n.fused_steps == 1) n.tile_rows = 0;
-    if (n.fused_steps == 1) n.tile_cols = 0;
+    if (n.fused_steps == 1) n.march_rows = 0;
+    if (n.fused_steps == 1 || n.march_rows > 0) n.tile_rows = 0;
+    if (n.fused_steps == 1 || n.march_rows > 0) n.tile_cols = 0;
     else if (n.tile_cols == 0) n.tile_cols = 64;
     if (!batch_tuning_valid(b, n)) return LBRD_EINVAL;
     if (std::memcmp(&n, &b->tune, sizeof(n)) == 0) return LBRD_OK;
     const bool tiling = n.fused_steps != b->tune.fused_steps || n.tile_rows != b->tune.tile_rows ||
-                        n.tile_cols != b->tune.tile_cols || n.nontemporal != b->tune.nontemporal;
+                        n.tile_cols != b->tune.tile_cols || n.nontemporal != b->tune.nontemporal ||
+                        n.march_rows != b->tune.march_rows;
     drop_graph(b);
     b->tune = n;
     if (tiling) {
@@ -558,8 +571,23 @@ int lbrd_batch_autotune(lbrd_batch *b, int steps, lbrd_tuning *chosen) {
                         t.blocks_per_cu = 0;
                         t.waves = w;
                         t.nontemporal = nt;
+                        t.march_rows = 0;
                         cands.push_back(t);
                     }
+    if (b->multi_ok)
+        for (int ts = 4; ts <= kMaxBatchFusedSteps; ++ts)
+            for (int rows : {16, 32, 64})
+                for (int w : {1, 4}) {
+                    lbrd_tuning t = keep;
+                    t.fused_steps = ts;
+                    t.march_rows = rows;
+                    t.tile_cols = 0;
+                    t.tile_rows = 0;
+                    t.blocks_per_cu = 0;
+                    t.waves = w;
+                    t.nontemporal = 0;
+                    cands.push_back(t);
+                }
     lbrd_tuning best = keep;
     double best_ms = 1e300;
     for (lbrd_tuning t : cands) {

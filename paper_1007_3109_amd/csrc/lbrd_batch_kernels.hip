@@ -203,6 +203,120 @@ hipError_t launch_batch_stepT(const BatchHeader *hdr, const BatchInst *inst, int
     }
 }
 
+// ------------------------------------------ marching strips in batches --
+
+template <int ST, int V, int TS>
+__device__ __forceinline__ void batch_stripW(const BatchInst &bi, int j, int64_t local, int m, bool nt, int lane) {
+    using T = typename Traits<ST>::T;
+    constexpr int U = 64 - 2 * (TS - 1);
+    const int in = bi.cur ^ (j & 1);
+    const int sy = (int)(local / bi.mt_ntx), sx = (int)(local - (int64_t)sy * bi.mt_ntx);
+    StripW sw;
+    sw.src = buffer_rsrc(bi.buf[in], bi.bytes);
+    sw.dst = buffer_rsrc(bi.buf[in ^ 1], bi.bytes);
+    sw.nx = bi.nx;
+    sw.ny = bi.ny;
+    sw.pitch_b = (uint32_t)bi.pitch * (uint32_t)sizeof(T);
+    sw.pstride_b = (uint32_t)bi.pstride * (uint32_t)sizeof(T);
+    sw.x0 = sx * U;
+    sw.y0 = sy * bi.mt_th;
+    sw.rows = min(bi.mt_th, bi.ny - sw.y0);
+    sw.nt = nt;
+    if constexpr (ST == kF64) stepW_strip<ST, V, TS, true>(sw, bi.pd, lane, m);
+    else stepW_strip<ST, V, TS, true>(sw, bi.pf, lane, m);
+}
+
+// Launch j of a chunk on marching strips, TS steps per launch: each wave
+// walks the global list of strip segments of every instance (a persistent
+// grid, so that a captured graph serves descriptors that change), finds the
+// owning instance by binary search over tile_begin (wave-uniform), and
+// advances it by m = min(TS, steps_i - j TS) steps when m > 0; its buffers
+// alternate once per launch.  No LDS and no barrier: the waves of a
+// workgroup are independent.
+template <int SET, int TS>
+__global__ __launch_bounds__(256) void k_batch_stepW(const BatchHeader *__restrict__ hdr,
+                                                     const BatchInst *__restrict__ inst, int j) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int waves = blockDim.x >> 6;
+    const int count = hdr->count;
+    const bool nt = hdr->nt_store != 0;
+    const int64_t total = hdr->total_tiles;
+    const int64_t stride = (int64_t)gridDim.x * waves;
+    int hint = 0;
+    for (int64_t t = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * waves + wave; t < total; t += stride) {
+        int lo = inst[hint].tile_begin <= t ? hint : 0, hi = count - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (inst[mid].tile_begin <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        hint = lo;
+        const BatchInst &bi = inst[lo];
+        const int64_t done = (int64_t)j * TS;
+        if (done >= bi.steps) continue;
+        const int m = (int)(bi.steps - done < TS ? bi.steps - done : TS);
+        const int64_t local = t - bi.tile_begin;
+        if constexpr (SET == kBatchGSF32) {
+            batch_stripW<kF32, kGS, TS>(bi, j, local, m, nt, lane);
+        } else {
+            const bool gs = bi.variant == kGS;
+            switch (bi.storage) {
+                case kF32:
+                    if (gs) batch_stripW<kF32, kGS, TS>(bi, j, local, m, nt, lane);
+                    else batch_stripW<kF32, kLin1, TS>(bi, j, local, m, nt, lane);
+                    break;
+                case kF16:
+                    if (gs) batch_stripW<kF16, kGS, TS>(bi, j, local, m, nt, lane);
+                    else batch_stripW<kF16, kLin1, TS>(bi, j, local, m, nt, lane);
+                    break;
+                default:
+                    if (gs) batch_stripW<kBF16, kGS, TS>(bi, j, local, m, nt, lane);
+                    else batch_stripW<kBF16, kLin1, TS>(bi, j, local, m, nt, lane);
+                    break;
+            }
+        }
+    }
+}
+
+template <int SET>
+static hipError_t launch_setW(const BatchHeader *hdr, const BatchInst *inst, int j, int64_t blocks, int waves, int ts,
+                              hipStream_t st) {
+    static_assert(kMaxBatchFusedSteps == 8, "instantiate every step count");
+    const dim3 grid((unsigned)blocks), block(64 * waves);
+    switch (ts) {
+        case 2: hipLaunchKernelGGL((k_batch_stepW<SET, 2>), grid, block, 0, st, hdr, inst, j); break;
+        case 3: hipLaunchKernelGGL((k_batch_stepW<SET, 3>), grid, block, 0, st, hdr, inst, j); break;
+        case 4: hipLaunchKernelGGL((k_batch_stepW<SET, 4>), grid, block, 0, st, hdr, inst, j); break;
+        case 5: hipLaunchKernelGGL((k_batch_stepW<SET, 5>), grid, block, 0, st, hdr, inst, j); break;
+        case 6: hipLaunchKernelGGL((k_batch_stepW<SET, 6>), grid, block, 0, st, hdr, inst, j); break;
+        case 7: hipLaunchKernelGGL((k_batch_stepW<SET, 7>), grid, block, 0, st, hdr, inst, j); break;
+        case 8: hipLaunchKernelGGL((k_batch_stepW<SET, 8>), grid, block, 0, st, hdr, inst, j); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_stepW(const BatchHeader *hdr, const BatchInst *inst, int j, int64_t blocks, int waves, int ts,
+                              int set, hipStream_t st) {
+    if (ts < 2 || ts > kMaxBatchFusedSteps || !(waves == 1 || waves == 2 || waves == 4) || blocks < 1 ||
+        blocks > 0x7fffffff)
+        return hipErrorInvalidValue;
+    switch (set) {
+        case kBatchGSF32: return launch_setW<kBatchGSF32>(hdr, inst, j, blocks, waves, ts, st);
+        case kBatchServe: return launch_setW<kBatchServe>(hdr, inst, j, blocks, waves, ts, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+void set_batch_tiling_march(BatchInst &bi, const Layout &L, int ts, int rows) {
+    const int cols = 64 - 2 * (ts - 1);
+    bi.mt_th = rows;
+    bi.mt_ntx = (L.nx + cols - 1) / cols;
+    bi.ntiles = (int64_t)bi.mt_ntx * ((L.ny + rows - 1) / rows);
+    bi.bytes = (uint32_t)L.buf_bytes;
+}
+
 bool batch_shape_fits(int ts, int rows, int cols, int waves) {
     return ts >= 2 && ts <= kMaxBatchFusedSteps && (cols == 32 || cols == 64) &&
            stepT_shape_fits(kF32, 2, cols, rows, ts, waves);

@@ -902,34 +902,52 @@ struct MarchCarry {
     T b[2][NS][3];
 };
 
+// Stores row q of the launch's last level: the 9N populations of each
+// result lane.
+template <int ST, int V>
+__device__ __forceinline__ void march_store(typename Traits<ST>::T (&o)[NSpecies<V>::value][9], int q,
+                                            __amdgpu_buffer_rsrc_t dst, uint32_t pstride_b, uint32_t pitch_b,
+                                            uint32_t col_b, bool nt) {
+    using T = typename Traits<ST>::T;
+    constexpr int NS = NSpecies<V>::value;
+    const uint32_t row = (uint32_t)q * pitch_b;
+    if (nt) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int i = 0; i < 9; ++i) buf_store<T, true>(dst, col_b, (uint32_t)(s * 9 + i) * pstride_b + row, o[s][i]);
+    } else {
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int i = 0; i < 9; ++i) buf_store<T>(dst, col_b, (uint32_t)(s * 9 + i) * pstride_b + row, o[s][i]);
+    }
+}
+
 // Level K+1 .. TS of an iteration of parity P, from level K's outputs o (row
 // q) and the carry of level K; level K+1 computes row q-1 when it is active
-// (iteration j >= 2K).  Level TS stores its row.
-template <int ST, int V, int TS, int K, int P>
+// (iteration j >= 2K).  Level TS stores its row.  With RM (a runtime step
+// count m <= TS, the batched launches) level m stores instead, from iteration
+// TS - 1 + m - 1 on (its first row of the segment), and the levels above it
+// are skipped; the wider x-halo of a TS-step strip covers m steps.
+template <int ST, int V, int TS, int K, int P, bool RM = false>
 __device__ __forceinline__ void march_levels(const Params<typename Traits<ST>::C> &p,
                                              typename Traits<ST>::T (&o)[NSpecies<V>::value][9],
                                              MarchCarry<typename Traits<ST>::T, NSpecies<V>::value> (&c)[TS - 1],
                                              int j, int q, int ny, __amdgpu_buffer_rsrc_t dst, uint32_t pstride_b,
-                                             uint32_t pitch_b, uint32_t col_b, bool store_lane, bool nt) {
+                                             uint32_t pitch_b, uint32_t col_b, bool store_lane, bool nt,
+                                             int msteps = TS) {
     using T = typename Traits<ST>::T;
     using C = typename Traits<ST>::C;
     constexpr int NS = NSpecies<V>::value;
+    if constexpr (RM && K < TS) {
+        if (K == msteps && j >= TS - 1 + K - 1 && store_lane)
+            march_store<ST, V>(o, q, dst, pstride_b, pitch_b, col_b, nt);
+    }
     if constexpr (K == TS) {
         // the last level: row q is the launch's result (active from j >= 2(TS-1))
-        if (j >= 2 * (TS - 1) && store_lane) {
-            const uint32_t row = (uint32_t)q * pitch_b;
-            if (nt) {
-#pragma unroll
-                for (int s = 0; s < NS; ++s)
-#pragma unroll
-                    for (int i = 0; i < 9; ++i) buf_store<T, true>(dst, col_b, (uint32_t)(s * 9 + i) * pstride_b + row, o[s][i]);
-            } else {
-#pragma unroll
-                for (int s = 0; s < NS; ++s)
-#pragma unroll
-                    for (int i = 0; i < 9; ++i) buf_store<T>(dst, col_b, (uint32_t)(s * 9 + i) * pstride_b + row, o[s][i]);
-            }
-        }
+        if ((!RM || msteps == TS) && j >= 2 * (TS - 1) && store_lane)
+            march_store<ST, V>(o, q, dst, pstride_b, pitch_b, col_b, nt);
     } else {
         MarchCarry<T, NS> &m = c[K - 1];
         C f[NS][9];
@@ -954,40 +972,43 @@ __device__ __forceinline__ void march_levels(const Params<typename Traits<ST>::C
         if (j >= 2 * K) {
             T o2[NS][9];
             collide_site<ST, V>(p, f, o2, kShear<V> ? wrap_mod(q - 1, ny) : 0);
-            march_levels<ST, V, TS, K + 1, P>(p, o2, c, j, q - 1, ny, dst, pstride_b, pitch_b, col_b, store_lane,
-                                              nt);
+            march_levels<ST, V, TS, K + 1, P, RM>(p, o2, c, j, q - 1, ny, dst, pstride_b, pitch_b, col_b,
+                                                  store_lane, nt, msteps);
         }
     }
 }
 
-// TS steps per launch (2 .. 8) on marching wave strips: g.tw = 64 - 2(TS-1)
-// result columns per strip, g.th rows per segment, g.ntx strips across and
-// g.nty segments down, one wave each (g.ntiles of them); buffers below 4 GiB.
-template <int ST, int V, int TS>
-__global__ __launch_bounds__(256) void k_stepW(GridT g, Params<typename Traits<ST>::C> p) {
+// One wave's strip of a marching launch: columns x0 - (TS-1) .. x0 + 64 -
+// TS (the lanes), result columns x0 .. x0 + 63 - 2(TS-1) below nx, rows y0 ..
+// y0 + rows - 1; buffers below 4 GiB.
+struct StripW {
+    __amdgpu_buffer_rsrc_t src, dst;
+    int nx, ny;
+    uint32_t pitch_b, pstride_b;
+    int x0, y0, rows;
+    bool nt;
+};
+
+// TS steps (or, with RM, m <= TS steps) on one strip.
+template <int ST, int V, int TS, bool RM = false>
+__device__ __forceinline__ void stepW_strip(const StripW &sw, const Params<typename Traits<ST>::C> &p, int lane,
+                                            int m = TS) {
     using T = typename Traits<ST>::T;
     using C = typename Traits<ST>::C;
     constexpr int NS = NSpecies<V>::value;
     constexpr int H = TS - 1;
     constexpr int U = 64 - 2 * H;
     constexpr uint32_t B = sizeof(T);
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int b = g.xcd_order ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    const int w = b * (int)(blockDim.x >> 6) + wave;
-    if (w >= (int)g.ntiles) return;
-    const int nx = g.nx, ny = g.ny;
-    const int sy = w / g.ntx, sx = w - sy * g.ntx;
-    const int x0 = sx * U, y0 = sy * g.th;
-    const int rows = min(g.th, ny - y0);
+    const int nx = sw.nx, ny = sw.ny;
+    const int x0 = sw.x0, y0 = sw.y0, rows = sw.rows;
     const int xc = x0 - H + lane;   // this lane's column, before the periodic wrap
     const uint32_t cx[3] = {(uint32_t)wrap_mod(xc - 1, nx) * B, (uint32_t)wrap_mod(xc, nx) * B,
                             (uint32_t)wrap_mod(xc + 1, nx) * B};
     const bool store_lane = lane >= H && lane < H + U && xc < nx;
-    const __amdgpu_buffer_rsrc_t src = buffer_rsrc(g.src, g.bytes), dst = buffer_rsrc(g.dst, g.bytes);
-    const uint32_t pitch_b = (uint32_t)g.pitch * B, pstride_b = (uint32_t)g.pstride * B;
-    const bool nt = g.nt_store != 0;
-    const int iters = rows + 2 * H;
+    const __amdgpu_buffer_rsrc_t src = sw.src, dst = sw.dst;
+    const uint32_t pitch_b = sw.pitch_b, pstride_b = sw.pstride_b;
+    const bool nt = sw.nt;
+    const int iters = RM ? rows + H + m - 1 : rows + 2 * H;
     MarchCarry<T, NS> c[TS - 1];
     // the source values of level 1 for iteration j: plane i at row r - e_iy,
     // column x - e_ix (r = y0 - h + j), loaded two iterations ahead into
@@ -1023,7 +1044,7 @@ __global__ __launch_bounds__(256) void k_stepW(GridT g, Params<typename Traits<S
         __builtin_amdgcn_sched_barrier(0);
         load_row(parity, r + 2);
         __builtin_amdgcn_sched_barrier(0);
-        march_levels<ST, V, TS, 1, P>(p, o, c, j, r, ny, dst, pstride_b, pitch_b, cx[1], store_lane, nt);
+        march_levels<ST, V, TS, 1, P, RM>(p, o, c, j, r, ny, dst, pstride_b, pitch_b, cx[1], store_lane, nt, m);
     };
     using I0 = std::integral_constant<int, 0>;
     using I1 = std::integral_constant<int, 1>;
@@ -1035,6 +1056,34 @@ __global__ __launch_bounds__(256) void k_stepW(GridT g, Params<typename Traits<S
         iteration(I1{}, j + 1);
     }
     if (j < iters) iteration(I0{}, j);
+}
+
+// TS steps per launch (2 .. 8) on marching wave strips: g.tw = 64 - 2(TS-1)
+// result columns per strip, g.th rows per segment, g.ntx strips across and
+// g.nty segments down, one wave each (g.ntiles of them); buffers below 4 GiB.
+template <int ST, int V, int TS>
+__global__ __launch_bounds__(256) void k_stepW(GridT g, Params<typename Traits<ST>::C> p) {
+    using T = typename Traits<ST>::T;
+    constexpr int U = 64 - 2 * (TS - 1);
+    constexpr uint32_t B = sizeof(T);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int b = g.xcd_order ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int w = b * (int)(blockDim.x >> 6) + wave;
+    if (w >= (int)g.ntiles) return;
+    const int sy = w / g.ntx, sx = w - sy * g.ntx;
+    StripW sw;
+    sw.src = buffer_rsrc(g.src, g.bytes);
+    sw.dst = buffer_rsrc(g.dst, g.bytes);
+    sw.nx = g.nx;
+    sw.ny = g.ny;
+    sw.pitch_b = (uint32_t)g.pitch * B;
+    sw.pstride_b = (uint32_t)g.pstride * B;
+    sw.x0 = sx * U;
+    sw.y0 = sy * g.th;
+    sw.rows = min(g.th, g.ny - sw.y0);
+    sw.nt = g.nt_store != 0;
+    stepW_strip<ST, V, TS>(sw, p, lane);
 }
 
 }  // namespace lbrd

@@ -240,6 +240,17 @@ hipError_t launch_batch_step(const BatchHeader *hdr, const BatchInst *inst, int 
 // `blocks` workgroups of `waves` waves walk the tiles.
 hipError_t launch_batch_stepT(const BatchHeader *hdr, const BatchInst *inst, int j, int64_t blocks, int waves, int ts,
                               int rows, int cols, int set, hipStream_t st);
+// Launch j of a chunk with `ts` steps per launch on marching wave strips
+// (64 - 2(ts-1) result columns by mt_th rows each, no LDS): instance i
+// advances min(ts, steps_i - j ts) steps if that is positive.  Sets
+// kBatchGSF32 and kBatchServe only; the descriptors must carry the marching
+// tiling of the same ts (set_batch_tiling_march).  `blocks` workgroups of
+// `waves` (1, 2 or 4) waves walk the strips.
+hipError_t launch_batch_stepW(const BatchHeader *hdr, const BatchInst *inst, int j, int64_t blocks, int waves, int ts,
+                              int set, hipStream_t st);
+// Fill the tiling fields of a descriptor for marching strips of ts steps and
+// `rows` rows per segment.
+void set_batch_tiling_march(BatchInst &bi, const Layout &L, int ts, int rows);
 // Whether a batched multi-step shape fits (LDS of the largest member of either
 // set, Gray-Scott in FP32).
 bool batch_shape_fits(int ts, int rows, int cols, int waves);

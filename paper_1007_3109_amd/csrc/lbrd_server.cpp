@@ -7,7 +7,9 @@
 //   2. advances every resident request by min(chunk, steps left) with a
 //      replayed graph of persistent batched launches (per-slot step limits
 //      live in device descriptors, so the graph is reused across rounds);
-//      rounds of the serving mix advance seven steps per launch on LDS tiles;
+//      rounds of the serving mix advance seven steps per launch, on
+//      marching wave strips when the resident buffers exceed the Infinity
+//      Cache, else on LDS tiles;
 //   3. enqueues the density read-out of requests that finish in this round
 //      and records an event;
 //   4. while the GPU works on that round, retires the previous round's
@@ -133,7 +135,8 @@ struct lbrd_server {
     bool failed = false;
     int64_t next_id = 1;
     int cus = 256;
-    hipGraphExec_t graph[4] = {nullptr, nullptr, nullptr, nullptr};   // per kernel set; [3]: multi-step serve
+    // per kernel set; [3]: multi-step serve on LDS tiles, [4]: on marching strips
+    hipGraphExec_t graph[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     std::chrono::steady_clock::time_point t0;
     lbrd_server_stats stats;
     double busy_since = -1;
@@ -174,25 +177,40 @@ int blocks_for(const lbrd_server *s) { return 8 * s->cus; }
 // steps on 32 x 10, 0.45 s / 1.77 s / 229 k with six on 32 x 12, and worse
 // with eight on 32 x 8 or seven on 32 x 16.
 constexpr int kServeSteps = 7, kServeRows = 12, kServeCols = 32, kServeWaves = 8, kServeBlocksPerCu = 4;
+// Rounds whose resident buffers exceed the 256 MB Infinity Cache run on
+// marching wave strips instead (the single-lattice default beyond the cache):
+// seven steps per launch, segments of 64 rows, a persistent grid of
+// workgroups of 4 waves (one wave per SIMD, the registers of the
+// Gray-Scott FP32 kernel), kServeMarchBlocksPerCu per CU.
+constexpr int kServeMarchRows = 64, kServeMarchWaves = 4, kServeMarchBlocksPerCu = 2;
 
-hipError_t enqueue_chunk(lbrd_server *s, int set, bool multi, hipStream_t st) {
-    const int64_t launches = launches_for(s->sc.chunk_steps, multi ? kServeSteps : 1);
+// Round kinds: one step per launch (any mix), multi-step on LDS tiles,
+// multi-step on marching strips.
+enum RoundKind : int { kRoundOne = 0, kRoundTiles = 1, kRoundMarch = 2 };
+
+hipError_t enqueue_chunk(lbrd_server *s, int set, int kind, hipStream_t st) {
+    const int64_t launches = launches_for(s->sc.chunk_steps, kind == kRoundOne ? 1 : kServeSteps);
     for (int64_t j = 0; j < launches; ++j) {
-        hipError_t e = multi ? launch_batch_stepT(s->d_hdr, s->d_inst, (int)j, (int64_t)kServeBlocksPerCu * s->cus,
-                                                  kServeWaves, kServeSteps, kServeRows, kServeCols, set, st)
-                             : launch_batch_step(s->d_hdr, s->d_inst, (int)j, blocks_for(s), 4, false, set, st);
+        hipError_t e =
+            kind == kRoundMarch
+                ? launch_batch_stepW(s->d_hdr, s->d_inst, (int)j, (int64_t)kServeMarchBlocksPerCu * s->cus,
+                                     kServeMarchWaves, kServeSteps, set, st)
+            : kind == kRoundTiles
+                ? launch_batch_stepT(s->d_hdr, s->d_inst, (int)j, (int64_t)kServeBlocksPerCu * s->cus, kServeWaves,
+                                     kServeSteps, kServeRows, kServeCols, set, st)
+                : launch_batch_step(s->d_hdr, s->d_inst, (int)j, blocks_for(s), 4, false, set, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
-hipError_t run_chunk(lbrd_server *s, int set, bool multi) {
-    const int slot = multi ? 3 : set;
+hipError_t run_chunk(lbrd_server *s, int set, int kind) {
+    const int slot = kind == kRoundMarch ? 4 : kind == kRoundTiles ? 3 : set;
     if (!s->graph[slot]) {
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamBeginCapture(s->capture, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return e;
-        hipError_t le = enqueue_chunk(s, set, multi, s->capture);
+        hipError_t le = enqueue_chunk(s, set, kind, s->capture);
         e = hipStreamEndCapture(s->capture, &g);
         if (le != hipSuccess) {
             if (g) hipGraphDestroy(g);
@@ -343,13 +361,20 @@ void worker_loop(lbrd_server *s) {
                 if (rp->cfg.storage == LBRD_F64 || !(v == kGS || v == kLin1)) serve = false;
                 if (!batch_multi_ok(rp->L, rp->cfg.storage)) serve = false;
             }
-            const int ts = serve ? kServeSteps : 1;
+            // the round's launch kind from the resident mix: marching strips
+            // once the resident buffers exceed the Infinity Cache, LDS tiles
+            // inside it, one step per launch for mixes outside the serving set
+            size_t bytes = 0;
+            for (Request *rp : resp) bytes += 2 * rp->L.buf_bytes;
+            const int kind = !serve ? kRoundOne : bytes > ((size_t)256 << 20) ? kRoundMarch : kRoundTiles;
+            const int ts = kind == kRoundOne ? 1 : kServeSteps;
             for (Request *rp : resp) {
                 Request &r = *rp;
                 const int vec = batch_vec(r.cfg.storage);
                 BatchInst bi;
                 fill_batch_inst(bi, r.cfg, r.L, slot_buf(s, r, 0), slot_buf(s, r, 1), vec, default_lanes(r.cfg.nx, vec));
-                set_batch_tiling(bi, r.L, ts, kServeRows, kServeCols);
+                if (kind == kRoundMarch) set_batch_tiling_march(bi, r.L, ts, kServeMarchRows);
+                else set_batch_tiling(bi, r.L, ts, kServeRows, kServeCols);
                 bi.tile_begin = tiles;
                 bi.cur = r.cur;
                 bi.steps = (int)std::min<int64_t>(r.left, s->sc.chunk_steps);
@@ -360,14 +385,11 @@ void worker_loop(lbrd_server *s) {
             std::memset(&h, 0, sizeof(h));
             h.count = (int)inst.size();
             h.total_tiles = tiles;
-            // streaming stores once the resident buffers exceed the Infinity Cache
-            size_t bytes = 0;
-            for (Request *rp : resp) bytes += 2 * rp->L.buf_bytes;
-            h.nt_store = serve && bytes > ((size_t)256 << 20) ? 1 : 0;
+            h.nt_store = 0;
             err = hipMemcpyAsync(s->d_inst, inst.data(), sizeof(BatchInst) * inst.size(), hipMemcpyHostToDevice,
                                  s->stream);
             if (err == hipSuccess) err = hipMemcpyAsync(s->d_hdr, &h, sizeof(h), hipMemcpyHostToDevice, s->stream);
-            if (err == hipSuccess) err = run_chunk(s, serve ? kBatchServe : kBatchAny, serve);
+            if (err == hipSuccess) err = run_chunk(s, serve ? kBatchServe : kBatchAny, kind);
             for (size_t q = 0; q < res.size() && err == hipSuccess; ++q) {
                 Request &r = *resp[q];
                 const int taken = inst[q].steps;

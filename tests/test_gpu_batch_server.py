@@ -93,16 +93,17 @@ def test_batch_gs_f32_equals_solo_and_oracle(mode):
 
 def test_full_size_sweep_batch_sampled():
     """The benchmark's batched workload at full size (256 Gray-Scott instances,
-    sides 128..512, seed 0, default launch shape: seven steps per launch on
-    32 x 12 tiles, graphs of 28 steps): after 70 steps (two graph replays and a ragged
-    remainder) a sample of instances equals their solo runs bitwise, and the
-    smallest sampled lattice equals the FP64 oracle within the FP32 floor."""
+    sides 128..512, seed 0, 4.2 GB of buffers, default launch shape: seven
+    steps per launch on marching strips of 64 rows, graphs of 28 steps):
+    after 70 steps (two graph replays and a ragged remainder) a sample of
+    instances equals their solo runs bitwise, and the smallest sampled
+    lattice equals the FP64 oracle within the FP32 floor."""
     insts = workloads.batch_sweep(0)
     cfgs = [lbrd.make_config(i.side, i.side, 2, tau=workloads.GS_TAU, storage="f32", reaction="gray_scott",
                              F=i.F, k=i.k) for i in insts]
     b = lbrd.Batch(cfgs)
     t = b.tuning()
-    assert (t.fused_steps, t.tile_cols, t.tile_rows, t.graph_steps) == (7, 32, 12, 28)
+    assert (t.fused_steps, t.march_rows, t.waves, t.graph_steps) == (7, 64, 4, 28)
     for idx, inst in enumerate(insts):
         b.init(idx, workloads.batch_initial(inst))
     steps = 70
@@ -157,6 +158,69 @@ def test_batch_multi_step_advance_equals_solo(ts, cols, graph_steps, nt):
         b.set_tuning(fused_steps=4, tile_rows=4, tile_cols=128, waves=8, blocks_per_cu=0, graph_steps=0)
 
 
+def march_cases():
+    """The serving mix plus lattices smaller than a strip or a segment (1 x 1,
+    2 x 3, 45 x 70), where strips wrap around the lattice."""
+    extra = []
+    for j, (nx, ny, storage) in enumerate([(1, 1, "f32"), (2, 3, "f16"), (45, 70, "bf16")]):
+        F, k = workloads.draw_gs_unstable(np.random.default_rng(40 + j))
+        cfg = lbrd.make_config(nx, ny, 2, tau=workloads.GS_TAU, storage=storage, reaction="gray_scott", F=F, k=k,
+                               rho_ref=(1.0, 0.0))
+        extra.append((cfg, workloads.gray_scott_square(nx, ny, rng=np.random.default_rng(50 + j))))
+    return serve_mix_cases() + extra
+
+
+@pytest.mark.parametrize("ts,rows,waves,bpc,graph_steps", [(2, 1, 1, 0, 0), (3, 7, 2, 1, 6), (5, 64, 4, 0, 10),
+                                                           (7, 64, 4, 2, 28), (8, 16, 4, 0, 0), (6, 33, 1, 3, 12),
+                                                           (4, 200, 4, 1, 8)])
+def test_batch_march_advance_equals_solo(ts, rows, waves, bpc, graph_steps):
+    """Batched marching strips (march_rows > 0) on the serving mix, T steps per
+    launch, one wave per strip segment or a persistent grid: per-instance
+    step counts that are not multiples of T end with a launch of fewer steps
+    (the wider strip's halo covers them), instances with 0 steps stay put,
+    and every instance equals its solo run bitwise."""
+    cases = march_cases()
+    b = lbrd.Batch([c for c, _ in cases])
+    b.set_tuning(fused_steps=ts, march_rows=rows, waves=waves, blocks_per_cu=bpc, graph_steps=graph_steps,
+                 nontemporal=int(ts % 2 == 0))
+    t = b.tuning()
+    assert (t.fused_steps, t.march_rows, t.tile_cols, t.tile_rows) == (ts, rows, 0, 0)
+    for idx, (_, rho0) in enumerate(cases):
+        b.init(idx, rho0)
+    counts = [1, 2, 3, 0, 5, 23, 7, 11, 4][:len(cases)]
+    b.advance(counts)
+    more = [7, 0, 1, 4, 30, 2, 9, 1, 13][:len(cases)]
+    b.advance(more)
+    b.step(9)
+    for idx, (cfg, rho0) in enumerate(cases):
+        n = counts[idx] + more[idx] + 9
+        assert b.time(idx) == n
+        assert torch.equal(b.moments(idx)[0], solo(cfg, rho0, n)), (idx, n)
+    with pytest.raises(lbrd.LbrdError):                 # one, two or four waves per workgroup
+        b.set_tuning(fused_steps=4, march_rows=8, waves=8, blocks_per_cu=0, graph_steps=0)
+    log(f"batched marching T {ts}, {rows} rows, {waves} waves, blocks per CU {bpc}: {len(cases)} instances bitwise "
+        f"equal to solo runs")
+    b.close()
+
+
+def test_batch_march_gray_scott_set_equals_solo():
+    """The FP32 Gray-Scott batch set on marching strips (the default beyond
+    the Infinity Cache), nine instances of sides 64 and 96 with a graph of 14
+    steps and a ragged remainder: every instance equals its solo run
+    bitwise."""
+    insts = workloads.batch_sweep(2, grid=3, sides=(64, 96))
+    cfgs = [lbrd.make_config(i.side, i.side, 2, tau=workloads.GS_TAU, storage="f32", reaction="gray_scott",
+                             F=i.F, k=i.k) for i in insts]
+    b = lbrd.Batch(cfgs)
+    b.set_tuning(fused_steps=7, march_rows=64, waves=4, blocks_per_cu=0, graph_steps=14)
+    for idx, inst in enumerate(insts):
+        b.init(idx, workloads.batch_initial(inst))
+    b.step(33)
+    for idx, inst in enumerate(insts):
+        assert torch.equal(b.moments(idx)[0], solo(cfgs[idx], workloads.batch_initial(inst), 33)), idx
+    b.close()
+
+
 @pytest.mark.parametrize("graph_steps", [0, 8])
 def test_batch_mixed_storage_and_reactions(graph_steps):
     cases = mixed_cases()
@@ -204,6 +268,9 @@ def test_batch_autotune_then_run():
     t = b.autotune(steps=3)
     if t.fused_steps == 1:
         assert 1 <= t.blocks_per_cu <= 32 and t.waves in (1, 2, 4)
+    elif t.march_rows > 0:
+        assert 4 <= t.fused_steps <= 8 and t.march_rows in (16, 32, 64) and t.waves in (1, 4)
+        assert t.graph_steps % (2 * t.fused_steps) == 0
     else:
         assert 2 <= t.fused_steps <= 8 and t.tile_cols in (32, 64) and t.tile_rows in (4, 8, 12, 16, 20)
         assert t.graph_steps % (2 * t.fused_steps) == 0
@@ -237,6 +304,31 @@ def test_server_results_equal_solo_runs():
     st = srv.stats()
     assert st.completed == len(tickets) and st.resident == 0 and st.queued == 0
     srv.close()
+
+
+def test_server_rounds_beyond_the_cache_equal_solo_runs():
+    """Rounds whose resident buffers exceed the Infinity Cache run on
+    marching strips, the others on LDS tiles: two 2048^2 FP32 Gray-Scott
+    requests (1.2 GB of buffers together) beside small ones of the serving
+    mix; once the large ones finish the rounds go back to LDS tiles.  Every
+    result equals its solo run bitwise."""
+    big = []
+    for j in range(2):
+        F, k = workloads.draw_gs_unstable(np.random.default_rng(70 + j))
+        cfg = lbrd.make_config(2048, 2048, 2, tau=workloads.GS_TAU, storage="f32", reaction="gray_scott", F=F, k=k)
+        big.append((cfg, workloads.gray_scott_square(2048, 2048, rng=np.random.default_rng(80 + j))))
+    cases = big + serve_mix_cases()
+    steps = [23, 9] + [130, 64, 300, 1, 77, 250][:len(cases) - 2]
+    srv = lbrd.Server(arena_bytes=3 << 30, chunk_steps=64)
+    tickets = [srv.submit(cfg, rho0, n) for (cfg, rho0), n in zip(cases, steps)]
+    for t in tickets:
+        srv.wait(t, 300)
+    for t, (cfg, rho0), n in zip(tickets, cases, steps):
+        rho, _, info = srv.take(t)
+        assert info.state == 2
+        assert np.array_equal(rho, solo(cfg, rho0, n).cpu().numpy()), (t, cfg.nx, n)
+    srv.close()
+    log(f"server: {len(cases)} requests, two of them 2048^2 (marching rounds), bitwise equal to solo runs")
 
 
 def test_server_with_an_advected_request_equals_solo():
