@@ -72,6 +72,7 @@ struct lbrd_batch {
     int graph_steps_built = 0;
     int64_t t = 0;
     bool multi_ok = false;          // every instance can take multi-step launches
+    int march_mask = 0;             // classes of the batched marching kernel present
 };
 
 namespace {
@@ -148,12 +149,18 @@ hipError_t upload(lbrd_batch *b, int steps) {
 hipError_t enqueue(lbrd_batch *b, int64_t launches, hipStream_t st) {
     const int ts = steps_per_launch(b);
     for (int64_t j = 0; j < launches; ++j) {
-        hipError_t e =
-            marching(b) ? launch_batch_stepW(b->d_hdr, b->d_inst, (int)j, blocks_of(b), b->tune.waves, ts, b->set, st)
-            : ts > 1    ? launch_batch_stepT(b->d_hdr, b->d_inst, (int)j, blocks_of(b), b->tune.waves, ts,
-                                             b->tune.tile_rows, b->tune.tile_cols, b->set, st)
-                        : launch_batch_step(b->d_hdr, b->d_inst, (int)j, (int)blocks_of(b), b->tune.waves,
-                                            b->tune.nontemporal != 0, b->set, st);
+        hipError_t e = hipSuccess;
+        if (marching(b)) {
+            // one launch per class present (each at its own registers)
+            for (int cls = 0; cls < kMarchClasses && e == hipSuccess; ++cls)
+                if (b->march_mask & (1 << cls))
+                    e = launch_batch_stepW(b->d_hdr, b->d_inst, (int)j, blocks_of(b), b->tune.waves, ts, cls, st);
+        } else {
+            e = ts > 1 ? launch_batch_stepT(b->d_hdr, b->d_inst, (int)j, blocks_of(b), b->tune.waves, ts,
+                                            b->tune.tile_rows, b->tune.tile_cols, b->set, st)
+                       : launch_batch_step(b->d_hdr, b->d_inst, (int)j, (int)blocks_of(b), b->tune.waves,
+                                           b->tune.nontemporal != 0, b->set, st);
+        }
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -245,6 +252,10 @@ int lbrd_batch_create(const lbrd_config *cfgs, int count, void *workspace, size_
     b->set = pick_set(b->cfg);
     b->cus = device_cu_count();
     b->multi_ok = b->set != kBatchAny;
+    for (const lbrd_config &c : b->cfg) {
+        const int cls = march_class(c.storage, variant_of(c));
+        if (cls >= 0) b->march_mask |= 1 << cls;
+    }
     for (int i = 0; i < count; ++i)
         if (!batch_multi_ok(b->L[i], b->cfg[i].storage)) b->multi_ok = false;
     std::memset(&b->tune, 0, sizeof(b->tune));

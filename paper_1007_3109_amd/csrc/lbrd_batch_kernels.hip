@@ -222,18 +222,25 @@ __device__ __forceinline__ void batch_stripW(const BatchInst &bi, int j, int64_t
     sw.y0 = sy * bi.mt_th;
     sw.rows = min(bi.mt_th, bi.ny - sw.y0);
     sw.nt = nt;
-    if constexpr (ST == kF64) stepW_strip<ST, V, TS, true>(sw, bi.pd, lane, m);
-    else stepW_strip<ST, V, TS, true>(sw, bi.pf, lane, m);
+    // a launch of all TS steps runs the single-lattice code (its stores at
+    // one level only leave the levels in one block for the scheduler); a
+    // shorter remainder the code that stores at level m
+    const Params<typename Traits<ST>::C> &p = *reinterpret_cast<const Params<typename Traits<ST>::C> *>(
+        ST == kF64 ? static_cast<const void *>(&bi.pd) : static_cast<const void *>(&bi.pf));
+    if (m == TS) stepW_strip<ST, V, TS>(sw, p, lane);
+    else stepW_strip<ST, V, TS, true>(sw, p, lane, m);
 }
 
-// Launch j of a chunk on marching strips, TS steps per launch: each wave
-// walks the global list of strip segments of every instance (a persistent
-// grid, so that a captured graph serves descriptors that change), finds the
-// owning instance by binary search over tile_begin (wave-uniform), and
-// advances it by m = min(TS, steps_i - j TS) steps when m > 0; its buffers
-// alternate once per launch.  No LDS and no barrier: the waves of a
-// workgroup are independent.
-template <int SET, int TS>
+// Launch j of a chunk on marching strips, TS steps per launch, for the
+// instances of one class (storage ST, reaction variant V): each wave walks
+// the global list of strip segments of every instance (a persistent grid, so
+// that a captured graph serves descriptors that change), finds the owning
+// instance by binary search over tile_begin (wave-uniform), skips instances
+// of other classes, and advances its own by m = min(TS, steps_i - j TS)
+// steps when m > 0; their buffers alternate once per launch.  One kernel per
+// class keeps each class at the registers (and waves per SIMD) of its own
+// update.  No LDS and no barrier: the waves of a workgroup are independent.
+template <int ST, int V, int TS>
 __global__ __launch_bounds__(256) void k_batch_stepW(const BatchHeader *__restrict__ hdr,
                                                      const BatchInst *__restrict__ inst, int j) {
     const int lane = threadIdx.x & 63;
@@ -253,58 +260,50 @@ __global__ __launch_bounds__(256) void k_batch_stepW(const BatchHeader *__restri
         }
         hint = lo;
         const BatchInst &bi = inst[lo];
+        if (bi.storage != ST || bi.variant != V) continue;
         const int64_t done = (int64_t)j * TS;
         if (done >= bi.steps) continue;
         const int m = (int)(bi.steps - done < TS ? bi.steps - done : TS);
-        const int64_t local = t - bi.tile_begin;
-        if constexpr (SET == kBatchGSF32) {
-            batch_stripW<kF32, kGS, TS>(bi, j, local, m, nt, lane);
-        } else {
-            const bool gs = bi.variant == kGS;
-            switch (bi.storage) {
-                case kF32:
-                    if (gs) batch_stripW<kF32, kGS, TS>(bi, j, local, m, nt, lane);
-                    else batch_stripW<kF32, kLin1, TS>(bi, j, local, m, nt, lane);
-                    break;
-                case kF16:
-                    if (gs) batch_stripW<kF16, kGS, TS>(bi, j, local, m, nt, lane);
-                    else batch_stripW<kF16, kLin1, TS>(bi, j, local, m, nt, lane);
-                    break;
-                default:
-                    if (gs) batch_stripW<kBF16, kGS, TS>(bi, j, local, m, nt, lane);
-                    else batch_stripW<kBF16, kLin1, TS>(bi, j, local, m, nt, lane);
-                    break;
-            }
-        }
+        batch_stripW<ST, V, TS>(bi, j, t - bi.tile_begin, m, nt, lane);
     }
 }
 
-template <int SET>
-static hipError_t launch_setW(const BatchHeader *hdr, const BatchInst *inst, int j, int64_t blocks, int waves, int ts,
-                              hipStream_t st) {
+template <int ST, int V>
+static hipError_t launch_classW(const BatchHeader *hdr, const BatchInst *inst, int j, int64_t blocks, int waves,
+                                int ts, hipStream_t st) {
     static_assert(kMaxBatchFusedSteps == 8, "instantiate every step count");
     const dim3 grid((unsigned)blocks), block(64 * waves);
     switch (ts) {
-        case 2: hipLaunchKernelGGL((k_batch_stepW<SET, 2>), grid, block, 0, st, hdr, inst, j); break;
-        case 3: hipLaunchKernelGGL((k_batch_stepW<SET, 3>), grid, block, 0, st, hdr, inst, j); break;
-        case 4: hipLaunchKernelGGL((k_batch_stepW<SET, 4>), grid, block, 0, st, hdr, inst, j); break;
-        case 5: hipLaunchKernelGGL((k_batch_stepW<SET, 5>), grid, block, 0, st, hdr, inst, j); break;
-        case 6: hipLaunchKernelGGL((k_batch_stepW<SET, 6>), grid, block, 0, st, hdr, inst, j); break;
-        case 7: hipLaunchKernelGGL((k_batch_stepW<SET, 7>), grid, block, 0, st, hdr, inst, j); break;
-        case 8: hipLaunchKernelGGL((k_batch_stepW<SET, 8>), grid, block, 0, st, hdr, inst, j); break;
+        case 2: hipLaunchKernelGGL((k_batch_stepW<ST, V, 2>), grid, block, 0, st, hdr, inst, j); break;
+        case 3: hipLaunchKernelGGL((k_batch_stepW<ST, V, 3>), grid, block, 0, st, hdr, inst, j); break;
+        case 4: hipLaunchKernelGGL((k_batch_stepW<ST, V, 4>), grid, block, 0, st, hdr, inst, j); break;
+        case 5: hipLaunchKernelGGL((k_batch_stepW<ST, V, 5>), grid, block, 0, st, hdr, inst, j); break;
+        case 6: hipLaunchKernelGGL((k_batch_stepW<ST, V, 6>), grid, block, 0, st, hdr, inst, j); break;
+        case 7: hipLaunchKernelGGL((k_batch_stepW<ST, V, 7>), grid, block, 0, st, hdr, inst, j); break;
+        case 8: hipLaunchKernelGGL((k_batch_stepW<ST, V, 8>), grid, block, 0, st, hdr, inst, j); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
+int march_class(int storage, int variant) {
+    if (variant != kGS && variant != kLin1) return -1;
+    const int s = storage == kF32 ? 0 : storage == kF16 ? 1 : storage == kBF16 ? 2 : -1;
+    return s < 0 ? -1 : 2 * s + (variant == kGS ? 0 : 1);
+}
+
 hipError_t launch_batch_stepW(const BatchHeader *hdr, const BatchInst *inst, int j, int64_t blocks, int waves, int ts,
-                              int set, hipStream_t st) {
+                              int cls, hipStream_t st) {
     if (ts < 2 || ts > kMaxBatchFusedSteps || !(waves == 1 || waves == 2 || waves == 4) || blocks < 1 ||
         blocks > 0x7fffffff)
         return hipErrorInvalidValue;
-    switch (set) {
-        case kBatchGSF32: return launch_setW<kBatchGSF32>(hdr, inst, j, blocks, waves, ts, st);
-        case kBatchServe: return launch_setW<kBatchServe>(hdr, inst, j, blocks, waves, ts, st);
+    switch (cls) {
+        case 0: return launch_classW<kF32, kGS>(hdr, inst, j, blocks, waves, ts, st);
+        case 1: return launch_classW<kF32, kLin1>(hdr, inst, j, blocks, waves, ts, st);
+        case 2: return launch_classW<kF16, kGS>(hdr, inst, j, blocks, waves, ts, st);
+        case 3: return launch_classW<kF16, kLin1>(hdr, inst, j, blocks, waves, ts, st);
+        case 4: return launch_classW<kBF16, kGS>(hdr, inst, j, blocks, waves, ts, st);
+        case 5: return launch_classW<kBF16, kLin1>(hdr, inst, j, blocks, waves, ts, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -240,14 +240,19 @@ hipError_t launch_batch_step(const BatchHeader *hdr, const BatchInst *inst, int 
 // `blocks` workgroups of `waves` waves walk the tiles.
 hipError_t launch_batch_stepT(const BatchHeader *hdr, const BatchInst *inst, int j, int64_t blocks, int waves, int ts,
                               int rows, int cols, int set, hipStream_t st);
+// Classes of the batched marching kernel, one kernel each: (FP32, F16,
+// BF16) x (Gray-Scott, one-species linear), numbered 2 storage + reaction;
+// march_class returns -1 for every other instance.
+constexpr int kMarchClasses = 6;
+int march_class(int storage, int variant);
 // Launch j of a chunk with `ts` steps per launch on marching wave strips
-// (64 - 2(ts-1) result columns by mt_th rows each, no LDS): instance i
-// advances min(ts, steps_i - j ts) steps if that is positive.  Sets
-// kBatchGSF32 and kBatchServe only; the descriptors must carry the marching
+// (64 - 2(ts-1) result columns by mt_th rows each, no LDS) for the instances
+// of class `cls`: each advances min(ts, steps_i - j ts) steps if that is
+// positive; the others are skipped.  The descriptors must carry the marching
 // tiling of the same ts (set_batch_tiling_march).  `blocks` workgroups of
 // `waves` (1, 2 or 4) waves walk the strips.
 hipError_t launch_batch_stepW(const BatchHeader *hdr, const BatchInst *inst, int j, int64_t blocks, int waves, int ts,
-                              int set, hipStream_t st);
+                              int cls, hipStream_t st);
 // Fill the tiling fields of a descriptor for marching strips of ts steps and
 // `rows` rows per segment.
 void set_batch_tiling_march(BatchInst &bi, const Layout &L, int ts, int rows);

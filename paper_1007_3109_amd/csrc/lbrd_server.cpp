@@ -121,6 +121,10 @@ struct lbrd_server {
     hipStream_t stream = nullptr;   // compute (owned)
     hipStream_t copy = nullptr;     // read-back copies
     hipStream_t capture = nullptr;  // graph recording only
+    // one branch per marching kernel class in a recorded round (forked from
+    // and joined back to the capture stream), so that the classes overlap
+    hipStream_t branch[kMarchClasses] = {};
+    hipEvent_t fork = nullptr, join[kMarchClasses] = {};
     BatchHeader *d_hdr = nullptr;
     BatchInst *d_inst = nullptr;
     double *partials = nullptr;
@@ -135,8 +139,10 @@ struct lbrd_server {
     bool failed = false;
     int64_t next_id = 1;
     int cus = 256;
-    // per kernel set; [3]: multi-step serve on LDS tiles, [4]: on marching strips
-    hipGraphExec_t graph[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    // per kernel set; [3]: multi-step serve on LDS tiles
+    hipGraphExec_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
+    // multi-step serve on marching strips, per set of kernel classes present
+    std::map<int, hipGraphExec_t> march_graph;
     std::chrono::steady_clock::time_point t0;
     lbrd_server_stats stats;
     double busy_since = -1;
@@ -179,49 +185,75 @@ int blocks_for(const lbrd_server *s) { return 8 * s->cus; }
 constexpr int kServeSteps = 7, kServeRows = 12, kServeCols = 32, kServeWaves = 8, kServeBlocksPerCu = 4;
 // Rounds whose resident buffers exceed the 256 MB Infinity Cache run on
 // marching wave strips instead (the single-lattice default beyond the cache):
-// seven steps per launch, segments of 64 rows, a persistent grid of
-// workgroups of 4 waves (one wave per SIMD, the registers of the
-// Gray-Scott FP32 kernel), kServeMarchBlocksPerCu per CU.
-constexpr int kServeMarchRows = 64, kServeMarchWaves = 4, kServeMarchBlocksPerCu = 2;
+// seven steps per launch, segments of 64 rows, a persistent grid of one
+// workgroup of 4 waves per CU: one wave per SIMD, all resident at once (the
+// registers of the Gray-Scott FP32 kernel allow one); a second workgroup per
+// CU would wait for the first to finish its whole share (on a 4096^2 FP32
+// lattice: 109 against 93 us per step).
+constexpr int kServeMarchRows = 64, kServeMarchWaves = 4, kServeMarchBlocksPerCu = 1;
 
 // Round kinds: one step per launch (any mix), multi-step on LDS tiles,
 // multi-step on marching strips.
 enum RoundKind : int { kRoundOne = 0, kRoundTiles = 1, kRoundMarch = 2 };
 
-hipError_t enqueue_chunk(lbrd_server *s, int set, int kind, hipStream_t st) {
+hipError_t enqueue_chunk(lbrd_server *s, int set, int kind, int mask, hipStream_t st) {
     const int64_t launches = launches_for(s->sc.chunk_steps, kind == kRoundOne ? 1 : kServeSteps);
+    if (kind == kRoundMarch) {
+        // The classes of a marching round touch disjoint instances: each runs
+        // its chain of launches on a branch of its own, forked from st and
+        // joined back, so one class's tail overlaps the others' work (their
+        // registers let two class kernels share a SIMD).
+        hipError_t e = hipEventRecord(s->fork, st);
+        for (int cls = 0; cls < kMarchClasses && e == hipSuccess; ++cls) {
+            if (!(mask & (1 << cls))) continue;
+            e = hipStreamWaitEvent(s->branch[cls], s->fork, 0);
+            for (int64_t j = 0; j < launches && e == hipSuccess; ++j)
+                e = launch_batch_stepW(s->d_hdr, s->d_inst, (int)j, (int64_t)kServeMarchBlocksPerCu * s->cus,
+                                       kServeMarchWaves, kServeSteps, cls, s->branch[cls]);
+            if (e == hipSuccess) e = hipEventRecord(s->join[cls], s->branch[cls]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(st, s->join[cls], 0);
+        }
+        return e;
+    }
     for (int64_t j = 0; j < launches; ++j) {
-        hipError_t e =
-            kind == kRoundMarch
-                ? launch_batch_stepW(s->d_hdr, s->d_inst, (int)j, (int64_t)kServeMarchBlocksPerCu * s->cus,
-                                     kServeMarchWaves, kServeSteps, set, st)
-            : kind == kRoundTiles
-                ? launch_batch_stepT(s->d_hdr, s->d_inst, (int)j, (int64_t)kServeBlocksPerCu * s->cus, kServeWaves,
-                                     kServeSteps, kServeRows, kServeCols, set, st)
-                : launch_batch_step(s->d_hdr, s->d_inst, (int)j, blocks_for(s), 4, false, set, st);
+        hipError_t e = kind == kRoundTiles
+                           ? launch_batch_stepT(s->d_hdr, s->d_inst, (int)j, (int64_t)kServeBlocksPerCu * s->cus,
+                                                kServeWaves, kServeSteps, kServeRows, kServeCols, set, st)
+                           : launch_batch_step(s->d_hdr, s->d_inst, (int)j, blocks_for(s), 4, false, set, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
-hipError_t run_chunk(lbrd_server *s, int set, int kind) {
-    const int slot = kind == kRoundMarch ? 4 : kind == kRoundTiles ? 3 : set;
-    if (!s->graph[slot]) {
+void release_streams(lbrd_server *s) {
+    for (int c = 0; c < kMarchClasses; ++c) {
+        if (s->branch[c]) hipStreamDestroy(s->branch[c]);
+        if (s->join[c]) hipEventDestroy(s->join[c]);
+    }
+    if (s->fork) hipEventDestroy(s->fork);
+    if (s->capture) hipStreamDestroy(s->capture);
+    if (s->copy) hipStreamDestroy(s->copy);
+    if (s->stream) hipStreamDestroy(s->stream);
+}
+
+hipError_t run_chunk(lbrd_server *s, int set, int kind, int mask) {
+    hipGraphExec_t &slot = kind == kRoundMarch ? s->march_graph[mask] : s->graph[kind == kRoundTiles ? 3 : set];
+    if (!slot) {
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamBeginCapture(s->capture, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return e;
-        hipError_t le = enqueue_chunk(s, set, kind, s->capture);
+        hipError_t le = enqueue_chunk(s, set, kind, mask, s->capture);
         e = hipStreamEndCapture(s->capture, &g);
         if (le != hipSuccess) {
             if (g) hipGraphDestroy(g);
             return le;
         }
         if (e != hipSuccess) return e;
-        e = hipGraphInstantiate(&s->graph[slot], g, nullptr, nullptr, 0);
+        e = hipGraphInstantiate(&slot, g, nullptr, nullptr, 0);
         hipGraphDestroy(g);
         if (e != hipSuccess) return e;
     }
-    return hipGraphLaunch(s->graph[slot], s->stream);
+    return hipGraphLaunch(slot, s->stream);
 }
 
 char *slot_buf(lbrd_server *s, const Request &r, int which) {
@@ -367,6 +399,9 @@ void worker_loop(lbrd_server *s) {
             size_t bytes = 0;
             for (Request *rp : resp) bytes += 2 * rp->L.buf_bytes;
             const int kind = !serve ? kRoundOne : bytes > ((size_t)256 << 20) ? kRoundMarch : kRoundTiles;
+            int mask = 0;
+            if (kind == kRoundMarch)
+                for (Request *rp : resp) mask |= 1 << march_class(rp->cfg.storage, variant_of(rp->cfg));
             const int ts = kind == kRoundOne ? 1 : kServeSteps;
             for (Request *rp : resp) {
                 Request &r = *rp;
@@ -389,7 +424,7 @@ void worker_loop(lbrd_server *s) {
             err = hipMemcpyAsync(s->d_inst, inst.data(), sizeof(BatchInst) * inst.size(), hipMemcpyHostToDevice,
                                  s->stream);
             if (err == hipSuccess) err = hipMemcpyAsync(s->d_hdr, &h, sizeof(h), hipMemcpyHostToDevice, s->stream);
-            if (err == hipSuccess) err = run_chunk(s, serve ? kBatchServe : kBatchAny, kind);
+            if (err == hipSuccess) err = run_chunk(s, serve ? kBatchServe : kBatchAny, kind, mask);
             for (size_t q = 0; q < res.size() && err == hipSuccess; ++q) {
                 Request &r = *resp[q];
                 const int taken = inst[q].steps;
@@ -476,11 +511,14 @@ int lbrd_server_create(const lbrd_server_config *sc, void *arena, size_t bytes, 
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->capture, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->fork, hipEventDisableTiming);
+    for (int c = 0; c < kMarchClasses && e == hipSuccess; ++c) {
+        e = hipStreamCreateWithFlags(&s->branch[c], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&s->join[c], hipEventDisableTiming);
+    }
     if (e != hipSuccess) {
         set_error("server streams", e);
-        if (s->stream) hipStreamDestroy(s->stream);
-        if (s->capture) hipStreamDestroy(s->capture);
-        if (s->copy) hipStreamDestroy(s->copy);
+        release_streams(s);
         delete s;
         return LBRD_EDEVICE;
     }
@@ -509,9 +547,9 @@ int lbrd_server_destroy(lbrd_server *s) {
     if (s->worker.joinable()) s->worker.join();
     for (auto &g : s->graph)
         if (g) hipGraphExecDestroy(g);
-    if (s->capture) hipStreamDestroy(s->capture);
-    if (s->copy) hipStreamDestroy(s->copy);
-    if (s->stream) hipStreamDestroy(s->stream);
+    for (auto &kv : s->march_graph)
+        if (kv.second) hipGraphExecDestroy(kv.second);
+    release_streams(s);
     delete s;
     return LBRD_OK;
 }
