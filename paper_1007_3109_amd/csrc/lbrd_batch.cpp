@@ -73,6 +73,10 @@ struct lbrd_batch {
     int64_t t = 0;
     bool multi_ok = false;          // every instance can take multi-step launches
     int march_mask = 0;             // classes of the batched marching kernel present
+    // with several classes, one branch stream per class (forked from the
+    // launch stream and joined back, also inside a recorded graph)
+    hipStream_t branch[kMarchClasses] = {};
+    hipEvent_t fork = nullptr, join[kMarchClasses] = {};
 };
 
 namespace {
@@ -80,6 +84,15 @@ namespace {
 int fail(const char *where, hipError_t e) {
     set_error(where, e);
     return LBRD_EDEVICE;
+}
+
+void release_streams(lbrd_batch *b) {
+    for (int c = 0; c < kMarchClasses; ++c) {
+        if (b->branch[c]) hipStreamDestroy(b->branch[c]);
+        if (b->join[c]) hipEventDestroy(b->join[c]);
+    }
+    if (b->fork) hipEventDestroy(b->fork);
+    if (b->capture) hipStreamDestroy(b->capture);
 }
 
 void drop_graph(lbrd_batch *b) {
@@ -148,6 +161,21 @@ hipError_t upload(lbrd_batch *b, int steps) {
 // Enqueue the launches j = 0 .. launches-1 of a chunk.
 hipError_t enqueue(lbrd_batch *b, int64_t launches, hipStream_t st) {
     const int ts = steps_per_launch(b);
+    if (marching(b) && b->fork) {
+        // several classes: each runs its chain of launches on a branch of its
+        // own (they touch disjoint instances), so the classes overlap
+        hipError_t e = hipEventRecord(b->fork, st);
+        for (int cls = 0; cls < kMarchClasses && e == hipSuccess; ++cls) {
+            if (!(b->march_mask & (1 << cls))) continue;
+            e = hipStreamWaitEvent(b->branch[cls], b->fork, 0);
+            for (int64_t j = 0; j < launches && e == hipSuccess; ++j)
+                e = launch_batch_stepW(b->d_hdr, b->d_inst, (int)j, blocks_of(b), b->tune.waves, ts, cls,
+                                       b->branch[cls]);
+            if (e == hipSuccess) e = hipEventRecord(b->join[cls], b->branch[cls]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(st, b->join[cls], 0);
+        }
+        return e;
+    }
     for (int64_t j = 0; j < launches; ++j) {
         hipError_t e = hipSuccess;
         if (marching(b)) {
@@ -286,7 +314,16 @@ int lbrd_batch_create(const lbrd_config *cfgs, int count, void *workspace, size_
     }
     hipError_t e = retile(b);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
+    if (e == hipSuccess && __builtin_popcount(b->march_mask) > 1) {
+        e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+        for (int c = 0; c < kMarchClasses && e == hipSuccess; ++c)
+            if (b->march_mask & (1 << c)) {
+                e = hipStreamCreateWithFlags(&b->branch[c], hipStreamNonBlocking);
+                if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join[c], hipEventDisableTiming);
+            }
+    }
     if (e != hipSuccess) {
+        release_streams(b);
         delete b;
         return fail("batch create", e);
     }
@@ -297,7 +334,7 @@ int lbrd_batch_create(const lbrd_config *cfgs, int count, void *workspace, size_
 int lbrd_batch_destroy(lbrd_batch *b) {
     if (!b) return LBRD_OK;
     drop_graph(b);
-    if (b->capture) hipStreamDestroy(b->capture);
+    release_streams(b);
     delete b;
     return LBRD_OK;
 }
