@@ -76,7 +76,7 @@ def dominant_mode(P: np.ndarray):
 
 def phase_diagram(points, Du_over_Dv: float = 8.0, L: int = 64, steps: int = 4000, phi: float = 1e-3,
                   noise: float = 1e-4, seed: int = 0, storage: str = "f32", device="cuda", zero_offset: float = 0.0,
-                  probe: int = 0):
+                  probe: int = 0, samples: int = 50):
     """Gray-Scott runs over (eta, tau_GS) points as one batch (Section III.D,
     Figs. 6-8): each lattice starts from the homogeneous state (A~-, B~-) plus
     phi cos(2 pi x / L) cos(2 pi y / L), seeded U(-noise, noise) on both
@@ -87,8 +87,9 @@ def phase_diagram(points, Du_over_Dv: float = 8.0, L: int = 64, steps: int = 400
     after `probe` steps (0: not measured) and at the end, the dominant mode
     and its growth after `probe` steps too (the linear stage, where the
     unstable band of Eq. "reac_diff32" applies; a saturated pattern can put
-    its power anywhere), the number of sign changes of mean v - v- at 50
-    samples over the run, and the linear stability prediction (Hopf line,
+    its power anywhere), the number of sign changes of mean v - v- at
+    `samples` equally spaced times over the run, and the linear stability
+    prediction (Hopf line,
     exact Turing onset, band of unstable wavenumbers in lattice units)."""
     import torch
 
@@ -121,7 +122,6 @@ def phase_diagram(points, Du_over_Dv: float = 8.0, L: int = 64, steps: int = 400
 
     p0 = [float(b.spectrum(i, 1).max()) for i in range(len(cfgs))]
     z0 = [zero_mode(i) for i in range(len(cfgs))]
-    samples = 50
     marks = sorted({int(round(steps * (q + 1) / samples)) for q in range(samples)} | ({probe} if probe else set()))
     series = [[] for _ in cfgs]
     zprobe = [None] * len(cfgs)

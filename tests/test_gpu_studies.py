@@ -130,7 +130,9 @@ def test_phase_diagram_at_the_papers_ratio():
     no cosine seed): points on both sides of the Hopf line and of the exact
     Turing onset, including the Fig. 7 point.  Hopf-unstable points
     (tr M(0) > 0) grow the zero mode by more than 30x within 1000 steps (its
-    linear rate is 0.006 to 0.01 per step), Hopf-stable ones damp it; among the
+    linear rate is 0.006 to 0.01 per step) and oscillate (its sign, sampled
+    every 30 steps, changes at least twice: the linear periods are 209 to 729
+    steps), Hopf-stable ones damp it; among the
     Hopf-stable points the Turing-unstable ones grow a pattern (the largest
     non-zero mode by more than 100x in power after 1000 steps, still linear:
     the fastest rates are 0.007 and 0.009 per step, amplitudes stay near
@@ -142,7 +144,7 @@ def test_phase_diagram_at_the_papers_ratio():
 
     points = [(analysis.eta_for_eta_B_minus(x), tau) for x, tau in RATIO2_POINTS]
     res, perf = studies.phase_diagram(points, Du_over_Dv=2.0, L=256, steps=6000, phi=0.0, noise=1e-6,
-                                      zero_offset=1e-5, probe=1000)
+                                      zero_offset=1e-5, probe=1000, samples=200)
     print(f"phase diagram at D_u/D_v = 2: {perf}", flush=True)
     kinds = set()
     for (x, tau), r in zip(RATIO2_POINTS, res):
@@ -154,6 +156,7 @@ def test_phase_diagram_at_the_papers_ratio():
         assert abs(r["eta_B_minus"] - x) <= 1e-12 * x
         if r["hopf_unstable"]:
             assert zratio > 30
+            assert r["zero_sign_changes"] >= 2     # an oscillation (the linear period is 209-729 steps)
         else:
             assert zratio < 1
             if r["turing_unstable"]:
