@@ -323,10 +323,10 @@ def serve_leg(torch, lbrd, workloads, n_requests, pool_gb, steps_range, seed=0, 
     resident footprint is rho / (1 - rho) x E[footprint x work] / E[work]),
     with the expectations over this stream's own requests and Theta from the
     plain kernel on a sample of them; while requests arrive, the rate is then
-    corrected every half second from the arena occupancy the server measured
-    over the last two seconds (arrival gaps exponential at the current rate:
-    a Poisson stream with a slowly varying rate).  A fixed `rate` disables
-    the correction."""
+    corrected every half second, by at most 5 %, from the arena occupancy the
+    server measured over the last two seconds (arrival gaps exponential at
+    the current rate: a Poisson stream with a slowly varying rate).  A fixed
+    `rate` disables the correction."""
     import threading
 
     reqs = workloads.request_stream(n_requests, 1.0, seed=seed, steps_range=steps_range)
@@ -358,7 +358,7 @@ def serve_leg(torch, lbrd, workloads, n_requests, pool_gb, steps_range, seed=0, 
     target = occupancy * pool
     rho = target / (target + m)
     controlled = rate is None
-    rate0 = rho * 0.9 * plain / float(work.mean()) if controlled else rate
+    rate0 = rho * plain / float(work.mean()) if controlled else rate
     lam = [rate0]
     srv = lbrd.Server(arena_bytes=int(pool), chunk_steps=500)
     tickets = [None] * len(reqs)
@@ -390,7 +390,10 @@ def serve_leg(torch, lbrd, workloads, n_requests, pool_gb, steps_range, seed=0, 
             if old:
                 c0, b0 = old[-1]
                 occ = (st.arena_used_byte_s - b0) / max(st.clock_s - c0, 1e-9) / st.arena_bytes
-                lam[0] *= float(np.clip((occupancy / max(occ, 0.05)) ** 0.25, 0.9, 1.1))
+                # gentle: the occupancy answers a change of rate only after
+                # about one residence time (seconds), so fast corrections
+                # overshoot
+                lam[0] *= float(np.clip((occupancy / max(occ, 0.05)) ** 0.15, 0.95, 1.05))
                 rates.append(lam[0])
     st_arr = srv.stats()          # the end of the arrivals: occupancy is averaged over the arrival period
     lat = []

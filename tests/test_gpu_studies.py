@@ -130,9 +130,12 @@ def test_phase_diagram_at_the_papers_ratio():
     no cosine seed): points on both sides of the Hopf line and of the exact
     Turing onset, including the Fig. 7 point.  Hopf-unstable points
     (tr M(0) > 0) grow the zero mode by more than 30x within 1000 steps (its
-    linear rate is 0.006 to 0.01 per step) and oscillate (its sign, sampled
-    every 30 steps, changes at least twice: the linear periods are 209 to 729
-    steps), Hopf-stable ones damp it; among the
+    linear rate is 0.006 to 0.01 per step) and oscillate: sampled every 30
+    steps through the linear stage, it follows the two-term recurrence of the
+    forward-Euler map of the linearised reaction, whose fitted roots equal
+    that map's complex eigenvalue pair within 5 % (linear periods 209 to 729
+    steps; the oracle on 64^2 gives 0.03-2.5 %); Hopf-stable points damp it;
+    among the
     Hopf-stable points the Turing-unstable ones grow a pattern (the largest
     non-zero mode by more than 100x in power after 1000 steps, still linear:
     the fastest rates are 0.007 and 0.009 per step, amplitudes stay near
@@ -156,7 +159,26 @@ def test_phase_diagram_at_the_papers_ratio():
         assert abs(r["eta_B_minus"] - x) <= 1e-12 * x
         if r["hopf_unstable"]:
             assert zratio > 30
-            assert r["zero_sign_changes"] >= 2     # an oscillation (the linear period is 209-729 steps)
+            # linear stage (samples every 30 steps while the zero mode stays
+            # below 1e-4 and the fastest spatial mode below 1e-3, as the
+            # linear rates predict): the mean evolves by the forward-Euler map
+            # of the linearised reaction, so its samples obey
+            # z(k+2) = tr(M) z(k+1) - det(M) z(k) with M = (I + J)^30; the
+            # fitted recurrence's roots are M's eigenvalues, a complex pair
+            # outside the unit circle (a growing oscillation)
+            u_m, v_m = analysis.lattice_state(r["F"], r["k"], "-")
+            J = analysis.lattice_linearisation(r["F"], r["k"], 1 / 6, 1 / 12, u_m, v_m, 0.0)
+            zrate = float(np.max(np.linalg.eigvals(J).real))
+            qs = 2 * np.pi * np.arange(1, 129) / 256
+            srate = max(analysis.continuum_growth(r["F"], r["k"], 1 / 6, 1 / 12, u_m, v_m, q * q) for q in qs)
+            t_end = min(600.0, np.log(10.0) / zrate, np.log(1e3) / max(srate, 1e-9))
+            zs = np.asarray(r["zero_series"][:max(6, int(t_end // 30))])
+            (a, b), *_ = np.linalg.lstsq(np.stack([zs[1:-1], zs[:-2]], axis=1), zs[2:], rcond=None)
+            fit = np.sort_complex(np.roots([1.0, -a, -b]))
+            want = np.sort_complex(np.linalg.eigvals(np.linalg.matrix_power(np.eye(2) + J, 30)))
+            print(f"  zero-mode recurrence over {len(zs)} samples: roots {fit}, linear {want}", flush=True)
+            assert np.all(np.abs(fit.imag) > 0) and np.all(np.abs(fit) > 1)
+            assert np.max(np.abs(fit - want)) <= 0.05 * np.abs(want[0])
         else:
             assert zratio < 1
             if r["turing_unstable"]:
