@@ -273,7 +273,29 @@ def solver_leg(torch, lbrd, workloads, n, storage, steps, warmup, tune=False, fu
     return out
 
 
-def batch_leg(torch, lbrd, workloads, steps, warmup, seed=0):
+def batch_cpu_baseline(workloads, insts, steps, sample_every=16, sample_steps=20):
+    """The FP64 oracle on a sample of the sweep's instances (every
+    `sample_every`-th, `sample_steps` steps each from its initial state),
+    extrapolated to the whole sweep at the sampled rate."""
+    import oracle
+
+    work, secs = 0, 0.0
+    for inst in insts[::sample_every]:
+        f = oracle.init(workloads.batch_initial(inst))
+        t0 = time.perf_counter()
+        f = oracle.run(f, sample_steps, list(workloads.GS_TAU), oracle.REACT_GRAY_SCOTT, F=inst.F, k=inst.k)
+        secs += time.perf_counter() - t0
+        work += 2 * inst.side * inst.side * sample_steps
+        del f
+    mlups = work / secs / 1e6
+    total = sum(2 * i.side * i.side for i in insts) * steps
+    return {"value": round(mlups, 2), "unit": "MLUPS per species", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"{len(insts[::sample_every])} of the {len(insts)} instances (every {sample_every}th), "
+                      f"{sample_steps} steps each, {secs:.2f} s",
+            "extrapolated_s_for_the_timed_steps": round(total / (mlups * 1e6), 1)}
+
+
+def batch_leg(torch, lbrd, workloads, steps, warmup, seed=0, cpu=True):
     insts = workloads.batch_sweep(seed)
     cfgs = [lbrd.make_config(i.side, i.side, 2, tau=workloads.GS_TAU, storage="f32", reaction="gray_scott",
                              F=i.F, k=i.k) for i in insts]
@@ -308,6 +330,8 @@ def batch_leg(torch, lbrd, workloads, steps, warmup, seed=0):
            "mlups_per_species": round(mlups, 1), "roofline": rl, "tuning": t.as_dict(),
            "plain_kernel_one_by_one_mlups_per_species": round(solo_mlups, 1),
            "vs_plain_kernel": round(mlups / solo_mlups, 3)}
+    if cpu:
+        out["cpu_baseline"] = batch_cpu_baseline(workloads, insts, steps)
     b.close()
     del b
     torch.cuda.empty_cache()
@@ -744,7 +768,7 @@ def main():
                                                           tune=args.tune)
         if "batch" in legs:
             log("bench: batched sweep")
-            extra["batched"] = batch_leg(torch, lbrd, workloads, 5000, 32)
+            extra["batched"] = batch_leg(torch, lbrd, workloads, 5000, 32, cpu=not args.no_cpu_baseline)
         if "serve" in legs:
             log("bench: serving")
             lo, hi = (int(x) for x in args.serve_steps.split(","))
