@@ -454,8 +454,10 @@ struct MarchShape {
 // the LDS defaults ("big": more than 2048^2 sites):
 //   Gray-Scott and two linear species: FP32 beyond T 7, 64 rows when big
 //     (4096^2: 86.4 against 110.8 us), else 32 (2048^2: 28.3 against 30.8);
-//     16-bit beyond T 6, 64 rows when big (F16 66.1 against 73.3, BF16 69.4
-//     against 75.2), else T 5, 16 rows (19.9 against 20.6); FP64 beyond T 7,
+//     16-bit beyond (the two species' values of a plane packed in one
+//     register) T 7, 64 rows when big (F16 58.0 against 73.3, BF16 58.5
+//     against 75.2), else T 6, 16 rows (F16 18.0, BF16 17.8 against 20.6);
+//     FP64 beyond T 7,
 //     64 rows when big (174 against 307), else T 8, 32 rows (47.0 against
 //     72.3); FP64 inside from 1024^2, one-wave workgroups: T 7, 32 rows (13.8
 //     against 18.2), at 512^2 T 5, 8 rows (4.9 against 6.6).  Inside the
@@ -490,7 +492,7 @@ MarchShape march_default(const lbrd_solver *h, bool in_cache, int64_t sites) {
                 return sites < (int64_t)1024 * 1024 ? MarchShape{5, 8, 1} : MarchShape{7, 32, 1};
             }
             if (f32) return {7, big ? 64 : 32, 4};
-            if (b16) return big ? MarchShape{6, 64, 4} : MarchShape{5, 16, 4};
+            if (b16) return big ? MarchShape{7, 64, 4} : MarchShape{6, 16, 4};
             return big ? MarchShape{7, 64, 4} : MarchShape{8, 32, 4};
         case kLin1:
             if (in_cache) return f64 && sites >= (int64_t)1024 * 1024 ? MarchShape{8, 32, 1} : MarchShape{};

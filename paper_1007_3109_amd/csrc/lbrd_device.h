@@ -129,13 +129,22 @@ __device__ __forceinline__ void encode_pair(float a, float b, uint16_t &oa, uint
     oa = (uint16_t)u;
     ob = (uint16_t)(u >> 16);
 }
-// The 9 NS results of one site, paired in species-major order.
-template <int ST, int NS>
+// The 9 NS results of one site, paired in species-major order; with PM and
+// two species, plane by plane (species 0 and 1 of plane i in one packed
+// word, which the marching kernel moves and keeps as one register).  The
+// rounding of each value is the same either way.
+template <int ST, int NS, bool PM = false>
 __device__ __forceinline__ void encode_sites(const float (&r)[NS][9], uint16_t (&o)[NS][9]) {
+    if constexpr (PM && NS == 2) {
 #pragma unroll
-    for (int k = 0; k + 1 < 9 * NS; k += 2)
-        encode_pair<ST>(r[k / 9][k % 9], r[(k + 1) / 9][(k + 1) % 9], o[k / 9][k % 9], o[(k + 1) / 9][(k + 1) % 9]);
-    if constexpr ((9 * NS) % 2) o[NS - 1][8] = encode_dev<ST>(r[NS - 1][8]);
+        for (int i = 0; i < 9; ++i) encode_pair<ST>(r[0][i], r[1][i], o[0][i], o[1][i]);
+    } else {
+#pragma unroll
+        for (int k = 0; k + 1 < 9 * NS; k += 2)
+            encode_pair<ST>(r[k / 9][k % 9], r[(k + 1) / 9][(k + 1) % 9], o[k / 9][k % 9],
+                            o[(k + 1) / 9][(k + 1) % 9]);
+        if constexpr ((9 * NS) % 2) o[NS - 1][8] = encode_dev<ST>(r[NS - 1][8]);
+    }
 }
 
 // D2Q9 weights w_i (Eq. "Weights") in the compute type.
@@ -245,8 +254,26 @@ __device__ __forceinline__ void shear_ceq(const Params<C> &p, int gy, C (&c)[9])
     }
 }
 
-// gy: the site's row (used by the shear variants only).
-template <int ST, int V>
+// The relaxation f (1 - 1/tau) + e of two species in a 16-bit form, rounded
+// plane by plane: species 0 and 1 of plane i in one packed conversion, each
+// value computed and rounded as in the species-major order.
+template <int ST>
+__device__ __forceinline__ void relax_planes(const Params<float> &p, const float (&f)[2][9], const float (&e)[2][9],
+                                             uint16_t (&o)[2][9]) {
+#pragma clang fp contract(off)
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        float r0 = fma_c(f[0][i], p.keep[0], e[0][i]);
+        float r1 = fma_c(f[1][i], p.keep[1], e[1][i]);
+        asm volatile("" : "+v"(r0));
+        asm volatile("" : "+v"(r1));
+        encode_pair<ST>(r0, r1, o[0][i], o[1][i]);
+    }
+}
+
+// gy: the site's row (used by the shear variants only).  PM: the 16-bit
+// results of two species are rounded plane by plane (encode_sites).
+template <int ST, int V, bool PM = false>
 __device__ __forceinline__ void collide_site(const Params<typename Traits<ST>::C> &p,
                                              const typename Traits<ST>::C (&f)[NSpecies<V>::value][9],
                                              typename Traits<ST>::T (&o)[NSpecies<V>::value][9], int gy) {
@@ -275,22 +302,30 @@ __device__ __forceinline__ void collide_site(const Params<typename Traits<ST>::C
 #pragma unroll
             for (int i = 0; i < 9; ++i) ceq[i] = p.ceq[i];
         }
+        C e[NS][9];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             // c_i m / tau + w_i R for the moving populations; the rest
             // population takes what makes the nine terms sum to m / tau + R
             const C om = p.omega[s] * m[s];
             const C a = om + R[s];
-            C e[9], moving = C(0);
+            C moving = C(0);
 #pragma unroll
             for (int i = 1; i < 9; ++i) {
-                e[i] = fma_c(ceq[i], om, wgt<C>(i) * R[s]);
-                moving += e[i];
+                e[s][i] = fma_c(ceq[i], om, wgt<C>(i) * R[s]);
+                moving += e[s][i];
             }
-            e[0] = a - moving;
+            e[s][0] = a - moving;
+        }
+        if constexpr (PM && kShifted<ST> && NS == 2) {
+            relax_planes<ST>(p, f, e, o);
+            return;
+        }
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
-                C r = fma_c(f[s][i], p.keep[s], e[i]);
+                C r = fma_c(f[s][i], p.keep[s], e[s][i]);
                 if constexpr (kShifted<ST>) {
                     asm volatile("" : "+v"(r));
                     res[s][i] = r;
@@ -299,9 +334,10 @@ __device__ __forceinline__ void collide_site(const Params<typename Traits<ST>::C
                 }
             }
         }
-        if constexpr (kShifted<ST>) encode_sites<ST, NS>(res, o);
+        if constexpr (kShifted<ST>) encode_sites<ST, NS, PM>(res, o);
         return;
     }
+    C ep[NS][9];   // two species in a 16-bit form, plane-major rounding: the e terms
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         // w_i (m / tau + R): the rest weight is taken as 1 - 4/9 - 4/36
@@ -312,6 +348,11 @@ __device__ __forceinline__ void collide_site(const Params<typename Traits<ST>::C
         const C a = fma_c(p.omega[s], m[s], R[s]);
         const C e1 = wgt<C>(1) * a, e5 = wgt<C>(5) * a;
         const C e0 = a - C(4) * e1 - C(4) * e5;   // 4 e1 and 4 e5 are exact
+        if constexpr (PM && kShifted<ST> && NS == 2) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) ep[s][i] = i == 0 ? e0 : (i < 5 ? e1 : e5);
+            continue;
+        }
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             const C e = i == 0 ? e0 : (i < 5 ? e1 : e5);
@@ -328,7 +369,8 @@ __device__ __forceinline__ void collide_site(const Params<typename Traits<ST>::C
             }
         }
     }
-    if constexpr (kShifted<ST>) encode_sites<ST, NS>(res, o);
+    if constexpr (PM && kShifted<ST> && NS == 2) relax_planes<ST>(p, f, ep, o);
+    else if constexpr (kShifted<ST>) encode_sites<ST, NS, PM>(res, o);
 }
 
 // ---------------------------------------------------------- step tile --
@@ -978,6 +1020,65 @@ __device__ __forceinline__ void march_levels(const Params<typename Traits<ST>::C
     }
 }
 
+// Two species in a 16-bit form: the carries hold packed words, species 0 in
+// the low half and species 1 in the high half of plane i's word, so one
+// lane shift moves both species and a carry takes one register per plane.
+struct MarchCarryPk {
+    uint32_t a[3];
+    uint32_t b[2][3];
+};
+
+__device__ __forceinline__ uint32_t pack_planes(uint16_t lo, uint16_t hi) { return (uint32_t)lo | ((uint32_t)hi << 16); }
+__device__ __forceinline__ uint16_t plane_half(uint32_t w, int s) { return s ? (uint16_t)(w >> 16) : (uint16_t)w; }
+
+// march_levels for two species in a 16-bit form on packed words (the same
+// values and the same update; the site's results are rounded plane by plane).
+template <int ST, int V, int TS, int K, int P, bool RM = false>
+__device__ __forceinline__ void march_levels_pk(const Params<float> &p, uint16_t (&o)[2][9], MarchCarryPk (&c)[TS - 1],
+                                                int j, int q, int ny, __amdgpu_buffer_rsrc_t dst, uint32_t pstride_b,
+                                                uint32_t pitch_b, uint32_t col_b, bool store_lane, bool nt,
+                                                int msteps = TS) {
+    if constexpr (RM && K < TS) {
+        if (K == msteps && j >= TS - 1 + K - 1 && store_lane)
+            march_store<ST, V>(o, q, dst, pstride_b, pitch_b, col_b, nt);
+    }
+    if constexpr (K == TS) {
+        if ((!RM || msteps == TS) && j >= 2 * (TS - 1) && store_lane)
+            march_store<ST, V>(o, q, dst, pstride_b, pitch_b, col_b, nt);
+    } else {
+        MarchCarryPk &m = c[K - 1];
+        uint32_t w[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) w[i] = pack_planes(o[0][i], o[1][i]);
+        const uint32_t w7 = from_right(w[7]), w8 = from_left(w[8]);
+        float f[2][9];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            f[s][4] = decode_dev<ST>(plane_half(w[4], s));      // e = ( 0,-1): row q, own column
+            f[s][7] = decode_dev<ST>(plane_half(w7, s));        // e = (-1,-1): row q, column x+1
+            f[s][8] = decode_dev<ST>(plane_half(w8, s));        // e = ( 1,-1): row q, column x-1
+            f[s][0] = decode_dev<ST>(plane_half(m.a[0], s));    // row q-1
+            f[s][1] = decode_dev<ST>(plane_half(m.a[1], s));
+            f[s][3] = decode_dev<ST>(plane_half(m.a[2], s));
+            f[s][2] = decode_dev<ST>(plane_half(m.b[P][0], s)); // row q-2
+            f[s][5] = decode_dev<ST>(plane_half(m.b[P][1], s));
+            f[s][6] = decode_dev<ST>(plane_half(m.b[P][2], s));
+        }
+        m.a[0] = w[0];
+        m.a[1] = from_left(w[1]);      // e = ( 1, 0)
+        m.a[2] = from_right(w[3]);     // e = (-1, 0)
+        m.b[P][0] = w[2];              // e = ( 0, 1)
+        m.b[P][1] = from_left(w[5]);   // e = ( 1, 1)
+        m.b[P][2] = from_right(w[6]);  // e = (-1, 1)
+        if (j >= 2 * K) {
+            uint16_t o2[2][9];
+            collide_site<ST, V, true>(p, f, o2, kShear<V> ? wrap_mod(q - 1, ny) : 0);
+            march_levels_pk<ST, V, TS, K + 1, P, RM>(p, o2, c, j, q - 1, ny, dst, pstride_b, pitch_b, col_b,
+                                                     store_lane, nt, msteps);
+        }
+    }
+}
+
 // One wave's strip of a marching launch: columns x0 - (TS-1) .. x0 + 64 -
 // TS (the lanes), result columns x0 .. x0 + 63 - 2(TS-1) below nx, rows y0 ..
 // y0 + rows - 1; buffers below 4 GiB.
@@ -1009,7 +1110,9 @@ __device__ __forceinline__ void stepW_strip(const StripW &sw, const Params<typen
     const uint32_t pitch_b = sw.pitch_b, pstride_b = sw.pstride_b;
     const bool nt = sw.nt;
     const int iters = RM ? rows + H + m - 1 : rows + 2 * H;
-    MarchCarry<T, NS> c[TS - 1];
+    // two species in a 16-bit form: packed carries (march_levels_pk)
+    constexpr bool PK = kShifted<ST> && NS == 2;
+    std::conditional_t<PK, MarchCarryPk, MarchCarry<T, NS>> c[TS - 1];
     // the source values of level 1 for iteration j: plane i at row r - e_iy,
     // column x - e_ix (r = y0 - h + j), loaded two iterations ahead into
     // raw[j & 1] (about two iterations of arithmetic hide the memory latency)
@@ -1036,7 +1139,7 @@ __device__ __forceinline__ void stepW_strip(const StripW &sw, const Params<typen
 #pragma unroll
             for (int i = 0; i < 9; ++i) f[s][i] = decode_dev<ST>(raw[P][s][i]);
         T o[NS][9];
-        collide_site<ST, V>(p, f, o, kShear<V> ? wrap_mod(r, ny) : 0);
+        collide_site<ST, V, PK>(p, f, o, kShear<V> ? wrap_mod(r, ny) : 0);
         // requested once level 1 has consumed raw[P], unconditionally (rows
         // wrap, so the two past the segment's end are valid rows): a load
         // under a branch leaves the wait counter unsure at the join, which
@@ -1044,7 +1147,11 @@ __device__ __forceinline__ void stepW_strip(const StripW &sw, const Params<typen
         __builtin_amdgcn_sched_barrier(0);
         load_row(parity, r + 2);
         __builtin_amdgcn_sched_barrier(0);
-        march_levels<ST, V, TS, 1, P, RM>(p, o, c, j, r, ny, dst, pstride_b, pitch_b, cx[1], store_lane, nt, m);
+        if constexpr (PK)
+            march_levels_pk<ST, V, TS, 1, P, RM>(p, o, c, j, r, ny, dst, pstride_b, pitch_b, cx[1], store_lane, nt,
+                                                 m);
+        else
+            march_levels<ST, V, TS, 1, P, RM>(p, o, c, j, r, ny, dst, pstride_b, pitch_b, cx[1], store_lane, nt, m);
     };
     using I0 = std::integral_constant<int, 0>;
     using I1 = std::integral_constant<int, 1>;
