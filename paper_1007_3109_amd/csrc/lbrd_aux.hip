@@ -370,6 +370,118 @@ __global__ void k_dft_cols(const double2 *R, int nx, int ny, double *P) {
     }
 }
 
+// ----------------------------------------------- FFT of rows and columns --
+//
+// A line of n complex values (a row of rho minus its mean, or a column of the
+// row transform) is transformed by one workgroup in LDS with the Stockham
+// autosort formulation: stage s of radix R (the radices, 4, 2, 3 and 5 as
+// they divide n, in that order) takes the n/R butterflies j of span Ns (the
+// product of the earlier radices), multiplies input r = 0..R-1, read at
+// j + r n/R, by e^{-2 pi i (j mod Ns) r / (Ns R)}, takes their R-point DFT
+// and writes output r at (j div Ns) Ns R + (j mod Ns) + r Ns of the other
+// half of LDS.  Every twiddle's phase is an exact integer fraction.  Lines
+// longer than kFftMax or with a prime factor above 5 take the direct sums
+// above.
+
+constexpr int kFftMax = 5120;     // 2 x 5120 complex doubles: 160 KB of LDS
+constexpr int kFftMaxStages = 32;
+
+struct FftPlan {
+    int n, count;
+    int r[kFftMaxStages];
+};
+
+// The plan of an n-point transform, or count = -1 when it takes the direct sums.
+FftPlan fft_plan(int n) {
+    FftPlan pl;
+    pl.n = n;
+    pl.count = 0;
+    int m = n;
+    for (int r : {4, 2, 3, 5})
+        while (m % r == 0 && pl.count < kFftMaxStages) {
+            pl.r[pl.count++] = r;
+            m /= r;
+        }
+    if (m != 1 || n > kFftMax) pl.count = -1;
+    return pl;
+}
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// e^{-2 pi i p / q}, 0 <= p < q
+__device__ __forceinline__ double2 cis_neg(int p, int q) {
+    double sn, cs;
+    sincospi(2.0 * (double)p / (double)q, &sn, &cs);
+    return make_double2(cs, -sn);
+}
+
+// Transforms the line in a (n values) using b as the other half; returns
+// the half that holds the result.  Called by the whole workgroup.
+__device__ double2 *fft_line(double2 *a, double2 *b, const FftPlan &pl) {
+    const int n = pl.n;
+    int ns = 1;
+    for (int s = 0; s < pl.count; ++s) {
+        const int R = pl.r[s], nr = n / R;
+        for (int j = threadIdx.x; j < nr; j += blockDim.x) {
+            const int k = j % ns;
+            double2 v[5], w[5];
+#pragma unroll
+            for (int r = 0; r < 5; ++r)
+                if (r < R) v[r] = r ? cmul(a[j + r * nr], cis_neg(k * r, ns * R)) : a[j];
+#pragma unroll
+            for (int kk = 0; kk < 5; ++kk) {
+                if (kk >= R) continue;
+                double2 acc = v[0];
+#pragma unroll
+                for (int q = 1; q < 5; ++q)
+                    if (q < R) {
+                        const double2 t = cmul(v[q], cis_neg((kk * q) % R, R));
+                        acc.x += t.x;
+                        acc.y += t.y;
+                    }
+                w[kk] = acc;
+            }
+            const int d = (j / ns) * ns * R + k;
+#pragma unroll
+            for (int r = 0; r < 5; ++r)
+                if (r < R) b[d + r * ns] = w[r];
+        }
+        __syncthreads();
+        double2 *t = a;
+        a = b;
+        b = t;
+        ns *= R;
+    }
+    return a;
+}
+
+// Row transform by FFT: R[y][kx] as k_dft_rows computes it.
+__global__ __launch_bounds__(256) void k_fft_rows(const double *rho, const double *mean, int nx, int ny, double2 *R,
+                                                  FftPlan pl) {
+    extern __shared__ double2 line[];
+    const double m = mean[0] / ((double)nx * ny);
+    for (int y = blockIdx.x; y < ny; y += gridDim.x) {
+        for (int x = threadIdx.x; x < nx; x += blockDim.x) line[x] = make_double2(rho[(int64_t)y * nx + x] - m, 0.0);
+        __syncthreads();
+        const double2 *res = fft_line(line, line + nx, pl);
+        for (int x = threadIdx.x; x < nx; x += blockDim.x) R[(int64_t)y * nx + x] = res[x];
+        __syncthreads();
+    }
+}
+
+// Column transform and power by FFT: P[ky][kx] as k_dft_cols computes it.
+__global__ __launch_bounds__(256) void k_fft_cols(const double2 *R, int nx, int ny, double *P, FftPlan pl) {
+    extern __shared__ double2 line[];
+    for (int kx = blockIdx.x; kx < nx; kx += gridDim.x) {
+        for (int y = threadIdx.x; y < ny; y += blockDim.x) line[y] = R[(int64_t)y * nx + kx];
+        __syncthreads();
+        const double2 *res = fft_line(line, line + ny, pl);
+        for (int y = threadIdx.x; y < ny; y += blockDim.x) P[(int64_t)y * nx + kx] = res[y].x * res[y].x + res[y].y * res[y].y;
+        __syncthreads();
+    }
+}
+
 // Sum of a double array with the deterministic two-pass reduction (slot 0).
 __global__ __launch_bounds__(kRedThreads) void k_sum(const double *a, int64_t n, double *partials) {
     double acc = 0.0;
@@ -399,6 +511,17 @@ hipError_t launch_spectrum(int storage, const Layout &L, const void *params, con
     double *rho = static_cast<double *>(work);
     double2 *R = reinterpret_cast<double2 *>(static_cast<char *>(work) + (((size_t)n * sizeof(double) + 255) / 256) * 256);
     hipError_t e = hipSuccess;
+    // rows, then columns: by FFT where the line fits in LDS and factors into
+    // 2, 3 and 5, else by the direct sums
+    static const hipError_t attr_r = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_rows),
+                                                         hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    static const hipError_t attr_c = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_cols),
+                                                         hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (attr_r != hipSuccess) return attr_r;
+    if (attr_c != hipSuccess) return attr_c;
+    const unsigned nb = (unsigned)std::min<int64_t>((n + 255) / 256, 8192);
+    const FftPlan prow = fft_plan(L.nx);
+    const FftPlan pcol = fft_plan(L.ny);
     LBRD_DISPATCH_ST(storage, {
         using C = typename Traits<ST>::C;
         using T = typename Traits<ST>::T;
@@ -412,11 +535,18 @@ hipError_t launch_spectrum(int storage, const Layout &L, const void *params, con
         hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedThreads), 0, st, partials, kRedBlocks, result);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
-        const unsigned nb = (unsigned)std::min<int64_t>((n + 255) / 256, 8192);
-        hipLaunchKernelGGL(k_dft_rows, dim3(nb), dim3(256), 0, st, rho, result, L.nx, L.ny, R);
+        if (prow.count >= 0)
+            hipLaunchKernelGGL(k_fft_rows, dim3((unsigned)std::min(L.ny, 65535)), dim3(256), 2 * L.nx * sizeof(double2),
+                               st, rho, result, L.nx, L.ny, R, prow);
+        else
+            hipLaunchKernelGGL(k_dft_rows, dim3(nb), dim3(256), 0, st, rho, result, L.nx, L.ny, R);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_dft_cols, dim3(nb), dim3(256), 0, st, R, L.nx, L.ny, out);
+        if (pcol.count >= 0)
+            hipLaunchKernelGGL(k_fft_cols, dim3((unsigned)std::min(L.nx, 65535)), dim3(256), 2 * L.ny * sizeof(double2),
+                               st, R, L.nx, L.ny, out, pcol);
+        else
+            hipLaunchKernelGGL(k_dft_cols, dim3(nb), dim3(256), 0, st, R, L.nx, L.ny, out);
         return hipGetLastError();
     })
 }
