@@ -244,7 +244,9 @@ int lbrd_time(const lbrd_solver *h, int64_t *t);
  * diagnostic of Section III.D (Eq. "reac_diff35": the excited wave numbers
  * (n_x, n_y) of a pattern): P[k_y][k_x] = |sum_{x,y} (rho_s(x,y) - mean)
  * exp(-2 pi i (k_x x / nx + k_y y / ny))|^2, computed in FP64 on the GPU by a
- * row transform followed by a column transform (direct sums).
+ * row transform followed by a column transform (a mixed-radix FFT in LDS
+ * for lines of at most 5120 points whose length factors into 2, 3 and 5;
+ * direct sums for other lines).
  * out: device double [ny][nx].  work: device scratch of
  * lbrd_spectrum_work_size() bytes.  Asynchronous. */
 int lbrd_spectrum_work_size(int nx, int ny, size_t *bytes);
