@@ -127,7 +127,8 @@ typedef struct lbrd_config {
  *       over tiles.
  *  plain_order: single solvers; 0 = consecutive tiles on the same XCD, 1 = the
  *       hardware's round-robin order.
- *  fused_steps: 1 = one step per launch; T = 2 .. 8 =
+ *  fused_steps: 1 = one step per launch; T = 2 .. 8 (2 .. 12 on marching
+ *       strips, see march_rows, except FP64) =
  *       T steps per launch on tile_cols x tile_rows tiles staged in LDS
  *       (temporal blocking; a remainder of 2 .. T-1 steps runs as one shorter
  *       launch on the same tiles, a single remaining step as a one-step
@@ -159,7 +160,11 @@ typedef struct lbrd_config {
  *       tile_strip are then ignored.  Ignored when fused_steps = 1 (one-step
  *       launches); refused (LBRD_EINVAL) with T >= 2 on buffers of 4 GiB or
  *       more.  lbrd_create chooses it from measurements (marching strips
- *       where they measured faster: most forms beyond the Infinity Cache).
+ *       where they measured faster: most forms beyond the Infinity Cache,
+ *       FP32 and FP64 inside it from 1024^2 sites), with R sized so that the
+ *       strips' segments make a fixed number of waves per SIMD (one round of
+ *       the launch for the kernels with one wave per SIMD).  Up to 12 steps
+ *       a launch in FP32 and the 16-bit forms; FP64 up to 8.
  *       Batches (FP32 Gray-Scott sets and serving mixes): R > 0 with T >= 2
  *       runs their multi-step launches on marching strips too (waves 1, 2
  *       or 4; blocks_per_cu 0 = one wave per strip segment, else a

@@ -441,78 +441,114 @@ int default_strip(const lbrd_solver *h, const lbrd_tuning &t) {
 }
 
 struct MarchShape {
-    int steps = 0, rows = 0, waves = 0;
+    int steps = 0;      // steps per launch; 0: the LDS tiles
+    int rows = 0;       // rows per segment; 0: sized for k waves per SIMD
+    int waves = 0;      // waves per workgroup
+    int k = 1;
 };
 
-// The default marching shape (steps per launch, rows per segment, waves per
-// workgroup), or steps 0 where the LDS tiles measured faster.  Marching
-// strips recompute only the x-halo and keep no tile in LDS, so they win where
-// the state streams from HBM (beyond the 256 MB Infinity Cache, "beyond"),
-// and in FP64 also inside it from 1024^2 sites (FP64 LDS tiles are small);
-// small lattices and FP32/16-bit lattices inside the cache keep the LDS tiles
-// (more workgroups, shorter launches).  Measured per step, marching against
-// the LDS defaults ("big": more than 2048^2 sites):
-//   Gray-Scott and two linear species: FP32 beyond T 7, 64 rows when big
-//     (4096^2: 86.4 against 110.8 us), else 32 (2048^2: 28.3 against 30.8);
-//     16-bit beyond (the two species' values of a plane packed in one
-//     register) T 7, 64 rows when big (F16 58.0 against 73.3, BF16 58.5
-//     against 75.2), else T 6, 16 rows (F16 18.0, BF16 17.8 against 20.6);
-//     FP64 beyond T 7,
-//     64 rows when big (174 against 307), else T 8, 32 rows (47.0 against
-//     72.3); FP64 inside from 1024^2, one-wave workgroups: T 7, 32 rows (13.8
-//     against 18.2), at 512^2 T 5, 8 rows (4.9 against 6.6).  Inside the
-//     cache FP32 loses (1024^2: 7.5 against 7.1; 256^2: 3.4 against 1.25).
-//   One linear species: FP32 beyond T 8, 32 rows (43.0 against 49.8;
-//     2048^2 10.4 against 14.0); 16-bit beyond T 7, 64 rows when big (31.0
-//     against 39.5), else T 4, 16 rows (9.5 against 9.8); FP64 beyond T 8,
-//     16 rows when big (78.8 against 87.5), else 64 rows, one wave (20.7
-//     against 25.4), inside from 1024^2 T 8, 32 rows, one wave (4.9 against
-//     7.6).
-//   Three species: FP32 beyond T 7, 64 rows when big, else 32, one wave
-//     (157 against 266; 50.6 against 68.3); 16-bit beyond T 5, 16 rows (F16
-//     125 against 155).  Four species: FP32 beyond T 5, 64 rows when big
-//     (276 against 361), else 16 rows, one wave (75.7 against 85.5); 16-bit
-//     even (210 against 205): LDS tiles.
-//   Shear flow, FP32 beyond, big: T 4, 32 rows (one species 78.3 against
-//     109; Gray-Scott 174 against 182).  Uniform velocity, one species,
-//     16-bit beyond: T 6, 64 rows (BF16 36.9 against 42.2).  Gray-Scott with
-//     a uniform velocity measured even or slower (FP32 4096^2 118.6 against
-//     118.2, 2048^2 37.0 against 33.6; F16 79.7 against 80.1): LDS tiles.
-// Forms not measured keep the LDS tiles (FP64 with three or more species,
-// with a velocity, or one species inside the cache below 1024^2).
+int max_march_steps(const lbrd_solver *h) { return h->cfg.storage == LBRD_F64 ? kMaxFusedSteps : kMaxMarchSteps; }
+
+// Rows per segment of a marching launch of `steps` steps that make strips x
+// segments about k waves per SIMD (k x 4 x CUs in all), with segments as
+// long as that allows: each segment reads about 2 x steps rows around it
+// again, so longer segments move fewer bytes.  k = 1 is one round of the
+// launch where the kernel's registers leave one wave per SIMD.
+int march_rows_for(const lbrd_solver *h, int steps, int k) {
+    const int u = 64 - 2 * (steps - 1);
+    const int64_t strips = (h->cfg.nx + u - 1) / u;
+    const int64_t segs = std::max<int64_t>(1, (int64_t)4 * h->cus * k / strips);
+    return (int)((h->cfg.ny + segs - 1) / segs);
+}
+
+// The default marching shape, or steps 0 where the LDS tiles measured
+// faster.  Marching strips recompute only the x-halo and keep no tile in
+// LDS; they win wherever the state streams from HBM (beyond the 256 MB
+// Infinity Cache, "beyond"), and inside it from 1024^2 sites in FP32 and
+// FP64.  Measured per step against the LDS defaults and the shapes these
+// replace (64-row segments, at most 8 steps a launch; "big": more than
+// 2048^2 sites; k: the segments' waves per SIMD):
+//   Gray-Scott and two linear species: FP32 beyond T 10 when big (4096^2:
+//     63.5 against 84.5 and 110.8 us), else T 9 (2048^2: 18.1 against 26.7),
+//     k 1; FP32 inside from 1024^2 T 7, k 1 (5.80 against 6.54).  F16 beyond
+//     T 8 when big (54.3 against 58.3), else T 7 (16.1 against 17.5), BF16
+//     one step fewer (57.7 against 57.8; 16.7 against 18.1), k 3.  FP64
+//     beyond T 7, k 1 (166.4 against 171.7; 2048^2 42.7 against 59.3; 1024^2
+//     11.5 against 16.4); inside from 512^2 T 6, 8 rows, one-wave workgroups
+//     (4.45 against 4.54).  16-bit inside the cache: LDS tiles (F16 1024^2
+//     5.58 against 5.96).
+//   One linear species: FP32 beyond T 11, k 2 (29.2 against 40.4; 2048^2 8.54
+//     against 10.9), inside from 1024^2 T 7, k 1 (3.01 against 3.49); F16
+//     beyond T 7, k 4 when big (30.5 against 30.6), else T 5, k 3 (8.75
+//     against 8.96); BF16 beyond and big T 6, k 4 (32.9 against 33.0), else
+//     LDS tiles (9.01 against 9.44); FP64 beyond T 8, k 1 (64.7 against 78.7;
+//     2048^2 17.9 against 20.6), inside from 1024^2 (4.14 against 4.60).
+//   Three species: FP32 beyond T 8, k 3 when big (132.5 against 147.7), else
+//     k 1 (33.8 against 42.9), inside from 1024^2 T 6, k 1 (10.5 against
+//     15.6); 16-bit beyond T 5, 16 rows when big (F16 123.2; k 1 126.6), else
+//     k 2 (30.0 against 34.0).  Four species: FP32 beyond T 5, k 4 when big
+//     (271.1 against 278.6), else k 1, one-wave workgroups (68.6 against
+//     72.5); F16 beyond T 5, one-wave workgroups, k 3 when big (195.3 against
+//     205.5), else k 1 (51.2 against 52.6).
+//   Shear flow, FP32 beyond, big: T 5, k 2 with Gray-Scott (134.0 against
+//     177.4), k 3 with one species (63.8 against 80.6).  Uniform velocity: one
+//     species, 16-bit beyond, T 5, k 4 when big (BF16 38.3 against 39.3, F16
+//     36.7 against 37.2), else T 6, 64 rows; Gray-Scott FP32 beyond T 7, k 2
+//     when big (82.7 against 118.1), else k 1 (22.6 against 31.3), 16-bit
+//     beyond and big T 6, k 3 (F16 66.2 against 80.3).
+// The step counts above 8 trade a wider x-halo (2(T-1) of a wave's 64
+// columns) for fewer passes over HBM; where a form's registers run out
+// (FP32 with three or four species above T 8) its time jumps.  Forms not
+// measured keep the LDS tiles (FP64 with three or more species, with a
+// shear or a velocity, or one species inside the cache below 1024^2).
 MarchShape march_default(const lbrd_solver *h, bool in_cache, int64_t sites) {
     const int st = h->cfg.storage;
-    const bool f64 = st == LBRD_F64, f32 = st == LBRD_F32, b16 = !f64 && !f32;
-    const bool big = sites > (int64_t)2048 * 2048;
-    switch (variant_of(h->cfg)) {
+    const bool f64 = st == LBRD_F64, f32 = st == LBRD_F32, f16 = st == LBRD_F16_SHIFTED, b16 = !f64 && !f32;
+    const bool big = sites > (int64_t)2048 * 2048, mid = sites >= (int64_t)1024 * 1024;
+    const int v = variant_of(h->cfg);
+    switch (v) {
         case kGS:
         case kLin2:
             if (in_cache) {
-                if (!f64 || sites < (int64_t)512 * 512) return {};
-                return sites < (int64_t)1024 * 1024 ? MarchShape{5, 8, 1} : MarchShape{7, 32, 1};
+                if (f32 && mid) return {7, 0, 4, 1};
+                if (f64 && sites >= (int64_t)512 * 512) return {6, 8, 1, 1};
+                return {};
             }
-            if (f32) return {7, big ? 64 : 32, 4};
-            if (b16) return big ? MarchShape{7, 64, 4} : MarchShape{6, 16, 4};
-            return big ? MarchShape{7, 64, 4} : MarchShape{8, 32, 4};
+            if (f32) return {big ? 10 : 9, 0, 4, 1};
+            if (f64) return {7, 0, 4, 1};
+            if (f16) return {big ? 8 : 7, 0, 4, 3};
+            return {big ? 7 : 6, 0, 4, 3};
         case kLin1:
-            if (in_cache) return f64 && sites >= (int64_t)1024 * 1024 ? MarchShape{8, 32, 1} : MarchShape{};
-            if (f32) return {8, 32, 4};
-            if (b16) return big ? MarchShape{7, 64, 4} : MarchShape{4, 16, 4};
-            return big ? MarchShape{8, 16, 4} : MarchShape{8, 64, 1};
+            if (in_cache) {
+                if (f32 && mid) return {7, 0, 4, 1};
+                if (f64 && mid) return {8, 0, 4, 1};
+                return {};
+            }
+            if (f32) return {11, 0, 4, 2};
+            if (f64) return {8, 0, 4, 1};
+            if (f16) return big ? MarchShape{7, 0, 4, 4} : MarchShape{5, 0, 4, 3};
+            return big ? MarchShape{6, 0, 4, 4} : MarchShape{};
         case kLin3:
-            if (in_cache || f64) return {};
-            if (f32) return big ? MarchShape{7, 64, 1} : MarchShape{7, 32, 1};
-            return {5, 16, 4};
+            if (f64) return {};
+            if (in_cache) return f32 && mid ? MarchShape{6, 0, 4, 1} : MarchShape{};
+            if (f32) return {8, 0, 4, big ? 3 : 1};
+            return big ? MarchShape{5, 16, 4, 1} : MarchShape{5, 0, 4, 2};
         case kLin4:
-            if (in_cache || !f32) return {};
-            return big ? MarchShape{5, 64, 4} : MarchShape{5, 16, 1};
+            if (in_cache || f64) return {};
+            if (f32) return big ? MarchShape{5, 0, 4, 4} : MarchShape{5, 0, 1, 1};
+            if (f16) return {5, 0, 1, big ? 3 : 1};
+            return {};
         case kShearLin1:
         case kShearGS:
             if (in_cache || !f32 || !big) return {};
-            return {4, 32, 4};
+            return {5, 0, 4, v == kShearGS ? 2 : 3};
         case kAdvLin1:
             if (in_cache || !b16) return {};
-            return {6, 64, 4};
+            return big ? MarchShape{5, 0, 4, 4} : MarchShape{6, 64, 4, 1};
+        case kAdvGS:
+            if (in_cache) return {};
+            if (f32) return {7, 0, 4, big ? 2 : 1};
+            return b16 && big ? MarchShape{6, 0, 4, 3} : MarchShape{};
         default:
             return {};
     }
@@ -532,8 +568,9 @@ bool tuning_valid(const lbrd_solver *h, const lbrd_tuning &t) {
     if (t.waves < 1 || t.waves > 16) return false;
     if (t.fused_steps == 1) return true;
     if (!multi_step_possible(h)) return false;
+    // marching wave strips: no LDS tile
+    if (t.march_rows > 0) return t.fused_steps >= 2 && t.fused_steps <= max_march_steps(h);
     if (t.fused_steps < 2 || t.fused_steps > kMaxFusedSteps) return false;
-    if (t.march_rows > 0) return true;   // marching wave strips: no LDS tile
     if (t.tile_rows < 1 || t.tile_rows > 64) return false;
     if (big_buffers(h) && t.tile_cols == 128) return false;   // plane-by-plane launches: 32 or 64 wide
     return stepT_shape_fits(h->cfg.storage, h->cfg.nspecies, t.tile_cols, t.tile_rows, t.fused_steps, t.waves);
@@ -683,7 +720,7 @@ int lbrd_create(const lbrd_config *cfg, void *workspace, size_t bytes, void *str
     const MarchShape ms = march_default(h, in_cache, sites);
     if (h->tune.fused_steps > 1 && !big_buffers(h) && ms.steps > 0) {
         h->tune.fused_steps = ms.steps;
-        h->tune.march_rows = ms.rows;
+        h->tune.march_rows = ms.rows > 0 ? ms.rows : march_rows_for(h, ms.steps, ms.k);
         h->tune.waves = ms.waves;
         h->tune.nontemporal = 0;
         h->tune.tile_strip = 0;
@@ -989,12 +1026,14 @@ int lbrd_autotune(lbrd_solver *h, int steps, const char *cache_path, lbrd_tuning
                             t.tile_strip = default_strip(h, t);
                             cands.push_back(t);
                         }
-    // marching wave strips: steps per launch, segment lengths, waves per
-    // workgroup, streaming stores
-    for (int ts = 2; ts <= kMaxFusedSteps; ++ts)
-        for (int rows : {16, 24, 32, 64, 128})
+    // marching wave strips: steps per launch, segment lengths (fixed, or
+    // sized for k = 1 .. 4 waves per SIMD), waves per workgroup, streaming
+    // stores
+    for (int ts = 2; ts <= max_march_steps(h); ++ts)
+        for (int r : {16, 32, 64, -1, -2, -3, -4})
             for (int w : {1, 4})
                 for (int nt = 0; nt < 2; ++nt) {
+                    const int rows = r > 0 ? r : march_rows_for(h, ts, -r);
                     lbrd_tuning t = h->tune;
                     t.vec = default_vec(h->cfg.storage);
                     t.lanes_x = default_lanes(h->cfg.nx, t.vec);

@@ -971,8 +971,11 @@ __device__ __forceinline__ void march_store(typename Traits<ST>::T (&o)[NSpecies
 // (iteration j >= 2K).  Level TS stores its row.  With RM (a runtime step
 // count m <= TS, the batched launches) level m stores instead, from iteration
 // TS - 1 + m - 1 on (its first row of the segment), and the levels above it
-// are skipped; the wider x-halo of a TS-step strip covers m steps.
-template <int ST, int V, int TS, int K, int P, bool RM = false>
+// are skipped; the wider x-halo of a TS-step strip covers m steps.  Without
+// G (the iterations from 2(TS-1) on, where every level is active) the
+// activity tests are left out: the branches they make cost the compiler a
+// copy of every carry of the levels they skip.
+template <int ST, int V, int TS, int K, int P, bool RM = false, bool G = true>
 __device__ __forceinline__ void march_levels(const Params<typename Traits<ST>::C> &p,
                                              typename Traits<ST>::T (&o)[NSpecies<V>::value][9],
                                              MarchCarry<typename Traits<ST>::T, NSpecies<V>::value> (&c)[TS - 1],
@@ -988,7 +991,7 @@ __device__ __forceinline__ void march_levels(const Params<typename Traits<ST>::C
     }
     if constexpr (K == TS) {
         // the last level: row q is the launch's result (active from j >= 2(TS-1))
-        if ((!RM || msteps == TS) && j >= 2 * (TS - 1) && store_lane)
+        if ((!RM || msteps == TS) && (!G || j >= 2 * (TS - 1)) && store_lane)
             march_store<ST, V>(o, q, dst, pstride_b, pitch_b, col_b, nt);
     } else {
         MarchCarry<T, NS> &m = c[K - 1];
@@ -1011,10 +1014,10 @@ __device__ __forceinline__ void march_levels(const Params<typename Traits<ST>::C
             m.b[P][s][1] = from_left(o[s][5]);   // e = ( 1, 1)
             m.b[P][s][2] = from_right(o[s][6]);  // e = (-1, 1)
         }
-        if (j >= 2 * K) {
+        if (!G || j >= 2 * K) {
             T o2[NS][9];
             collide_site<ST, V>(p, f, o2, kShear<V> ? wrap_mod(q - 1, ny) : 0);
-            march_levels<ST, V, TS, K + 1, P, RM>(p, o2, c, j, q - 1, ny, dst, pstride_b, pitch_b, col_b,
+            march_levels<ST, V, TS, K + 1, P, RM, G>(p, o2, c, j, q - 1, ny, dst, pstride_b, pitch_b, col_b,
                                                   store_lane, nt, msteps);
         }
     }
@@ -1033,7 +1036,7 @@ __device__ __forceinline__ uint16_t plane_half(uint32_t w, int s) { return s ? (
 
 // march_levels for two species in a 16-bit form on packed words (the same
 // values and the same update; the site's results are rounded plane by plane).
-template <int ST, int V, int TS, int K, int P, bool RM = false>
+template <int ST, int V, int TS, int K, int P, bool RM = false, bool G = true>
 __device__ __forceinline__ void march_levels_pk(const Params<float> &p, uint16_t (&o)[2][9], MarchCarryPk (&c)[TS - 1],
                                                 int j, int q, int ny, __amdgpu_buffer_rsrc_t dst, uint32_t pstride_b,
                                                 uint32_t pitch_b, uint32_t col_b, bool store_lane, bool nt,
@@ -1043,7 +1046,7 @@ __device__ __forceinline__ void march_levels_pk(const Params<float> &p, uint16_t
             march_store<ST, V>(o, q, dst, pstride_b, pitch_b, col_b, nt);
     }
     if constexpr (K == TS) {
-        if ((!RM || msteps == TS) && j >= 2 * (TS - 1) && store_lane)
+        if ((!RM || msteps == TS) && (!G || j >= 2 * (TS - 1)) && store_lane)
             march_store<ST, V>(o, q, dst, pstride_b, pitch_b, col_b, nt);
     } else {
         MarchCarryPk &m = c[K - 1];
@@ -1070,10 +1073,10 @@ __device__ __forceinline__ void march_levels_pk(const Params<float> &p, uint16_t
         m.b[P][0] = w[2];              // e = ( 0, 1)
         m.b[P][1] = from_left(w[5]);   // e = ( 1, 1)
         m.b[P][2] = from_right(w[6]);  // e = (-1, 1)
-        if (j >= 2 * K) {
+        if (!G || j >= 2 * K) {
             uint16_t o2[2][9];
             collide_site<ST, V, true>(p, f, o2, kShear<V> ? wrap_mod(q - 1, ny) : 0);
-            march_levels_pk<ST, V, TS, K + 1, P, RM>(p, o2, c, j, q - 1, ny, dst, pstride_b, pitch_b, col_b,
+            march_levels_pk<ST, V, TS, K + 1, P, RM, G>(p, o2, c, j, q - 1, ny, dst, pstride_b, pitch_b, col_b,
                                                      store_lane, nt, msteps);
         }
     }
@@ -1129,9 +1132,11 @@ __device__ __forceinline__ void stepW_strip(const StripW &sw, const Params<typen
     };
     // one iteration of parity P: level 1 at row r = y0 - h + j from the
     // prefetched values, then the values of iteration j + 2 requested, then
-    // the levels above (level k from iteration 2(k-1) on).
-    auto iteration = [&](auto parity, int j) {
+    // the levels above (level k from iteration 2(k-1) on; with guarded =
+    // false all of them, without testing).
+    auto iteration = [&](auto parity, auto guarded, int j) {
         constexpr int P = decltype(parity)::value;
+        constexpr bool G = decltype(guarded)::value;
         const int r = y0 - H + j;
         C f[NS][9];
 #pragma unroll
@@ -1148,26 +1153,44 @@ __device__ __forceinline__ void stepW_strip(const StripW &sw, const Params<typen
         load_row(parity, r + 2);
         __builtin_amdgcn_sched_barrier(0);
         if constexpr (PK)
-            march_levels_pk<ST, V, TS, 1, P, RM>(p, o, c, j, r, ny, dst, pstride_b, pitch_b, cx[1], store_lane, nt,
-                                                 m);
+            march_levels_pk<ST, V, TS, 1, P, RM, G>(p, o, c, j, r, ny, dst, pstride_b, pitch_b, cx[1], store_lane,
+                                                    nt, m);
         else
-            march_levels<ST, V, TS, 1, P, RM>(p, o, c, j, r, ny, dst, pstride_b, pitch_b, cx[1], store_lane, nt, m);
+            march_levels<ST, V, TS, 1, P, RM, G>(p, o, c, j, r, ny, dst, pstride_b, pitch_b, cx[1], store_lane, nt,
+                                                 m);
     };
     using I0 = std::integral_constant<int, 0>;
     using I1 = std::integral_constant<int, 1>;
+    using Guarded = std::true_type;
+    using Full = std::false_type;
     load_row(I0{}, y0 - H);
     load_row(I1{}, y0 - H + 1);
     int j = 0;
-    for (; j + 1 < iters; j += 2) {
-        iteration(I0{}, j);
-        iteration(I1{}, j + 1);
+    if constexpr (!RM) {
+        // iters = rows + 2h > 2h: the first 2h iterations fill the pipeline,
+        // every later one runs all levels
+        for (; j < 2 * H; j += 2) {
+            iteration(I0{}, Guarded{}, j);
+            iteration(I1{}, Guarded{}, j + 1);
+        }
+        for (; j + 1 < iters; j += 2) {
+            iteration(I0{}, Full{}, j);
+            iteration(I1{}, Full{}, j + 1);
+        }
+        if (j < iters) iteration(I0{}, Full{}, j);
+    } else {
+        for (; j + 1 < iters; j += 2) {
+            iteration(I0{}, Guarded{}, j);
+            iteration(I1{}, Guarded{}, j + 1);
+        }
+        if (j < iters) iteration(I0{}, Guarded{}, j);
     }
-    if (j < iters) iteration(I0{}, j);
 }
 
-// TS steps per launch (2 .. 8) on marching wave strips: g.tw = 64 - 2(TS-1)
-// result columns per strip, g.th rows per segment, g.ntx strips across and
-// g.nty segments down, one wave each (g.ntiles of them); buffers below 4 GiB.
+// TS steps per launch (2 .. 12; FP64 2 .. 8) on marching wave strips: g.tw =
+// 64 - 2(TS-1) result columns per strip, g.th rows per segment, g.ntx strips
+// across and g.nty segments down, one wave each (g.ntiles of them); buffers
+// below 4 GiB.
 template <int ST, int V, int TS>
 __global__ __launch_bounds__(256) void k_stepW(GridT g, Params<typename Traits<ST>::C> p) {
     using T = typename Traits<ST>::T;

@@ -113,6 +113,10 @@ struct GridT {
 };
 
 constexpr int kMaxFusedSteps = 8;
+// Marching wave strips of a single solver keep every level in registers and
+// no tile in LDS: up to 12 steps a launch in the 32- and 16-bit forms (FP64
+// holds 8, its carries take twice the registers).
+constexpr int kMaxMarchSteps = 12;
 constexpr int kMaxBatchFusedSteps = 8;
 
 GridT make_gridT(const Layout &L, const void *src, void *dst, int tw, int th, int steps);

@@ -102,7 +102,7 @@ inline hipError_t launch_stepW_t(const StepLaunch &sl, const GridT &g, const voi
 
 template <int ST, int V>
 inline hipError_t launch_stepW_n(const StepLaunch &sl, const GridT &g, const void *params, hipStream_t st) {
-    static_assert(kMaxFusedSteps == 8, "instantiate every step count");
+    static_assert(kMaxFusedSteps == 8 && kMaxMarchSteps == 12, "instantiate every step count");
     switch (g.steps) {
         case 2: return launch_stepW_t<ST, V, 2>(sl, g, params, st);
         case 3: return launch_stepW_t<ST, V, 3>(sl, g, params, st);
@@ -111,8 +111,18 @@ inline hipError_t launch_stepW_n(const StepLaunch &sl, const GridT &g, const voi
         case 6: return launch_stepW_t<ST, V, 6>(sl, g, params, st);
         case 7: return launch_stepW_t<ST, V, 7>(sl, g, params, st);
         case 8: return launch_stepW_t<ST, V, 8>(sl, g, params, st);
-        default: return hipErrorInvalidValue;
+        default: break;
     }
+    if constexpr (ST != kF64) {
+        switch (g.steps) {
+            case 9: return launch_stepW_t<ST, V, 9>(sl, g, params, st);
+            case 10: return launch_stepW_t<ST, V, 10>(sl, g, params, st);
+            case 11: return launch_stepW_t<ST, V, 11>(sl, g, params, st);
+            case 12: return launch_stepW_t<ST, V, 12>(sl, g, params, st);
+            default: break;
+        }
+    }
+    return hipErrorInvalidValue;
 }
 
 template <int ST, int V>

@@ -2,7 +2,7 @@
 intermediate rows carried in registers.  Every site runs the one-step
 kernel's arithmetic on the same stored inputs, so after any number of steps
 every population is bitwise equal to one-step launches: checked for every
-storage form and reaction variant, 2 .. 8 steps per launch, several segment
+storage form and reaction variant, 2 .. 12 steps per launch (FP64 2 .. 8), several segment
 lengths (1 row, a ragged one, more than the lattice), workgroup sizes, both
 tile orders and streaming stores, on tiny lattices (where a strip wraps
 around the lattice several times), ragged ones and wider ones."""
@@ -51,7 +51,7 @@ def test_march_launch_is_bitwise_identical(storage, reaction, ns):
         want = ref.get_populations()
         ref.close()
         s = lbrd.Solver(cfg)
-        for steps in range(2, 9):
+        for steps in range(2, 9 if storage == "f64" else 13):
             for rows in (1, 7, 64):
                 waves = (1, 2, 4)[ran % 3]
                 s.set_tuning(fused_steps=steps, march_rows=rows, waves=waves, graph_steps=0,
@@ -68,16 +68,23 @@ def test_march_tuning_limits():
     cfg = _config("f32", "gray_scott", 2, 40, 30)
     s = lbrd.Solver(cfg)
     for bad in (dict(fused_steps=4, march_rows=-1), dict(fused_steps=4, march_rows=65537),
-                dict(fused_steps=1, march_rows=-1)):
+                dict(fused_steps=1, march_rows=-1), dict(fused_steps=13, march_rows=8),
+                dict(fused_steps=9, march_rows=0)):
         with pytest.raises(lbrd.LbrdError):
             s.set_tuning(graph_steps=0, **bad)
     s.set_tuning(fused_steps=4, march_rows=65536, graph_steps=0)
+    s.set_tuning(fused_steps=12, march_rows=8, graph_steps=0)   # marching: up to 12 steps a launch
     s.set_tuning(fused_steps=1, graph_steps=0)       # one-step launches ignore march_rows
-    assert s.tuning().march_rows == 65536 and s.tuning().fused_steps == 1
+    assert s.tuning().march_rows == 8 and s.tuning().fused_steps == 1
     s.close()
+    d = lbrd.Solver(_config("f64", "gray_scott", 2, 40, 30))
+    d.set_tuning(fused_steps=8, march_rows=8, graph_steps=0)
+    with pytest.raises(lbrd.LbrdError):   # FP64 marching: at most 8
+        d.set_tuning(fused_steps=9, march_rows=8, graph_steps=0)
+    d.close()
 
 
-@pytest.mark.parametrize("ts,rows,graph", [(4, 32, 8), (7, 64, 28), (8, 128, 16)])
+@pytest.mark.parametrize("ts,rows,graph", [(4, 32, 8), (7, 64, 28), (8, 128, 16), (11, 342, 22)])
 def test_march_with_graphs_and_oracle(ts, rows, graph):
     """Captured graphs of marching launches replayed between eager remainders
     equal plain one-step launches bitwise, and the FP64 oracle within 1e-5

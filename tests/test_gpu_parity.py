@@ -865,7 +865,7 @@ def test_default_shape_for_every_species_count(storage):
                                    K=-0.01 * np.eye(ns), rho_ref=(0.3,) * ns)
             s = lbrd.Solver(cfg)
             t = s.tuning()
-            assert 2 <= t.fused_steps <= 8, (ns, nx, t.as_dict())
+            assert 2 <= t.fused_steps <= (8 if storage == "f64" or t.march_rows == 0 else 12), (ns, nx, t.as_dict())
             if nx > 96 and ns <= 2:
                 assert t.march_rows > 0, (ns, nx, t.as_dict())
             if t.march_rows > 0:
@@ -893,10 +893,11 @@ def test_default_tile_order():
     CUs / 8 per XCD), when the lattice is more than 2S tiles wide, else
     row-major (0); the 16-bit forms take strips at exactly 2S tiles too.
     Marching strips (the default for one or two species beyond the Infinity
-    Cache, below 4 GiB buffers) take no tile order."""
+    Cache, below 4 GiB buffers, and in FP32 and FP64 from 1024^2 sites inside
+    it) take no tile order."""
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     seen = set()
-    for n, storage, ns in ((1024, "f32", 2), (4096, "f32", 2), (8192, "f32", 2), (4096, "f16", 3),
+    for n, storage, ns in ((1024, "f32", 2), (1024, "f16", 2), (4096, "f32", 2), (8192, "f32", 2), (4096, "f16", 3),
                            (2048, "f32", 3), (6144, "f32", 4), (2048, "f64", 3)):
         b = {"f64": 8, "f32": 4, "f16": 2}[storage]
         if ns == 2:
@@ -915,8 +916,10 @@ def test_default_tile_order():
         beyond = 2 * 9 * ns * b * n * n > (256 << 20)
         if ns <= 2 and beyond and 9 * ns * b * n * n < (1 << 32):
             assert t.march_rows > 0, (n, storage, t.as_dict())
+        if n >= 1024 and storage == "f32" and 9 * ns * b * n * n < (1 << 32):
+            assert t.march_rows > 0, (n, storage, t.as_dict())
         if t.march_rows > 0:
-            assert beyond and t.tile_strip == 0, (n, storage, ns, t.as_dict())
+            assert (beyond or storage != "f16") and t.tile_strip == 0, (n, storage, ns, t.as_dict())
             continue
         h = t.fused_steps - 1
         ew = t.tile_cols + 2 * h
