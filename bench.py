@@ -247,15 +247,17 @@ def cpu_baseline(workloads, n, budget_s, max_steps=200):
             "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS")}
 
 
-def solver_leg(torch, lbrd, workloads, n, storage, steps, warmup, tune=False, fused=None, note=None):
+def solver_leg(torch, lbrd, workloads, n, storage, steps, warmup, tune=False, fused=None, shape=None, note=None):
     """One Gray-Scott lattice, the headline timing protocol; the roofline of
-    its step kernel."""
+    its step kernel.  `shape`: tuning fields set instead of the default."""
     cfg = gs_config(lbrd, workloads, n, storage)
     s = lbrd.Solver(cfg)
     if tune:
         s.autotune(steps=10)
     if fused is not None:
         s.set_tuning(fused_steps=fused)
+    if shape is not None:
+        s.set_tuning(**shape)
     s.init(workloads.gray_scott_square(n, n, seed=0))
     wins = time_windows(torch, s, steps, warmup)
     med, stats = window_stats(wins, steps)
@@ -645,7 +647,7 @@ def copy_leg(torch, nbytes=1 << 30, reps=20):
     return out
 
 
-ALL_LEGS = ("gs1024_f32,one_step_4096_f32,hbm4096_f16,hbm4096_bf16,batch,serve,precision,rescaling,truncation,config1,"
+ALL_LEGS = ("gs1024_f32,tiles1024_f32,one_step_4096_f32,hbm4096_f16,hbm4096_bf16,batch,serve,precision,rescaling,truncation,config1,"
             "copy")
 
 
@@ -755,6 +757,14 @@ def main():
             extra["gs_1024_f32"] = solver_leg(torch, lbrd, workloads, 1024, "f32", 5000, 100, tune=args.tune,
                                               note="1024^2 x 2 species x 9 x 2 buffers x 4 B = 151 MB: resident in "
                                                    "the 256 MB Infinity Cache, not an HBM measurement")
+        if "tiles1024_f32" in legs:
+            log("bench: 1024^2 f32 on LDS tiles")
+            extra["tiles_1024_f32"] = solver_leg(
+                torch, lbrd, workloads, 1024, "f32", 5000, 100,
+                shape=dict(march_rows=0, fused_steps=5, tile_cols=32, tile_rows=10, waves=8, tile_strip=0,
+                           nontemporal=0, graph_steps=0),
+                note="the LDS-tile kernel (the default inside the Infinity Cache for the 16-bit forms and below "
+                     "1024^2 sites) on the 1024^2 lattice, for comparison with its marching default")
         if "one_step_4096_f32" in legs:
             log("bench: 4096^2 f32, one step per launch")
             extra["one_step_4096_f32"] = solver_leg(torch, lbrd, workloads, 4096, "f32", args.extra_steps, 20,
