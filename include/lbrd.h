@@ -331,7 +331,7 @@ int lbrd_batch_spectrum(lbrd_batch *b, int idx, int species, void *out, void *wo
  * fused_steps = T in 2..8 on tile_cols x tile_rows tiles, tile_cols 32 or 64,
  * or with march_rows > 0 on marching strips (default 5 steps on 32 x 10
  * tiles, 8 waves, while the buffers fit in the 256 MB Infinity Cache;
- * beyond it 7 steps on marching strips of 64 rows, 4 waves; blocks_per_cu 0
+ * beyond it 8 steps on marching strips of 128 rows, 4 waves; blocks_per_cu 0
  * = one workgroup per tile or strip segments, graph_steps the multiple of 2T
  * nearest 32):
  * launch j advances each instance by min(T, its steps left in the chunk), and

@@ -288,19 +288,21 @@ int lbrd_batch_create(const lbrd_config *cfgs, int count, void *workspace, size_
         if (!batch_multi_ok(b->L[i], b->cfg[i].storage)) b->multi_ok = false;
     std::memset(&b->tune, 0, sizeof(b->tune));
     if (b->multi_ok) {
-        // the single-lattice FP32 Gray-Scott shapes: while the buffers fit in
-        // the Infinity Cache, five steps per launch on 32 x 10 LDS tiles (the
-        // LDS of both sets is sized for it), one workgroup of 8 waves per
-        // tile; beyond it, marching wave strips (seven steps per launch,
-        // segments of 64 rows, one wave per segment, four to a workgroup);
-        // graphs of about 32 steps (an even number of launches)
+        // while the buffers fit in the Infinity Cache, five steps per launch
+        // on 32 x 10 LDS tiles (the LDS of both sets is sized for it), one
+        // workgroup of 8 waves per tile; beyond it, marching wave strips
+        // (eight steps per launch, segments of 128 rows, one wave per
+        // segment, four to a workgroup: on the benchmark's 256-instance
+        // Gray-Scott sweep 128.6 us per step, against 145.2 with seven steps
+        // on 64 rows and 141.8 with eight on 256); graphs of about 32 steps
+        // (an even number of launches)
         size_t bytes = 0;
         for (const Layout &L : b->L) bytes += 2 * L.buf_bytes;
         const bool in_cache = bytes <= ((size_t)256 << 20);
-        b->tune.fused_steps = in_cache ? 5 : 7;
+        b->tune.fused_steps = in_cache ? 5 : 8;
         b->tune.tile_rows = in_cache ? 10 : 0;
         b->tune.tile_cols = in_cache ? 32 : 0;
-        b->tune.march_rows = in_cache ? 0 : 64;
+        b->tune.march_rows = in_cache ? 0 : 128;
         b->tune.waves = in_cache ? 8 : 4;
         b->tune.blocks_per_cu = 0;
         const int unit = 2 * b->tune.fused_steps;
@@ -624,7 +626,7 @@ int lbrd_batch_autotune(lbrd_batch *b, int steps, lbrd_tuning *chosen) {
                     }
     if (b->multi_ok)
         for (int ts = 4; ts <= kMaxBatchFusedSteps; ++ts)
-            for (int rows : {16, 32, 64})
+            for (int rows : {16, 32, 64, 128, 256})
                 for (int w : {1, 4}) {
                     lbrd_tuning t = keep;
                     t.fused_steps = ts;

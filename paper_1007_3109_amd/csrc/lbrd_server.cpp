@@ -184,20 +184,23 @@ int blocks_for(const lbrd_server *s) { return 8 * s->cus; }
 // with eight on 32 x 8 or seven on 32 x 16.
 constexpr int kServeSteps = 7, kServeRows = 12, kServeCols = 32, kServeWaves = 8, kServeBlocksPerCu = 4;
 // Rounds whose resident buffers exceed the 256 MB Infinity Cache run on
-// marching wave strips instead (the single-lattice default beyond the cache):
-// seven steps per launch, segments of 64 rows, a persistent grid of one
-// workgroup of 4 waves per CU: one wave per SIMD, all resident at once (the
-// registers of the Gray-Scott FP32 kernel allow one); a second workgroup per
-// CU would wait for the first to finish its whole share (on a 4096^2 FP32
-// lattice: 109 against 93 us per step).
-constexpr int kServeMarchRows = 64, kServeMarchWaves = 4, kServeMarchBlocksPerCu = 1;
+// marching wave strips instead: eight steps per launch, segments of 128
+// rows, a persistent grid of one workgroup of 4 waves per CU: one wave per
+// SIMD, all resident at once (the registers of the Gray-Scott FP32 kernel
+// allow one); a second workgroup per CU would wait for the first to finish
+// its whole share (on a 4096^2 FP32 lattice: 109 against 93 us per step).
+// On the benchmark's 256-instance Gray-Scott sweep with this grid: 134.8 us
+// per step, against 144.9 with seven steps on 64 rows.
+constexpr int kServeMarchSteps = 8, kServeMarchRows = 128, kServeMarchWaves = 4, kServeMarchBlocksPerCu = 1;
 
 // Round kinds: one step per launch (any mix), multi-step on LDS tiles,
 // multi-step on marching strips.
 enum RoundKind : int { kRoundOne = 0, kRoundTiles = 1, kRoundMarch = 2 };
 
+int round_steps(int kind) { return kind == kRoundOne ? 1 : kind == kRoundMarch ? kServeMarchSteps : kServeSteps; }
+
 hipError_t enqueue_chunk(lbrd_server *s, int set, int kind, int mask, hipStream_t st) {
-    const int64_t launches = launches_for(s->sc.chunk_steps, kind == kRoundOne ? 1 : kServeSteps);
+    const int64_t launches = launches_for(s->sc.chunk_steps, round_steps(kind));
     if (kind == kRoundMarch) {
         // The classes of a marching round touch disjoint instances: each runs
         // its chain of launches on a branch of its own, forked from st and
@@ -209,7 +212,7 @@ hipError_t enqueue_chunk(lbrd_server *s, int set, int kind, int mask, hipStream_
             e = hipStreamWaitEvent(s->branch[cls], s->fork, 0);
             for (int64_t j = 0; j < launches && e == hipSuccess; ++j)
                 e = launch_batch_stepW(s->d_hdr, s->d_inst, (int)j, (int64_t)kServeMarchBlocksPerCu * s->cus,
-                                       kServeMarchWaves, kServeSteps, cls, s->branch[cls]);
+                                       kServeMarchWaves, kServeMarchSteps, cls, s->branch[cls]);
             if (e == hipSuccess) e = hipEventRecord(s->join[cls], s->branch[cls]);
             if (e == hipSuccess) e = hipStreamWaitEvent(st, s->join[cls], 0);
         }
@@ -402,7 +405,7 @@ void worker_loop(lbrd_server *s) {
             int mask = 0;
             if (kind == kRoundMarch)
                 for (Request *rp : resp) mask |= 1 << march_class(rp->cfg.storage, variant_of(rp->cfg));
-            const int ts = kind == kRoundOne ? 1 : kServeSteps;
+            const int ts = round_steps(kind);
             for (Request *rp : resp) {
                 Request &r = *rp;
                 const int vec = batch_vec(r.cfg.storage);

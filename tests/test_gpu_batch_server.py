@@ -93,8 +93,8 @@ def test_batch_gs_f32_equals_solo_and_oracle(mode):
 
 def test_full_size_sweep_batch_sampled():
     """The benchmark's batched workload at full size (256 Gray-Scott instances,
-    sides 128..512, seed 0, 4.2 GB of buffers, default launch shape: seven
-    steps per launch on marching strips of 64 rows, graphs of 28 steps):
+    sides 128..512, seed 0, 4.2 GB of buffers, default launch shape: eight
+    steps per launch on marching strips of 128 rows, graphs of 32 steps):
     after 70 steps (two graph replays and a ragged remainder) a sample of
     instances equals their solo runs bitwise, and the smallest sampled
     lattice equals the FP64 oracle within the FP32 floor."""
@@ -103,7 +103,7 @@ def test_full_size_sweep_batch_sampled():
                              F=i.F, k=i.k) for i in insts]
     b = lbrd.Batch(cfgs)
     t = b.tuning()
-    assert (t.fused_steps, t.march_rows, t.waves, t.graph_steps) == (7, 64, 4, 28)
+    assert (t.fused_steps, t.march_rows, t.waves, t.graph_steps) == (8, 128, 4, 32)
     for idx, inst in enumerate(insts):
         b.init(idx, workloads.batch_initial(inst))
     steps = 70
@@ -269,7 +269,7 @@ def test_batch_autotune_then_run():
     if t.fused_steps == 1:
         assert 1 <= t.blocks_per_cu <= 32 and t.waves in (1, 2, 4)
     elif t.march_rows > 0:
-        assert 4 <= t.fused_steps <= 8 and t.march_rows in (16, 32, 64) and t.waves in (1, 4)
+        assert 4 <= t.fused_steps <= 8 and t.march_rows in (16, 32, 64, 128, 256) and t.waves in (1, 4)
         assert t.graph_steps % (2 * t.fused_steps) == 0
     else:
         assert 2 <= t.fused_steps <= 8 and t.tile_cols in (32, 64) and t.tile_rows in (4, 8, 12, 16, 20)
