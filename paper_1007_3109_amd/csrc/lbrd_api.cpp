@@ -476,20 +476,24 @@ int march_rows_for(const lbrd_solver *h, int steps, int k) {
 //     beyond T 7, k 1 (166.4 against 171.7; 2048^2 42.7 against 59.3; 1024^2
 //     11.5 against 16.4); inside from 512^2 T 6, 8 rows, one-wave workgroups
 //     (4.45 against 4.54).  16-bit inside the cache: LDS tiles (F16 1024^2
-//     5.58 against 5.96).
+//     5.58 against 5.96).  F16 once its population sums read the packed
+//     halves in place: 49.7 us at 4096^2 (T 8), 14.8 at 2048^2 (T 7).
 //   One linear species: FP32 beyond T 11, k 2 (29.2 against 40.4; 2048^2 8.54
 //     against 10.9), inside from 1024^2 T 7, k 1 (3.01 against 3.49); F16
 //     beyond T 7, k 4 when big (30.5 against 30.6), else T 5, k 3 (8.75
-//     against 8.96); BF16 beyond and big T 6, k 4 (32.9 against 33.0), else
+//     against 8.96; inside the cache at 2048^2 the same, 8.64 against 8.98);
+//     BF16 beyond and big T 6, k 4 (32.9 against 33.0), else
 //     LDS tiles (9.01 against 9.44); FP64 beyond T 8, k 1 (64.7 against 78.7;
 //     2048^2 17.9 against 20.6), inside from 1024^2 (4.14 against 4.60).
 //   Three species: FP32 beyond T 8, k 3 when big (132.5 against 147.7), else
 //     k 1 (33.8 against 42.9), inside from 1024^2 T 6, k 1 (10.5 against
-//     15.6); 16-bit beyond T 5, 16 rows when big (F16 123.2; k 1 126.6), else
-//     k 2 (30.0 against 34.0).  Four species: FP32 beyond T 5, k 4 when big
-//     (271.1 against 278.6), else k 1, one-wave workgroups (68.6 against
-//     72.5); F16 beyond T 5, one-wave workgroups, k 3 when big (195.3 against
-//     205.5), else k 1 (51.2 against 52.6).
+//     15.6); F16 beyond T 6, k 1 when big (109.2 against 123.0), else k 2
+//     (28.4 against 29.8); BF16 beyond T 5, 16 rows when big (F16 at the
+//     time 123.2; k 1 126.6), else k 2 (F16 30.0 against 34.0).  Four
+//     species: FP32 beyond T 5, k 4 when big (271.1 against 278.6), else
+//     k 1, one-wave workgroups (68.6 against 72.5); F16 beyond T 5, one-wave
+//     workgroups, k 3 when big (195.3 against 205.5), else k 1 (51.2
+//     against 52.6).
 //   Shear flow, FP32 beyond, big: T 5, k 2 with Gray-Scott (134.0 against
 //     177.4), k 3 with one species (63.8 against 80.6).  Uniform velocity: one
 //     species, 16-bit beyond, T 5, k 4 when big (BF16 38.3 against 39.3, F16
@@ -522,6 +526,7 @@ MarchShape march_default(const lbrd_solver *h, bool in_cache, int64_t sites) {
             if (in_cache) {
                 if (f32 && mid) return {7, 0, 4, 1};
                 if (f64 && mid) return {8, 0, 4, 1};
+                if (f16 && sites >= (int64_t)2048 * 2048) return {5, 0, 4, 3};
                 return {};
             }
             if (f32) return {11, 0, 4, 2};
@@ -532,6 +537,7 @@ MarchShape march_default(const lbrd_solver *h, bool in_cache, int64_t sites) {
             if (f64) return {};
             if (in_cache) return f32 && mid ? MarchShape{6, 0, 4, 1} : MarchShape{};
             if (f32) return {8, 0, 4, big ? 3 : 1};
+            if (f16) return {6, 0, 4, big ? 1 : 2};
             return big ? MarchShape{5, 16, 4, 1} : MarchShape{5, 0, 4, 2};
         case kLin4:
             if (in_cache || f64) return {};

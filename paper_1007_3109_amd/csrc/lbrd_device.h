@@ -93,10 +93,14 @@ constexpr bool kShifted = ST == kF16 || ST == kBF16;
 // acc + h in FP32 (one rounding; h converts exactly), reading the binary16
 // operand directly: one mixed-precision multiply-add by 1.0 instead of a
 // conversion and an add.  The population sums of the 16-bit form take it.
+// The 1.0 comes from a scalar register the compiler cannot see into, so the
+// multiply-add is not folded into an add of a converted value; the compiler
+// then selects the mixed multiply-add itself and reads either half of a
+// packed register in place.
 __device__ __forceinline__ float add_half(float acc, _Float16 h) {
-    float r;
-    asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(h), "v"(acc));
-    return r;
+    float one;
+    asm("s_mov_b32 %0, 1.0" : "=s"(one));
+    return __builtin_fmaf((float)h, one, acc);
 }
 
 // Stored value <-> deviation d (= f for F64 / F32, f - w_i rho_ref,s for the
