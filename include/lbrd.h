@@ -329,9 +329,9 @@ int lbrd_batch_spectrum(lbrd_batch *b, int idx, int species, void *out, void *wo
  * or all from the serving mix (one-species linear or Gray-Scott without a
  * velocity, in FP32 / F16 / BF16 storage, each buffer below 4 GiB), take
  * fused_steps = T in 2..8 on tile_cols x tile_rows tiles, tile_cols 32 or 64,
- * or with march_rows > 0 on marching strips (default 5 steps on 32 x 10
+ * or with march_rows > 0 on marching strips, T in 2..12 (default 5 steps on 32 x 10
  * tiles, 8 waves, while the buffers fit in the 256 MB Infinity Cache;
- * beyond it 8 steps on marching strips of 128 rows, 4 waves; blocks_per_cu 0
+ * beyond it 9 steps on marching strips of 128 rows, 4 waves; blocks_per_cu 0
  * = one workgroup per tile or strip segments, graph_steps the multiple of 2T
  * nearest 32):
  * launch j advances each instance by min(T, its steps left in the chunk), and

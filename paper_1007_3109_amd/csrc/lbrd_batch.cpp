@@ -220,7 +220,8 @@ bool batch_tuning_valid(const lbrd_batch *b, const lbrd_tuning &t) {
                !(t.graph_steps & 1);
     // multi-step launches: an even number of launches per captured chunk, so
     // every instance ends a chunk in the buffer it started from
-    if (!b->multi_ok || t.fused_steps < 2 || t.fused_steps > kMaxBatchFusedSteps) return false;
+    if (!b->multi_ok || t.fused_steps < 2) return false;
+    if (t.fused_steps > (t.march_rows > 0 ? kMaxBatchMarchSteps : kMaxBatchFusedSteps)) return false;
     if (t.graph_steps % (2 * t.fused_steps)) return false;
     if (t.blocks_per_cu < 0 || t.blocks_per_cu > 32) return false;
     if (t.march_rows < 0 || t.march_rows > 65536) return false;
@@ -291,15 +292,15 @@ int lbrd_batch_create(const lbrd_config *cfgs, int count, void *workspace, size_
         // while the buffers fit in the Infinity Cache, five steps per launch
         // on 32 x 10 LDS tiles (the LDS of both sets is sized for it), one
         // workgroup of 8 waves per tile; beyond it, marching wave strips
-        // (eight steps per launch, segments of 128 rows, one wave per
+        // (nine steps per launch, segments of 128 rows, one wave per
         // segment, four to a workgroup: on the benchmark's 256-instance
-        // Gray-Scott sweep 128.6 us per step, against 145.2 with seven steps
-        // on 64 rows and 141.8 with eight on 256); graphs of about 32 steps
-        // (an even number of launches)
+        // Gray-Scott sweep 120.6 us per step, against 129.0 with eight
+        // steps, 143.2 with ten, 145.2 with seven on 64 rows, 134.5 with nine
+        // on 256); graphs of about 32 steps (an even number of launches)
         size_t bytes = 0;
         for (const Layout &L : b->L) bytes += 2 * L.buf_bytes;
         const bool in_cache = bytes <= ((size_t)256 << 20);
-        b->tune.fused_steps = in_cache ? 5 : 8;
+        b->tune.fused_steps = in_cache ? 5 : 9;
         b->tune.tile_rows = in_cache ? 10 : 0;
         b->tune.tile_cols = in_cache ? 32 : 0;
         b->tune.march_rows = in_cache ? 0 : 128;
@@ -625,7 +626,7 @@ int lbrd_batch_autotune(lbrd_batch *b, int steps, lbrd_tuning *chosen) {
                         cands.push_back(t);
                     }
     if (b->multi_ok)
-        for (int ts = 4; ts <= kMaxBatchFusedSteps; ++ts)
+        for (int ts = 4; ts <= kMaxBatchMarchSteps; ++ts)
             for (int rows : {16, 32, 64, 128, 256})
                 for (int w : {1, 4}) {
                     lbrd_tuning t = keep;

@@ -271,7 +271,7 @@ __global__ __launch_bounds__(256) void k_batch_stepW(const BatchHeader *__restri
 template <int ST, int V>
 static hipError_t launch_classW(const BatchHeader *hdr, const BatchInst *inst, int j, int64_t blocks, int waves,
                                 int ts, hipStream_t st) {
-    static_assert(kMaxBatchFusedSteps == 8, "instantiate every step count");
+    static_assert(kMaxBatchMarchSteps == 12, "instantiate every step count");
     const dim3 grid((unsigned)blocks), block(64 * waves);
     switch (ts) {
         case 2: hipLaunchKernelGGL((k_batch_stepW<ST, V, 2>), grid, block, 0, st, hdr, inst, j); break;
@@ -281,6 +281,10 @@ static hipError_t launch_classW(const BatchHeader *hdr, const BatchInst *inst, i
         case 6: hipLaunchKernelGGL((k_batch_stepW<ST, V, 6>), grid, block, 0, st, hdr, inst, j); break;
         case 7: hipLaunchKernelGGL((k_batch_stepW<ST, V, 7>), grid, block, 0, st, hdr, inst, j); break;
         case 8: hipLaunchKernelGGL((k_batch_stepW<ST, V, 8>), grid, block, 0, st, hdr, inst, j); break;
+        case 9: hipLaunchKernelGGL((k_batch_stepW<ST, V, 9>), grid, block, 0, st, hdr, inst, j); break;
+        case 10: hipLaunchKernelGGL((k_batch_stepW<ST, V, 10>), grid, block, 0, st, hdr, inst, j); break;
+        case 11: hipLaunchKernelGGL((k_batch_stepW<ST, V, 11>), grid, block, 0, st, hdr, inst, j); break;
+        case 12: hipLaunchKernelGGL((k_batch_stepW<ST, V, 12>), grid, block, 0, st, hdr, inst, j); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -294,7 +298,7 @@ int march_class(int storage, int variant) {
 
 hipError_t launch_batch_stepW(const BatchHeader *hdr, const BatchInst *inst, int j, int64_t blocks, int waves, int ts,
                               int cls, hipStream_t st) {
-    if (ts < 2 || ts > kMaxBatchFusedSteps || !(waves == 1 || waves == 2 || waves == 4) || blocks < 1 ||
+    if (ts < 2 || ts > kMaxBatchMarchSteps || !(waves == 1 || waves == 2 || waves == 4) || blocks < 1 ||
         blocks > 0x7fffffff)
         return hipErrorInvalidValue;
     switch (cls) {

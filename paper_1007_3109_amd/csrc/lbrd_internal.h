@@ -118,6 +118,9 @@ constexpr int kMaxFusedSteps = 8;
 // holds 8, its carries take twice the registers).
 constexpr int kMaxMarchSteps = 12;
 constexpr int kMaxBatchFusedSteps = 8;
+// Batched marching strips (FP32 and 16-bit classes) take up to 12 steps a
+// launch, as the single-lattice ones.
+constexpr int kMaxBatchMarchSteps = 12;
 
 GridT make_gridT(const Layout &L, const void *src, void *dst, int tw, int th, int steps);
 // LDS row stride (elements) of the multi-step region of width ew with 9 N
@@ -249,8 +252,9 @@ hipError_t launch_batch_stepT(const BatchHeader *hdr, const BatchInst *inst, int
 // march_class returns -1 for every other instance.
 constexpr int kMarchClasses = 6;
 int march_class(int storage, int variant);
-// Launch j of a chunk with `ts` steps per launch on marching wave strips
-// (64 - 2(ts-1) result columns by mt_th rows each, no LDS) for the instances
+// Launch j of a chunk with `ts` steps per launch (2 .. kMaxBatchMarchSteps)
+// on marching wave strips (64 - 2(ts-1) result columns by mt_th rows each,
+// no LDS) for the instances
 // of class `cls`: each advances min(ts, steps_i - j ts) steps if that is
 // positive; the others are skipped.  The descriptors must carry the marching
 // tiling of the same ts (set_batch_tiling_march).  `blocks` workgroups of

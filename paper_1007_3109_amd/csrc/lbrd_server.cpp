@@ -184,14 +184,14 @@ int blocks_for(const lbrd_server *s) { return 8 * s->cus; }
 // with eight on 32 x 8 or seven on 32 x 16.
 constexpr int kServeSteps = 7, kServeRows = 12, kServeCols = 32, kServeWaves = 8, kServeBlocksPerCu = 4;
 // Rounds whose resident buffers exceed the 256 MB Infinity Cache run on
-// marching wave strips instead: eight steps per launch, segments of 128
+// marching wave strips instead: nine steps per launch, segments of 128
 // rows, a persistent grid of one workgroup of 4 waves per CU: one wave per
 // SIMD, all resident at once (the registers of the Gray-Scott FP32 kernel
 // allow one); a second workgroup per CU would wait for the first to finish
 // its whole share (on a 4096^2 FP32 lattice: 109 against 93 us per step).
-// On the benchmark's 256-instance Gray-Scott sweep with this grid: 134.8 us
-// per step, against 144.9 with seven steps on 64 rows.
-constexpr int kServeMarchSteps = 8, kServeMarchRows = 128, kServeMarchWaves = 4, kServeMarchBlocksPerCu = 1;
+// On the benchmark's 256-instance Gray-Scott sweep with this grid: 122.0 us
+// per step, against 135.3 with eight steps and 144.9 with seven on 64 rows.
+constexpr int kServeMarchSteps = 9, kServeMarchRows = 128, kServeMarchWaves = 4, kServeMarchBlocksPerCu = 1;
 
 // Round kinds: one step per launch (any mix), multi-step on LDS tiles,
 // multi-step on marching strips.

@@ -93,9 +93,9 @@ def test_batch_gs_f32_equals_solo_and_oracle(mode):
 
 def test_full_size_sweep_batch_sampled():
     """The benchmark's batched workload at full size (256 Gray-Scott instances,
-    sides 128..512, seed 0, 4.2 GB of buffers, default launch shape: eight
-    steps per launch on marching strips of 128 rows, graphs of 32 steps):
-    after 70 steps (two graph replays and a ragged remainder) a sample of
+    sides 128..512, seed 0, 4.2 GB of buffers, default launch shape: nine
+    steps per launch on marching strips of 128 rows, graphs of 36 steps):
+    after 70 steps (one graph replay and a ragged remainder) a sample of
     instances equals their solo runs bitwise, and the smallest sampled
     lattice equals the FP64 oracle within the FP32 floor."""
     insts = workloads.batch_sweep(0)
@@ -103,7 +103,7 @@ def test_full_size_sweep_batch_sampled():
                              F=i.F, k=i.k) for i in insts]
     b = lbrd.Batch(cfgs)
     t = b.tuning()
-    assert (t.fused_steps, t.march_rows, t.waves, t.graph_steps) == (8, 128, 4, 32)
+    assert (t.fused_steps, t.march_rows, t.waves, t.graph_steps) == (9, 128, 4, 36)
     for idx, inst in enumerate(insts):
         b.init(idx, workloads.batch_initial(inst))
     steps = 70
@@ -172,7 +172,8 @@ def march_cases():
 
 @pytest.mark.parametrize("ts,rows,waves,bpc,graph_steps", [(2, 1, 1, 0, 0), (3, 7, 2, 1, 6), (5, 64, 4, 0, 10),
                                                            (7, 64, 4, 2, 28), (8, 16, 4, 0, 0), (6, 33, 1, 3, 12),
-                                                           (4, 200, 4, 1, 8)])
+                                                           (4, 200, 4, 1, 8), (10, 128, 4, 0, 20),
+                                                           (12, 9, 1, 1, 24), (11, 300, 4, 0, 0)])
 def test_batch_march_advance_equals_solo(ts, rows, waves, bpc, graph_steps):
     """Batched marching strips (march_rows > 0) on the serving mix, T steps per
     launch, one wave per strip segment or a persistent grid: per-instance
@@ -198,6 +199,8 @@ def test_batch_march_advance_equals_solo(ts, rows, waves, bpc, graph_steps):
         assert torch.equal(b.moments(idx)[0], solo(cfg, rho0, n)), (idx, n)
     with pytest.raises(lbrd.LbrdError):                 # one, two or four waves per workgroup
         b.set_tuning(fused_steps=4, march_rows=8, waves=8, blocks_per_cu=0, graph_steps=0)
+    with pytest.raises(lbrd.LbrdError):                 # at most 12 steps per launch on marching strips
+        b.set_tuning(fused_steps=13, march_rows=8, waves=4, blocks_per_cu=0, graph_steps=0)
     log(f"batched marching T {ts}, {rows} rows, {waves} waves, blocks per CU {bpc}: {len(cases)} instances bitwise "
         f"equal to solo runs")
     b.close()
@@ -269,7 +272,7 @@ def test_batch_autotune_then_run():
     if t.fused_steps == 1:
         assert 1 <= t.blocks_per_cu <= 32 and t.waves in (1, 2, 4)
     elif t.march_rows > 0:
-        assert 4 <= t.fused_steps <= 8 and t.march_rows in (16, 32, 64, 128, 256) and t.waves in (1, 4)
+        assert 4 <= t.fused_steps <= 12 and t.march_rows in (16, 32, 64, 128, 256) and t.waves in (1, 4)
         assert t.graph_steps % (2 * t.fused_steps) == 0
     else:
         assert 2 <= t.fused_steps <= 8 and t.tile_cols in (32, 64) and t.tile_rows in (4, 8, 12, 16, 20)
