@@ -351,7 +351,9 @@ __device__ __forceinline__ void collide_site(const Params<typename Traits<ST>::C
         // drift every step).
         const C a = fma_c(p.omega[s], m[s], R[s]);
         const C e1 = wgt<C>(1) * a, e5 = wgt<C>(5) * a;
-        const C e0 = a - C(4) * e1 - C(4) * e5;   // 4 e1 and 4 e5 are exact
+        // (a - 4 e1) - 4 e5: 4 e1 and 4 e5 are exact, so each multiply-add
+        // rounds exactly as the subtraction it stands for
+        const C e0 = fma_c(C(-4), e5, fma_c(C(-4), e1, a));
         if constexpr (PM && kShifted<ST> && NS == 2) {
 #pragma unroll
             for (int i = 0; i < 9; ++i) ep[s][i] = i == 0 ? e0 : (i < 5 ? e1 : e5);
