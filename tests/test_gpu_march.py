@@ -104,3 +104,25 @@ def test_march_with_graphs_and_oracle(ts, rows, graph):
         assert torch.equal(a.moments()[0], b.moments()[0])
     ref = oracle.solve(rho0, 52, list(workloads.GS_TAU), oracle.REACT_GRAY_SCOTT, **kw)
     assert np.all(oracle.rel_l2(b.moments()[0].cpu().numpy(), ref) <= 1e-5)
+
+
+@pytest.mark.parametrize("storage,reaction,ns,n,want_t,want_k", [
+    ("f32", "gray_scott", 2, 4096, 10, 1), ("f32", "gray_scott", 2, 2048, 9, 1), ("f16", "gray_scott", 2, 4096, 8, 3),
+    ("bf16", "gray_scott", 2, 2048, 6, 3), ("f32", "linear", 1, 4096, 11, 2), ("f64", "gray_scott", 2, 2048, 7, 1),
+    ("f32", "gray_scott", 2, 1024, 7, 1)])
+def test_default_segments_fill_k_waves_per_simd(storage, reaction, ns, n, want_t, want_k):
+    """The default marching shape of a lattice beyond (or, FP32 from 1024^2,
+    inside) the Infinity Cache: T steps per launch and segments of
+    R = ceil(ny / floor(4 CUs k / strips)) rows, strips = ceil(nx / (64 -
+    2(T-1))), so that strips x segments come to about k waves per SIMD."""
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    kw = dict(F=0.04, k=0.06) if reaction == "gray_scott" else dict(K=-0.01 * np.eye(ns))
+    cfg = lbrd.make_config(n, n, ns, tau=[0.7, 1.2][:ns], storage=storage, reaction=reaction,
+                           rho_ref=(1.0,) * ns, **kw)
+    s = lbrd.Solver(cfg)
+    t = s.tuning()
+    s.close()
+    strips = -(-n // (64 - 2 * (want_t - 1)))
+    segs = max(1, 4 * cus * want_k // strips)
+    assert (t.fused_steps, t.march_rows, t.waves) == (want_t, -(-n // segs), 4), t.as_dict()
+    assert strips * -(-n // t.march_rows) <= 4 * cus * want_k
