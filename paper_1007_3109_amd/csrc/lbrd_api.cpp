@@ -473,8 +473,9 @@ int march_rows_for(const lbrd_solver *h, int steps, int k) {
 //     k 1; FP32 inside from 1024^2 T 7, k 1 (5.80 against 6.54).  F16 beyond
 //     T 8 when big (54.3 against 58.3), else T 7 (16.1 against 17.5), BF16
 //     one step fewer (57.7 against 57.8; 16.7 against 18.1), k 3.  FP64
-//     beyond T 7, k 1 (166.4 against 171.7; 2048^2 42.7 against 59.3; 1024^2
-//     11.5 against 16.4); inside from 512^2 T 6, 8 rows, one-wave workgroups
+//     beyond T 8, k 1 (155.5 against 171.7; 2048^2 39.2 against 59.3; 1024^2
+//     11.0 against 16.4; T 7 was best before FP64 strips stored from every
+//     lane: 166.4, 42.7, 11.5); inside from 512^2 T 6, 8 rows, one-wave workgroups
 //     (4.45 against 4.54).  16-bit inside the cache: LDS tiles (F16 1024^2
 //     5.58 against 5.96).  F16 once its population sums read the packed
 //     halves in place: 49.7 us at 4096^2 (T 8), 14.8 at 2048^2 (T 7).
@@ -519,7 +520,7 @@ MarchShape march_default(const lbrd_solver *h, bool in_cache, int64_t sites) {
                 return {};
             }
             if (f32) return {big ? 10 : 9, 0, 4, 1};
-            if (f64) return {7, 0, 4, 1};
+            if (f64) return {8, 0, 4, 1};
             if (f16) return {big ? 8 : 7, 0, 4, 3};
             return {big ? 7 : 6, 0, 4, 3};
         case kLin1:

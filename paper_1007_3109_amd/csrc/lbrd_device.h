@@ -950,8 +950,25 @@ struct MarchCarry {
     T b[2][NS][3];
 };
 
+// FP64 strips store from every lane: a result lane at its column, a halo
+// lane out of range (march_store).  The other forms store from the result
+// lanes only, under a branch on the lane.
+template <int ST>
+constexpr bool kMarchStoreAll = ST == kF64;
+
 // Stores row q of the launch's last level: the 9N populations of each
-// result lane.
+// result lane.  With kMarchStoreAll every lane stores (nt is not used):
+// col_b is the lane's byte column for a result lane and 0xffffffff for a
+// halo lane, and the whole byte offset is formed in the lane with a
+// saturating add, so a halo lane's stays 0xffffffff, at or past the end of
+// every buffer below 4 GiB, and the hardware drops the store (a raw buffer
+// access is out of range when its offset reaches the descriptor's byte
+// count; the scalar offset is 0, so that holds whether or not the range
+// check counts it).  Without the branch the compiler's waits in the FP64
+// loop no longer assume the path without stores (measured: 4096^2 FP64
+// Gray-Scott at T 8 155.6 against 183.3 us per step).  For FP32 and the
+// 16-bit forms the two extra instructions per store cost more than the
+// waits (64.9 against 61.7 us at 4096^2 FP32).
 template <int ST, int V>
 __device__ __forceinline__ void march_store(typename Traits<ST>::T (&o)[NSpecies<V>::value][9], int q,
                                             __amdgpu_buffer_rsrc_t dst, uint32_t pstride_b, uint32_t pitch_b,
@@ -959,6 +976,15 @@ __device__ __forceinline__ void march_store(typename Traits<ST>::T (&o)[NSpecies
     using T = typename Traits<ST>::T;
     constexpr int NS = NSpecies<V>::value;
     const uint32_t row = (uint32_t)q * pitch_b;
+    if constexpr (kMarchStoreAll<ST>) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                buf_store<T>(dst, __builtin_elementwise_add_sat(col_b, (uint32_t)(s * 9 + i) * pstride_b + row), 0u,
+                             o[s][i]);
+        return;
+    }
     if (nt) {
 #pragma unroll
         for (int s = 0; s < NS; ++s)
@@ -992,12 +1018,12 @@ __device__ __forceinline__ void march_levels(const Params<typename Traits<ST>::C
     using C = typename Traits<ST>::C;
     constexpr int NS = NSpecies<V>::value;
     if constexpr (RM && K < TS) {
-        if (K == msteps && j >= TS - 1 + K - 1 && store_lane)
+        if (K == msteps && j >= TS - 1 + K - 1 && (kMarchStoreAll<ST> || store_lane))
             march_store<ST, V>(o, q, dst, pstride_b, pitch_b, col_b, nt);
     }
     if constexpr (K == TS) {
         // the last level: row q is the launch's result (active from j >= 2(TS-1))
-        if ((!RM || msteps == TS) && (!G || j >= 2 * (TS - 1)) && store_lane)
+        if ((!RM || msteps == TS) && (!G || j >= 2 * (TS - 1)) && (kMarchStoreAll<ST> || store_lane))
             march_store<ST, V>(o, q, dst, pstride_b, pitch_b, col_b, nt);
     } else {
         MarchCarry<T, NS> &m = c[K - 1];
@@ -1115,6 +1141,8 @@ __device__ __forceinline__ void stepW_strip(const StripW &sw, const Params<typen
     const uint32_t cx[3] = {(uint32_t)wrap_mod(xc - 1, nx) * B, (uint32_t)wrap_mod(xc, nx) * B,
                             (uint32_t)wrap_mod(xc + 1, nx) * B};
     const bool store_lane = lane >= H && lane < H + U && xc < nx;
+    // the byte column the lane stores at (kMarchStoreAll: out of range for a halo lane)
+    const uint32_t col_out = kMarchStoreAll<ST> && !store_lane ? 0xffffffffu : cx[1];
     const __amdgpu_buffer_rsrc_t src = sw.src, dst = sw.dst;
     const uint32_t pitch_b = sw.pitch_b, pstride_b = sw.pstride_b;
     const bool nt = sw.nt;
@@ -1159,11 +1187,11 @@ __device__ __forceinline__ void stepW_strip(const StripW &sw, const Params<typen
         load_row(parity, r + 2);
         __builtin_amdgcn_sched_barrier(0);
         if constexpr (PK)
-            march_levels_pk<ST, V, TS, 1, P, RM, G>(p, o, c, j, r, ny, dst, pstride_b, pitch_b, cx[1], store_lane,
+            march_levels_pk<ST, V, TS, 1, P, RM, G>(p, o, c, j, r, ny, dst, pstride_b, pitch_b, col_out, store_lane,
                                                     nt, m);
         else
-            march_levels<ST, V, TS, 1, P, RM, G>(p, o, c, j, r, ny, dst, pstride_b, pitch_b, cx[1], store_lane, nt,
-                                                 m);
+            march_levels<ST, V, TS, 1, P, RM, G>(p, o, c, j, r, ny, dst, pstride_b, pitch_b, col_out, store_lane,
+                                                 nt, m);
     };
     using I0 = std::integral_constant<int, 0>;
     using I1 = std::integral_constant<int, 1>;
@@ -1179,6 +1207,11 @@ __device__ __forceinline__ void stepW_strip(const StripW &sw, const Params<typen
             iteration(I0{}, Guarded{}, j);
             iteration(I1{}, Guarded{}, j + 1);
         }
+        // FP64, once per segment: every access done (vmcnt 0, lgkmcnt 0), so
+        // the loop below is entered with nothing in flight and the waits the
+        // compiler places in it are set by the loop's own accesses alone, not
+        // by the fewer ones in flight on the way in
+        if constexpr (kMarchStoreAll<ST>) __builtin_amdgcn_s_waitcnt(0x0070);
         for (; j + 1 < iters; j += 2) {
             iteration(I0{}, Full{}, j);
             iteration(I1{}, Full{}, j + 1);

@@ -108,7 +108,7 @@ def test_march_with_graphs_and_oracle(ts, rows, graph):
 
 @pytest.mark.parametrize("storage,reaction,ns,n,want_t,want_k", [
     ("f32", "gray_scott", 2, 4096, 10, 1), ("f32", "gray_scott", 2, 2048, 9, 1), ("f16", "gray_scott", 2, 4096, 8, 3),
-    ("bf16", "gray_scott", 2, 2048, 6, 3), ("f32", "linear", 1, 4096, 11, 2), ("f64", "gray_scott", 2, 2048, 7, 1),
+    ("bf16", "gray_scott", 2, 2048, 6, 3), ("f32", "linear", 1, 4096, 11, 2), ("f64", "gray_scott", 2, 2048, 8, 1),
     ("f32", "gray_scott", 2, 1024, 7, 1)])
 def test_default_segments_fill_k_waves_per_simd(storage, reaction, ns, n, want_t, want_k):
     """The default marching shape of a lattice beyond (or, FP32 from 1024^2,
