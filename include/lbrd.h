@@ -116,7 +116,8 @@ typedef struct lbrd_config {
  *  waves: waves (64 lanes) per workgroup, 1..16 except 3.  One-step
  *       launches use min(waves, 4); multi-step launches use all of them.
  *  nontemporal: 1 = streaming (non-temporal) accesses: loads and stores of
- *       one-step launches, the result stores of multi-step launches.
+ *       one-step launches, the result stores of multi-step launches (FP64
+ *       marching strips store cached either way).
  *  graph_steps: steps per captured HIP graph (0 = plain launches; else even;
  *       batches with T steps per launch: a multiple of 2T).  Single solvers
  *       default to 32 for one-step launches on lattices of at most 2^18
