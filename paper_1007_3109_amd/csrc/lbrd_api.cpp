@@ -476,16 +476,21 @@ int march_rows_for(const lbrd_solver *h, int steps, int k) {
 //     beyond T 8, k 1 (155.5 against 171.7; 2048^2 39.2 against 59.3; 1024^2
 //     11.0 against 16.4; T 7 was best before FP64 strips stored from every
 //     lane: 166.4, 42.7, 11.5); inside from 512^2 T 6, 8 rows, one-wave workgroups
-//     (4.45 against 4.54).  16-bit inside the cache: LDS tiles (F16 1024^2
-//     5.58 against 5.96).  F16 once its population sums read the packed
-//     halves in place: 49.7 us at 4096^2 (T 8), 14.8 at 2048^2 (T 7).
+//     (4.45 against 4.54).  F16 once its population sums read the packed
+//     halves in place: 49.7 us at 4096^2 (T 8), 14.8 at 2048^2 (T 7); and
+//     inside the cache from 1024^2, k 2: T 6 (5.43 against 5.57), from
+//     1448^2 T 5 (8.24 against 9.10); BF16 inside from 1448^2 T 4, k 3 (9.21
+//     against 9.61), below it LDS tiles (1024^2 5.64 against 5.97; F16 at
+//     768^2 3.66 against 4.03).
 //   One linear species: FP32 beyond T 11, k 2 (29.2 against 40.4; 2048^2 8.54
 //     against 10.9), inside from 1024^2 T 7, k 1 (3.01 against 3.49); F16
 //     beyond T 7, k 4 when big (30.5 against 30.6), else T 5, k 3 (8.75
-//     against 8.96; inside the cache at 2048^2 the same, 8.64 against 8.98);
-//     BF16 beyond and big T 6, k 4 (32.9 against 33.0), else
-//     LDS tiles (9.01 against 9.44); FP64 beyond T 8, k 1 (64.7 against 78.7;
-//     2048^2 17.9 against 20.6), inside from 1024^2 (4.14 against 4.60).
+//     against 8.96; inside the cache from 1448^2 T 5, k 2, 5.26 against 5.64,
+//     and k 3 from 2048^2, 8.64 against 8.98); BF16 beyond and big T 6, k 4
+//     (32.9 against 33.0), else LDS tiles (2048^2 inside the cache: 9.01
+//     against 9.44 in one run, 9.62 against 9.21 in another); FP64 beyond T
+//     8, k 1 (64.7 against 78.7; 2048^2 17.9 against 20.6), inside from
+//     1024^2 (4.14 against 4.60).
 //   Three species: FP32 beyond T 8, k 3 when big (132.5 against 147.7), else
 //     k 1 (33.8 against 42.9), inside from 1024^2 T 6, k 1 (10.5 against
 //     15.6); F16 beyond T 6, k 1 when big (109.2 against 123.0), else k 2
@@ -516,6 +521,8 @@ MarchShape march_default(const lbrd_solver *h, bool in_cache, int64_t sites) {
         case kLin2:
             if (in_cache) {
                 if (f32 && mid) return {7, 0, 4, 1};
+                if (f16 && mid) return {sites >= (int64_t)1448 * 1448 ? 5 : 6, 0, 4, 2};
+                if (b16 && sites >= (int64_t)1448 * 1448) return {4, 0, 4, 3};
                 if (f64 && sites >= (int64_t)512 * 512) return {6, 8, 1, 1};
                 return {};
             }
@@ -527,7 +534,7 @@ MarchShape march_default(const lbrd_solver *h, bool in_cache, int64_t sites) {
             if (in_cache) {
                 if (f32 && mid) return {7, 0, 4, 1};
                 if (f64 && mid) return {8, 0, 4, 1};
-                if (f16 && sites >= (int64_t)2048 * 2048) return {5, 0, 4, 3};
+                if (f16 && sites >= (int64_t)1448 * 1448) return {5, 0, 4, sites >= (int64_t)2048 * 2048 ? 3 : 2};
                 return {};
             }
             if (f32) return {11, 0, 4, 2};
