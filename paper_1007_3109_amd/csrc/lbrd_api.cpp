@@ -506,11 +506,20 @@ int march_rows_for(const lbrd_solver *h, int steps, int k) {
 //     36.7 against 37.2), else T 6, 64 rows; Gray-Scott FP32 beyond T 7, k 2
 //     when big (82.7 against 118.1), else k 1 (22.6 against 31.3), 16-bit
 //     beyond and big T 6, k 3 (F16 66.2 against 80.3).
+//   FP64 beyond the cache, once its strips stored from every lane: three
+//     species T 5, k 1 (4096^2 336.3 against 997.8; 2048^2 85.3 against
+//     211.5); four species T 4, k 1, one-wave workgroups (2048^2 165.4
+//     against 288.0); shear flow Gray-Scott T 4, k 4 when big, else k 1
+//     (293.1 against 387.3; 75.3 against 93.0), one species T 6, k 1
+//     (118.5 against 210.2); uniform velocity Gray-Scott T 8 when big,
+//     else 7, k 1 (166.4 against 313.1; 44.8 against 73.8), one species T 8,
+//     k 1 (65.4 against 105.5).
 // The step counts above 8 trade a wider x-halo (2(T-1) of a wave's 64
 // columns) for fewer passes over HBM; where a form's registers run out
 // (FP32 with three or four species above T 8) its time jumps.  Forms not
-// measured keep the LDS tiles (FP64 with three or more species, with a
-// shear or a velocity, or one species inside the cache below 1024^2).
+// measured keep the LDS tiles (FP64 inside the cache with three or more
+// species or a shear or a velocity, one species inside the cache below
+// 1024^2).
 MarchShape march_default(const lbrd_solver *h, bool in_cache, int64_t sites) {
     const int st = h->cfg.storage;
     const bool f64 = st == LBRD_F64, f32 = st == LBRD_F32, f16 = st == LBRD_F16_SHIFTED, b16 = !f64 && !f32;
@@ -542,26 +551,32 @@ MarchShape march_default(const lbrd_solver *h, bool in_cache, int64_t sites) {
             if (f16) return big ? MarchShape{7, 0, 4, 4} : MarchShape{5, 0, 4, 3};
             return big ? MarchShape{6, 0, 4, 4} : MarchShape{};
         case kLin3:
-            if (f64) return {};
+            if (f64) return in_cache ? MarchShape{} : MarchShape{5, 0, 4, 1};
             if (in_cache) return f32 && mid ? MarchShape{6, 0, 4, 1} : MarchShape{};
             if (f32) return {8, 0, 4, big ? 3 : 1};
             if (f16) return {6, 0, 4, big ? 1 : 2};
             return big ? MarchShape{5, 16, 4, 1} : MarchShape{5, 0, 4, 2};
         case kLin4:
-            if (in_cache || f64) return {};
+            if (in_cache) return {};
+            if (f64) return {4, 0, 1, 1};
             if (f32) return big ? MarchShape{5, 0, 4, 4} : MarchShape{5, 0, 1, 1};
             if (f16) return {5, 0, 1, big ? 3 : 1};
             return {};
         case kShearLin1:
         case kShearGS:
-            if (in_cache || !f32 || !big) return {};
+            if (in_cache) return {};
+            if (f64) return v == kShearGS ? MarchShape{4, 0, 4, big ? 4 : 1} : MarchShape{6, 0, 4, 1};
+            if (!f32 || !big) return {};
             return {5, 0, 4, v == kShearGS ? 2 : 3};
         case kAdvLin1:
-            if (in_cache || !b16) return {};
+            if (in_cache) return {};
+            if (f64) return {8, 0, 4, 1};
+            if (!b16) return {};
             return big ? MarchShape{5, 0, 4, 4} : MarchShape{6, 64, 4, 1};
         case kAdvGS:
             if (in_cache) return {};
             if (f32) return {7, 0, 4, big ? 2 : 1};
+            if (f64) return {big ? 8 : 7, 0, 4, 1};
             return b16 && big ? MarchShape{6, 0, 4, 3} : MarchShape{};
         default:
             return {};
