@@ -500,12 +500,15 @@ int march_rows_for(const lbrd_solver *h, int steps, int k) {
 //     k 1, one-wave workgroups (68.6 against 72.5); F16 beyond T 5, one-wave
 //     workgroups, k 3 when big (195.3 against 205.5), else k 1 (51.2
 //     against 52.6).
-//   Shear flow, FP32 beyond, big: T 5, k 2 with Gray-Scott (134.0 against
-//     177.4), k 3 with one species (63.8 against 80.6).  Uniform velocity: one
+//   Shear flow, FP32 beyond: T 5, Gray-Scott k 2 when big (134.0 against
+//     177.4), else k 1 (2048^2 36.2 against 47.1), one species k 3 (63.8
+//     against 80.6; 2048^2 17.9 against 28.9).  Uniform velocity: one
 //     species, 16-bit beyond, T 5, k 4 when big (BF16 38.3 against 39.3, F16
-//     36.7 against 37.2), else T 6, 64 rows; Gray-Scott FP32 beyond T 7, k 2
-//     when big (82.7 against 118.1), else k 1 (22.6 against 31.3), 16-bit
-//     beyond and big T 6, k 3 (F16 66.2 against 80.3).
+//     36.7 against 37.2), else T 6, 64 rows; FP32 T 9, k 2 (33.7 against
+//     50.6; 2048^2 9.94 against 14.7); Gray-Scott FP32 beyond T 7, k 2 when
+//     big (82.7 against 118.1), else k 1 (22.6 against 31.3), 16-bit beyond
+//     T 6, k 3 when big (F16 66.2 against 80.3), else F16 T 6, BF16 T 5, k 3
+//     (2048^2 18.5 against 22.0, 19.9 against 22.2).
 //   FP64 beyond the cache, once its strips stored from every lane: three
 //     species T 5, k 1 (4096^2 336.3 against 997.8; 2048^2 85.3 against
 //     211.5); four species T 4, k 1, one-wave workgroups (2048^2 165.4
@@ -566,18 +569,18 @@ MarchShape march_default(const lbrd_solver *h, bool in_cache, int64_t sites) {
         case kShearGS:
             if (in_cache) return {};
             if (f64) return v == kShearGS ? MarchShape{4, 0, 4, big ? 4 : 1} : MarchShape{6, 0, 4, 1};
-            if (!f32 || !big) return {};
-            return {5, 0, 4, v == kShearGS ? 2 : 3};
+            if (!f32) return {};
+            return {5, 0, 4, v == kShearGS ? (big ? 2 : 1) : 3};
         case kAdvLin1:
             if (in_cache) return {};
             if (f64) return {8, 0, 4, 1};
-            if (!b16) return {};
+            if (f32) return {9, 0, 4, 2};
             return big ? MarchShape{5, 0, 4, 4} : MarchShape{6, 64, 4, 1};
         case kAdvGS:
             if (in_cache) return {};
             if (f32) return {7, 0, 4, big ? 2 : 1};
             if (f64) return {big ? 8 : 7, 0, 4, 1};
-            return b16 && big ? MarchShape{6, 0, 4, 3} : MarchShape{};
+            return {big || f16 ? 6 : 5, 0, 4, 3};
         default:
             return {};
     }
