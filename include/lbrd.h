@@ -152,17 +152,20 @@ typedef struct lbrd_config {
  *       shape) when the lattice is wider than twice that many tiles (16-bit
  *       forms: at least twice), else 0.
  *       Results are bitwise identical for every order.
- *  march_rows: single solvers with fused_steps = T >= 2 and buffers below
- *       4 GiB: 0 = the LDS tiles above; R = 1..65536 = marching wave strips
+ *  march_rows: single solvers with fused_steps = T >= 2: 0 = the LDS tiles
+ *       above; R = 1..65536 = marching wave strips
  *       instead: each wave (min(waves, 4) waves per workgroup) owns 64
  *       columns, 2(T-1) of them recomputed halo, and marches down segments of
  *       R rows carrying the launch's intermediate rows in registers (no LDS,
  *       no barriers; only the x-halo is recomputed).  tile_cols, tile_rows and
  *       tile_strip are then ignored.  Ignored when fused_steps = 1 (one-step
- *       launches); refused (LBRD_EINVAL) with T >= 2 on buffers of 4 GiB or
- *       more.  lbrd_create chooses it from measurements (marching strips
+ *       launches).  On buffers of 4 GiB or more (each plane addressed by a
+ *       resource of its own) only Gray-Scott and one or two linear species
+ *       with T = 8, or 10 outside FP64, are accepted (else LBRD_EINVAL); a
+ *       shorter remainder of a run there runs on the strips of T.
+ *       lbrd_create chooses it from measurements (marching strips
  *       where they measured faster: most forms beyond the Infinity Cache,
- *       FP32 and FP64 inside it from 1024^2 sites), with R sized so that the
+ *       most inside it from 1024^2 sites), with R sized so that the
  *       strips' segments make a fixed number of waves per SIMD (one round of
  *       the launch for the kernels with one wave per SIMD).  Up to 12 steps
  *       a launch in FP32 and the 16-bit forms; FP64 up to 8.

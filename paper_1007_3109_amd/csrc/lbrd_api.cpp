@@ -336,8 +336,11 @@ hipError_t enqueue_steps(lbrd_solver *h, int from, int64_t n, hipStream_t st, in
         if (T >= 2 && left >= 2) {
             const int m = left < T ? (int)left : T;
             if (h->tune.march_rows > 0) {
-                // marching wave strips: 64 - 2(m-1) result columns a wave
-                GridT g = make_gridT(h->L, h->buf[a], h->buf[a ^ 1], 64 - 2 * (m - 1), h->tune.march_rows, m);
+                // marching wave strips: 64 - 2(m-1) result columns a wave (on
+                // buffers of 4 GiB or more the strips of T steps, which the
+                // kernel of T steps also runs for m < T)
+                const int ts = h->L.buf_bytes >= ((size_t)1 << 32) ? T : m;
+                GridT g = make_gridT(h->L, h->buf[a], h->buf[a ^ 1], 64 - 2 * (ts - 1), h->tune.march_rows, m);
                 g.march = 1;
                 g.xcd_order = h->tune.plain_order == 0 ? 1 : 0;
                 g.nt_store = h->tune.nontemporal;
@@ -594,7 +597,9 @@ bool tuning_valid(const lbrd_solver *h, const lbrd_tuning &t) {
     if (t.plain_order != 0 && t.plain_order != 1) return false;
     if (t.tile_strip < 0 || t.tile_strip > 65536) return false;
     if (t.march_rows < 0 || t.march_rows > 65536) return false;
-    if (t.march_rows > 0 && t.fused_steps >= 2 && big_buffers(h)) return false;
+    if (t.march_rows > 0 && t.fused_steps >= 2 && big_buffers(h) &&
+        !march_big_ok(h->cfg.storage, variant_of(h->cfg), t.fused_steps))
+        return false;
     if (t.graph_steps < 0 || (t.graph_steps & 1) || t.graph_steps > 4096) return false;
     if (t.nontemporal != 0 && t.nontemporal != 1) return false;
     if (t.waves < 1 || t.waves > 16) return false;
@@ -749,8 +754,19 @@ int lbrd_create(const lbrd_config *cfg, void *workspace, size_t bytes, void *str
         if (h->tune.fused_steps > 1) h->tune.tile_strip = default_strip(h, h->tune);
     }
     // Marching wave strips replace the LDS tiles where they measured faster.
-    const MarchShape ms = march_default(h, in_cache, sites);
-    if (h->tune.fused_steps > 1 && !big_buffers(h) && ms.steps > 0) {
+    MarchShape ms = march_default(h, in_cache, sites);
+    if (ms.steps > 0 && big_buffers(h)) {
+        // buffers of 4 GiB or more: marching strips with a descriptor per
+        // plane (march_big_ok), 8 steps a launch, segments for 3 waves per
+        // SIMD (8192^2 FP32 Gray-Scott 317 us per step against 686 on the
+        // LDS tiles and 420 with 10 steps in one round; 12288^2 F16 554
+        // against 820)
+        ms.steps = march_big_ok(h->cfg.storage, variant_of(h->cfg), 8) ? 8 : 0;
+        ms.rows = 0;
+        ms.k = 3;
+        ms.waves = 4;
+    }
+    if (h->tune.fused_steps > 1 && ms.steps > 0) {
         h->tune.fused_steps = ms.steps;
         h->tune.march_rows = ms.rows > 0 ? ms.rows : march_rows_for(h, ms.steps, ms.k);
         h->tune.waves = ms.waves;

@@ -969,10 +969,28 @@ constexpr bool kMarchStoreAll = ST == kF64;
 // Gray-Scott at T 8 155.6 against 183.3 us per step).  For FP32 and the
 // 16-bit forms the two extra instructions per store cost more than the
 // waits (64.9 against 61.7 us at 4096^2 FP32).
-template <int ST, int V>
+// Where a marching launch stores: one descriptor for a buffer below 4 GiB
+// (plane P at P * pstride_b bytes), or, with BIG (a buffer of 4 GiB or more,
+// each plane below it), a descriptor per plane from the 64-bit base.
+struct MarchOut {
+    __amdgpu_buffer_rsrc_t dst;
+    uint32_t pstride_b;
+    char *dst_p;
+    uint64_t pstride_64;
+    uint32_t plane_b;
+};
+
+// Stores v to plane P at byte offset voff + row of its plane (row < the
+// plane's bytes).
+template <class T, bool NT, bool BIG>
+__device__ __forceinline__ void store_plane(const MarchOut &out, int P, uint32_t voff, uint32_t row, T v) {
+    if constexpr (BIG) buf_store<T, NT>(buffer_rsrc(out.dst_p + (uint64_t)P * out.pstride_64, out.plane_b), voff, row, v);
+    else buf_store<T, NT>(out.dst, voff, (uint32_t)P * out.pstride_b + row, v);
+}
+
+template <int ST, int V, bool BIG = false>
 __device__ __forceinline__ void march_store(typename Traits<ST>::T (&o)[NSpecies<V>::value][9], int q,
-                                            __amdgpu_buffer_rsrc_t dst, uint32_t pstride_b, uint32_t pitch_b,
-                                            uint32_t col_b, bool nt) {
+                                            const MarchOut &out, uint32_t pitch_b, uint32_t col_b, bool nt) {
     using T = typename Traits<ST>::T;
     constexpr int NS = NSpecies<V>::value;
     const uint32_t row = (uint32_t)q * pitch_b;
@@ -980,21 +998,27 @@ __device__ __forceinline__ void march_store(typename Traits<ST>::T (&o)[NSpecies
 #pragma unroll
         for (int s = 0; s < NS; ++s)
 #pragma unroll
-            for (int i = 0; i < 9; ++i)
-                buf_store<T>(dst, __builtin_elementwise_add_sat(col_b, (uint32_t)(s * 9 + i) * pstride_b + row), 0u,
-                             o[s][i]);
+            for (int i = 0; i < 9; ++i) {
+                const int P = s * 9 + i;
+                if constexpr (BIG)
+                    buf_store<T>(buffer_rsrc(out.dst_p + (uint64_t)P * out.pstride_64, out.plane_b),
+                                 __builtin_elementwise_add_sat(col_b, row), 0u, o[s][i]);
+                else
+                    buf_store<T>(out.dst, __builtin_elementwise_add_sat(col_b, (uint32_t)P * out.pstride_b + row), 0u,
+                                 o[s][i]);
+            }
         return;
     }
     if (nt) {
 #pragma unroll
         for (int s = 0; s < NS; ++s)
 #pragma unroll
-            for (int i = 0; i < 9; ++i) buf_store<T, true>(dst, col_b, (uint32_t)(s * 9 + i) * pstride_b + row, o[s][i]);
+            for (int i = 0; i < 9; ++i) store_plane<T, true, BIG>(out, s * 9 + i, col_b, row, o[s][i]);
     } else {
 #pragma unroll
         for (int s = 0; s < NS; ++s)
 #pragma unroll
-            for (int i = 0; i < 9; ++i) buf_store<T>(dst, col_b, (uint32_t)(s * 9 + i) * pstride_b + row, o[s][i]);
+            for (int i = 0; i < 9; ++i) store_plane<T, false, BIG>(out, s * 9 + i, col_b, row, o[s][i]);
     }
 }
 
@@ -1007,24 +1031,23 @@ __device__ __forceinline__ void march_store(typename Traits<ST>::T (&o)[NSpecies
 // G (the iterations from 2(TS-1) on, where every level is active) the
 // activity tests are left out: the branches they make cost the compiler a
 // copy of every carry of the levels they skip.
-template <int ST, int V, int TS, int K, int P, bool RM = false, bool G = true>
+template <int ST, int V, int TS, int K, int P, bool RM = false, bool G = true, bool BIG = false>
 __device__ __forceinline__ void march_levels(const Params<typename Traits<ST>::C> &p,
                                              typename Traits<ST>::T (&o)[NSpecies<V>::value][9],
                                              MarchCarry<typename Traits<ST>::T, NSpecies<V>::value> (&c)[TS - 1],
-                                             int j, int q, int ny, __amdgpu_buffer_rsrc_t dst, uint32_t pstride_b,
-                                             uint32_t pitch_b, uint32_t col_b, bool store_lane, bool nt,
-                                             int msteps = TS) {
+                                             int j, int q, int ny, const MarchOut &out, uint32_t pitch_b,
+                                             uint32_t col_b, bool store_lane, bool nt, int msteps = TS) {
     using T = typename Traits<ST>::T;
     using C = typename Traits<ST>::C;
     constexpr int NS = NSpecies<V>::value;
     if constexpr (RM && K < TS) {
         if (K == msteps && j >= TS - 1 + K - 1 && (kMarchStoreAll<ST> || store_lane))
-            march_store<ST, V>(o, q, dst, pstride_b, pitch_b, col_b, nt);
+            march_store<ST, V, BIG>(o, q, out, pitch_b, col_b, nt);
     }
     if constexpr (K == TS) {
         // the last level: row q is the launch's result (active from j >= 2(TS-1))
         if ((!RM || msteps == TS) && (!G || j >= 2 * (TS - 1)) && (kMarchStoreAll<ST> || store_lane))
-            march_store<ST, V>(o, q, dst, pstride_b, pitch_b, col_b, nt);
+            march_store<ST, V, BIG>(o, q, out, pitch_b, col_b, nt);
     } else {
         MarchCarry<T, NS> &m = c[K - 1];
         C f[NS][9];
@@ -1049,8 +1072,8 @@ __device__ __forceinline__ void march_levels(const Params<typename Traits<ST>::C
         if (!G || j >= 2 * K) {
             T o2[NS][9];
             collide_site<ST, V>(p, f, o2, kShear<V> ? wrap_mod(q - 1, ny) : 0);
-            march_levels<ST, V, TS, K + 1, P, RM, G>(p, o2, c, j, q - 1, ny, dst, pstride_b, pitch_b, col_b,
-                                                  store_lane, nt, msteps);
+            march_levels<ST, V, TS, K + 1, P, RM, G, BIG>(p, o2, c, j, q - 1, ny, out, pitch_b, col_b, store_lane,
+                                                       nt, msteps);
         }
     }
 }
@@ -1068,18 +1091,17 @@ __device__ __forceinline__ uint16_t plane_half(uint32_t w, int s) { return s ? (
 
 // march_levels for two species in a 16-bit form on packed words (the same
 // values and the same update; the site's results are rounded plane by plane).
-template <int ST, int V, int TS, int K, int P, bool RM = false, bool G = true>
+template <int ST, int V, int TS, int K, int P, bool RM = false, bool G = true, bool BIG = false>
 __device__ __forceinline__ void march_levels_pk(const Params<float> &p, uint16_t (&o)[2][9], MarchCarryPk (&c)[TS - 1],
-                                                int j, int q, int ny, __amdgpu_buffer_rsrc_t dst, uint32_t pstride_b,
-                                                uint32_t pitch_b, uint32_t col_b, bool store_lane, bool nt,
-                                                int msteps = TS) {
+                                                int j, int q, int ny, const MarchOut &out, uint32_t pitch_b,
+                                                uint32_t col_b, bool store_lane, bool nt, int msteps = TS) {
     if constexpr (RM && K < TS) {
         if (K == msteps && j >= TS - 1 + K - 1 && store_lane)
-            march_store<ST, V>(o, q, dst, pstride_b, pitch_b, col_b, nt);
+            march_store<ST, V, BIG>(o, q, out, pitch_b, col_b, nt);
     }
     if constexpr (K == TS) {
         if ((!RM || msteps == TS) && (!G || j >= 2 * (TS - 1)) && store_lane)
-            march_store<ST, V>(o, q, dst, pstride_b, pitch_b, col_b, nt);
+            march_store<ST, V, BIG>(o, q, out, pitch_b, col_b, nt);
     } else {
         MarchCarryPk &m = c[K - 1];
         uint32_t w[9];
@@ -1108,8 +1130,8 @@ __device__ __forceinline__ void march_levels_pk(const Params<float> &p, uint16_t
         if (!G || j >= 2 * K) {
             uint16_t o2[2][9];
             collide_site<ST, V, true>(p, f, o2, kShear<V> ? wrap_mod(q - 1, ny) : 0);
-            march_levels_pk<ST, V, TS, K + 1, P, RM, G>(p, o2, c, j, q - 1, ny, dst, pstride_b, pitch_b, col_b,
-                                                     store_lane, nt, msteps);
+            march_levels_pk<ST, V, TS, K + 1, P, RM, G, BIG>(p, o2, c, j, q - 1, ny, out, pitch_b, col_b,
+                                                          store_lane, nt, msteps);
         }
     }
 }
@@ -1123,10 +1145,16 @@ struct StripW {
     uint32_t pitch_b, pstride_b;
     int x0, y0, rows;
     bool nt;
+    // BIG (a buffer of 4 GiB or more): base pointers, plane stride and
+    // plane bytes, a descriptor per plane
+    const char *src_p;
+    char *dst_p;
+    uint64_t pstride_64;
+    uint32_t plane_b;
 };
 
 // TS steps (or, with RM, m <= TS steps) on one strip.
-template <int ST, int V, int TS, bool RM = false>
+template <int ST, int V, int TS, bool RM = false, bool BIG = false>
 __device__ __forceinline__ void stepW_strip(const StripW &sw, const Params<typename Traits<ST>::C> &p, int lane,
                                             int m = TS) {
     using T = typename Traits<ST>::T;
@@ -1143,9 +1171,15 @@ __device__ __forceinline__ void stepW_strip(const StripW &sw, const Params<typen
     const bool store_lane = lane >= H && lane < H + U && xc < nx;
     // the byte column the lane stores at (kMarchStoreAll: out of range for a halo lane)
     const uint32_t col_out = kMarchStoreAll<ST> && !store_lane ? 0xffffffffu : cx[1];
-    const __amdgpu_buffer_rsrc_t src = sw.src, dst = sw.dst;
+    const __amdgpu_buffer_rsrc_t src = sw.src;
     const uint32_t pitch_b = sw.pitch_b, pstride_b = sw.pstride_b;
     const bool nt = sw.nt;
+    MarchOut out;
+    out.dst = sw.dst;
+    out.pstride_b = pstride_b;
+    out.dst_p = sw.dst_p;
+    out.pstride_64 = sw.pstride_64;
+    out.plane_b = sw.plane_b;
     const int iters = RM ? rows + H + m - 1 : rows + 2 * H;
     // two species in a 16-bit form: packed carries (march_levels_pk)
     constexpr bool PK = kShifted<ST> && NS == 2;
@@ -1161,8 +1195,13 @@ __device__ __forceinline__ void stepW_strip(const StripW &sw, const Params<typen
 #pragma unroll
         for (int s = 0; s < NS; ++s)
 #pragma unroll
-            for (int i = 0; i < 9; ++i)
-                raw[P][s][i] = buf_load<T>(src, cx[1 - kEx[i]], (uint32_t)(s * 9 + i) * pstride_b + ry[1 - kEy[i]]);
+            for (int i = 0; i < 9; ++i) {
+                if constexpr (BIG)
+                    raw[P][s][i] = buf_load<T>(buffer_rsrc(sw.src_p + (uint64_t)(s * 9 + i) * sw.pstride_64, sw.plane_b),
+                                               cx[1 - kEx[i]], ry[1 - kEy[i]]);
+                else
+                    raw[P][s][i] = buf_load<T>(src, cx[1 - kEx[i]], (uint32_t)(s * 9 + i) * pstride_b + ry[1 - kEy[i]]);
+            }
     };
     // one iteration of parity P: level 1 at row r = y0 - h + j from the
     // prefetched values, then the values of iteration j + 2 requested, then
@@ -1187,11 +1226,10 @@ __device__ __forceinline__ void stepW_strip(const StripW &sw, const Params<typen
         load_row(parity, r + 2);
         __builtin_amdgcn_sched_barrier(0);
         if constexpr (PK)
-            march_levels_pk<ST, V, TS, 1, P, RM, G>(p, o, c, j, r, ny, dst, pstride_b, pitch_b, col_out, store_lane,
-                                                    nt, m);
+            march_levels_pk<ST, V, TS, 1, P, RM, G, BIG>(p, o, c, j, r, ny, out, pitch_b, col_out, store_lane, nt,
+                                                         m);
         else
-            march_levels<ST, V, TS, 1, P, RM, G>(p, o, c, j, r, ny, dst, pstride_b, pitch_b, col_out, store_lane,
-                                                 nt, m);
+            march_levels<ST, V, TS, 1, P, RM, G, BIG>(p, o, c, j, r, ny, out, pitch_b, col_out, store_lane, nt, m);
     };
     using I0 = std::integral_constant<int, 0>;
     using I1 = std::integral_constant<int, 1>;
@@ -1229,8 +1267,10 @@ __device__ __forceinline__ void stepW_strip(const StripW &sw, const Params<typen
 // TS steps per launch (2 .. 12; FP64 2 .. 8) on marching wave strips: g.tw =
 // 64 - 2(TS-1) result columns per strip, g.th rows per segment, g.ntx strips
 // across and g.nty segments down, one wave each (g.ntiles of them); buffers
-// below 4 GiB.
-template <int ST, int V, int TS>
+// below 4 GiB, or with BIG of 4 GiB or more (g.bytes 0), each plane below it
+// (g.plane_bytes), addressed plane by plane; a BIG kernel also runs launches
+// of g.steps < TS steps on the strips of TS.
+template <int ST, int V, int TS, bool BIG = false>
 __global__ __launch_bounds__(256) void k_stepW(GridT g, Params<typename Traits<ST>::C> p) {
     using T = typename Traits<ST>::T;
     constexpr int U = 64 - 2 * (TS - 1);
@@ -1252,7 +1292,18 @@ __global__ __launch_bounds__(256) void k_stepW(GridT g, Params<typename Traits<S
     sw.y0 = sy * g.th;
     sw.rows = min(g.th, g.ny - sw.y0);
     sw.nt = g.nt_store != 0;
-    stepW_strip<ST, V, TS>(sw, p, lane);
+    sw.src_p = static_cast<const char *>(g.src);
+    sw.dst_p = static_cast<char *>(g.dst);
+    sw.pstride_64 = (uint64_t)g.pstride * B;
+    sw.plane_b = g.plane_bytes;
+    if constexpr (BIG) {
+        // g.steps = m <= TS: a shorter launch stores at level m (the strip's
+        // halo, laid out for TS steps, covers m)
+        if (g.steps == TS) stepW_strip<ST, V, TS, false, true>(sw, p, lane);
+        else stepW_strip<ST, V, TS, true, true>(sw, p, lane, g.steps);
+    } else {
+        stepW_strip<ST, V, TS>(sw, p, lane);
+    }
 }
 
 }  // namespace lbrd

@@ -117,6 +117,13 @@ constexpr int kMaxFusedSteps = 8;
 // no tile in LDS: up to 12 steps a launch in the 32- and 16-bit forms (FP64
 // holds 8, its carries take twice the registers).
 constexpr int kMaxMarchSteps = 12;
+// Marching strips on buffers of 4 GiB or more (a descriptor per plane, each
+// plane below 4 GiB): Gray-Scott and one or two linear species, 8 steps a
+// launch, or 10 outside FP64.
+constexpr bool march_big_ok(int storage, int variant, int steps) {
+    return (variant == kGS || variant == kLin1 || variant == kLin2) &&
+           (steps == 8 || (steps == 10 && storage != kF64));
+}
 constexpr int kMaxBatchFusedSteps = 8;
 // Batched marching strips (FP32 and 16-bit classes) take up to 12 steps a
 // launch, as the single-lattice ones.

@@ -92,10 +92,18 @@ template <int ST, int V, int TS>
 inline hipError_t launch_stepW_t(const StepLaunch &sl, const GridT &g, const void *params, hipStream_t st) {
     using C = typename Traits<ST>::C;
     const Params<C> &p = *static_cast<const Params<C> *>(params);
-    if (g.tw != 64 - 2 * (TS - 1) || g.th < 1 || g.bytes == 0 || sl.waves < 1 || sl.waves > 4)
-        return hipErrorInvalidValue;
+    if (g.tw != 64 - 2 * (TS - 1) || g.th < 1 || sl.waves < 1 || sl.waves > 4) return hipErrorInvalidValue;
     const int64_t nb = (g.ntiles + sl.waves - 1) / sl.waves;
     if (nb > 0x7fffffff) return hipErrorInvalidValue;
+    if (g.bytes == 0) {
+        // a buffer of 4 GiB or more: a descriptor per plane; g.steps <= TS
+        if constexpr (march_big_ok(ST, V, TS)) {
+            if (g.plane_bytes == 0 || g.steps < 2 || g.steps > TS) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((k_stepW<ST, V, TS, true>), dim3((unsigned)nb), dim3(64 * sl.waves), 0, st, g, p);
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
+    }
     hipLaunchKernelGGL((k_stepW<ST, V, TS>), dim3((unsigned)nb), dim3(64 * sl.waves), 0, st, g, p);
     return hipGetLastError();
 }
@@ -103,6 +111,17 @@ inline hipError_t launch_stepW_t(const StepLaunch &sl, const GridT &g, const voi
 template <int ST, int V>
 inline hipError_t launch_stepW_n(const StepLaunch &sl, const GridT &g, const void *params, hipStream_t st) {
     static_assert(kMaxFusedSteps == 8 && kMaxMarchSteps == 12, "instantiate every step count");
+    if (g.bytes == 0) {
+        // buffers of 4 GiB or more: the kernel of the strips' step count
+        // (g.tw) runs g.steps of them
+        switch ((64 - g.tw) / 2 + 1) {
+            case 8: return launch_stepW_t<ST, V, 8>(sl, g, params, st);
+            case 10:
+                if constexpr (ST != kF64) return launch_stepW_t<ST, V, 10>(sl, g, params, st);
+                return hipErrorInvalidValue;
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (g.steps) {
         case 2: return launch_stepW_t<ST, V, 2>(sl, g, params, st);
         case 3: return launch_stepW_t<ST, V, 3>(sl, g, params, st);

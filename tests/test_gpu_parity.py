@@ -694,7 +694,8 @@ def test_largest_lattices_sampled_windows(n, small, fused):
     """The addressing limits of the kernels, FP32 Gray-Scott: at 7680^2 each
     buffer is just under 4 GiB, the largest one buffer resource with 32-bit
     byte offsets covers; at 8192^2 a buffer exceeds 4 GiB and the default
-    multi-step launch addresses it plane by plane (each plane 256 MiB); the
+    multi-step launch (marching strips, 8 steps) addresses it plane by plane
+    (each plane 256 MiB), 26 steps ending with a launch of 2; the
     one-step kernel (64-bit offsets) is forced there too.  26 steps (ragged
     against the steps per launch); sampled windows touching the first and
     last rows and columns against the FP64 oracle within 1e-5."""
@@ -709,7 +710,9 @@ def test_largest_lattices_sampled_windows(n, small, fused):
         assert t.fused_steps >= 2 and t.tile_cols in (32, 64), t.as_dict()
         if not small:
             with pytest.raises(lbrd.LbrdError):   # 128-wide tiles need buffers below 4 GiB
-                s.set_tuning(tile_cols=128, tile_rows=4, fused_steps=4)
+                s.set_tuning(tile_cols=128, tile_rows=4, fused_steps=4, march_rows=0)
+            with pytest.raises(lbrd.LbrdError):   # marching strips there: 8 or 10 steps a launch
+                s.set_tuning(fused_steps=7, march_rows=64)
         if fused is not None:
             s.set_tuning(fused_steps=fused)
         s.init(rho0).step(steps)
@@ -733,9 +736,12 @@ def test_largest_lattices_sampled_windows(n, small, fused):
 @pytest.mark.parametrize("storage", ["f32", "f16"])
 def test_plane_addressed_multi_step_is_bitwise_identical(storage):
     """Buffers of 4 GiB or more (8192^2 FP32; 12288^2 F16 with two species):
-    the multi-step launch that addresses each plane with its own 32-bit
-    resource equals one-step launches (64-bit offsets) bitwise on every
-    population, default shape and a 64-wide one, 2..T-1 remainders included."""
+    the multi-step launches that address each plane with its own 32-bit
+    resource equal one-step launches (64-bit offsets) bitwise on every
+    population: the default (marching strips, T = 8, 13 steps so that a
+    launch of 5 steps on the strips of 8 follows), 10 steps a launch (a
+    launch of 3 follows), and LDS tiles 64 wide (T = 4, remainders
+    included)."""
     n = 8192 if storage == "f32" else 12288
     extra = dict(rho_ref=(1.0, 0.0)) if storage == "f16" else {}
     cfg = lbrd.make_config(n, n, 2, storage=storage, tau=workloads.GS_TAU, reaction="gray_scott",
@@ -745,18 +751,20 @@ def test_plane_addressed_multi_step_is_bitwise_identical(storage):
     s = lbrd.Solver(cfg)
     try:
         d = s.tuning()
-        assert d.fused_steps >= 2
+        assert d.fused_steps == 8 and d.march_rows > 0, d.as_dict()
         s.set_tuning(fused_steps=1, graph_steps=0)
-        s.init(rho0).step(11)
+        s.init(rho0).step(13)
         want = s.get_populations(dtype=torch.float32)
-        for T, cols, rows in ((d.fused_steps, d.tile_cols, d.tile_rows), (4, 64, 8)):
-            s.set_tuning(fused_steps=T, tile_cols=cols, tile_rows=rows, tile_strip=d.tile_strip)
-            s.init(rho0).step(11)
+        for shape in (dict(fused_steps=d.fused_steps, march_rows=d.march_rows, waves=d.waves),
+                      dict(fused_steps=10, march_rows=777, waves=1),
+                      dict(fused_steps=4, tile_cols=64, tile_rows=8, march_rows=0, waves=8, tile_strip=0)):
+            s.set_tuning(**shape)
+            s.init(rho0).step(13)
             got = s.get_populations(dtype=torch.float32)
-            assert torch.equal(got, want), (storage, T, cols, rows)
+            assert torch.equal(got, want), (storage, shape)
             del got
-        log(f"{n}^2 {storage}: plane-addressed multi-step ({d.fused_steps}, {d.tile_cols} x {d.tile_rows}) "
-            f"bitwise equal to one-step launches")
+        log(f"{n}^2 {storage}: plane-addressed marching strips (T {d.fused_steps}, {d.march_rows} rows) and LDS "
+            f"tiles bitwise equal to one-step launches")
     finally:
         s.close()
         del s
