@@ -733,6 +733,36 @@ def test_largest_lattices_sampled_windows(n, small, fused):
     assert np.all(np.isfinite(mass))
 
 
+@pytest.mark.parametrize("ny,multi", [((1 << 24) + 64, False), (1 << 24, True)])
+def test_tall_lattices_keep_multi_step_row_offsets_in_range(ny, multi):
+    """The multi-step kernels form row offsets with 24-bit multiplies (row
+    index times row pitch), so a lattice with more than 2^24 rows must run
+    one-step launches (64-bit offsets): its default tuning takes one step per
+    launch and every multi-step tuning is refused, while at exactly 2^24 rows
+    several steps per launch remain the default.  16 x ny FP32, one linear
+    species (each buffer about 9.7 GB, addressed plane by plane); only the
+    solver's tuning is examined, no step is launched."""
+    cfg = lbrd.make_config(16, ny, 1, storage="f32", tau=1.0, reaction="linear", K=[-1e-3])
+    assert lbrd.workspace_size(cfg) // 2 >= (1 << 32)
+    s = lbrd.Solver(cfg)
+    try:
+        t = s.tuning()
+        log(f"16 x {ny} f32: default {t.as_dict()}")
+        if multi:
+            assert t.fused_steps >= 2, t.as_dict()
+        else:
+            assert t.fused_steps == 1, t.as_dict()
+            with pytest.raises(lbrd.LbrdError):   # marching strips
+                s.set_tuning(fused_steps=8, march_rows=64, waves=4)
+            with pytest.raises(lbrd.LbrdError):   # LDS tiles
+                s.set_tuning(fused_steps=4, tile_cols=64, tile_rows=4, march_rows=0)
+            assert s.tuning().fused_steps == 1
+    finally:
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("storage", ["f32", "f16"])
 def test_plane_addressed_multi_step_is_bitwise_identical(storage):
     """Buffers of 4 GiB or more (8192^2 FP32; 12288^2 F16 with two species):
